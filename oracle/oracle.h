@@ -1,0 +1,131 @@
+/*
+ * oracle.h -- plain FP64 CPU reference of the multi-scale semi-Lagrangian
+ * lattice Boltzmann step (Kallikounis, Dorschner & Karlin, arXiv 2102.12559).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or calls
+ * this library: only the test suite, the smoke check and the CPU leg of the
+ * benchmark do.  It shares no source with the GPU library.
+ *
+ * The oracle follows the paper's definitions literally:
+ *   - Gauss-Hermite rules by Newton iteration on He_n (Sec. II.A, Tab. I);
+ *   - tensor-product velocity sets, W_i = w_ix w_iy (w_iz) (eqs. ci, wi);
+ *   - moment matrix M[(m,n),i] = c_ix^m c_iy^n, m,n < sqrt(Q) (eq. momf), inverted
+ *     in long double;
+ *   - lattice equilibrium f^L = M_L^{-1} M_{u,T} f^eq with f^eq = rho W
+ *     (Sec. II.C.2, eqs. feqL, geqL, feqL0);
+ *   - lifting m_q (+) M^eq_{Q-q} and projection M_q (Sec. III.B, III.C, App. C);
+ *   - semi-Lagrangian propagation with lifting / projection applied to each
+ *     collocation point of the other order (Sec. III.D), then BGK collision
+ *     (eqs. Pond_f, Pond_g with omega1 = omega2).
+ *
+ * Pins (tests/test_oracle_*.py): Table I nodes and weights, Gauss-Hermite
+ * exactness, the printed diagonal moments (eqs. QxxxL, RxxL, QxxxPonD, RxxPond)
+ * and Fig. 1's 3 %, the closed Hermite product form of f^L, lifting/projection
+ * moment properties and round trips, exact equality with a textbook D2Q9 LBM
+ * at CFL 1, conservation, fixed points, the shear-wave viscosity, vortex
+ * translation, Couette symmetry, finite-difference gradients of the MLP.
+ * Parity unpinned: the per-tile error check of the learned closure
+ * (or_mlp_check) is a rule of this implementation with no closed form to test
+ * against; only its consistency with the GPU path is checked.
+ *
+ * Conventions: cell index = x + nx*(y + ny*z); population index
+ * i = a + n*b (+ n*n*c) with a, b, c the ascending 1D node indices along x, y, z;
+ * population arrays are [Q][ncell].  All functions return 0 on success and a
+ * negative value on invalid input.
+ */
+#ifndef MSL_ORACLE_H
+#define MSL_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct or_config {
+  int dim, nx, ny, nz;
+  int n_low, n_high;          /* 1D Gauss-Hermite orders; n_high = 0: one lattice */
+  int thermal;                /* 0: T = T_L, f only; 1: f and g, ideal gas with cv */
+  double tau, cv, cfl;
+  int tau_mode;               /* 0: constant tau; 1: mu = mu_ref (T/T_ref)^mu_exp */
+  double mu_exp, tau_ref_rho, tau_ref_T;
+  double rho0, T0;            /* reference state of the reduced-precision storage */
+  int store;                  /* 0 fp64, 1 fp32, 2 fp16 deviation, 3 bf16 deviation */
+  int lift_mode;              /* 0 raw moments (App. C), 1 Hermite coefficients, 2 MLP */
+  int bc[6];                  /* face = 2*axis + side: 0 periodic, 1 fixed eq, 2 zero gradient, 3 diffuse wall */
+  double bc_state[6][5];      /* rho, ux, uy, uz, T (walls: u_w, T_w) */
+  double slot_state[6][5];
+  int slot[6][4];             /* [lo0,hi0) [lo1,hi1) on the tangential axes; lo>=hi: none */
+  int crit_kind;              /* 0 none, 1 Mach, 2 |Pi_neq|/p */
+  double crit_thr;
+  int crit_every;
+} or_config;
+
+typedef struct or_ctx or_ctx;
+
+/* ---- lattice-level routines (for pins) ---- */
+int or_gh_rule(int n, double *x, double *w);
+int or_lattice_feq(int dim, int n, double rho, const double *u, double theta, double *out);
+int or_moment_matrix(int dim, int n, double *M, double *Minv);
+/* lifting / projection of one cell's populations; g may be NULL when thermal=0 */
+int or_lift(int dim, int nq, int nQ, int thermal, double cv, int mode,
+            const double *fq, const double *gq, double *fQ, double *gQ);
+int or_project(int dim, int nQ, int nq, const double *fQ, const double *gQ,
+               double *fq, double *gq);
+/* Lagrange weights of the 3-point stencil through -1, 0, 1 at xi */
+int or_lagrange3(double xi, double *a);
+/* round-to-nearest-even conversions used by the deviation-storage emulation */
+double or_round_fp16(double v);
+double or_round_bf16(double v);
+
+/* ---- stepper ---- */
+int or_create(const or_config *cfg, or_ctx **out);
+void or_destroy(or_ctx *ctx);
+double or_dt(const or_ctx *ctx);
+int or_reach(const or_ctx *ctx);
+/* per population of lattice `which`: base offsets n0[Q][D] and weights a[Q][D][3] */
+int or_stencil(const or_ctx *ctx, int which, int *n0, double *a);
+int or_set_mask_raw(or_ctx *ctx, const uint8_t *mask);   /* no conversion */
+int or_set_mask(or_ctx *ctx, const uint8_t *mask);       /* lift/project switched cells */
+int or_get_mask(const or_ctx *ctx, uint8_t *mask);
+int or_eval_criterion(const or_ctx *ctx, uint8_t *newmask, double *value);
+int or_init(or_ctx *ctx, const double *rho, const double *u, const double *T);
+int or_step(or_ctx *ctx, int nsteps);
+long or_step_count(const or_ctx *ctx);
+int or_get_pops(const or_ctx *ctx, int which, int fg, double *out);
+int or_set_pops(or_ctx *ctx, int which, int fg, const double *in);
+int or_macros(const or_ctx *ctx, double *rho, double *u, double *T);
+int or_conservation(const or_ctx *ctx, double *out);     /* sum rho, sum j (3), sum rhoE */
+/* next-step populations (native lattice) of selected cells, state untouched */
+int or_step_cells(const or_ctx *ctx, int ncells, const int64_t *cells,
+                  double *fout, double *gout);
+
+/* ---- learned lifting closure (MLP) ---- */
+/* MLP F -> H -> H -> O, SiLU hidden activations; flat parameter layout
+ * W1[F][H], b1[H], W2[H][H], b2[H], W3[H][O], b3[O]. */
+int or_mlp_nparams(int F, int H, int O);
+int or_mlp_forward(const double *p, int F, int H, int O, int n, const double *X,
+                   double *Y, int bf16_inputs);
+int or_mlp_loss_grad(const double *p, int F, int H, int O, int n, const double *X,
+                     const double *T, double *loss, double *grad);
+int or_adam(double *p, double *m, double *v, const double *g, int np, int t,
+            double lr, double b1, double b2, double eps);
+/* features / targets of the closure */
+int or_mlp_dims(int dim, int nq, int nQ, int *F, int *O);
+int or_mlp_features(int dim, int nq, int thermal, double cv, const double *fq,
+                    const double *gq, double *feat);
+int or_mlp_targets(int dim, int nq, int nQ, int thermal, double cv, const double *fQ,
+                   const double *gQ, double *targ);
+/* install a network for lift_mode 2: params, input mean/std [F], target mean/std [O] */
+int or_set_mlp(or_ctx *ctx, int H, const double *params, const double *xmean,
+               const double *xstd, const double *tmean, const double *tstd, int bf16);
+/* per check tile (64 x 64 (x 64) cells) flag: 1 = use the network, 0 = Grad */
+int or_set_mlp_flags(or_ctx *ctx, const uint8_t *flags);
+int or_get_mlp_flags(const or_ctx *ctx, uint8_t *flags, double *emlp, double *egrad);
+int or_mlp_check(or_ctx *ctx);   /* recompute the flags from the high-order band cells */
+int or_lift_cell(const or_ctx *ctx, const double *fq, const double *gq, int tile,
+                 double *fQ, double *gQ);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
