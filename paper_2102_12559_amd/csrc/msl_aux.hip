@@ -1,0 +1,728 @@
+// msl_aux.hip -- the kernels around the fused stream-and-collide: equilibrium
+// initialisation, ghost-layer fill (boundary rules), band conversion by lifting
+// and projection, refinement criterion and switching, class / band / tile
+// bookkeeping with an ordered compaction of the band cells, macroscopic
+// fields, population import/export and the deterministic FP64 reductions.
+#include "msl_device.hpp"
+
+#define MSL_MAXQ 64
+#define AUX_BLOCK 256
+
+// ---------------------------------------------------------------------------
+// per-cell state access (FP64 view of the stored planes)
+// ---------------------------------------------------------------------------
+struct StateView {
+  char *f[2];        // base of lattice l's planes in the chosen buffer
+  int Q[2], nplanes[2];
+};
+
+template <typename S>
+__device__ __forceinline__ void read_cell(const Tab *tab, const Geo &g, const char *base, int l,
+                                          int off, double *f, double *gg) {
+  const LatTab &L = tab->lat[l];
+  const S *p = (const S *)base;
+  for (int i = 0; i < L.Q; ++i) {
+    const double W = pop_weight(L, g.dim, i);
+    f[i] = load_pop<S>(p + (long long)i * g.plane, off, tab->rho0 * W);
+    if (tab->thermal)
+      gg[i] = load_pop<S>(p + (long long)(L.Q + i) * g.plane, off,
+                          tab->gfac * tab->rho0 * tab->T0 * W);
+  }
+}
+
+template <typename S>
+__device__ __forceinline__ void write_cell(const Tab *tab, const Geo &g, char *base, int l, int off,
+                                           const double *f, const double *gg) {
+  const LatTab &L = tab->lat[l];
+  S *p = (S *)base;
+  for (int i = 0; i < L.Q; ++i) {
+    const double W = pop_weight(L, g.dim, i);
+    store_pop<S>(p + (long long)i * g.plane, off, f[i], tab->rho0 * W);
+    if (tab->thermal)
+      store_pop<S>(p + (long long)(L.Q + i) * g.plane, off, gg[i],
+                   tab->gfac * tab->rho0 * tab->T0 * W);
+  }
+}
+
+// Apply a 1D matrix A[nout][nin] (row stride MSL_MAXN) along every axis of a
+// tensor-product population array: out = (A x A (x A)) in.
+__device__ void tensor_apply(const double (*A)[MSL_MAXN], int nout, int nin, int dim,
+                             const double *in, double *out) {
+  double t1[MSL_MAXQ], t2[MSL_MAXQ];
+  if (dim == 2) {
+    // contract y: t1[a'][b] = sum_b' A[b][b'] in[a' + nin b']
+    for (int b = 0; b < nout; ++b)
+      for (int ap = 0; ap < nin; ++ap) {
+        double s = 0;
+        for (int bp = 0; bp < nin; ++bp) s += A[b][bp] * in[ap + nin * bp];
+        t1[ap + nin * b] = s;
+      }
+    for (int b = 0; b < nout; ++b)
+      for (int a = 0; a < nout; ++a) {
+        double s = 0;
+        for (int ap = 0; ap < nin; ++ap) s += A[a][ap] * t1[ap + nin * b];
+        out[a + nout * b] = s;
+      }
+  } else {
+    // z, then y, then x
+    for (int c = 0; c < nout; ++c)
+      for (int bp = 0; bp < nin; ++bp)
+        for (int ap = 0; ap < nin; ++ap) {
+          double s = 0;
+          for (int cp = 0; cp < nin; ++cp) s += A[c][cp] * in[ap + nin * (bp + nin * cp)];
+          t1[ap + nin * (bp + nin * c)] = s;
+        }
+    for (int c = 0; c < nout; ++c)
+      for (int b = 0; b < nout; ++b)
+        for (int ap = 0; ap < nin; ++ap) {
+          double s = 0;
+          for (int bp = 0; bp < nin; ++bp) s += A[b][bp] * t1[ap + nin * (bp + nin * c)];
+          t2[ap + nin * (b + nout * c)] = s;
+        }
+    for (int c = 0; c < nout; ++c)
+      for (int b = 0; b < nout; ++b)
+        for (int a = 0; a < nout; ++a) {
+          double s = 0;
+          for (int ap = 0; ap < nin; ++ap) s += A[a][ap] * t2[ap + nin * (b + nout * c)];
+          out[a + nout * (b + nout * c)] = s;
+        }
+  }
+}
+
+// Lifting (Sec. III.B, App. C).  With the completion M_{q->Q} = m_q (+)
+// M^eq_{Q-q}, and both velocity sets reproducing the equilibrium moments below
+// their order, f_Q = f^L_Q + M_Q^{-1} ((M_q (f_q - f^L_q)) (+) 0).  In tensor
+// form the second term is (K x K) (f_q - f^L_q) with K[a][a'] the degree < n_q
+// part of the high-order Lagrange basis polynomial l_a evaluated at the
+// low-order node c_a' (raw completion), or w_a sum_{j<n_q} He_j(C_a) He_j(c_a')/j!
+// (Hermite completion).  The learned closure adds (Vi x Vi) dM with dM the
+// predicted non-equilibrium parts of the missing raw moments.
+__device__ void lift_cell(const Tab *tab, int dim, const double *fq, const double *gq,
+                          const double *dM, double *fQ, double *gQ) {
+  const LatTab &Lq = tab->lat[0], &LQ = tab->lat[1];
+  double rho, u[3], T;
+  cell_macros(Lq, dim, tab->thermal, tab->cv, fq, gq, rho, u, T);
+  double eq_q[MSL_MAXQ], eq_Q[MSL_MAXQ], neq[MSL_MAXQ], corr[MSL_MAXQ];
+  cell_feq(Lq, dim, rho, u, T, eq_q);
+  cell_feq(LQ, dim, rho, u, T, eq_Q);
+  const double (*K)[MSL_MAXN] = tab->lift_mode == MSL_LIFT_GRAD_HERMITE ? tab->KH : tab->K;
+  for (int i = 0; i < Lq.Q; ++i) neq[i] = fq[i] - eq_q[i];
+  tensor_apply(K, LQ.n, Lq.n, dim, neq, corr);
+  for (int i = 0; i < LQ.Q; ++i) fQ[i] = eq_Q[i] + corr[i];
+  if (dM) {
+    tensor_apply(tab->Vi, LQ.n, LQ.n, dim, dM, corr);
+    for (int i = 0; i < LQ.Q; ++i) fQ[i] += corr[i];
+  }
+  if (tab->thermal) {
+    const double s = tab->gfac * T;
+    for (int i = 0; i < Lq.Q; ++i) neq[i] = gq[i] - s * eq_q[i];
+    tensor_apply(K, LQ.n, Lq.n, dim, neq, corr);
+    for (int i = 0; i < LQ.Q; ++i) gQ[i] = s * eq_Q[i] + corr[i];
+  }
+}
+
+// Projection (Sec. III.C, App. C): f_q = M_q^{-1} M_q f_Q, i.e. (P x P) f_Q with
+// P[a'][a] = l^low_{a'}(C_a), the low-order Lagrange basis at the high nodes.
+__device__ void project_cell(const Tab *tab, int dim, const double *fQ, const double *gQ,
+                             double *fq, double *gq) {
+  const LatTab &Lq = tab->lat[0], &LQ = tab->lat[1];
+  tensor_apply(tab->P, Lq.n, LQ.n, dim, fQ, fq);
+  if (tab->thermal) tensor_apply(tab->P, Lq.n, LQ.n, dim, gQ, gq);
+}
+
+__device__ __forceinline__ void cell_coords(const Geo &g, long long k, int &x, int &y, int &z) {
+  x = (int)(k % g.nx);
+  k /= g.nx;
+  y = (int)(k % g.ny);
+  z = (int)(k / g.ny);
+}
+
+// ---------------------------------------------------------------------------
+// initialisation: lattice equilibrium of each cell's own velocity set
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ void k_init_eq(const Tab *__restrict__ tab, Geo g, char *b0, char *b1,
+                          const uint8_t *__restrict__ cls, const double *__restrict__ rho,
+                          const double *__restrict__ u, const double *__restrict__ T) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.ncell) return;
+  int x, y, z;
+  cell_coords(g, k, x, y, z);
+  const int l = cls[k] & 1;
+  double uu[3] = {0, 0, 0};
+  for (int a = 0; a < g.dim; ++a) uu[a] = u[a * g.ncell + k];
+  const double Tk = (tab->thermal && T) ? T[k] : 1.0;
+  double f[MSL_MAXQ], gg[MSL_MAXQ];
+  cell_feq(tab->lat[l], g.dim, rho[k], uu, Tk, f);
+  for (int i = 0; i < tab->lat[l].Q; ++i) gg[i] = tab->gfac * Tk * f[i];
+  write_cell<S>(tab, g, l ? b1 : b0, l, g.idx(x, y, z), f, gg);
+}
+
+// ---------------------------------------------------------------------------
+// ghost layers, one pass per axis (x, then y over the x ghosts, then z over
+// the x and y ghosts), matching the resolution order highest axis first
+// ---------------------------------------------------------------------------
+struct BCArgs {
+  int bc[6];
+  double st[6][5];
+  double slot_st[6][5];
+  int slot[6][4];
+};
+
+__device__ __forceinline__ int in_slot(const BCArgs &b, int face, int dim, const int *p) {
+  const int *s = b.slot[face];
+  if (s[0] >= s[1]) return 0;
+  const int ax = face / 2;
+  int t[2], nt = 0;
+  for (int a = 0; a < dim; ++a)
+    if (a != ax) t[nt++] = a;
+  if (p[t[0]] < s[0] || p[t[0]] >= s[1]) return 0;
+  if (dim == 3 && s[2] < s[3] && (p[t[1]] < s[2] || p[t[1]] >= s[3])) return 0;
+  return 1;
+}
+
+template <typename S>
+__global__ void k_bc_pass(const Tab *__restrict__ tab, Geo g, int ax, BCArgs b, char *bl, char *bh,
+                          const uint8_t *__restrict__ cls) {
+  const int N[3] = {g.nx, g.ny, g.nz};
+  // extent of the pass: lower axes with ghosts, higher axes interior
+  int ext[3], lo[3];
+  for (int a = 0; a < 3; ++a) {
+    if (a >= g.dim) { ext[a] = 1; lo[a] = 0; continue; }
+    if (a < ax) { ext[a] = N[a] + 2 * MSL_G; lo[a] = -MSL_G; }
+    else if (a == ax) { ext[a] = 2 * MSL_G; lo[a] = 0; }
+    else { ext[a] = N[a]; lo[a] = 0; }
+  }
+  const long long tot = (long long)ext[0] * ext[1] * ext[2];
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tot) return;
+  int p[3];
+  long long r = t;
+  for (int a = 0; a < 3; ++a) {
+    p[a] = lo[a] + (int)(r % ext[a]);
+    r /= ext[a];
+  }
+  // ghost coordinate along ax
+  const int gi = p[ax];
+  const int side = gi < MSL_G ? 0 : 1;
+  p[ax] = side ? N[ax] + (gi - MSL_G) : gi - MSL_G;
+  const int face = 2 * ax + side;
+  const int rule = b.bc[face];
+  char *bases[2] = {bl, bh};
+  const int dst = g.idx(p[0], p[1], p[2]);
+  if (rule == MSL_BC_PERIODIC || rule == MSL_BC_OUTFLOW_ZG) {
+    int q[3] = {p[0], p[1], p[2]};
+    if (rule == MSL_BC_PERIODIC) q[ax] = (q[ax] % N[ax] + N[ax]) % N[ax];
+    else q[ax] = side ? N[ax] - 1 : 0;
+    const int src = g.idx(q[0], q[1], q[2]);
+    for (int l = 0; l < tab->nlat; ++l) {
+      S *pl = (S *)bases[l];
+      const int np = tab->lat[l].Q * (tab->thermal ? 2 : 1);
+      for (int i = 0; i < np; ++i) pl[(long long)i * g.plane + dst] = pl[(long long)i * g.plane + src];
+    }
+    return;
+  }
+  if (rule == MSL_BC_FIXED_EQ) {
+    const double *st = in_slot(b, face, g.dim, p) ? b.slot_st[face] : b.st[face];
+    for (int l = 0; l < tab->nlat; ++l) {
+      double f[MSL_MAXQ], gg[MSL_MAXQ];
+      cell_feq(tab->lat[l], g.dim, st[0], st + 1, st[4], f);
+      for (int i = 0; i < tab->lat[l].Q; ++i) gg[i] = tab->gfac * st[4] * f[i];
+      write_cell<S>(tab, g, bases[l], l, dst, f, gg);
+    }
+    return;
+  }
+  // diffuse wall: zero net wall-normal mass flux through the wall
+  int q[3] = {p[0], p[1], p[2]};
+  q[ax] = side ? N[ax] - 1 : 0;
+  // velocity set of the adjacent point: lower-axis ghosts map through their rule
+  int c[3] = {q[0], q[1], q[2]};
+  int use_low = 0;
+  for (int a = 0; a < ax; ++a) {
+    if (c[a] >= 0 && c[a] < N[a]) continue;
+    const int fr = b.bc[2 * a + (c[a] < 0 ? 0 : 1)];
+    if (fr == MSL_BC_PERIODIC) c[a] = (c[a] % N[a] + N[a]) % N[a];
+    else if (fr == MSL_BC_OUTFLOW_ZG) c[a] = c[a] < 0 ? 0 : N[a] - 1;
+    else use_low = 1;
+  }
+  const int m = use_low ? 0 : (cls[((long long)c[2] * g.ny + c[1]) * g.nx + c[0]] & 1);
+  const LatTab &Lm = tab->lat[m];
+  double f[MSL_MAXQ], gg[MSL_MAXQ], weq[MSL_MAXQ];
+  read_cell<S>(tab, g, bases[m], m, g.idx(q[0], q[1], q[2]), f, gg);
+  const double *ws = b.st[face];
+  cell_feq(Lm, g.dim, 1.0, ws + 1, ws[4], weq);
+  double in = 0, out = 0;
+  const int n = Lm.n;
+  for (int i = 0; i < Lm.Q; ++i) {
+    const int d = ax == 0 ? i % n : (ax == 1 ? (i / n) % n : i / (n * n));
+    const double cn = Lm.c[d];
+    if (side ? cn > 0 : cn < 0) in += fabs(cn) * f[i];
+    if (side ? cn < 0 : cn > 0) out += fabs(cn) * weq[i];
+  }
+  const double rw = in / out;
+  for (int l = 0; l < tab->nlat; ++l) {
+    cell_feq(tab->lat[l], g.dim, 1.0, ws + 1, ws[4], f);
+    for (int i = 0; i < tab->lat[l].Q; ++i) {
+      f[i] *= rw;
+      gg[i] = tab->gfac * ws[4] * f[i];
+    }
+    write_cell<S>(tab, g, bases[l], l, dst, f, gg);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// band conversion: low-order band cells are lifted into the high-order planes,
+// high-order band cells projected into the low-order planes
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ void k_band_convert(const Tab *__restrict__ tab, Geo g, char *bl, char *bh,
+                               const int *__restrict__ list_lo, const int *__restrict__ list_hi,
+                               const int *__restrict__ counts, int grad_only_mlp) {
+  const int nlo = counts[0], nhi = counts[1];
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < nlo + nhi; t += stride) {
+    const int lift = t < nlo;
+    const long long k = lift ? list_lo[t] : list_hi[t - nlo];
+    // with the learned closure, lifted band cells are written by the closure kernels
+    if (lift && grad_only_mlp) continue;
+    int x, y, z;
+    cell_coords(g, k, x, y, z);
+    const int off = g.idx(x, y, z);
+    double f[MSL_MAXQ], gg[MSL_MAXQ], fo[MSL_MAXQ], go[MSL_MAXQ];
+    if (lift) {
+      read_cell<S>(tab, g, bl, 0, off, f, gg);
+      lift_cell(tab, g.dim, f, gg, nullptr, fo, go);
+      write_cell<S>(tab, g, bh, 1, off, fo, go);
+    } else {
+      read_cell<S>(tab, g, bh, 1, off, f, gg);
+      project_cell(tab, g.dim, f, gg, fo, go);
+      write_cell<S>(tab, g, bl, 0, off, fo, go);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// refinement criterion, switching, classes, tiles, band compaction
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ void k_criterion(const Tab *__restrict__ tab, Geo g, const char *bl, const char *bh,
+                            const uint8_t *__restrict__ cls, uint8_t *__restrict__ newmask,
+                            int kind, double thr) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.ncell) return;
+  int x, y, z;
+  cell_coords(g, k, x, y, z);
+  const int l = cls[k] & 1;
+  const LatTab &L = tab->lat[l];
+  double f[MSL_MAXQ], gg[MSL_MAXQ], rho, u[3], T;
+  read_cell<S>(tab, g, l ? bh : bl, l, g.idx(x, y, z), f, gg);
+  cell_macros(L, g.dim, tab->thermal, tab->cv, f, gg, rho, u, T);
+  double v = 0;
+  if (kind == MSL_CRIT_MA) {
+    const double gam = (tab->cv + 1.0) / tab->cv;
+    const double cs = tab->thermal ? sqrt(gam * T) : 1.0;
+    v = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / cs;
+  } else {
+    double P[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    const int n = L.n;
+    for (int i = 0; i < L.Q; ++i) {
+      const double c[3] = {L.c[i % n], L.c[(i / n) % n], g.dim == 3 ? L.c[i / (n * n)] : 0.0};
+      for (int a = 0; a < g.dim; ++a)
+        for (int bb = 0; bb < g.dim; ++bb) P[a][bb] += (c[a] - u[a]) * (c[bb] - u[bb]) * f[i];
+    }
+    const double p = rho * T;
+    double s = 0;
+    for (int a = 0; a < g.dim; ++a)
+      for (int bb = 0; bb < g.dim; ++bb) {
+        const double d = P[a][bb] - (a == bb ? p : 0.0);
+        s += d * d;
+      }
+    v = sqrt(s) / p;
+  }
+  newmask[k] = v > thr ? 1 : 0;
+}
+
+__global__ void k_mask_out(const uint8_t *__restrict__ cls, long long n, uint8_t *__restrict__ m) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) m[k] = cls[k] & 1;
+}
+
+__global__ void k_check_mask(const uint8_t *__restrict__ m, long long n, int allow_high,
+                             int *__restrict__ flag) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  if (m[k] > 1 || (m[k] == 1 && !allow_high)) atomicOr(flag, 1);
+}
+
+// switching: cells whose order changes lift / project their own state
+template <typename S>
+__global__ void k_switch(const Tab *__restrict__ tab, Geo g, char *bl, char *bh,
+                         uint8_t *__restrict__ cls, const uint8_t *__restrict__ newmask,
+                         int convert) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.ncell) return;
+  const int from = cls[k] & 1, to = newmask[k] & 1;
+  if (from != to && convert) {
+    int x, y, z;
+    cell_coords(g, k, x, y, z);
+    const int off = g.idx(x, y, z);
+    double f[MSL_MAXQ], gg[MSL_MAXQ], fo[MSL_MAXQ], go[MSL_MAXQ];
+    if (to == 1) {
+      read_cell<S>(tab, g, bl, 0, off, f, gg);
+      lift_cell(tab, g.dim, f, gg, nullptr, fo, go);
+      write_cell<S>(tab, g, bh, 1, off, fo, go);
+    } else {
+      read_cell<S>(tab, g, bh, 1, off, f, gg);
+      project_cell(tab, g.dim, f, gg, fo, go);
+      write_cell<S>(tab, g, bl, 0, off, fo, go);
+    }
+  }
+  cls[k] = (uint8_t)to;
+}
+
+// band bit: a cell of one order within the stencil reach (Chebyshev distance
+// <= G, through periodic wrap, clamped at other faces) of a cell of the other
+__global__ void k_classify(Geo g, int bc_periodic_mask, uint8_t *__restrict__ cls) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.ncell) return;
+  int x, y, z;
+  cell_coords(g, k, x, y, z);
+  const int o = cls[k] & 1;
+  const int N[3] = {g.nx, g.ny, g.nz};
+  int band = 0;
+  const int R = MSL_G;
+  const int zr = g.dim == 3 ? R : 0;
+  for (int dz = -zr; dz <= zr && !band; ++dz)
+    for (int dy = -R; dy <= R && !band; ++dy)
+      for (int dx = -R; dx <= R && !band; ++dx) {
+        int q[3] = {x + dx, y + dy, z + dz};
+        for (int a = 0; a < g.dim; ++a) {
+          if (q[a] >= 0 && q[a] < N[a]) continue;
+          const int side = q[a] < 0 ? 0 : 1;
+          if (bc_periodic_mask & (1 << (2 * a + side))) q[a] = (q[a] % N[a] + N[a]) % N[a];
+          else q[a] = side ? N[a] - 1 : 0;
+        }
+        const long long kk = ((long long)q[2] * g.ny + q[1]) * g.nx + q[0];
+        if ((cls[kk] & 1) != o) band = 1;
+      }
+  cls[k] = (uint8_t)(o | (band << 1));
+}
+
+// per micro-tile (64 x 4 (x 1)) presence of each order
+__global__ void k_tileflags(Geo g, const uint8_t *__restrict__ cls, uint8_t *__restrict__ tflag) {
+  const long long t = blockIdx.x;   // one 64-thread block per micro-tile
+  const int mx = (int)(t % g.ntx);
+  const int my = (int)((t / g.ntx) % g.nty);
+  const int mz = (int)(t / ((long long)g.ntx * g.nty));
+  const int x = mx * MSL_TX + threadIdx.x;
+  uint32_t bits = 0;
+  if (x < g.nx)
+    for (int r = 0; r < MSL_MTY; ++r) {
+      const int y = my * MSL_MTY + r;
+      if (y < g.ny) bits |= 1u << (cls[((long long)mz * g.ny + y) * g.nx + x] & 1);
+    }
+  __shared__ uint32_t s[64];
+  s[threadIdx.x] = bits;
+  __syncthreads();
+  for (int w = 32; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] |= s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tflag[t] = (uint8_t)s[0];
+}
+
+// ordered compaction of the band cells of each order: counts per block of
+// 4096 cells, one scan over the blocks, then an ordered scatter
+#define CMP_CELLS 4096
+__global__ void k_band_count(Geo g, const uint8_t *__restrict__ cls, int *__restrict__ blk, int nblk) {
+  const long long base = (long long)blockIdx.x * CMP_CELLS;
+  int c0 = 0, c1 = 0;
+  for (int j = threadIdx.x; j < CMP_CELLS; j += blockDim.x) {
+    const long long k = base + j;
+    if (k < g.ncell) {
+      const uint8_t v = cls[k];
+      if (v & 2) { if (v & 1) ++c1; else ++c0; }
+    }
+  }
+  __shared__ int s0[AUX_BLOCK], s1[AUX_BLOCK];
+  s0[threadIdx.x] = c0;
+  s1[threadIdx.x] = c1;
+  __syncthreads();
+  for (int w = AUX_BLOCK / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s0[threadIdx.x] += s0[threadIdx.x + w];
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    blk[blockIdx.x] = s0[0];
+    blk[nblk + blockIdx.x] = s1[0];
+  }
+}
+
+__global__ void k_band_scan(int *__restrict__ blk, int nblk, int *__restrict__ counts) {
+  // single thread per list: nblk is at most a few thousand
+  const int l = threadIdx.x;
+  if (l > 1) return;
+  int *b = blk + (long long)l * nblk;
+  int run = 0;
+  for (int i = 0; i < nblk; ++i) {
+    const int v = b[i];
+    b[i] = run;
+    run += v;
+  }
+  counts[l] = run;
+}
+
+__global__ void k_band_scatter(Geo g, const uint8_t *__restrict__ cls, const int *__restrict__ blk,
+                               int nblk, int *__restrict__ lo, int *__restrict__ hi) {
+  // one wavefront per block walks its 4096 cells in 64-cell chunks, in order
+  const long long base = (long long)blockIdx.x * CMP_CELLS;
+  int off0 = blk[blockIdx.x], off1 = blk[nblk + blockIdx.x];
+  const int lane = threadIdx.x;
+  for (int j = 0; j < CMP_CELLS; j += 64) {
+    const long long k = base + j + lane;
+    uint8_t v = k < g.ncell ? cls[k] : 0;
+    const bool p0 = (v & 2) && !(v & 1), p1 = (v & 2) && (v & 1);
+    const unsigned long long m0 = __ballot(p0), m1 = __ballot(p1);
+    const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    if (p0) lo[off0 + __popcll(m0 & below)] = (int)k;
+    if (p1) hi[off1 + __popcll(m1 & below)] = (int)k;
+    off0 += __popcll(m0);
+    off1 += __popcll(m1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// macroscopic fields, population import / export
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ void k_macros(const Tab *__restrict__ tab, Geo g, const char *bl, const char *bh,
+                         const uint8_t *__restrict__ cls, double *rho, double *u, double *T) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.ncell) return;
+  int x, y, z;
+  cell_coords(g, k, x, y, z);
+  const int l = cls[k] & 1;
+  double f[MSL_MAXQ], gg[MSL_MAXQ], r, uu[3], t;
+  read_cell<S>(tab, g, l ? bh : bl, l, g.idx(x, y, z), f, gg);
+  cell_macros(tab->lat[l], g.dim, tab->thermal, tab->cv, f, gg, r, uu, t);
+  if (rho) rho[k] = r;
+  if (u)
+    for (int a = 0; a < g.dim; ++a) u[a * g.ncell + k] = uu[a];
+  if (T) T[k] = t;
+}
+
+template <typename S>
+__global__ void k_pops(const Tab *__restrict__ tab, Geo g, char *base, int l, int fg,
+                       const uint8_t *__restrict__ cls, double *out, const double *in) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.ncell) return;
+  int x, y, z;
+  cell_coords(g, k, x, y, z);
+  const int off = g.idx(x, y, z);
+  const LatTab &L = tab->lat[l];
+  S *p = (S *)base;
+  for (int i = 0; i < L.Q; ++i) {
+    const double W = pop_weight(L, g.dim, i);
+    const double sc = fg ? tab->gfac * tab->rho0 * tab->T0 * W : tab->rho0 * W;
+    S *pl = p + (long long)(fg * L.Q + i) * g.plane;
+    if (out) out[(long long)i * g.ncell + k] = load_pop<S>(pl, off, sc);
+    else if ((cls[k] & 1) == l) store_pop<S>(pl, off, in[(long long)i * g.ncell + k], sc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// deterministic FP64 sums of rho, rho u, rho E over each cell's own state, with
+// a sentinel for NaN / Inf / rho <= 0
+// ---------------------------------------------------------------------------
+#define RED_BLOCKS 1024
+template <typename S>
+__global__ void __launch_bounds__(AUX_BLOCK)
+k_conserve_partial(const Tab *__restrict__ tab, Geo g, const char *bl, const char *bh,
+                   const uint8_t *__restrict__ cls, double *__restrict__ part) {
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < g.ncell;
+       k += (long long)gridDim.x * blockDim.x) {
+    int x, y, z;
+    cell_coords(g, k, x, y, z);
+    const int l = cls[k] & 1;
+    const LatTab &L = tab->lat[l];
+    double f[MSL_MAXQ], gg[MSL_MAXQ];
+    read_cell<S>(tab, g, l ? bh : bl, l, g.idx(x, y, z), f, gg);
+    const int n = L.n;
+    double r = 0;
+    for (int i = 0; i < L.Q; ++i) {
+      const double c[3] = {L.c[i % n], L.c[(i / n) % n], g.dim == 3 ? L.c[i / (n * n)] : 0.0};
+      r += f[i];
+      acc[1] += c[0] * f[i];
+      acc[2] += c[1] * f[i];
+      acc[3] += c[2] * f[i];
+      acc[4] += 0.5 * (c[0] * c[0] + c[1] * c[1] + c[2] * c[2]) * f[i];
+      if (tab->thermal) acc[4] += gg[i];
+    }
+    acc[0] += r;
+    if (!(r > 0.0) || isinf(r)) acc[5] = 1.0;
+  }
+  __shared__ double s[6][AUX_BLOCK];
+  for (int m = 0; m < 6; ++m) s[m][threadIdx.x] = acc[m];
+  __syncthreads();
+  for (int w = AUX_BLOCK / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int m = 0; m < 6; ++m) {
+        if (m == 5) s[m][threadIdx.x] = fmax(s[m][threadIdx.x], s[m][threadIdx.x + w]);
+        else s[m][threadIdx.x] += s[m][threadIdx.x + w];
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int m = 0; m < 6; ++m) part[blockIdx.x * 6 + m] = s[m][0];
+}
+
+__global__ void k_conserve_final(const double *__restrict__ part, int nb, double *__restrict__ out) {
+  __shared__ double s[6][AUX_BLOCK];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nb; b += blockDim.x)
+    for (int m = 0; m < 6; ++m) {
+      const double v = part[b * 6 + m];
+      if (m == 5) acc[m] = fmax(acc[m], v);
+      else acc[m] += v;
+    }
+  for (int m = 0; m < 6; ++m) s[m][threadIdx.x] = acc[m];
+  __syncthreads();
+  for (int w = AUX_BLOCK / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int m = 0; m < 6; ++m) {
+        if (m == 5) s[m][threadIdx.x] = fmax(s[m][threadIdx.x], s[m][threadIdx.x + w]);
+        else s[m][threadIdx.x] += s[m][threadIdx.x + w];
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int m = 0; m < 5; ++m) out[m] = s[m][0];
+    // a NaN anywhere propagates into the sums
+    const bool bad = s[5][0] > 0.0 || isnan(s[0][0]) || isnan(s[4][0]) || isinf(s[0][0]) ||
+                     isinf(s[4][0]);
+    out[5] = bad ? 1.0 : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nblocks(long long n) { return (unsigned)((n + AUX_BLOCK - 1) / AUX_BLOCK); }
+
+#define DISPATCH_STORE(c, KERNEL, grid, block, ...)                                         \
+  do {                                                                                      \
+    switch ((c)->cfg.store) {                                                               \
+      case MSL_FP64: hipLaunchKernelGGL(KERNEL<double>, grid, block, 0, (c)->stream, __VA_ARGS__); break; \
+      case MSL_FP32: hipLaunchKernelGGL(KERNEL<float>, grid, block, 0, (c)->stream, __VA_ARGS__); break;  \
+      case MSL_FP16_DEV: hipLaunchKernelGGL(KERNEL<_Float16>, grid, block, 0, (c)->stream, __VA_ARGS__); break; \
+      case MSL_BF16_DEV: hipLaunchKernelGGL(KERNEL<bf16_t>, grid, block, 0, (c)->stream, __VA_ARGS__); break;  \
+      default: return MSL_EINVAL;                                                           \
+    }                                                                                       \
+  } while (0)
+
+static inline int last_err() { return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP; }
+
+int msl_launch_init_eq(msl_ctx *c, const double *rho, const double *u, const double *T) {
+  char *b0 = c->planes[0][c->cur], *b1 = c->nlat > 1 ? c->planes[1][c->cur] : nullptr;
+  DISPATCH_STORE(c, k_init_eq, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), c->dtab, c->geo, b0, b1,
+                 c->cls, rho, u, T);
+  return last_err();
+}
+
+int msl_launch_bc(msl_ctx *c, char *bl, char *bh) {
+  BCArgs b;
+  for (int f = 0; f < 6; ++f) {
+    b.bc[f] = c->cfg.bc[f];
+    for (int m = 0; m < 5; ++m) {
+      b.st[f][m] = c->cfg.bc_state[f][m];
+      b.slot_st[f][m] = c->cfg.slot_state[f][m];
+    }
+    for (int m = 0; m < 4; ++m) b.slot[f][m] = c->cfg.slot[f][m];
+  }
+  const Geo &g = c->geo;
+  const int N[3] = {g.nx, g.ny, g.nz};
+  for (int ax = 0; ax < c->D; ++ax) {
+    long long tot = 2 * MSL_G;
+    for (int a = 0; a < c->D; ++a)
+      if (a != ax) tot *= a < ax ? N[a] + 2 * MSL_G : N[a];
+    DISPATCH_STORE(c, k_bc_pass, dim3(nblocks(tot)), dim3(AUX_BLOCK), c->dtab, g, ax, b, bl, bh,
+                   c->cls);
+  }
+  return last_err();
+}
+
+int msl_launch_band_convert(msl_ctx *c, char *bl, char *bh) {
+  if (c->nlat < 2) return MSL_OK;
+  const int mlp = c->cfg.lift_mode == MSL_LIFT_MLP && c->mlp_on;
+  DISPATCH_STORE(c, k_band_convert, dim3(512), dim3(AUX_BLOCK), c->dtab, c->geo, bl, bh,
+                 c->blist[0], c->blist[1], c->bcount, mlp);
+  return last_err();
+}
+
+int msl_launch_criterion(msl_ctx *c) {
+  DISPATCH_STORE(c, k_criterion, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), c->dtab, c->geo,
+                 c->planes[0][c->cur], c->nlat > 1 ? c->planes[1][c->cur] : nullptr, c->cls,
+                 c->newmask, c->cfg.crit_kind, c->cfg.crit_thr);
+  return last_err();
+}
+
+int msl_launch_check_mask(msl_ctx *c, const uint8_t *mask) {
+  hipLaunchKernelGGL(k_check_mask, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), 0, c->stream, mask,
+                     c->ncell, c->nlat > 1, c->flag);
+  return last_err();
+}
+
+int msl_launch_get_mask(msl_ctx *c, uint8_t *mask) {
+  hipLaunchKernelGGL(k_mask_out, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), 0, c->stream, c->cls,
+                     c->ncell, mask);
+  return last_err();
+}
+
+int msl_launch_switch(msl_ctx *c, const uint8_t *newmask) {
+  char *bl = c->planes[0][c->cur], *bh = c->nlat > 1 ? c->planes[1][c->cur] : nullptr;
+  DISPATCH_STORE(c, k_switch, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), c->dtab, c->geo, bl, bh,
+                 c->cls, newmask, c->initialized && c->nlat > 1);
+  return last_err();
+}
+
+int msl_launch_classify(msl_ctx *c) {
+  int pm = 0;
+  for (int f = 0; f < 2 * c->D; ++f)
+    if (c->cfg.bc[f] == MSL_BC_PERIODIC) pm |= 1 << f;
+  hipLaunchKernelGGL(k_classify, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), 0, c->stream, c->geo, pm,
+                     c->cls);
+  const Geo &g = c->geo;
+  const long long nt = (long long)g.ntx * g.nty * g.ntz;
+  hipLaunchKernelGGL(k_tileflags, dim3((unsigned)nt), dim3(64), 0, c->stream, g, c->cls, c->tflag);
+  hipLaunchKernelGGL(k_band_count, dim3(c->nblk), dim3(AUX_BLOCK), 0, c->stream, g, c->cls, c->blk,
+                     c->nblk);
+  hipLaunchKernelGGL(k_band_scan, dim3(1), dim3(64), 0, c->stream, c->blk, c->nblk, c->bcount);
+  hipLaunchKernelGGL(k_band_scatter, dim3(c->nblk), dim3(64), 0, c->stream, g, c->cls, c->blk,
+                     c->nblk, c->blist[0], c->blist[1]);
+  return last_err();
+}
+
+int msl_launch_macros(msl_ctx *c, double *rho, double *u, double *T) {
+  DISPATCH_STORE(c, k_macros, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), c->dtab, c->geo,
+                 c->planes[0][c->cur], c->nlat > 1 ? c->planes[1][c->cur] : nullptr, c->cls, rho,
+                 u, T);
+  return last_err();
+}
+
+int msl_launch_pops(msl_ctx *c, int which, int fg, double *out, const double *in) {
+  DISPATCH_STORE(c, k_pops, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), c->dtab, c->geo,
+                 c->planes[which][c->cur], which, fg, c->cls, out, in);
+  return last_err();
+}
+
+int msl_launch_conservation(msl_ctx *c, double *dev_out6) {
+  DISPATCH_STORE(c, k_conserve_partial, dim3(RED_BLOCKS), dim3(AUX_BLOCK), c->dtab, c->geo,
+                 c->planes[0][c->cur], c->nlat > 1 ? c->planes[1][c->cur] : nullptr, c->cls, c->red);
+  hipLaunchKernelGGL(k_conserve_final, dim3(1), dim3(AUX_BLOCK), 0, c->stream, c->red, RED_BLOCKS,
+                     dev_out6);
+  return last_err();
+}

@@ -1,0 +1,651 @@
+// msl_capi.hip -- the C-ABI entry points: configuration checks, velocity-set
+// tables, workspace layout and the time-step driver.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "msl_device.hpp"
+
+typedef long double ld;
+
+// ---------------------------------------------------------------------------
+// host tables
+// ---------------------------------------------------------------------------
+
+// Gauss-Hermite rule for the weight exp(-c^2/2)/sqrt(2 pi) by the Golub-Welsch
+// method: the nodes are the eigenvalues of the Jacobi matrix of the orthonormal
+// Hermite recurrence x p_k = sqrt(k+1) p_{k+1} + sqrt(k) p_{k-1}, the weights
+// the squared first components of its unit eigenvectors.  Cyclic Jacobi
+// rotations in long double.
+static int gauss_hermite(int n, ld *x, ld *w) {
+  if (n < 1 || n > MSL_MAXN) return -1;
+  ld A[MSL_MAXN][MSL_MAXN] = {{0}}, V[MSL_MAXN][MSL_MAXN] = {{0}};
+  for (int k = 0; k < n; ++k) V[k][k] = 1.0L;
+  for (int k = 0; k + 1 < n; ++k) A[k][k + 1] = A[k + 1][k] = sqrtl((ld)(k + 1));
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    ld off = 0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += A[p][q] * A[p][q];
+    if (off < 1e-60L) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        if (A[p][q] == 0.0L) continue;
+        const ld th = (A[q][q] - A[p][p]) / (2.0L * A[p][q]);
+        const ld t = (th >= 0 ? 1.0L : -1.0L) / (fabsl(th) + sqrtl(th * th + 1.0L));
+        const ld cs = 1.0L / sqrtl(t * t + 1.0L), sn = t * cs;
+        for (int k = 0; k < n; ++k) {
+          const ld akp = A[k][p], akq = A[k][q];
+          A[k][p] = cs * akp - sn * akq;
+          A[k][q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const ld apk = A[p][k], aqk = A[q][k];
+          A[p][k] = cs * apk - sn * aqk;
+          A[q][k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const ld vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = cs * vkp - sn * vkq;
+          V[k][q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+  // sort ascending
+  int idx[MSL_MAXN];
+  for (int k = 0; k < n; ++k) idx[k] = k;
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j)
+      if (A[idx[j]][idx[j]] < A[idx[i]][idx[i]]) { int t = idx[i]; idx[i] = idx[j]; idx[j] = t; }
+  for (int k = 0; k < n; ++k) {
+    x[k] = A[idx[k]][idx[k]];
+    w[k] = V[0][idx[k]] * V[0][idx[k]];
+  }
+  // symmetrise (the rule is symmetric about 0)
+  for (int k = 0; k < n / 2; ++k) {
+    const ld xs = 0.5L * (x[n - 1 - k] - x[k]), ws = 0.5L * (w[k] + w[n - 1 - k]);
+    x[k] = -xs; x[n - 1 - k] = xs;
+    w[k] = ws; w[n - 1 - k] = ws;
+  }
+  if (n % 2) x[n / 2] = 0.0L;
+  return 0;
+}
+
+static ld hermite_he(int j, ld x) {
+  ld h0 = 1.0L, h1 = x;
+  if (j == 0) return h0;
+  for (int k = 1; k < j; ++k) {
+    const ld h2 = x * h1 - (ld)k * h0;
+    h0 = h1;
+    h1 = h2;
+  }
+  return h1;
+}
+
+// coefficients (ascending powers) of the Lagrange basis polynomial l_a of `nodes`
+static void lagrange_coeffs(int n, const ld *nodes, int a, ld *coef) {
+  ld p[MSL_MAXN + 1] = {0};
+  p[0] = 1.0L;
+  int deg = 0;
+  ld den = 1.0L;
+  for (int b = 0; b < n; ++b) {
+    if (b == a) continue;
+    for (int k = deg + 1; k >= 1; --k) p[k] = p[k - 1] - nodes[b] * p[k];
+    p[0] = -nodes[b] * p[0];
+    ++deg;
+    den *= nodes[a] - nodes[b];
+  }
+  for (int k = 0; k < n; ++k) coef[k] = p[k] / den;
+}
+
+static ld lagrange_eval(int n, const ld *nodes, int a, ld x) {
+  ld v = 1.0L;
+  for (int b = 0; b < n; ++b)
+    if (b != a) v *= (x - nodes[b]) / (nodes[a] - nodes[b]);
+  return v;
+}
+
+static void build_lat(LatTab &L, int n, int dim, const ld *x, const ld *w, double dt) {
+  memset(&L, 0, sizeof(L));
+  L.n = n;
+  L.Q = dim == 2 ? n * n : n * n * n;
+  for (int a = 0; a < n; ++a) {
+    L.c[a] = (double)x[a];
+    L.w[a] = (double)w[a];
+    L.cf[a] = (float)x[a];
+    L.wf[a] = (float)w[a];
+    ld fact = 1.0L;
+    for (int j = 0; j < n; ++j) {
+      if (j > 0) fact *= (ld)j;
+      const ld v = w[a] * hermite_he(j, x[a]) / fact;
+      L.hw[a][j] = (double)v;
+      L.hwf[a][j] = (float)v;
+    }
+    // departure point x - c dt: base node n0 = nearest integer offset, xi in [-1/2, 1/2)
+    const ld d = -x[a] * (ld)dt;
+    const int n0 = (int)floorl(d + 0.5L);
+    const ld xi = d - (ld)n0;
+    const ld wts[3] = {0.5L * xi * (xi - 1.0L), 1.0L - xi * xi, 0.5L * xi * (xi + 1.0L)};
+    L.n0[a] = n0;
+    for (int s = 0; s < 3; ++s) {
+      L.a[a][s] = (double)wts[s];
+      L.af[a][s] = (float)wts[s];
+    }
+  }
+}
+
+static void set_err(msl_ctx *c, const char *m) {
+  if (c) snprintf(c->err, sizeof(c->err), "%s", m);
+}
+
+// ---------------------------------------------------------------------------
+// configuration checks and workspace layout
+// ---------------------------------------------------------------------------
+
+static size_t store_size(int s) {
+  switch (s) {
+    case MSL_FP64: return 8;
+    case MSL_FP32: return 4;
+    case MSL_FP16_DEV:
+    case MSL_BF16_DEV: return 2;
+  }
+  return 0;
+}
+
+static const char *check_config(const msl_config *cfg) {
+  if (!cfg) return "null config";
+  if (cfg->dim != 2 && cfg->dim != 3) return "dim must be 2 or 3";
+  if (cfg->nx < 4 || cfg->ny < 4 || (cfg->dim == 3 && cfg->nz < 4)) return "grid smaller than the stencil";
+  const int maxn = cfg->dim == 2 ? 6 : 4;
+  if (cfg->n_low < 3 || cfg->n_low > maxn) return "unsupported low order";
+  if (cfg->n_high && (cfg->n_high <= cfg->n_low || cfg->n_high > maxn)) return "need n_low < n_high <= 6 (2D) / 4 (3D)";
+  if (!(cfg->tau > 0.5)) return "tau must exceed 1/2";
+  if (!(cfg->cfl > 0.0) || cfg->cfl > 1.0) return "cfl must be in (0, 1] for the 3-point stencil";
+  if (store_size(cfg->store) == 0) return "unknown storage precision";
+  if (cfg->thermal && !(cfg->cv > 0.5 * cfg->dim)) return "thermal model needs cv > D/2";
+  if (cfg->lift_mode < 0 || cfg->lift_mode > 2) return "unknown lift mode";
+  if (cfg->lift_mode == MSL_LIFT_MLP && !cfg->n_high) return "learned lifting needs two velocity sets";
+  if (cfg->crit_kind < 0 || cfg->crit_kind > 2) return "unknown criterion";
+  if (cfg->store >= MSL_FP16_DEV && !(cfg->rho0 > 0.0 && cfg->T0 > 0.0)) return "deviation storage needs rho0, T0 > 0";
+  const long long cells = (long long)cfg->nx * cfg->ny * (cfg->dim == 3 ? cfg->nz : 1);
+  if (cells >= (1ll << 31)) return "grid too large";
+  for (int f = 0; f < 2 * cfg->dim; ++f) {
+    if (cfg->bc[f] < 0 || cfg->bc[f] > 3) return "unknown boundary rule";
+    if ((cfg->bc[f] == MSL_BC_PERIODIC) != (cfg->bc[f ^ 1] == MSL_BC_PERIODIC)) return "periodic faces must come in pairs";
+    if (cfg->bc[f] == MSL_BC_DIFFUSE_WALL) {
+      if (f / 2 == 0) return "diffuse walls only on y or z faces";
+      for (int g = 0; g < 2 * (f / 2); ++g)
+        if (cfg->bc[g] != MSL_BC_PERIODIC && cfg->bc[g] != MSL_BC_OUTFLOW_ZG)
+          return "diffuse walls need periodic or zero-gradient lower faces";
+    }
+  }
+  return nullptr;
+}
+
+struct Layout {
+  Geo geo;
+  size_t esz;
+  size_t off_tab, off_planes[2], off_cls, off_newmask, off_tflag, off_blist[2], off_bcount, off_blk,
+      off_red, off_flag, off_mlp, total;
+  int nblk, Q[2], np[2];
+  long long plane_bytes;
+  int mlpF, mlpO, mlpH, mlpP, nctile, nct[3];
+  size_t mlp_off[12];
+};
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+static int roundup(int v, int m) { return (v + m - 1) / m * m; }
+
+static void make_layout(const msl_config *cfg, Layout &L) {
+  memset(&L, 0, sizeof(L));
+  Geo &g = L.geo;
+  g.dim = cfg->dim;
+  g.nx = cfg->nx;
+  g.ny = cfg->ny;
+  g.nz = cfg->dim == 3 ? cfg->nz : 1;
+  L.esz = store_size(cfg->store);
+  const int e64 = (int)(64 / L.esz);
+  g.xo = e64 > MSL_G ? e64 : MSL_G + 1;
+  g.pitch = roundup(g.xo + roundup(g.nx, MSL_TX) + MSL_G + 2, e64);
+  if (cfg->dim == 2) {
+    g.rows = MSL_G + roundup(g.ny, 16) + MSL_G + 2;
+    g.slabs = 1;
+  } else {
+    g.rows = MSL_G + roundup(g.ny, MSL_MTY) + MSL_G + 2;
+    g.slabs = MSL_G + roundup(g.nz, 4) + MSL_G + 2;
+  }
+  g.plane = (long long)g.slabs * g.rows * g.pitch;
+  g.ncell = (long long)g.nx * g.ny * g.nz;
+  g.ntx = (g.nx + MSL_TX - 1) / MSL_TX;
+  g.nty = (g.ny + MSL_MTY - 1) / MSL_MTY;
+  g.ntz = g.nz;
+  const int nl = cfg->n_high ? 2 : 1;
+  const int ns[2] = {cfg->n_low, cfg->n_high};
+  size_t off = 0;
+  L.off_tab = off;
+  off = align256(off + sizeof(Tab));
+  for (int l = 0; l < nl; ++l) {
+    L.Q[l] = cfg->dim == 2 ? ns[l] * ns[l] : ns[l] * ns[l] * ns[l];
+    L.np[l] = L.Q[l] * (cfg->thermal ? 2 : 1);
+    L.off_planes[l] = off;
+    off = align256(off + 2 * (size_t)L.np[l] * g.plane * L.esz);
+  }
+  L.off_cls = off;
+  off = align256(off + g.ncell);
+  L.off_newmask = off;
+  off = align256(off + g.ncell);
+  L.off_tflag = off;
+  off = align256(off + (size_t)g.ntx * g.nty * g.ntz);
+  for (int l = 0; l < 2; ++l) {
+    L.off_blist[l] = off;
+    off = align256(off + (nl > 1 ? (size_t)g.ncell * 4 : 4));
+  }
+  L.off_bcount = off;
+  off = align256(off + 16);
+  L.nblk = (int)((g.ncell + 4095) / 4096);
+  L.off_blk = off;
+  off = align256(off + (size_t)2 * L.nblk * 4);
+  L.off_red = off;
+  off = align256(off + (size_t)1024 * 6 * 8 + 64);
+  L.off_flag = off;
+  off = align256(off + 64);
+  // learned closure
+  if (cfg->lift_mode == MSL_LIFT_MLP && nl > 1) {
+    const int q = L.Q[0], Q = L.Q[1];
+    L.mlpF = 2 + cfg->dim + (q - 1 - cfg->dim);
+    L.mlpO = Q - q;
+    L.mlpH = cfg->mlp_hidden > 0 ? cfg->mlp_hidden : 64;
+    L.mlpP = L.mlpF * L.mlpH + L.mlpH + L.mlpH * L.mlpH + L.mlpH + L.mlpH * L.mlpO + L.mlpO;
+    for (int a = 0; a < 3; ++a) {
+      const int n = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
+      L.nct[a] = (n + MSL_CHECK_TILE - 1) / MSL_CHECK_TILE;
+    }
+    L.nctile = L.nct[0] * L.nct[1] * L.nct[2];
+    const size_t sizes[12] = {
+        (size_t)L.mlpP * 4,                       // 0 weights
+        (size_t)(2 * L.mlpF + 2 * L.mlpO) * 4,    // 1 stats
+        (size_t)g.ncell * L.mlpF * 4,             // 2 features
+        (size_t)g.ncell * L.mlpO * 4,             // 3 outputs
+        (size_t)L.mlpP * 4,                       // 4 adam m
+        (size_t)L.mlpP * 4,                       // 5 adam v
+        (size_t)L.mlpP * 4,                       // 6 grad
+        64,                                       // 7 loss
+        (size_t)L.nctile,                         // 8 flags
+        (size_t)L.nctile * 2 * 8,                 // 9 errors
+        0, 0};
+    for (int k = 0; k < 12; ++k) {
+      L.mlp_off[k] = off;
+      off = align256(off + sizes[k]);
+    }
+  }
+  L.total = off;
+  L.plane_bytes = g.plane * (long long)L.esz;
+}
+
+// ---------------------------------------------------------------------------
+// entry points
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int msl_workspace_bytes(const msl_config *cfg, size_t *bytes) {
+  if (!bytes || check_config(cfg)) return MSL_EINVAL;
+  Layout L;
+  make_layout(cfg, L);
+  if (L.geo.plane >= (1ll << 31)) return MSL_EINVAL;
+  *bytes = L.total;
+  return MSL_OK;
+}
+
+const char *msl_last_error(const msl_ctx *c) { return c ? c->err : "null context"; }
+
+int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_ctx **out) {
+  if (!out) return MSL_EINVAL;
+  *out = nullptr;
+  const char *why = check_config(cfg);
+  if (why) return MSL_EINVAL;
+  Layout L;
+  make_layout(cfg, L);
+  if (L.geo.plane >= (1ll << 31)) return MSL_EINVAL;
+  if (!ws || bytes < L.total) return MSL_ENOMEM;
+  msl_ctx *c = new (std::nothrow) msl_ctx;
+  if (!c) return MSL_ENOMEM;
+  memset(c, 0, sizeof(*c));
+  c->cfg = *cfg;
+  c->stream = (hipStream_t)stream;
+  c->geo = L.geo;
+  c->D = cfg->dim;
+  c->nlat = cfg->n_high ? 2 : 1;
+  c->Q[0] = L.Q[0];
+  c->Q[1] = L.Q[1];
+  c->ncell = L.geo.ncell;
+  c->esz = L.esz;
+  char *base = (char *)ws;
+  // tables
+  ld xs[2][MSL_MAXN], wsl[2][MSL_MAXN];
+  const int ns[2] = {cfg->n_low, cfg->n_high};
+  ld cmax = 0;
+  for (int l = 0; l < c->nlat; ++l) {
+    if (gauss_hermite(ns[l], xs[l], wsl[l])) { delete c; return MSL_EINVAL; }
+    for (int a = 0; a < ns[l]; ++a)
+      if (fabsl(xs[l][a]) > cmax) cmax = fabsl(xs[l][a]);
+  }
+  Tab &t = c->htab;
+  memset(&t, 0, sizeof(t));
+  // CFL = max|c_i| dt / dx over every configured velocity set (Sec. IV)
+  const double dt = (double)((ld)cfg->cfl / cmax);
+  for (int l = 0; l < c->nlat; ++l) build_lat(t.lat[l], ns[l], cfg->dim, xs[l], wsl[l], dt);
+  for (int l = 0; l < c->nlat; ++l)
+    for (int a = 0; a < ns[l]; ++a)
+      if (abs(t.lat[l].n0[a]) + 1 > MSL_G) { delete c; return MSL_EINVAL; }
+  if (c->nlat > 1) {
+    const int nq = ns[0], nQ = ns[1];
+    for (int a = 0; a < nQ; ++a) {
+      ld coef[MSL_MAXN];
+      lagrange_coeffs(nQ, xs[1], a, coef);
+      for (int m = 0; m < nQ; ++m) t.Vi[a][m] = (double)coef[m];
+      for (int ap = 0; ap < nq; ++ap) {
+        ld s = 0, sh = 0, fact = 1;
+        for (int m = 0; m < nq; ++m) s += coef[m] * powl(xs[0][ap], m);
+        for (int j = 0; j < nq; ++j) {
+          if (j > 0) fact *= (ld)j;
+          sh += hermite_he(j, xs[1][a]) * hermite_he(j, xs[0][ap]) / fact;
+        }
+        t.K[a][ap] = (double)s;
+        t.KH[a][ap] = (double)(wsl[1][a] * sh);
+      }
+    }
+    for (int ap = 0; ap < nq; ++ap)
+      for (int a = 0; a < nQ; ++a) t.P[ap][a] = (double)lagrange_eval(nq, xs[0], ap, xs[1][a]);
+  }
+  t.dt = dt;
+  t.cv = cfg->cv;
+  t.gfac = cfg->thermal ? cfg->cv - 0.5 * cfg->dim : 0.0;
+  t.tau = cfg->tau;
+  t.omega = 1.0 / cfg->tau;
+  t.omegaf = (float)t.omega;
+  t.mu_ref = (cfg->tau - 0.5) * cfg->tau_ref_rho * cfg->tau_ref_T * dt;
+  t.mu_exp = cfg->mu_exp;
+  t.tau_ref_T = cfg->tau_ref_T > 0 ? cfg->tau_ref_T : 1.0;
+  t.rho0 = cfg->rho0 > 0 ? cfg->rho0 : 1.0;
+  t.T0 = cfg->T0 > 0 ? cfg->T0 : 1.0;
+  t.tau_mode = cfg->tau_mode;
+  t.thermal = cfg->thermal;
+  t.dim = cfg->dim;
+  t.nlat = c->nlat;
+  t.lift_mode = cfg->lift_mode;
+  // workspace
+  c->dtab = (Tab *)(base + L.off_tab);
+  for (int l = 0; l < c->nlat; ++l) {
+    c->planes[l][0] = base + L.off_planes[l];
+    c->planes[l][1] = base + L.off_planes[l] + (size_t)L.np[l] * L.geo.plane * L.esz;
+  }
+  c->cls = (uint8_t *)(base + L.off_cls);
+  c->newmask = (uint8_t *)(base + L.off_newmask);
+  c->tflag = (uint8_t *)(base + L.off_tflag);
+  c->blist[0] = (int *)(base + L.off_blist[0]);
+  c->blist[1] = (int *)(base + L.off_blist[1]);
+  c->bcount = (int *)(base + L.off_bcount);
+  c->blk = (int *)(base + L.off_blk);
+  c->nblk = L.nblk;
+  c->red = (double *)(base + L.off_red);
+  c->flag = (int *)(base + L.off_flag);
+  if (L.mlpP) {
+    c->mlpF = L.mlpF; c->mlpO = L.mlpO; c->mlpH = L.mlpH; c->mlpP = L.mlpP;
+    c->mlp_w = (float *)(base + L.mlp_off[0]);
+    c->mlp_stats = (float *)(base + L.mlp_off[1]);
+    c->mlp_feat = (float *)(base + L.mlp_off[2]);
+    c->mlp_out = (float *)(base + L.mlp_off[3]);
+    c->mlp_m = (float *)(base + L.mlp_off[4]);
+    c->mlp_v = (float *)(base + L.mlp_off[5]);
+    c->mlp_g = (float *)(base + L.mlp_off[6]);
+    c->mlp_loss = (float *)(base + L.mlp_off[7]);
+    c->mlp_flag = (uint8_t *)(base + L.mlp_off[8]);
+    c->mlp_err = (double *)(base + L.mlp_off[9]);
+    c->nctile = L.nctile;
+    for (int a = 0; a < 3; ++a) c->nct[a] = L.nct[a];
+  }
+  // zero the whole workspace once (padding included), upload the tables,
+  // start with every cell on the low-order set
+  if (hipMemsetAsync(ws, 0, L.total, c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->dtab, &t, sizeof(Tab), hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+    delete c;
+    return MSL_EHIP;
+  }
+  if (c->mlp_flag && hipMemsetAsync(c->mlp_flag, 1, c->nctile, c->stream) != hipSuccess) {
+    delete c;
+    return MSL_EHIP;
+  }
+  if (msl_launch_classify(c) != MSL_OK) { delete c; return MSL_EHIP; }
+  // the host copy of the tables must stay valid until the upload has run
+  if (hipStreamSynchronize(c->stream) != hipSuccess) { delete c; return MSL_EHIP; }
+  *out = c;
+  return MSL_OK;
+}
+
+void msl_destroy(msl_ctx *c) { delete c; }
+
+int msl_get_dt(const msl_ctx *c, double *dt) {
+  if (!c || !dt) return MSL_EINVAL;
+  *dt = c->htab.dt;
+  return MSL_OK;
+}
+
+int msl_get_step(const msl_ctx *c, long *step) {
+  if (!c || !step) return MSL_EINVAL;
+  *step = c->step;
+  return MSL_OK;
+}
+
+static int refresh_band(msl_ctx *c) {
+  int rc = msl_launch_classify(c);
+  if (rc) return rc;
+  if (c->initialized && c->nlat > 1) {
+    rc = msl_launch_band_convert(c, c->planes[0][c->cur], c->planes[1][c->cur]);
+    if (rc) return rc;
+    if (c->cfg.lift_mode == MSL_LIFT_MLP && c->mlp_on)
+      rc = msl_mlp_band_lift(c, c->planes[0][c->cur], c->planes[1][c->cur]);
+  }
+  return rc;
+}
+
+int msl_init(msl_ctx *c, const double *rho, const double *u, const double *T) {
+  if (!c || !rho || !u || (c->cfg.thermal && !T)) return MSL_EINVAL;
+  int rc = msl_launch_init_eq(c, rho, u, T);
+  if (rc) { set_err(c, "init kernel launch failed"); return rc; }
+  c->initialized = 1;
+  c->step = 0;
+  rc = refresh_band(c);
+  if (rc) set_err(c, "band conversion failed");
+  return rc;
+}
+
+int msl_set_mask(msl_ctx *c, const uint8_t *mask) {
+  if (!c || !mask) return MSL_EINVAL;
+  if (hipMemsetAsync(c->flag, 0, sizeof(int), c->stream) != hipSuccess) return MSL_EHIP;
+  int rc = msl_launch_check_mask(c, mask);
+  if (rc) return rc;
+  int bad = 0;
+  if (hipMemcpyAsync(&bad, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return MSL_EHIP;
+  if (bad) { set_err(c, "mask values must be 0/1 (1 only with a high order)"); return MSL_EINVAL; }
+  rc = msl_launch_switch(c, mask);
+  if (rc) return rc;
+  return refresh_band(c);
+}
+
+int msl_get_mask(msl_ctx *c, uint8_t *mask) {
+  if (!c || !mask) return MSL_EINVAL;
+  // the order is bit 0 of the class byte
+  return msl_launch_get_mask(c, mask);
+}
+
+static int mask_step(msl_ctx *c) {
+  int rc = msl_launch_criterion(c);
+  if (rc) return rc;
+  rc = msl_launch_switch(c, c->newmask);
+  if (rc) return rc;
+  return refresh_band(c);
+}
+
+int msl_step(msl_ctx *c, int nsteps) {
+  if (!c || nsteps < 0) return MSL_EINVAL;
+  if (!c->initialized) { set_err(c, "msl_step before msl_init"); return MSL_ESTATE; }
+  for (int s = 0; s < nsteps; ++s) {
+    int rc;
+    if (c->cfg.crit_kind && c->cfg.crit_every > 0 && c->nlat > 1 && c->step % c->cfg.crit_every == 0) {
+      rc = mask_step(c);
+      if (rc) { set_err(c, "criterion / switching failed"); return rc; }
+    }
+    if (c->cfg.lift_mode == MSL_LIFT_MLP && c->mlp_on && !c->mlp_manual) {
+      const int every = c->cfg.mlp_check_every > 0 ? c->cfg.mlp_check_every : 20;
+      if (c->step % every == 0 && (rc = msl_mlp_check_launch(c))) return rc;
+    }
+    const int cur = c->cur, nxt = cur ^ 1;
+    char *bl = c->planes[0][cur], *bh = c->nlat > 1 ? c->planes[1][cur] : nullptr;
+    rc = msl_launch_bc(c, bl, bh);
+    if (rc) { set_err(c, "ghost fill failed"); return rc; }
+    for (int l = 0; l < c->nlat; ++l) {
+      rc = msl_launch_stream_collide(c, l, c->planes[l][cur], c->planes[l][nxt]);
+      if (rc) { set_err(c, "stream-collide launch failed"); return rc; }
+    }
+    if (c->nlat > 1) {
+      char *nl = c->planes[0][nxt], *nh = c->planes[1][nxt];
+      rc = msl_launch_band_convert(c, nl, nh);
+      if (!rc && c->cfg.lift_mode == MSL_LIFT_MLP && c->mlp_on) rc = msl_mlp_band_lift(c, nl, nh);
+      if (rc) { set_err(c, "band conversion failed"); return rc; }
+    }
+    c->cur = nxt;
+    ++c->step;
+    if (c->cfg.check_every > 0 && c->step % c->cfg.check_every == 0) {
+      double out[5];
+      rc = msl_conservation(c, out);
+      if (rc) return rc;
+    }
+  }
+  return MSL_OK;
+}
+
+int msl_macros(msl_ctx *c, double *rho, double *u, double *T) {
+  if (!c) return MSL_EINVAL;
+  if (!c->initialized) return MSL_ESTATE;
+  return msl_launch_macros(c, rho, u, T);
+}
+
+int msl_get_populations(msl_ctx *c, int which, int fg, double *out) {
+  if (!c || !out || which < 0 || which >= c->nlat || (fg && !c->cfg.thermal)) return MSL_EINVAL;
+  return msl_launch_pops(c, which, fg, out, nullptr);
+}
+
+int msl_set_populations(msl_ctx *c, int which, int fg, const double *in) {
+  if (!c || !in || which < 0 || which >= c->nlat || (fg && !c->cfg.thermal)) return MSL_EINVAL;
+  int rc = msl_launch_pops(c, which, fg, nullptr, in);
+  if (rc) return rc;
+  c->initialized = 1;
+  return refresh_band(c);
+}
+
+int msl_conservation(msl_ctx *c, double *out) {
+  if (!c || !out) return MSL_EINVAL;
+  if (!c->initialized) return MSL_ESTATE;
+  double *dev = c->red + 1024 * 6;
+  int rc = msl_launch_conservation(c, dev);
+  if (rc) return rc;
+  double h[6];
+  if (hipMemcpyAsync(h, dev, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return MSL_EHIP;
+  for (int m = 0; m < 5; ++m) out[m] = h[m];
+  if (h[5] != 0.0) { set_err(c, "sentinel: NaN/Inf or non-positive density"); return MSL_EUNSTABLE; }
+  return MSL_OK;
+}
+
+// checkpoint: [header][cls][planes of each lattice (both buffers)][closure]
+struct StateHeader {
+  char magic[8];
+  long step;
+  int cur, nlat;
+  long long ncell, plane_bytes[2];
+  int mlpP;
+};
+
+int msl_get_state(msl_ctx *c, void *buf, size_t *bytes) {
+  if (!c || !bytes) return MSL_EINVAL;
+  size_t pb[2] = {0, 0};
+  for (int l = 0; l < c->nlat; ++l)
+    pb[l] = (size_t)c->Q[l] * (c->cfg.thermal ? 2 : 1) * c->geo.plane * c->esz * 2;
+  const size_t need = sizeof(StateHeader) + c->ncell + pb[0] + pb[1] +
+                      (size_t)(c->mlpP + 2 * c->mlpF + 2 * c->mlpO) * 4 * (c->mlpP ? 1 : 0);
+  if (!buf) { *bytes = need; return MSL_OK; }
+  if (*bytes < need) return MSL_ENOMEM;
+  StateHeader h;
+  memset(&h, 0, sizeof(h));
+  memcpy(h.magic, "MSLSTAT", 8);
+  h.step = c->step; h.cur = c->cur; h.nlat = c->nlat; h.ncell = c->ncell;
+  h.plane_bytes[0] = (long long)pb[0]; h.plane_bytes[1] = (long long)pb[1];
+  h.mlpP = c->mlpP;
+  char *p = (char *)buf;
+  memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  MSL_HIP(hipMemcpyAsync(p, c->cls, c->ncell, hipMemcpyDeviceToHost, c->stream));
+  p += c->ncell;
+  for (int l = 0; l < c->nlat; ++l) {
+    MSL_HIP(hipMemcpyAsync(p, c->planes[l][0], pb[l], hipMemcpyDeviceToHost, c->stream));
+    p += pb[l];
+  }
+  if (c->mlpP) {
+    MSL_HIP(hipMemcpyAsync(p, c->mlp_w, (size_t)c->mlpP * 4, hipMemcpyDeviceToHost, c->stream));
+    p += (size_t)c->mlpP * 4;
+    MSL_HIP(hipMemcpyAsync(p, c->mlp_stats, (size_t)(2 * c->mlpF + 2 * c->mlpO) * 4,
+                           hipMemcpyDeviceToHost, c->stream));
+  }
+  MSL_HIP(hipStreamSynchronize(c->stream));
+  *bytes = need;
+  return MSL_OK;
+}
+
+int msl_set_state(msl_ctx *c, const void *buf, size_t bytes) {
+  if (!c || !buf || bytes < sizeof(StateHeader)) return MSL_EINVAL;
+  StateHeader h;
+  memcpy(&h, buf, sizeof(h));
+  size_t pb[2] = {0, 0};
+  for (int l = 0; l < c->nlat; ++l)
+    pb[l] = (size_t)c->Q[l] * (c->cfg.thermal ? 2 : 1) * c->geo.plane * c->esz * 2;
+  if (memcmp(h.magic, "MSLSTAT", 8) || h.nlat != c->nlat || h.ncell != c->ncell ||
+      h.plane_bytes[0] != (long long)pb[0] || h.plane_bytes[1] != (long long)pb[1] ||
+      h.mlpP != c->mlpP) {
+    set_err(c, "checkpoint does not match this configuration");
+    return MSL_EINVAL;
+  }
+  const char *p = (const char *)buf + sizeof(h);
+  MSL_HIP(hipMemcpyAsync(c->cls, p, c->ncell, hipMemcpyHostToDevice, c->stream));
+  p += c->ncell;
+  for (int l = 0; l < c->nlat; ++l) {
+    MSL_HIP(hipMemcpyAsync(c->planes[l][0], p, pb[l], hipMemcpyHostToDevice, c->stream));
+    p += pb[l];
+  }
+  if (c->mlpP) {
+    MSL_HIP(hipMemcpyAsync(c->mlp_w, p, (size_t)c->mlpP * 4, hipMemcpyHostToDevice, c->stream));
+    p += (size_t)c->mlpP * 4;
+    MSL_HIP(hipMemcpyAsync(c->mlp_stats, p, (size_t)(2 * c->mlpF + 2 * c->mlpO) * 4,
+                           hipMemcpyHostToDevice, c->stream));
+    c->mlp_on = 1;
+  }
+  c->step = h.step;
+  c->cur = h.cur;
+  c->initialized = 1;
+  // class bits, tiles and band lists follow from the restored mask
+  int rc = msl_launch_classify(c);
+  if (rc) return rc;
+  MSL_HIP(hipStreamSynchronize(c->stream));
+  return MSL_OK;
+}
+
+int msl_num_check_tiles(const msl_ctx *c, int *n) {
+  if (!c || !n) return MSL_EINVAL;
+  *n = c->nctile;
+  return MSL_OK;
+}
+
+}  // extern "C"

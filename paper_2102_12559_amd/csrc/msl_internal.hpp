@@ -1,0 +1,164 @@
+// msl_internal.hpp -- shared declarations of the MI355X library: device-side
+// tables, grid geometry, storage codecs and the host context.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/msl.h"
+
+#define MSL_MAXN 8
+#define MSL_G 2            // ghost layers (stencil reach of a 3-point stencil at CFL <= 1)
+#define MSL_TX 64          // tile width in x (one wavefront)
+#define MSL_MTY 4          // micro-tile height (rows) of the per-tile class flags
+#define MSL_CHECK_TILE 64  // check tiles of the learned closure
+
+// Per velocity set: 1D nodes, weights, Hermite-weighted basis for the
+// equilibrium, and the 1D stencil (base offset and 3 Lagrange weights) of the
+// departure point of each node.
+struct LatTab {
+  int n, Q;
+  double c[MSL_MAXN], w[MSL_MAXN];
+  double hw[MSL_MAXN][MSL_MAXN];   // w_a He_j(c_a) / j!
+  int n0[MSL_MAXN];
+  double a[MSL_MAXN][3];
+  float cf[MSL_MAXN], wf[MSL_MAXN];
+  float hwf[MSL_MAXN][MSL_MAXN];
+  float af[MSL_MAXN][3];
+};
+
+struct Tab {
+  LatTab lat[2];
+  double K[MSL_MAXN][MSL_MAXN];    // lift, raw completion: K[a][a'] (high node a, low node a')
+  double KH[MSL_MAXN][MSL_MAXN];   // lift, Hermite completion
+  double P[MSL_MAXN][MSL_MAXN];    // project: P[a'][a] = l^low_{a'}(C_a)
+  double Vi[MSL_MAXN][MSL_MAXN];   // inverse Vandermonde of the high nodes: Vi[a][m]
+  double dt, cv, gfac, tau, omega, mu_ref, mu_exp, tau_ref_T, rho0, T0;
+  float omegaf;
+  int tau_mode, thermal, dim, nlat, lift_mode;
+};
+
+struct Geo {
+  int nx, ny, nz, dim;
+  int xo;                 // column of interior x = 0 inside a row
+  int pitch;              // elements per row
+  int rows;               // ny + 2G
+  int slabs;              // nz + 2G (3D) or 1
+  long long plane;        // elements per population plane
+  long long ncell;
+  int ntx, nty, ntz;      // micro-tiles (64 x 4 (x 1))
+  // element offset of interior cell (x, y, z) inside a plane (planes are
+  // padded so that every staged window of a tile stays inside the plane)
+  __host__ __device__ int idx(int x, int y, int z) const {
+    int zz = dim == 3 ? z + MSL_G : 0;
+    return (zz * rows + (y + MSL_G)) * pitch + xo + x;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// storage codecs: FP64 / FP32 populations, or 16-bit deviations
+// h = f / (rho0 W_i) - 1 (g: scale (cv - D/2) rho0 T0 W_i) in FP16 or BF16,
+// rounded to nearest even.
+// ---------------------------------------------------------------------------
+struct bf16_t { uint16_t u; };
+
+template <typename S> struct StoreTraits;
+template <> struct StoreTraits<double> {
+  using C = double;
+  static constexpr bool dev = false;
+  __device__ static double load(double v) { return v; }
+  __device__ static double store(double v) { return v; }
+};
+template <> struct StoreTraits<float> {
+  using C = float;
+  static constexpr bool dev = false;
+  __device__ static float load(float v) { return v; }
+  __device__ static float store(float v) { return v; }
+};
+template <> struct StoreTraits<_Float16> {
+  using C = float;
+  static constexpr bool dev = true;
+  __device__ static float load(_Float16 v) { return (float)v; }
+  __device__ static _Float16 store(float v) { return (_Float16)v; }
+};
+template <> struct StoreTraits<bf16_t> {
+  using C = float;
+  static constexpr bool dev = true;
+  __device__ static float load(bf16_t v) { return __uint_as_float(((uint32_t)v.u) << 16); }
+  __device__ static bf16_t store(float v) {
+    uint32_t b = __float_as_uint(v);
+    bf16_t r;
+    if ((b & 0x7fffffffu) > 0x7f800000u) { r.u = (uint16_t)((b >> 16) | 0x40u); return r; }
+    b += 0x7fffu + ((b >> 16) & 1u);
+    r.u = (uint16_t)(b >> 16);
+    return r;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// host context
+// ---------------------------------------------------------------------------
+struct msl_ctx {
+  msl_config cfg;
+  hipStream_t stream;
+  char err[256];
+  Geo geo;
+  int D, nlat, Q[2];
+  long long ncell;
+  Tab htab;
+  Tab *dtab;
+  size_t esz;
+  char *planes[2][2];     // [lattice][buffer]: f planes then g planes
+  int cur;
+  uint8_t *cls;           // bit0 order (0 low, 1 high), bit1 band
+  uint8_t *newmask;
+  uint8_t *tflag;         // per micro-tile: bit0 has low cells, bit1 has high cells
+  int *blist[2];          // band cells of each order, ascending cell index
+  int *bcount;            // device: [0] low band, [1] high band counts
+  int *blk;               // compaction scratch: per-block counts / offsets (2 lists)
+  int nblk;
+  double *red;            // reduction partials
+  int nred;
+  int *flag;              // device error flag (mask values)
+  double *wall_rho;       // diffuse wall densities
+  long step;
+  int initialized;
+  // learned closure
+  int mlpF, mlpO, mlpH, mlpP, mlp_on, mlp_manual;
+  float *mlp_w;           // fp32 master parameters [P]
+  float *mlp_stats;       // xmean[F], xstd[F], tmean[O], tstd[O]
+  float *mlp_feat;        // [ncell cap][F] features of band cells
+  float *mlp_out;         // [ncell cap][O]
+  float *mlp_m, *mlp_v, *mlp_g;  // Adam moments, gradient
+  float *mlp_loss;        // device scalars
+  uint8_t *mlp_flag;      // per check tile
+  double *mlp_err;        // per check tile: E_mlp, E_grad
+  int nctile, nct[3];
+};
+
+// launch helpers implemented in the .hip files
+int msl_launch_stream_collide(msl_ctx *c, int lat, const char *in, char *out);
+int msl_launch_bc(msl_ctx *c, char *buf_low, char *buf_high);
+int msl_launch_band_convert(msl_ctx *c, char *buf_low, char *buf_high);
+int msl_launch_init_eq(msl_ctx *c, const double *rho, const double *u, const double *T);
+int msl_launch_criterion(msl_ctx *c);
+int msl_launch_switch(msl_ctx *c, const uint8_t *newmask);
+int msl_launch_classify(msl_ctx *c);
+int msl_launch_macros(msl_ctx *c, double *rho, double *u, double *T);
+int msl_launch_pops(msl_ctx *c, int which, int fg, double *out, const double *in);
+int msl_launch_conservation(msl_ctx *c, double *dev_out5);
+int msl_launch_check_mask(msl_ctx *c, const uint8_t *mask);
+int msl_launch_get_mask(msl_ctx *c, uint8_t *mask);
+// closure
+int msl_mlp_band_lift(msl_ctx *c, char *buf_low, char *buf_high);
+int msl_mlp_check_launch(msl_ctx *c);
+int msl_mlp_snapshots_launch(msl_ctx *c, float *feats, float *targets, int max, int *count_dev);
+int msl_mlp_forward_launch(msl_ctx *c, const float *X, int n, float *Y);
+int msl_mlp_grad_launch(msl_ctx *c, const float *X, const float *Y, int n, float *grad,
+                        float *loss_dev);
+int msl_mlp_adam_launch(msl_ctx *c, int t, float lr);
+
+#define MSL_HIP(call)                                                       \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess) return MSL_EHIP;                                  \
+  } while (0)

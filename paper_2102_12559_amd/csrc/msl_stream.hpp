@@ -1,0 +1,323 @@
+// msl_stream.hpp -- the fused stream-and-collide kernel, one instantiation per
+// (dimension, velocity-set order, storage precision, thermal model).
+//
+// One workgroup owns a tile of 64 x TY cells (2D) or 64 x 4 x TZ cells (3D).
+// For each population plane (f_0..f_{Q-1}, then g_0..g_{Q-1}) the workgroup
+// stages the plane's (64+2) x (TY+2) neighbourhood of the departure points into
+// LDS -- the departure offset x - c_i dt is the same for every cell of a plane,
+// so the staged window is the tile shifted by the population's base offset --
+// while the next plane's global loads are in flight (double-buffered LDS, one
+// barrier per plane).  Each thread interpolates its cells separably (rows,
+// then columns; eq. reconstructionPond with 3-point Lagrange functions) into
+// registers.  After the last plane every cell holds all its streamed
+// populations and is collided in registers: moments, Hermite product-form
+// equilibrium, BGK (eqs. Pond_f/g, omega1 = omega2), and stored coalesced.
+// Cells of the other velocity set are skipped; tiles without a cell of this
+// set exit before loading anything.
+#pragma once
+#include <utility>
+
+#include "msl_device.hpp"
+
+template <typename S, bool TH, int N, int D>
+struct SCTraits {
+  using T = StoreTraits<S>;
+  using C = typename T::C;
+  static constexpr int Q = D == 2 ? N * N : N * N * N;
+  static constexpr int NP = TH ? 2 * Q : Q;
+  static constexpr int R = msl_rows_for(NP, (int)(sizeof(C) / 4), D == 2 ? 96 : 128);
+};
+
+// Collision of the R cells of one thread; ft[k][r] holds the streamed value of
+// plane k (raw storage domain) at cell r.
+template <typename S, bool TH, int N, int D, int R, int NP>
+__device__ __forceinline__ void collide_store(const Tab *__restrict__ tab, int lat, const Geo &g,
+                                              typename StoreTraits<S>::C (&ft)[NP][R],
+                                              S *__restrict__ out, const uint8_t *__restrict__ cls,
+                                              int x, int y0, int z0, int ystep, int zstep) {
+  using T = StoreTraits<S>;
+  using C = typename T::C;
+  constexpr int Q = D == 2 ? N * N : N * N * N;
+  const LatTab &L = tab->lat[lat];
+  const C rho0 = (C)tab->rho0;
+  const C gsc0 = (C)(tab->gfac * tab->rho0 * tab->T0);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int y = y0 + r * ystep, z = z0 + r * zstep;
+    if (x >= g.nx || y >= g.ny || (D == 3 && z >= g.nz)) continue;
+    const long long cell = ((long long)z * g.ny + y) * g.nx + x;
+    if ((cls[cell] & 1) != lat) continue;
+    C f[Q];
+    C gg[TH ? Q : 1];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int a = i % N, b = (i / N) % N, cc = D == 3 ? i / (N * N) : 0;
+      C W = tsel<C>(L.w[a], L.wf[a]) * tsel<C>(L.w[b], L.wf[b]);
+      if (D == 3) W *= tsel<C>(L.w[cc], L.wf[cc]);
+      f[i] = T::dev ? rho0 * W * (C(1) + ft[i][r]) : ft[i][r];
+      if (TH) gg[TH ? i : 0] = T::dev ? gsc0 * W * (C(1) + ft[TH ? Q + i : 0][r]) : ft[TH ? Q + i : 0][r];
+    }
+    // moments (Sec. II.B)
+    C rho = C(0), jx = C(0), jy = C(0), jz = C(0), e = C(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int a = i % N, b = (i / N) % N, cc = D == 3 ? i / (N * N) : 0;
+      const C cx = tsel<C>(L.c[a], L.cf[a]), cy = tsel<C>(L.c[b], L.cf[b]);
+      const C cz = D == 3 ? tsel<C>(L.c[cc], L.cf[cc]) : C(0);
+      rho += f[i];
+      jx += cx * f[i];
+      jy += cy * f[i];
+      if (D == 3) jz += cz * f[i];
+      if (TH) e += C(0.5) * (cx * cx + cy * cy + cz * cz) * f[i] + gg[TH ? i : 0];
+    }
+    // the equilibrium factors are evaluated in FP64 for every storage type:
+    // single-precision Hermite tables would bias the equilibrium's mass and
+    // momentum by their rounding, the same way every step
+    const double rd = (double)rho, ird = 1.0 / rd;
+    const double ux = (double)jx * ird, uy = (double)jy * ird, uz = (double)jz * ird;
+    double Tm = 1.0;
+    if (TH) Tm = ((double)e - 0.5 * rd * (ux * ux + uy * uy + uz * uz)) / (tab->cv * rd);
+    C om = tsel<C>(tab->omega, tab->omegaf);
+    if (tab->tau_mode == 1) {
+      const double mu = tab->mu_ref * pow(Tm / tab->tau_ref_T, tab->mu_exp);
+      om = (C)(1.0 / (mu / (rd * Tm * tab->dt) + 0.5));
+    }
+    double Px[N], Py[N], Pz[N];
+    eq_axis<double, N>(L, ux, Tm, Px);
+    eq_axis<double, N>(L, uy, Tm, Py);
+    if (D == 3) eq_axis<double, N>(L, uz, Tm, Pz);
+#pragma unroll
+    for (int a = 0; a < N; ++a) Px[a] *= rd;
+    const C gf = (C)(tab->gfac * Tm);
+    const int base = g.idx(x, y, z);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int a = i % N, b = (i / N) % N, cc = D == 3 ? i / (N * N) : 0;
+      double feqd = Px[a] * Py[b];
+      if (D == 3) feqd *= Pz[cc];
+      const C feq = (C)feqd;
+      const C fo = f[i] + om * (feq - f[i]);
+      C W = tsel<C>(L.w[a], L.wf[a]) * tsel<C>(L.w[b], L.wf[b]);
+      if (D == 3) W *= tsel<C>(L.w[cc], L.wf[cc]);
+      out[(long long)i * g.plane + base] = T::store(T::dev ? fo / (rho0 * W) - C(1) : fo);
+      if (TH) {
+        const C go = gg[TH ? i : 0] + om * (gf * feq - gg[TH ? i : 0]);
+        out[(long long)(Q + i) * g.plane + base] = T::store(T::dev ? go / (gsc0 * W) - C(1) : go);
+      }
+    }
+  }
+}
+
+template <int NP, typename F>
+__device__ __forceinline__ void for_planes(F &&f) {
+  [&]<int... Ks>(std::integer_sequence<int, Ks...>) {
+    (f.template operator()<Ks>(), ...);
+  }(std::make_integer_sequence<int, NP>{});
+}
+
+template <typename S, bool TH, int N>
+__global__ void __launch_bounds__(256)
+k_sc2d(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in, S *__restrict__ out,
+       const uint8_t *__restrict__ cls, const uint8_t *__restrict__ tflag) {
+  using Tr = SCTraits<S, TH, N, 2>;
+  using T = typename Tr::T;
+  using C = typename Tr::C;
+  constexpr int Q = Tr::Q, NP = Tr::NP, R = Tr::R;
+  constexpr int TY = MSL_MTY * R;
+  constexpr int LW = MSL_TX + 2, LR = TY + 2, NE = LW * LR, NLD = (NE + 255) / 256;
+  __shared__ C sm[2][NE];
+  const LatTab &L = tab->lat[lat];
+  const int bx = blockIdx.x, by = blockIdx.y;
+  const int x0 = bx * MSL_TX, y0 = by * TY;
+  {
+    uint8_t any = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int my = by * R + r;
+      if (my < g.nty) any |= tflag[my * g.ntx + bx];
+    }
+    if (!(any & (1 << lat))) return;
+  }
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  // per-thread offsets of the staged window elements (plane independent)
+  int eoff[NLD];
+#pragma unroll
+  for (int m = 0; m < NLD; ++m) {
+    int e = threadIdx.x + 256 * m;
+    e = e < NE ? e : NE - 1;
+    const int rr = e / LW, cc = e - rr * LW;
+    eoff[m] = rr * g.pitch + cc;
+  }
+  C ft[NP][R];
+  C reg[NLD];
+  auto gload = [&]<int K>() {
+    constexpr int i = K % Q, a = i % N, b = i / N;
+    const int ox = L.n0[a] - 1, oy = L.n0[b] - 1;
+    const S *base = in + (long long)K * g.plane + g.idx(x0 + ox, y0 + oy, 0);
+#pragma unroll
+    for (int m = 0; m < NLD; ++m) reg[m] = (C)T::load(base[eoff[m]]);
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int m = 0; m < NLD; ++m) {
+      const int e = threadIdx.x + 256 * m;
+      if (NE % 256 == 0 || m + 1 < NLD || e < NE) sm[buf][e] = reg[m];
+    }
+  };
+  auto step = [&]<int K>() {
+    if constexpr (K + 1 < NP) gload.template operator()<K + 1>();
+    constexpr int i = K % Q, a = i % N, b = i / N;
+    constexpr int buf = K & 1;
+    const C wx0 = tsel<C>(L.a[a][0], L.af[a][0]), wx1 = tsel<C>(L.a[a][1], L.af[a][1]),
+            wx2 = tsel<C>(L.a[a][2], L.af[a][2]);
+    const C wy0 = tsel<C>(L.a[b][0], L.af[b][0]), wy1 = tsel<C>(L.a[b][1], L.af[b][1]),
+            wy2 = tsel<C>(L.a[b][2], L.af[b][2]);
+    // differenced form: the centre weight is 1 - w0 - w2 exactly, so a
+    // uniform field is reproduced without a rounding bias in the weights
+    (void)wx1;
+    (void)wy1;
+    C h[R + 2];
+#pragma unroll
+    for (int r = 0; r < R + 2; ++r) {
+      const C *row = &sm[buf][(ty * R + r) * LW + tx];
+      h[r] = row[1] + wx0 * (row[0] - row[1]) + wx2 * (row[2] - row[1]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) ft[K][r] = h[r + 1] + wy0 * (h[r] - h[r + 1]) + wy2 * (h[r + 2] - h[r + 1]);
+    if constexpr (K + 1 < NP) lstore((K + 1) & 1);
+    __syncthreads();
+  };
+  gload.template operator()<0>();
+  lstore(0);
+  __syncthreads();
+  for_planes<NP>(step);
+  collide_store<S, TH, N, 2, R, NP>(tab, lat, g, ft, out, cls, x0 + tx, y0 + ty * R, 0, 1, 0);
+}
+
+// 3D: tile 64 x 4 x TZ; each thread owns one (x, y) column of TZ cells.
+template <typename S, bool TH, int N>
+__global__ void __launch_bounds__(256)
+k_sc3d(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in, S *__restrict__ out,
+       const uint8_t *__restrict__ cls, const uint8_t *__restrict__ tflag) {
+  using Tr = SCTraits<S, TH, N, 3>;
+  using T = typename Tr::T;
+  using C = typename Tr::C;
+  constexpr int Q = Tr::Q, NP = Tr::NP, R = Tr::R;
+  constexpr int TZ = R;
+  constexpr int LW = MSL_TX + 2, LY = MSL_MTY + 2, LZ = TZ + 2;
+  constexpr int NE = LW * LY * LZ, NLD = (NE + 255) / 256;
+  __shared__ C sm[2][NE];
+  const LatTab &L = tab->lat[lat];
+  const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+  const int x0 = bx * MSL_TX, y0 = by * MSL_MTY, z0 = bz * TZ;
+  {
+    uint8_t any = 0;
+#pragma unroll
+    for (int r = 0; r < TZ; ++r) {
+      const int mz = z0 + r;
+      if (mz < g.ntz) any |= tflag[((long long)mz * g.nty + by) * g.ntx + bx];
+    }
+    if (!(any & (1 << lat))) return;
+  }
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  int eoff[NLD];
+#pragma unroll
+  for (int m = 0; m < NLD; ++m) {
+    int e = threadIdx.x + 256 * m;
+    e = e < NE ? e : NE - 1;
+    const int rz = e / (LW * LY), rem = e - rz * (LW * LY);
+    const int ry = rem / LW, rx = rem - ry * LW;
+    eoff[m] = (rz * g.rows + ry) * g.pitch + rx;
+  }
+  C ft[NP][R];
+  C reg[NLD];
+  auto gload = [&]<int K>() {
+    constexpr int i = K % Q, a = i % N, b = (i / N) % N, cc = i / (N * N);
+    const int ox = L.n0[a] - 1, oy = L.n0[b] - 1, oz = L.n0[cc] - 1;
+    const S *base = in + (long long)K * g.plane + g.idx(x0 + ox, y0 + oy, z0 + oz);
+#pragma unroll
+    for (int m = 0; m < NLD; ++m) reg[m] = (C)T::load(base[eoff[m]]);
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int m = 0; m < NLD; ++m) {
+      const int e = threadIdx.x + 256 * m;
+      if (NE % 256 == 0 || m + 1 < NLD || e < NE) sm[buf][e] = reg[m];
+    }
+  };
+  auto step = [&]<int K>() {
+    if constexpr (K + 1 < NP) gload.template operator()<K + 1>();
+    constexpr int i = K % Q, a = i % N, b = (i / N) % N, cc = i / (N * N);
+    constexpr int buf = K & 1;
+    C wx[3], wy[3], wz[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      wx[s] = tsel<C>(L.a[a][s], L.af[a][s]);
+      wy[s] = tsel<C>(L.a[b][s], L.af[b][s]);
+      wz[s] = tsel<C>(L.a[cc][s], L.af[cc][s]);
+    }
+    // differenced form along each axis (centre weight 1 - w0 - w2 exactly)
+    C hz[R + 2];
+#pragma unroll
+    for (int rz = 0; rz < R + 2; ++rz) {
+      C hy[3];
+#pragma unroll
+      for (int sy = 0; sy < 3; ++sy) {
+        const C *row = &sm[buf][(rz * LY + ty + sy) * LW + tx];
+        hy[sy] = row[1] + wx[0] * (row[0] - row[1]) + wx[2] * (row[2] - row[1]);
+      }
+      hz[rz] = hy[1] + wy[0] * (hy[0] - hy[1]) + wy[2] * (hy[2] - hy[1]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) ft[K][r] = hz[r + 1] + wz[0] * (hz[r] - hz[r + 1]) + wz[2] * (hz[r + 2] - hz[r + 1]);
+    if constexpr (K + 1 < NP) lstore((K + 1) & 1);
+    __syncthreads();
+  };
+  gload.template operator()<0>();
+  lstore(0);
+  __syncthreads();
+  for_planes<NP>(step);
+  collide_store<S, TH, N, 3, R, NP>(tab, lat, g, ft, out, cls, x0 + tx, y0 + ty, z0, 0, 1);
+}
+
+template <typename S, bool TH, int N, int D>
+static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
+  using Tr = SCTraits<S, TH, N, D>;
+  const Geo &g = c->geo;
+  dim3 block(256);
+  if constexpr (D == 2) {
+    dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + MSL_MTY * Tr::R - 1) / (MSL_MTY * Tr::R));
+    hipLaunchKernelGGL((k_sc2d<S, TH, N>), grid, block, 0, c->stream, c->dtab, lat, g,
+                       (const S *)in, (S *)out, c->cls, c->tflag);
+  } else {
+    dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + MSL_MTY - 1) / MSL_MTY,
+              (g.nz + Tr::R - 1) / Tr::R);
+    hipLaunchKernelGGL((k_sc3d<S, TH, N>), grid, block, 0, c->stream, c->dtab, lat, g,
+                       (const S *)in, (S *)out, c->cls, c->tflag);
+  }
+  return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
+}
+
+template <typename S, bool TH>
+static int launch_n(msl_ctx *c, int lat, const char *in, char *out) {
+  const int n = c->htab.lat[lat].n;
+  if (c->D == 2) {
+    switch (n) {
+      case 3: return launch_one<S, TH, 3, 2>(c, lat, in, out);
+      case 4: return launch_one<S, TH, 4, 2>(c, lat, in, out);
+      case 5: return launch_one<S, TH, 5, 2>(c, lat, in, out);
+      case 6: return launch_one<S, TH, 6, 2>(c, lat, in, out);
+    }
+  } else {
+    switch (n) {
+      case 3: return launch_one<S, TH, 3, 3>(c, lat, in, out);
+      case 4: return launch_one<S, TH, 4, 3>(c, lat, in, out);
+    }
+  }
+  return MSL_EINVAL;
+}
+
+template <typename S>
+int msl_launch_store(msl_ctx *c, int lat, const char *in, char *out) {
+  return c->cfg.thermal ? launch_n<S, true>(c, lat, in, out) : launch_n<S, false>(c, lat, in, out);
+}

@@ -1,0 +1,77 @@
+"""The C-ABI library loads and exports every entry point include/msl.h
+declares; configuration errors are reported without touching the GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2102_12559_amd import inputs, msl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "msl.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(msl_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_declared_symbols():
+    L = msl.lib()
+    names = declared_symbols()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(msl.SYMBOLS)
+
+
+def test_config_struct_matches_header():
+    txt = open(os.path.join(ROOT, "include", "msl.h")).read()
+    body = txt[txt.index("typedef struct msl_config"):txt.index("} msl_config;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl or decl.startswith("typedef"):
+            decl = decl.split("{", 1)[-1].strip()
+            if not decl:
+                continue
+        parts = decl.split(None, 1)
+        for name in parts[1].split(","):
+            fields.append(re.sub(r"\[.*", "", name.strip()))
+    assert fields == [f for f, _ in msl.MslConfig._fields_]
+
+
+@pytest.mark.parametrize("bad", [
+    dict(tau=0.5), dict(n_low=4, n_high=3), dict(n_high=7), dict(dim=4), dict(nx=2),
+    dict(cfl=1.5), dict(store=9), dict(lift_mode=2, n_high=0),
+    dict(bc=[3, 3, 0, 0, 0, 0]), dict(bc=[0, 2, 0, 0, 0, 0]),
+    dict(dim=3, nz=8, n_low=3, n_high=5), dict(thermal=1, cv=1.0),
+])
+def test_invalid_configs_rejected(bad):
+    cfg = inputs.base_config(nx=16, ny=16, n_low=3, n_high=4)
+    cfg.update(bad)
+    c = msl.make_config(cfg)
+    n = C.c_size_t()
+    assert msl.lib().msl_workspace_bytes(C.byref(c), C.byref(n)) == msl.MSL_EINVAL
+    ctx = C.c_void_p()
+    assert msl.lib().msl_create(C.byref(c), None, 0, None, C.byref(ctx)) == msl.MSL_EINVAL
+
+
+def test_workspace_too_small_is_enomem():
+    cfg = inputs.base_config(nx=16, ny=16, n_low=3, n_high=4)
+    need = msl.workspace_bytes(cfg)
+    c = msl.make_config(cfg)
+    ctx = C.c_void_p()
+    rc = msl.lib().msl_create(C.byref(c), C.c_void_p(1 << 20), need - 1, None, C.byref(ctx))
+    assert rc == msl.MSL_ENOMEM
+
+
+def test_workspace_sizes_of_the_workloads():
+    w = inputs.jet_c2()
+    b = msl.workspace_bytes(w["cfg"])
+    # two buffers of f and g planes for D2Q9 and D2Q16 (fp32) plus bookkeeping
+    cells = 1024 * 512
+    assert b > 2 * 2 * (9 + 16) * cells * 4
+    assert b < 1.3 * 2 * 2 * (9 + 16) * cells * 4 + 64 * cells
