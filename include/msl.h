@@ -73,6 +73,9 @@ typedef struct msl_config {
   double slot_state[6][5];    /* state inside the face's slot */
   int slot[6][4];             /* slot [lo0,hi0) x [lo1,hi1) on the face's tangential axes
                                  (ascending axis order); lo0 >= hi0: no slot */
+  double slot_edge[6];        /* > 0: the face state blends from bc_state to slot_state with
+                                 weight 1/2[tanh((t-lo+1/2)/w) - tanh((t-hi+1/2)/w)] per
+                                 restricted tangential axis; 0: sharp slot */
   int crit_kind;              /* MSL_CRIT_* */
   double crit_thr;
   int crit_every;             /* evaluate the criterion every k steps (from step 0); 0: never */
@@ -177,6 +180,24 @@ int msl_mlp_forward(msl_ctx *ctx, const float *X, int n, float *Yout);
 int msl_mlp_get_flags(msl_ctx *ctx, uint8_t *flags);
 int msl_mlp_set_flags(msl_ctx *ctx, const uint8_t *flags);
 int msl_num_check_tiles(const msl_ctx *ctx, int *n);
+
+/* ---- measurement ---- */
+
+/* Per-kernel timing of msl_step with HIP events recorded on the context's
+ * stream around every launch (enable = 1).  While enabled the stream is
+ * synchronised every 512 timed launches and after each criterion evaluation
+ * (to read the number of high-order cells). */
+int msl_profile(msl_ctx *ctx, int enable);
+/* stats[k][0..3] for launch class k = 0 ghost fill, 1 stream-collide of the
+ * low-order set, 2 stream-collide of the high-order set, 3 band conversion,
+ * 4 criterion and switching, 5 learned closure: number of launches, total
+ * milliseconds, algorithmic bytes (classes 1, 2: read and write of every
+ * population of each cell of that order), cells updated.  Host out, 24
+ * doubles; the counters restart.  Synchronises. */
+int msl_profile_read(msl_ctx *ctx, double *stats);
+/* Plain device-to-device copy of `bytes` (a multiple of 16) on `hip_stream`:
+ * the bandwidth reference for roofline figures.  Device pointers. */
+int msl_device_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -25,6 +25,7 @@ class OrConfig(C.Structure):
         ("store", C.c_int), ("lift_mode", C.c_int),
         ("bc", C.c_int * 6), ("bc_state", (C.c_double * 5) * 6),
         ("slot_state", (C.c_double * 5) * 6), ("slot", (C.c_int * 4) * 6),
+        ("slot_edge", C.c_double * 6),
         ("crit_kind", C.c_int), ("crit_thr", C.c_double), ("crit_every", C.c_int),
     ]
 
@@ -83,6 +84,9 @@ def make_config(cfg: dict) -> OrConfig:
             for k in range(6):
                 for m in range(4):
                     c.slot[k][m] = int(v[k][m])
+        elif name == "slot_edge":
+            for k in range(6):
+                c.slot_edge[k] = float(v[k])
         else:
             setattr(c, name, v)
     return c

@@ -145,8 +145,23 @@ static void resolve(const or_ctx *c, const int *pin, src_t *out) {
         p[ax] = side ? c->N[ax] - 1 : 0;
         break;
       case 1: {
-        const double *st = in_slot(c, face, p) ? c->cfg.slot_state[face] : c->cfg.bc_state[face];
         out->kind = 1;
+        const double w = c->cfg.slot_edge[face];
+        if (w > 0.0 && c->cfg.slot[face][0] < c->cfg.slot[face][1]) {
+          /* smooth slot: weight 1/2 [tanh((t - lo + 1/2)/w) - tanh((t - hi + 1/2)/w)]
+           * along each restricted tangential axis */
+          int t[2], nt = 0;
+          for (int a = 0; a < c->D; a++) if (a != ax) t[nt++] = a;
+          const int *s = c->cfg.slot[face];
+          double lam = 0.5 * (tanh((p[t[0]] - s[0] + 0.5) / w) - tanh((p[t[0]] - s[1] + 0.5) / w));
+          if (c->D == 3 && s[2] < s[3])
+            lam *= 0.5 * (tanh((p[t[1]] - s[2] + 0.5) / w) - tanh((p[t[1]] - s[3] + 0.5) / w));
+          for (int m = 0; m < 5; m++)
+            out->st[m] = c->cfg.bc_state[face][m] +
+                         lam * (c->cfg.slot_state[face][m] - c->cfg.bc_state[face][m]);
+          return;
+        }
+        const double *st = in_slot(c, face, p) ? c->cfg.slot_state[face] : c->cfg.bc_state[face];
         memcpy(out->st, st, sizeof(double) * 5);
         return;
       }

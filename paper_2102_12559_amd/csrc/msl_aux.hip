@@ -167,6 +167,7 @@ struct BCArgs {
   double st[6][5];
   double slot_st[6][5];
   int slot[6][4];
+  double slot_edge[6];
 };
 
 __device__ __forceinline__ int in_slot(const BCArgs &b, int face, int dim, const int *p) {
@@ -181,9 +182,55 @@ __device__ __forceinline__ int in_slot(const BCArgs &b, int face, int dim, const
   return 1;
 }
 
+// ghost cells of one axis pass: lower axes with ghosts, the axis itself in its
+// 2G ghost layers, higher axes interior
+__device__ __forceinline__ long long pass_cells(const Geo &g, int ax, int *ext, int *lo) {
+  const int N[3] = {g.nx, g.ny, g.nz};
+  long long tot = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (a >= g.dim) { ext[a] = 1; lo[a] = 0; }
+    else if (a < ax) { ext[a] = N[a] + 2 * MSL_G; lo[a] = -MSL_G; }
+    else if (a == ax) { ext[a] = 2 * MSL_G; lo[a] = 0; }
+    else { ext[a] = N[a]; lo[a] = 0; }
+    tot *= ext[a];
+  }
+  return tot;
+}
+
+// periodic and zero-gradient ghosts: one thread per (ghost cell, plane)
+template <typename S>
+__global__ void k_bc_copy(const Tab *__restrict__ tab, Geo g, int ax, BCArgs b, char *bl, char *bh,
+                          int np0, int np1) {
+  const int N[3] = {g.nx, g.ny, g.nz};
+  int ext[3], lo[3];
+  const long long tot = pass_cells(g, ax, ext, lo);
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tot * (np0 + np1)) return;
+  const long long cellid = t % tot;
+  const int plane = (int)(t / tot);
+  int p[3];
+  long long r = cellid;
+  for (int a = 0; a < 3; ++a) {
+    p[a] = lo[a] + (int)(r % ext[a]);
+    r /= ext[a];
+  }
+  const int gi = p[ax];
+  const int side = gi < MSL_G ? 0 : 1;
+  p[ax] = side ? N[ax] + (gi - MSL_G) : gi - MSL_G;
+  const int rule = b.bc[2 * ax + side];
+  if (rule != MSL_BC_PERIODIC && rule != MSL_BC_OUTFLOW_ZG) return;
+  int q[3] = {p[0], p[1], p[2]};
+  if (rule == MSL_BC_PERIODIC) q[ax] = (q[ax] % N[ax] + N[ax]) % N[ax];
+  else q[ax] = side ? N[ax] - 1 : 0;
+  S *pl = plane < np0 ? (S *)bl + (long long)plane * g.plane : (S *)bh + (long long)(plane - np0) * g.plane;
+  pl[g.idx(p[0], p[1], p[2])] = pl[g.idx(q[0], q[1], q[2])];
+}
+
+// fixed-equilibrium ghosts (constant: written once per buffer) and diffuse
+// walls (every step); `rules` selects which faces this launch fills
 template <typename S>
 __global__ void k_bc_pass(const Tab *__restrict__ tab, Geo g, int ax, BCArgs b, char *bl, char *bh,
-                          const uint8_t *__restrict__ cls) {
+                          const uint8_t *__restrict__ cls, int rules) {
   const int N[3] = {g.nx, g.ny, g.nz};
   // extent of the pass: lower axes with ghosts, higher axes interior
   int ext[3], lo[3];
@@ -208,6 +255,7 @@ __global__ void k_bc_pass(const Tab *__restrict__ tab, Geo g, int ax, BCArgs b, 
   p[ax] = side ? N[ax] + (gi - MSL_G) : gi - MSL_G;
   const int face = 2 * ax + side;
   const int rule = b.bc[face];
+  if (!(rules & (1 << rule))) return;
   char *bases[2] = {bl, bh};
   const int dst = g.idx(p[0], p[1], p[2]);
   if (rule == MSL_BC_PERIODIC || rule == MSL_BC_OUTFLOW_ZG) {
@@ -223,7 +271,21 @@ __global__ void k_bc_pass(const Tab *__restrict__ tab, Geo g, int ax, BCArgs b, 
     return;
   }
   if (rule == MSL_BC_FIXED_EQ) {
+    double stb[5];
     const double *st = in_slot(b, face, g.dim, p) ? b.slot_st[face] : b.st[face];
+    const int *s = b.slot[face];
+    const double w = b.slot_edge[face];
+    if (w > 0.0 && s[0] < s[1]) {
+      // smooth slot profile: tanh edges of width w
+      int t[2], nt = 0;
+      for (int a = 0; a < g.dim; ++a)
+        if (a != ax) t[nt++] = a;
+      double lam = 0.5 * (tanh((p[t[0]] - s[0] + 0.5) / w) - tanh((p[t[0]] - s[1] + 0.5) / w));
+      if (g.dim == 3 && s[2] < s[3])
+        lam *= 0.5 * (tanh((p[t[1]] - s[2] + 0.5) / w) - tanh((p[t[1]] - s[3] + 0.5) / w));
+      for (int m = 0; m < 5; ++m) stb[m] = b.st[face][m] + lam * (b.slot_st[face][m] - b.st[face][m]);
+      st = stb;
+    }
     for (int l = 0; l < tab->nlat; ++l) {
       double f[MSL_MAXQ], gg[MSL_MAXQ];
       cell_feq(tab->lat[l], g.dim, st[0], st + 1, st[4], f);
@@ -435,36 +497,41 @@ __global__ void k_tileflags(Geo g, const uint8_t *__restrict__ cls, uint8_t *__r
 // 4096 cells, one scan over the blocks, then an ordered scatter
 #define CMP_CELLS 4096
 __global__ void k_band_count(Geo g, const uint8_t *__restrict__ cls, int *__restrict__ blk, int nblk) {
+  // lists: 0 low-order band cells, 1 high-order band cells, 2 all high-order cells
   const long long base = (long long)blockIdx.x * CMP_CELLS;
-  int c0 = 0, c1 = 0;
+  int c0 = 0, c1 = 0, c2 = 0;
   for (int j = threadIdx.x; j < CMP_CELLS; j += blockDim.x) {
     const long long k = base + j;
     if (k < g.ncell) {
       const uint8_t v = cls[k];
       if (v & 2) { if (v & 1) ++c1; else ++c0; }
+      c2 += v & 1;
     }
   }
-  __shared__ int s0[AUX_BLOCK], s1[AUX_BLOCK];
+  __shared__ int s0[AUX_BLOCK], s1[AUX_BLOCK], s2[AUX_BLOCK];
   s0[threadIdx.x] = c0;
   s1[threadIdx.x] = c1;
+  s2[threadIdx.x] = c2;
   __syncthreads();
   for (int w = AUX_BLOCK / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
       s0[threadIdx.x] += s0[threadIdx.x + w];
       s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] += s2[threadIdx.x + w];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     blk[blockIdx.x] = s0[0];
     blk[nblk + blockIdx.x] = s1[0];
+    blk[2 * nblk + blockIdx.x] = s2[0];
   }
 }
 
 __global__ void k_band_scan(int *__restrict__ blk, int nblk, int *__restrict__ counts) {
   // single thread per list: nblk is at most a few thousand
   const int l = threadIdx.x;
-  if (l > 1) return;
+  if (l > 2) return;
   int *b = blk + (long long)l * nblk;
   int run = 0;
   for (int i = 0; i < nblk; ++i) {
@@ -633,8 +700,7 @@ int msl_launch_init_eq(msl_ctx *c, const double *rho, const double *u, const dou
   return last_err();
 }
 
-int msl_launch_bc(msl_ctx *c, char *bl, char *bh) {
-  BCArgs b;
+static void bc_args(const msl_ctx *c, BCArgs &b) {
   for (int f = 0; f < 6; ++f) {
     b.bc[f] = c->cfg.bc[f];
     for (int m = 0; m < 5; ++m) {
@@ -642,15 +708,52 @@ int msl_launch_bc(msl_ctx *c, char *bl, char *bh) {
       b.slot_st[f][m] = c->cfg.slot_state[f][m];
     }
     for (int m = 0; m < 4; ++m) b.slot[f][m] = c->cfg.slot[f][m];
+    b.slot_edge[f] = c->cfg.slot_edge[f];
   }
-  const Geo &g = c->geo;
+}
+
+static long long host_pass_cells(const Geo &g, int ax) {
   const int N[3] = {g.nx, g.ny, g.nz};
+  long long tot = 2 * MSL_G;
+  for (int a = 0; a < g.dim; ++a)
+    if (a != ax) tot *= a < ax ? N[a] + 2 * MSL_G : N[a];
+  return tot;
+}
+
+// per step: periodic / zero-gradient copies and diffuse walls, axis by axis
+int msl_launch_bc(msl_ctx *c, char *bl, char *bh) {
+  BCArgs b;
+  bc_args(c, b);
+  const Geo &g = c->geo;
+  const int np0 = c->Q[0] * (c->cfg.thermal ? 2 : 1);
+  const int np1 = c->nlat > 1 ? c->Q[1] * (c->cfg.thermal ? 2 : 1) : 0;
   for (int ax = 0; ax < c->D; ++ax) {
-    long long tot = 2 * MSL_G;
-    for (int a = 0; a < c->D; ++a)
-      if (a != ax) tot *= a < ax ? N[a] + 2 * MSL_G : N[a];
-    DISPATCH_STORE(c, k_bc_pass, dim3(nblocks(tot)), dim3(AUX_BLOCK), c->dtab, g, ax, b, bl, bh,
-                   c->cls);
+    const int r0 = b.bc[2 * ax], r1 = b.bc[2 * ax + 1];
+    const long long tot = host_pass_cells(g, ax);
+    const bool copy = r0 == MSL_BC_PERIODIC || r0 == MSL_BC_OUTFLOW_ZG || r1 == MSL_BC_PERIODIC ||
+                      r1 == MSL_BC_OUTFLOW_ZG;
+    if (copy)
+      DISPATCH_STORE(c, k_bc_copy, dim3(nblocks(tot * (np0 + np1))), dim3(AUX_BLOCK), c->dtab, g, ax,
+                     b, bl, bh, np0, np1);
+    if (r0 == MSL_BC_DIFFUSE_WALL || r1 == MSL_BC_DIFFUSE_WALL)
+      DISPATCH_STORE(c, k_bc_pass, dim3(nblocks(tot)), dim3(AUX_BLOCK), c->dtab, g, ax, b, bl, bh,
+                     c->cls, 1 << MSL_BC_DIFFUSE_WALL);
+  }
+  return last_err();
+}
+
+// once per state load: the constant fixed-equilibrium ghosts of both buffers
+int msl_launch_bc_fixed(msl_ctx *c) {
+  BCArgs b;
+  bc_args(c, b);
+  const Geo &g = c->geo;
+  for (int buf = 0; buf < 2; ++buf) {
+    char *bl = c->planes[0][buf], *bh = c->nlat > 1 ? c->planes[1][buf] : nullptr;
+    for (int ax = 0; ax < c->D; ++ax) {
+      if (b.bc[2 * ax] != MSL_BC_FIXED_EQ && b.bc[2 * ax + 1] != MSL_BC_FIXED_EQ) continue;
+      DISPATCH_STORE(c, k_bc_pass, dim3(nblocks(host_pass_cells(g, ax))), dim3(AUX_BLOCK), c->dtab,
+                     g, ax, b, bl, bh, c->cls, 1 << MSL_BC_FIXED_EQ);
+    }
   }
   return last_err();
 }
@@ -710,6 +813,21 @@ int msl_launch_macros(msl_ctx *c, double *rho, double *u, double *T) {
   DISPATCH_STORE(c, k_macros, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), c->dtab, c->geo,
                  c->planes[0][c->cur], c->nlat > 1 ? c->planes[1][c->cur] : nullptr, c->cls, rho,
                  u, T);
+  return last_err();
+}
+
+// plain vectorised copy: the bandwidth reference of the roofline figures
+__global__ void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, long long n) {
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x)
+    dst[k] = src[k];
+}
+
+extern "C" int msl_device_copy(void *dst, const void *src, size_t bytes, void *stream) {
+  if (!dst || !src || bytes % 16) return MSL_EINVAL;
+  const long long n = (long long)(bytes / 16);
+  hipLaunchKernelGGL(k_copy, dim3(4096), dim3(AUX_BLOCK), 0, (hipStream_t)stream, (const uint4 *)src,
+                     (uint4 *)dst, n);
   return last_err();
 }
 

@@ -245,7 +245,7 @@ static void make_layout(const msl_config *cfg, Layout &L) {
   off = align256(off + 16);
   L.nblk = (int)((g.ncell + 4095) / 4096);
   L.off_blk = off;
-  off = align256(off + (size_t)2 * L.nblk * 4);
+  off = align256(off + (size_t)3 * L.nblk * 4);
   L.off_red = off;
   off = align256(off + (size_t)1024 * 6 * 8 + 64);
   L.off_flag = off;
@@ -423,7 +423,10 @@ int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_
   return MSL_OK;
 }
 
-void msl_destroy(msl_ctx *c) { delete c; }
+void msl_destroy(msl_ctx *c) {
+  if (c && c->prof) msl_profile(c, 0);
+  delete c;
+}
 
 int msl_get_dt(const msl_ctx *c, double *dt) {
   if (!c || !dt) return MSL_EINVAL;
@@ -452,6 +455,7 @@ static int refresh_band(msl_ctx *c) {
 int msl_init(msl_ctx *c, const double *rho, const double *u, const double *T) {
   if (!c || !rho || !u || (c->cfg.thermal && !T)) return MSL_EINVAL;
   int rc = msl_launch_init_eq(c, rho, u, T);
+  if (!rc) rc = msl_launch_bc_fixed(c);
   if (rc) { set_err(c, "init kernel launch failed"); return rc; }
   c->initialized = 1;
   c->step = 0;
@@ -489,32 +493,123 @@ static int mask_step(msl_ctx *c) {
   return refresh_band(c);
 }
 
+// ---- per-kernel timing ----
+static int prof_flush(msl_ctx *c) {
+  if (!c->nrec) return MSL_OK;
+  MSL_HIP(hipEventSynchronize(c->ev[2 * c->nrec - 1]));
+  for (int r = 0; r < c->nrec; ++r) {
+    float ms = 0.f;
+    MSL_HIP(hipEventElapsedTime(&ms, c->ev[2 * r], c->ev[2 * r + 1]));
+    double *st = c->pstat[c->rec_cls[r]];
+    st[0] += 1.0;
+    st[1] += ms;
+    st[2] += c->rec_bytes[r];
+    st[3] += c->rec_cells[r];
+  }
+  c->nrec = 0;
+  return MSL_OK;
+}
+
+static void prof_begin(msl_ctx *c) {
+  if (c->prof) hipEventRecord(c->ev[2 * c->nrec], c->stream);
+}
+
+static int prof_end(msl_ctx *c, int cls, double bytes, double cells) {
+  if (!c->prof) return MSL_OK;
+  hipEventRecord(c->ev[2 * c->nrec + 1], c->stream);
+  c->rec_cls[c->nrec] = cls;
+  c->rec_bytes[c->nrec] = bytes;
+  c->rec_cells[c->nrec] = cells;
+  if (++c->nrec == MSL_PROF_REC) return prof_flush(c);
+  return MSL_OK;
+}
+
+static int read_nhigh(msl_ctx *c) {
+  int h = 0;
+  if (c->nlat > 1) {
+    MSL_HIP(hipMemcpyAsync(&h, c->bcount + 2, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    MSL_HIP(hipStreamSynchronize(c->stream));
+  }
+  c->nhigh = h;
+  return MSL_OK;
+}
+
+int msl_profile(msl_ctx *c, int enable) {
+  if (!c) return MSL_EINVAL;
+  if (enable && !c->prof) {
+    for (int k = 0; k < 2 * MSL_PROF_REC; ++k) MSL_HIP(hipEventCreate(&c->ev[k]));
+    memset(c->pstat, 0, sizeof(c->pstat));
+    c->nrec = 0;
+    c->prof = 1;
+    return read_nhigh(c);
+  }
+  if (!enable && c->prof) {
+    int rc = prof_flush(c);
+    for (int k = 0; k < 2 * MSL_PROF_REC; ++k) hipEventDestroy(c->ev[k]);
+    c->prof = 0;
+    return rc;
+  }
+  return MSL_OK;
+}
+
+int msl_profile_read(msl_ctx *c, double *stats) {
+  if (!c || !stats) return MSL_EINVAL;
+  if (!c->prof) return MSL_ESTATE;
+  int rc = prof_flush(c);
+  if (rc) return rc;
+  memcpy(stats, c->pstat, sizeof(c->pstat));
+  memset(c->pstat, 0, sizeof(c->pstat));
+  return MSL_OK;
+}
+
 int msl_step(msl_ctx *c, int nsteps) {
   if (!c || nsteps < 0) return MSL_EINVAL;
   if (!c->initialized) { set_err(c, "msl_step before msl_init"); return MSL_ESTATE; }
   for (int s = 0; s < nsteps; ++s) {
     int rc;
     if (c->cfg.crit_kind && c->cfg.crit_every > 0 && c->nlat > 1 && c->step % c->cfg.crit_every == 0) {
+      prof_begin(c);
       rc = mask_step(c);
       if (rc) { set_err(c, "criterion / switching failed"); return rc; }
+      if ((rc = prof_end(c, 4, 0, (double)c->ncell))) return rc;
+      if (c->prof && (rc = read_nhigh(c))) return rc;
     }
     if (c->cfg.lift_mode == MSL_LIFT_MLP && c->mlp_on && !c->mlp_manual) {
       const int every = c->cfg.mlp_check_every > 0 ? c->cfg.mlp_check_every : 20;
-      if (c->step % every == 0 && (rc = msl_mlp_check_launch(c))) return rc;
+      if (c->step % every == 0) {
+        prof_begin(c);
+        if ((rc = msl_mlp_check_launch(c))) return rc;
+        if ((rc = prof_end(c, 5, 0, 0))) return rc;
+      }
     }
     const int cur = c->cur, nxt = cur ^ 1;
     char *bl = c->planes[0][cur], *bh = c->nlat > 1 ? c->planes[1][cur] : nullptr;
+    prof_begin(c);
     rc = msl_launch_bc(c, bl, bh);
     if (rc) { set_err(c, "ghost fill failed"); return rc; }
+    if ((rc = prof_end(c, 0, 0, 0))) return rc;
     for (int l = 0; l < c->nlat; ++l) {
+      // compulsory traffic: read and write every population plane of each native cell
+      const double cells = c->nlat == 1 ? (double)c->ncell
+                                        : (l == 0 ? (double)(c->ncell - c->nhigh) : (double)c->nhigh);
+      const double bytes = cells * 2.0 * c->Q[l] * (c->cfg.thermal ? 2 : 1) * (double)c->esz;
+      prof_begin(c);
       rc = msl_launch_stream_collide(c, l, c->planes[l][cur], c->planes[l][nxt]);
       if (rc) { set_err(c, "stream-collide launch failed"); return rc; }
+      if ((rc = prof_end(c, 1 + l, bytes, cells))) return rc;
     }
     if (c->nlat > 1) {
       char *nl = c->planes[0][nxt], *nh = c->planes[1][nxt];
+      prof_begin(c);
       rc = msl_launch_band_convert(c, nl, nh);
-      if (!rc && c->cfg.lift_mode == MSL_LIFT_MLP && c->mlp_on) rc = msl_mlp_band_lift(c, nl, nh);
       if (rc) { set_err(c, "band conversion failed"); return rc; }
+      if ((rc = prof_end(c, 3, 0, 0))) return rc;
+      if (c->cfg.lift_mode == MSL_LIFT_MLP && c->mlp_on) {
+        prof_begin(c);
+        rc = msl_mlp_band_lift(c, nl, nh);
+        if (rc) { set_err(c, "learned lifting failed"); return rc; }
+        if ((rc = prof_end(c, 5, 0, 0))) return rc;
+      }
     }
     c->cur = nxt;
     ++c->step;
@@ -541,6 +636,7 @@ int msl_get_populations(msl_ctx *c, int which, int fg, double *out) {
 int msl_set_populations(msl_ctx *c, int which, int fg, const double *in) {
   if (!c || !in || which < 0 || which >= c->nlat || (fg && !c->cfg.thermal)) return MSL_EINVAL;
   int rc = msl_launch_pops(c, which, fg, nullptr, in);
+  if (!rc) rc = msl_launch_bc_fixed(c);
   if (rc) return rc;
   c->initialized = 1;
   return refresh_band(c);

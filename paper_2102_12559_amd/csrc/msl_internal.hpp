@@ -11,6 +11,8 @@
 #define MSL_TX 64          // tile width in x (one wavefront)
 #define MSL_MTY 4          // micro-tile height (rows) of the per-tile class flags
 #define MSL_CHECK_TILE 64  // check tiles of the learned closure
+#define MSL_PROF_REC 512   // timed launches buffered between synchronisations
+#define MSL_PROF_K 6       // launch classes of msl_profile_read
 
 // Per velocity set: 1D nodes, weights, Hermite-weighted basis for the
 // equilibrium, and the 1D stencil (base offset and 3 Lagrange weights) of the
@@ -133,11 +135,20 @@ struct msl_ctx {
   uint8_t *mlp_flag;      // per check tile
   double *mlp_err;        // per check tile: E_mlp, E_grad
   int nctile, nct[3];
+  // per-kernel timing with HIP events (msl_profile)
+  int prof;
+  hipEvent_t ev[2 * MSL_PROF_REC];
+  int nrec;
+  int rec_cls[MSL_PROF_REC];
+  double rec_bytes[MSL_PROF_REC], rec_cells[MSL_PROF_REC];
+  double pstat[MSL_PROF_K][4];
+  long long nhigh;        // high-order cells (host copy, refreshed while profiling)
 };
 
 // launch helpers implemented in the .hip files
 int msl_launch_stream_collide(msl_ctx *c, int lat, const char *in, char *out);
 int msl_launch_bc(msl_ctx *c, char *buf_low, char *buf_high);
+int msl_launch_bc_fixed(msl_ctx *c);
 int msl_launch_band_convert(msl_ctx *c, char *buf_low, char *buf_high);
 int msl_launch_init_eq(msl_ctx *c, const double *rho, const double *u, const double *T);
 int msl_launch_criterion(msl_ctx *c);

@@ -36,6 +36,7 @@ class MslConfig(C.Structure):
         ("store", C.c_int), ("lift_mode", C.c_int),
         ("bc", C.c_int * 6), ("bc_state", (C.c_double * 5) * 6),
         ("slot_state", (C.c_double * 5) * 6), ("slot", (C.c_int * 4) * 6),
+        ("slot_edge", C.c_double * 6),
         ("crit_kind", C.c_int), ("crit_thr", C.c_double), ("crit_every", C.c_int),
         ("check_every", C.c_int), ("mlp_hidden", C.c_int), ("mlp_check_every", C.c_int),
     ]
@@ -50,7 +51,8 @@ SYMBOLS = [
     "msl_get_populations", "msl_set_populations", "msl_conservation", "msl_get_state",
     "msl_set_state", "msl_mlp_dims", "msl_collect_snapshots", "msl_mlp_set_weights",
     "msl_mlp_get_weights", "msl_mlp_train", "msl_mlp_grad", "msl_mlp_forward",
-    "msl_mlp_get_flags", "msl_mlp_set_flags", "msl_num_check_tiles",
+    "msl_mlp_get_flags", "msl_mlp_set_flags", "msl_num_check_tiles", "msl_profile",
+    "msl_profile_read", "msl_device_copy",
 ]
 
 
@@ -90,6 +92,9 @@ def lib():
         L.msl_mlp_get_flags.argtypes = [vp, vp]
         L.msl_mlp_set_flags.argtypes = [vp, vp]
         L.msl_num_check_tiles.argtypes = [vp, C.POINTER(C.c_int)]
+        L.msl_profile.argtypes = [vp, C.c_int]
+        L.msl_profile_read.argtypes = [vp, C.POINTER(C.c_double)]
+        L.msl_device_copy.argtypes = [vp, vp, sz, vp]
         _lib = L
     return _lib
 
@@ -110,6 +115,9 @@ def make_config(cfg: dict) -> MslConfig:
             for k in range(6):
                 for m in range(4):
                     c.slot[k][m] = int(v[k][m])
+        elif name == "slot_edge":
+            for k in range(6):
+                c.slot_edge[k] = float(v[k]) if v else 0.0
         else:
             setattr(c, name, v)
     return c
@@ -122,6 +130,15 @@ def workspace_bytes(cfg: dict) -> int:
     if rc:
         raise MslError(rc, "msl_workspace_bytes")
     return n.value
+
+
+def device_copy(dst, src, stream):
+    """Plain device copy (bandwidth reference); torch tensors of equal byte size."""
+    nbytes = src.numel() * src.element_size()
+    rc = lib().msl_device_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes,
+                               C.c_void_p(stream.cuda_stream))
+    if rc:
+        raise MslError(rc, "msl_device_copy")
 
 
 def _ptr(t):
@@ -241,6 +258,20 @@ class Solver:
     def set_state(self, data: bytes):
         buf = C.create_string_buffer(data, len(data))
         self._check(lib().msl_set_state(self._ctx, buf, len(data)), "msl_set_state")
+
+    # --- measurement --------------------------------------------------------
+    PROFILE_CLASSES = ("ghost_fill", "stream_collide_low", "stream_collide_high",
+                       "band_convert", "criterion_switch", "closure")
+
+    def profile(self, enable=True):
+        self._check(lib().msl_profile(self._ctx, int(enable)), "msl_profile")
+
+    def profile_read(self):
+        st = (C.c_double * 24)()
+        self._check(lib().msl_profile_read(self._ctx, st), "msl_profile_read")
+        a = np.array(st[:]).reshape(6, 4)
+        return {k: dict(launches=a[i, 0], ms=a[i, 1], bytes=a[i, 2], cells=a[i, 3])
+                for i, k in enumerate(self.PROFILE_CLASSES)}
 
     # --- learned closure --------------------------------------------------
     def mlp_dims(self):
