@@ -3,6 +3,7 @@
 // and projection, refinement criterion and switching, class / band / tile
 // bookkeeping with an ordered compaction of the band cells, macroscopic
 // fields, population import/export and the deterministic FP64 reductions.
+#include "msl_band.hpp"
 #include "msl_device.hpp"
 
 #define MSL_MAXQ 64
@@ -758,12 +759,91 @@ int msl_launch_bc_fixed(msl_ctx *c) {
   return last_err();
 }
 
+// band conversion and switching with compile-time velocity-set sizes
+template <typename S, int D, int NL, int NH>
+__global__ void __launch_bounds__(AUX_BLOCK)
+k_band_convert_t(const Tab *__restrict__ tab, Geo g, char *bl, char *bh,
+                 const int *__restrict__ list_lo, const int *__restrict__ list_hi,
+                 const int *__restrict__ counts, int skip_lift) {
+  constexpr int q = Pow<D, NL>::v, Q = Pow<D, NH>::v;
+  const int nlo = counts[0], nhi = counts[1];
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < nlo + nhi; t += stride) {
+    const bool lift = t < nlo;
+    if (lift && skip_lift) continue;   // the learned closure writes those
+    const long long k = lift ? list_lo[t] : list_hi[t - nlo];
+    int x, y, z;
+    cell_coords(g, k, x, y, z);
+    const int off = g.idx(x, y, z);
+    if (lift) {
+      double f[q], gg[q], fo[Q], go[Q];
+      read_cell_t<S, D, NL>(tab, g, bl, 0, off, f, gg);
+      lift_t<D, NL, NH>(tab, f, gg, nullptr, fo, go);
+      write_cell_t<S, D, NH>(tab, g, bh, 1, off, fo, go);
+    } else {
+      double f[Q], gg[Q], fo[q], go[q];
+      read_cell_t<S, D, NH>(tab, g, bh, 1, off, f, gg);
+      project_t<D, NL, NH>(tab, f, gg, fo, go);
+      write_cell_t<S, D, NL>(tab, g, bl, 0, off, fo, go);
+    }
+  }
+}
+
+template <typename S, int D, int NL, int NH>
+__global__ void __launch_bounds__(AUX_BLOCK)
+k_switch_t(const Tab *__restrict__ tab, Geo g, char *bl, char *bh, uint8_t *__restrict__ cls,
+           const uint8_t *__restrict__ newmask, int convert) {
+  constexpr int q = Pow<D, NL>::v, Q = Pow<D, NH>::v;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.ncell) return;
+  const int from = cls[k] & 1, to = newmask[k] & 1;
+  if (from != to && convert) {
+    int x, y, z;
+    cell_coords(g, k, x, y, z);
+    const int off = g.idx(x, y, z);
+    if (to == 1) {
+      double f[q], gg[q], fo[Q], go[Q];
+      read_cell_t<S, D, NL>(tab, g, bl, 0, off, f, gg);
+      lift_t<D, NL, NH>(tab, f, gg, nullptr, fo, go);
+      write_cell_t<S, D, NH>(tab, g, bh, 1, off, fo, go);
+    } else {
+      double f[Q], gg[Q], fo[q], go[q];
+      read_cell_t<S, D, NH>(tab, g, bh, 1, off, f, gg);
+      project_t<D, NL, NH>(tab, f, gg, fo, go);
+      write_cell_t<S, D, NL>(tab, g, bl, 0, off, fo, go);
+    }
+  }
+  cls[k] = (uint8_t)to;
+}
+
+template <typename S>
+static int band_convert_s(msl_ctx *c, char *bl, char *bh, int skip) {
+  return msl_pair_dispatch(c->D, c->htab.lat[0].n, c->htab.lat[1].n, [&]<int D, int NL, int NH>() {
+    hipLaunchKernelGGL((k_band_convert_t<S, D, NL, NH>), dim3(512), dim3(AUX_BLOCK), 0, c->stream,
+                       c->dtab, c->geo, bl, bh, c->blist[0], c->blist[1], c->bcount, skip);
+    return last_err();
+  });
+}
+
+template <typename S>
+static int switch_s(msl_ctx *c, char *bl, char *bh, const uint8_t *newmask, int convert) {
+  return msl_pair_dispatch(c->D, c->htab.lat[0].n, c->htab.lat[1].n, [&]<int D, int NL, int NH>() {
+    hipLaunchKernelGGL((k_switch_t<S, D, NL, NH>), dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), 0,
+                       c->stream, c->dtab, c->geo, bl, bh, c->cls, newmask, convert);
+    return last_err();
+  });
+}
+
 int msl_launch_band_convert(msl_ctx *c, char *bl, char *bh) {
   if (c->nlat < 2) return MSL_OK;
   const int mlp = c->cfg.lift_mode == MSL_LIFT_MLP && c->mlp_on;
-  DISPATCH_STORE(c, k_band_convert, dim3(512), dim3(AUX_BLOCK), c->dtab, c->geo, bl, bh,
-                 c->blist[0], c->blist[1], c->bcount, mlp);
-  return last_err();
+  switch (c->cfg.store) {
+    case MSL_FP64: return band_convert_s<double>(c, bl, bh, mlp);
+    case MSL_FP32: return band_convert_s<float>(c, bl, bh, mlp);
+    case MSL_FP16_DEV: return band_convert_s<_Float16>(c, bl, bh, mlp);
+    case MSL_BF16_DEV: return band_convert_s<bf16_t>(c, bl, bh, mlp);
+  }
+  return MSL_EINVAL;
 }
 
 int msl_launch_criterion(msl_ctx *c) {
@@ -787,9 +867,19 @@ int msl_launch_get_mask(msl_ctx *c, uint8_t *mask) {
 
 int msl_launch_switch(msl_ctx *c, const uint8_t *newmask) {
   char *bl = c->planes[0][c->cur], *bh = c->nlat > 1 ? c->planes[1][c->cur] : nullptr;
-  DISPATCH_STORE(c, k_switch, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), c->dtab, c->geo, bl, bh,
-                 c->cls, newmask, c->initialized && c->nlat > 1);
-  return last_err();
+  if (c->nlat < 2) {
+    DISPATCH_STORE(c, k_switch, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), c->dtab, c->geo, bl, bh,
+                   c->cls, newmask, 0);
+    return last_err();
+  }
+  const int conv = c->initialized;
+  switch (c->cfg.store) {
+    case MSL_FP64: return switch_s<double>(c, bl, bh, newmask, conv);
+    case MSL_FP32: return switch_s<float>(c, bl, bh, newmask, conv);
+    case MSL_FP16_DEV: return switch_s<_Float16>(c, bl, bh, newmask, conv);
+    case MSL_BF16_DEV: return switch_s<bf16_t>(c, bl, bh, newmask, conv);
+  }
+  return MSL_EINVAL;
 }
 
 int msl_launch_classify(msl_ctx *c) {

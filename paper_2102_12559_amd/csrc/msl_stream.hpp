@@ -18,6 +18,7 @@
 #include <utility>
 
 #include "msl_device.hpp"
+#include "msl_stream2.hpp"
 
 template <typename S, bool TH, int N, int D>
 struct SCTraits {
@@ -25,7 +26,19 @@ struct SCTraits {
   using C = typename T::C;
   static constexpr int Q = D == 2 ? N * N : N * N * N;
   static constexpr int NP = TH ? 2 * Q : Q;
+#ifndef MSL_ROWS_OVERRIDE
   static constexpr int R = msl_rows_for(NP, (int)(sizeof(C) / 4), D == 2 ? 96 : 128);
+#else
+  static constexpr int R = MSL_ROWS_OVERRIDE;
+#endif
+  // occupancy target: registers for the streamed values of all planes plus
+  // the collision of one cell
+  static constexpr int VREG = NP * R * (int)(sizeof(C) / 4) + 2 * Q * (int)(sizeof(C) / 4) + 48;
+#ifndef MSL_WAVES_OVERRIDE
+  static constexpr int WAVES = 512 / VREG >= 8 ? 8 : (512 / VREG < 1 ? 1 : 512 / VREG);
+#else
+  static constexpr int WAVES = MSL_WAVES_OVERRIDE;
+#endif
 };
 
 // Collision of the R cells of one thread; ft[k][r] holds the streamed value of
@@ -44,9 +57,12 @@ __device__ __forceinline__ void collide_store(const Tab *__restrict__ tab, int l
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int y = y0 + r * ystep, z = z0 + r * zstep;
-    if (x >= g.nx || y >= g.ny || (D == 3 && z >= g.nz)) continue;
-    const long long cell = ((long long)z * g.ny + y) * g.nx + x;
-    if ((cls[cell] & 1) != lat) continue;
+    // every lane collides (values of foreign or outside cells are discarded at
+    // the store): a branch here would let the compiler sink the interpolation
+    // into it and keep the staged window values alive across the collision
+    const bool inside = x < g.nx && y < g.ny && (D == 2 || z < g.nz);
+    const long long cell = inside ? ((long long)z * g.ny + y) * g.nx + x : 0;
+    const bool mine = inside && (cls[cell] & 1) == lat;
     C f[Q];
     C gg[TH ? Q : 1];
 #pragma unroll
@@ -89,7 +105,9 @@ __device__ __forceinline__ void collide_store(const Tab *__restrict__ tab, int l
 #pragma unroll
     for (int a = 0; a < N; ++a) Px[a] *= rd;
     const C gf = (C)(tab->gfac * Tm);
-    const int base = g.idx(x, y, z);
+    const unsigned boff = (unsigned)g.idx(x, y, z) * (unsigned)sizeof(S);
+    S so[Q];
+    S sg[TH ? Q : 1];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int a = i % N, b = (i / N) % N, cc = D == 3 ? i / (N * N) : 0;
@@ -99,10 +117,17 @@ __device__ __forceinline__ void collide_store(const Tab *__restrict__ tab, int l
       const C fo = f[i] + om * (feq - f[i]);
       C W = tsel<C>(L.w[a], L.wf[a]) * tsel<C>(L.w[b], L.wf[b]);
       if (D == 3) W *= tsel<C>(L.w[cc], L.wf[cc]);
-      out[(long long)i * g.plane + base] = T::store(T::dev ? fo / (rho0 * W) - C(1) : fo);
+      so[i] = T::store(T::dev ? fo / (rho0 * W) - C(1) : fo);
       if (TH) {
         const C go = gg[TH ? i : 0] + om * (gf * feq - gg[TH ? i : 0]);
-        out[(long long)(Q + i) * g.plane + base] = T::store(T::dev ? go / (gsc0 * W) - C(1) : go);
+        sg[TH ? i : 0] = T::store(T::dev ? go / (gsc0 * W) - C(1) : go);
+      }
+    }
+    if (mine) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        *(S *)((char *)(out + (long long)i * g.plane) + boff) = so[i];
+        if (TH) *(S *)((char *)(out + (long long)(Q + i) * g.plane) + boff) = sg[TH ? i : 0];
       }
     }
   }
@@ -116,7 +141,7 @@ __device__ __forceinline__ void for_planes(F &&f) {
 }
 
 template <typename S, bool TH, int N>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCTraits<S, TH, N, 2>::WAVES)))
 k_sc2d(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in, S *__restrict__ out,
        const uint8_t *__restrict__ cls, const uint8_t *__restrict__ tflag) {
   using Tr = SCTraits<S, TH, N, 2>;
@@ -146,7 +171,7 @@ k_sc2d(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in, S 
     int e = threadIdx.x + 256 * m;
     e = e < NE ? e : NE - 1;
     const int rr = e / LW, cc = e - rr * LW;
-    eoff[m] = rr * g.pitch + cc;
+    eoff[m] = (rr * g.pitch + cc) * (int)sizeof(S);   // byte offset from the window origin
   }
   C ft[NP][R];
   C reg[NLD];
@@ -155,7 +180,8 @@ k_sc2d(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in, S 
     const int ox = L.n0[a] - 1, oy = L.n0[b] - 1;
     const S *base = in + (long long)K * g.plane + g.idx(x0 + ox, y0 + oy, 0);
 #pragma unroll
-    for (int m = 0; m < NLD; ++m) reg[m] = (C)T::load(base[eoff[m]]);
+    for (int m = 0; m < NLD; ++m)
+      reg[m] = (C)T::load(*(const S *)((const char *)base + (unsigned)eoff[m]));
   };
   auto lstore = [&](int buf) {
 #pragma unroll
@@ -196,7 +222,7 @@ k_sc2d(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in, S 
 
 // 3D: tile 64 x 4 x TZ; each thread owns one (x, y) column of TZ cells.
 template <typename S, bool TH, int N>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCTraits<S, TH, N, 3>::WAVES)))
 k_sc3d(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in, S *__restrict__ out,
        const uint8_t *__restrict__ cls, const uint8_t *__restrict__ tflag) {
   using Tr = SCTraits<S, TH, N, 3>;
@@ -227,7 +253,7 @@ k_sc3d(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in, S 
     e = e < NE ? e : NE - 1;
     const int rz = e / (LW * LY), rem = e - rz * (LW * LY);
     const int ry = rem / LW, rx = rem - ry * LW;
-    eoff[m] = (rz * g.rows + ry) * g.pitch + rx;
+    eoff[m] = ((rz * g.rows + ry) * g.pitch + rx) * (int)sizeof(S);   // byte offset
   }
   C ft[NP][R];
   C reg[NLD];
@@ -236,7 +262,8 @@ k_sc3d(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in, S 
     const int ox = L.n0[a] - 1, oy = L.n0[b] - 1, oz = L.n0[cc] - 1;
     const S *base = in + (long long)K * g.plane + g.idx(x0 + ox, y0 + oy, z0 + oz);
 #pragma unroll
-    for (int m = 0; m < NLD; ++m) reg[m] = (C)T::load(base[eoff[m]]);
+    for (int m = 0; m < NLD; ++m)
+      reg[m] = (C)T::load(*(const S *)((const char *)base + (unsigned)eoff[m]));
   };
   auto lstore = [&](int buf) {
 #pragma unroll
@@ -285,7 +312,13 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
   using Tr = SCTraits<S, TH, N, D>;
   const Geo &g = c->geo;
   dim3 block(256);
-  if constexpr (D == 2) {
+  if constexpr (D == 2 && SC2Traits<S, TH, N>::fits) {
+    // every plane resident in LDS
+    using T2 = SC2Traits<S, TH, N>;
+    dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + T2::TY - 1) / T2::TY);
+    hipLaunchKernelGGL((k_sc2d_res<S, TH, N>), grid, block, 0, c->stream, c->dtab, lat, g,
+                       (const S *)in, (S *)out, c->cls, c->tflag);
+  } else if constexpr (D == 2) {
     dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + MSL_MTY * Tr::R - 1) / (MSL_MTY * Tr::R));
     hipLaunchKernelGGL((k_sc2d<S, TH, N>), grid, block, 0, c->stream, c->dtab, lat, g,
                        (const S *)in, (S *)out, c->cls, c->tflag);

@@ -1,0 +1,251 @@
+// msl_stream2.hpp -- the 2D stream-and-collide kernel with every population
+// plane resident in LDS.
+//
+// A workgroup owns a tile of 64 x TY cells.  It first issues, for every plane
+// (f_0..f_{Q-1}, then g_0..g_{Q-1}), direct-to-LDS buffer loads of the plane's
+// (66 x (TY+2)) window around the departure points of the tile (the departure
+// offset x - c_i dt is the same for all cells of a plane, so the window is
+// the tile shifted by the plane's base offset).  All windows are in flight at
+// once -- tens of KB per workgroup -- and no VGPR stages them.  After one wait
+// and one barrier, two passes over the resident windows follow:
+//   pass 1: separable 3-point Lagrange reconstruction of every population
+//           (eq. reconstructionPond), accumulating rho, rho u (, rho E);
+//   pass 2: the reconstruction again, BGK relaxation towards the Hermite
+//           product-form lattice equilibrium (eqs. Pond_f/g, feqL, geqL) and
+//           the store, with buffer stores whose out-of-range offset drops the
+//           writes of foreign or outside cells.
+// Reconstructing twice costs LDS reads but keeps only the moments and the
+// per-axis equilibrium factors in registers.
+#pragma once
+#include <utility>
+
+#include "msl_device.hpp"
+
+typedef __attribute__((address_space(3))) void msl_lds_t;
+#define MSL_RSRC_WORD3 0x00020000   // raw buffer, gfx9-family descriptor word 3
+
+template <typename S, bool TH, int N>
+struct SC2Traits {
+  using T = StoreTraits<S>;
+  using C = typename T::C;
+  static constexpr int Q = N * N;
+  static constexpr int NP = TH ? 2 * Q : Q;
+  static constexpr int SZ = (int)sizeof(S);
+  // dwords per window row: 66 elements plus one dword of slack for 16-bit
+  // windows that start at an odd element
+  static constexpr int LWD = (66 * SZ + 3) / 4 + (SZ < 4 ? 1 : 0);
+  static constexpr int dwords_per_plane(int ty) { return ((ty + 2) * LWD + 255) / 256 * 256; }
+  static constexpr int LDS_BUDGET = 72 * 1024;
+  static constexpr int TY = NP * dwords_per_plane(16) * 4 <= LDS_BUDGET ? 16
+                          : (NP * dwords_per_plane(8) * 4 <= LDS_BUDGET ? 8 : 4);
+  static constexpr int R = TY / 4;
+  static constexpr int PD = dwords_per_plane(TY);     // LDS dwords per plane window
+  static constexpr int M = PD / 256;                    // DMA instructions per wave per plane
+  static constexpr int LDS_BYTES = NP * PD * 4;
+  static constexpr bool fits = LDS_BYTES <= 150 * 1024;
+  // workgroups per CU allowed by LDS (160 KB); with 4 waves per workgroup that
+  // is also the waves per SIMD the register budget has to allow
+  static constexpr int WGS = (160 * 1024) / LDS_BYTES;
+  static constexpr int WAVES = WGS >= 3 ? 3 : (WGS < 1 ? 1 : WGS);
+};
+
+template <int NP, typename F>
+__device__ __forceinline__ void msl_for_planes(F &&f) {
+  [&]<int... Ks>(std::integer_sequence<int, Ks...>) {
+    (f.template operator()<Ks>(), ...);
+  }(std::make_integer_sequence<int, NP>{});
+}
+
+template <typename S>
+__device__ __forceinline__ float lds_elem(const char *p);
+template <>
+__device__ __forceinline__ float lds_elem<float>(const char *p) { return *(const float *)p; }
+template <>
+__device__ __forceinline__ float lds_elem<_Float16>(const char *p) { return (float)*(const _Float16 *)p; }
+template <>
+__device__ __forceinline__ float lds_elem<bf16_t>(const char *p) {
+  return __uint_as_float(((uint32_t)*(const uint16_t *)p) << 16);
+}
+template <typename S>
+__device__ __forceinline__ double lds_elem_d(const char *p) { return *(const double *)p; }
+
+template <typename S, bool TH, int N>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SC2Traits<S, TH, N>::WAVES)))
+k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
+           S *__restrict__ out, const uint8_t *__restrict__ cls,
+           const uint8_t *__restrict__ tflag) {
+  using Tr = SC2Traits<S, TH, N>;
+  using T = typename Tr::T;
+  using C = typename Tr::C;
+  constexpr int Q = Tr::Q, NP = Tr::NP, R = Tr::R, TY = Tr::TY, PD = Tr::PD, M = Tr::M;
+  constexpr int LWD = Tr::LWD, SZ = Tr::SZ;
+  constexpr int LR = TY + 2;
+  __shared__ uint32_t sm[NP * PD];
+  const LatTab &L = tab->lat[lat];
+  const int bx = blockIdx.x, by = blockIdx.y;
+  const int x0 = bx * MSL_TX, y0 = by * TY;
+  {
+    uint8_t any = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int my = by * R + r;
+      if (my < g.nty) any |= tflag[my * g.ntx + bx];
+    }
+    if (!(any & (1 << lat))) return;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tx = lane, ty = w;
+  const unsigned pitch_b = (unsigned)g.pitch * SZ;
+  const unsigned plane_b = (unsigned)g.plane * SZ;
+  // plane-independent byte offsets of this lane's window dwords
+  unsigned voff[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    int d = lane + 64 * (w + 4 * m);
+    d = d < LR * LWD ? d : LR * LWD - 1;
+    const int row = d / LWD, col = d - row * LWD;
+    voff[m] = (unsigned)row * pitch_b + (unsigned)col * 4u;
+  }
+  // 1. every plane's window in flight at once (direct-to-LDS loads)
+  auto issue = [&]<int K>() {
+    constexpr int i = K % Q, a = i % N, b = i / N;
+    const int ox = L.n0[a] - 1, oy = L.n0[b] - 1;
+    const unsigned org = (unsigned)g.idx(x0 + ox, y0 + oy, 0) * SZ;   // window origin (bytes)
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(in + (long long)K * g.plane), (short)0, (int)plane_b, MSL_RSRC_WORD3);
+    const int soff = (int)(org & ~3u);
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rs, (msl_lds_t *)(sm + K * PD + 64 * (w + 4 * m)), 4, (int)voff[m], soff, 0, 0);
+  };
+  msl_for_planes<NP>(issue);
+  // my cells: inside the domain and of this velocity set
+  bool mine[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int x = x0 + tx, y = y0 + ty * R + r;
+    const bool inside = x < g.nx && y < g.ny;
+    mine[r] = inside && (cls[inside ? (long long)y * g.nx + x : 0] & 1) == lat;
+  }
+  __syncthreads();   // the compiler waits for the loads before the barrier
+
+  // reconstruction of plane K at this thread's R cells (raw storage domain)
+  auto recon = [&]<int K>(C (&ft)[R]) {
+    constexpr int i = K % Q, a = i % N, b = i / N;
+    const int ox = L.n0[a] - 1, oy = L.n0[b] - 1;
+    const unsigned org = (unsigned)g.idx(x0 + ox, y0 + oy, 0) * SZ;
+    const char *base = (const char *)(sm + K * PD) + (org & 3u);
+    const C wx0 = tsel<C>(L.a[a][0], L.af[a][0]), wx2 = tsel<C>(L.a[a][2], L.af[a][2]);
+    const C wy0 = tsel<C>(L.a[b][0], L.af[b][0]), wy2 = tsel<C>(L.a[b][2], L.af[b][2]);
+    C h[R + 2];
+#pragma unroll
+    for (int r = 0; r < R + 2; ++r) {
+      const char *row = base + (ty * R + r) * LWD * 4 + tx * SZ;
+      C v0, v1, v2;
+      if constexpr (SZ == 8) {
+        v0 = (C)lds_elem_d<S>(row); v1 = (C)lds_elem_d<S>(row + 8); v2 = (C)lds_elem_d<S>(row + 16);
+      } else {
+        v0 = (C)lds_elem<S>(row); v1 = (C)lds_elem<S>(row + SZ); v2 = (C)lds_elem<S>(row + 2 * SZ);
+      }
+      // differenced form: centre weight 1 - w0 - w2 exactly
+      h[r] = v1 + wx0 * (v0 - v1) + wx2 * (v2 - v1);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) ft[r] = h[r + 1] + wy0 * (h[r] - h[r + 1]) + wy2 * (h[r + 2] - h[r + 1]);
+  };
+
+  const C rho0 = (C)tab->rho0;
+  const C gsc0 = (C)(tab->gfac * tab->rho0 * tab->T0);
+  // 2. moments
+  C rho[R], jx[R], jy[R], en[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) { rho[r] = C(0); jx[r] = C(0); jy[r] = C(0); en[r] = C(0); }
+  auto pass1 = [&]<int K>() {
+    constexpr int i = K % Q, a = i % N, b = i / N;
+    C ft[R];
+    recon.template operator()<K>(ft);
+    const C W = tsel<C>(L.w[a], L.wf[a]) * tsel<C>(L.w[b], L.wf[b]);
+    const C cx = tsel<C>(L.c[a], L.cf[a]), cy = tsel<C>(L.c[b], L.cf[b]);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if constexpr (K < Q) {
+        const C f = T::dev ? rho0 * W * (C(1) + ft[r]) : ft[r];
+        rho[r] += f;
+        jx[r] += cx * f;
+        jy[r] += cy * f;
+        if (TH) en[r] += C(0.5) * (cx * cx + cy * cy) * f;
+      } else {
+        en[r] += T::dev ? gsc0 * W * (C(1) + ft[r]) : ft[r];
+      }
+    }
+  };
+  msl_for_planes<NP>(pass1);
+  // LDS is re-read in pass 2: without this barrier the compiler would keep
+  // every reconstructed value of pass 1 in registers to reuse it
+  __syncthreads();
+
+  // 3. equilibrium factors per cell, in FP64 (no rounding bias in the
+  //    equilibrium's mass and momentum), kept in the compute precision
+  C Px[R][N], Py[R][N], om[R], gf[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double rd = (double)rho[r], ird = 1.0 / rd;
+    const double ux = (double)jx[r] * ird, uy = (double)jy[r] * ird;
+    double Tm = 1.0;
+    if (TH) Tm = ((double)en[r] - 0.5 * rd * (ux * ux + uy * uy)) / (tab->cv * rd);
+    double px[N], py[N];
+    eq_axis<double, N>(L, ux, Tm, px);
+    eq_axis<double, N>(L, uy, Tm, py);
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      Px[r][q] = (C)(px[q] * rd);
+      Py[r][q] = (C)py[q];
+    }
+    om[r] = tsel<C>(tab->omega, tab->omegaf);
+    if (tab->tau_mode == 1) {
+      const double mu = tab->mu_ref * pow(Tm / tab->tau_ref_T, tab->mu_exp);
+      om[r] = (C)(1.0 / (mu / (rd * Tm * tab->dt) + 0.5));
+    }
+    gf[r] = (C)(tab->gfac * Tm);
+  }
+  // 4. collide and store
+  unsigned soff_cell[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int x = x0 + tx, y = y0 + ty * R + r;
+    soff_cell[r] = mine[r] ? (unsigned)g.idx(x, y, 0) * SZ : 0x80000000u;
+  }
+  auto pass2 = [&]<int K>() {
+    constexpr int i = K % Q, a = i % N, b = i / N;
+    C ft[R];
+    recon.template operator()<K>(ft);
+    const C W = tsel<C>(L.w[a], L.wf[a]) * tsel<C>(L.w[b], L.wf[b]);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(out + (long long)K * g.plane), (short)0, (int)plane_b, MSL_RSRC_WORD3);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const C feq = Px[r][a] * Py[r][b];
+      C o;
+      if constexpr (K < Q) {
+        const C f = T::dev ? rho0 * W * (C(1) + ft[r]) : ft[r];
+        const C fo = f + om[r] * (feq - f);
+        o = T::dev ? fo / (rho0 * W) - C(1) : fo;
+      } else {
+        const C gv = T::dev ? gsc0 * W * (C(1) + ft[r]) : ft[r];
+        const C go = gv + om[r] * (gf[r] * feq - gv);
+        o = T::dev ? go / (gsc0 * W) - C(1) : go;
+      }
+      const S sv = T::store(o);
+      if constexpr (SZ == 8) {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, sv), rs, (int)soff_cell[r], 0, 0);
+      } else if constexpr (SZ == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, sv), rs, (int)soff_cell[r], 0, 0);
+      } else {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, sv), rs, (int)soff_cell[r], 0, 0);
+      }
+    }
+  };
+  msl_for_planes<NP>(pass2);
+}
