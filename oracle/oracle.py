@@ -324,3 +324,12 @@ class Oracle:
 
     def mlp_check(self):
         _check(lib().or_mlp_check(self._ctx), "mlp_check")
+
+    def lift_cell(self, fq, gq=None, tile=0):
+        fq = np.ascontiguousarray(fq, dtype=np.float64)
+        gqa = np.ascontiguousarray(gq, dtype=np.float64) if gq is not None else np.zeros_like(fq)
+        fQ = np.zeros(self.Q[1])
+        gQ = np.zeros(self.Q[1])
+        _check(lib().or_lift_cell(self._ctx, _p(fq), _p(gqa), int(tile), _p(fQ), _p(gQ)),
+               "lift_cell")
+        return (fQ, gQ) if gq is not None else fQ

@@ -421,7 +421,12 @@ int or_set_mask(or_ctx *c, const uint8_t *mask) {
     native_state(c, k, f, g);
     int p[3];
     cell_coords(c, k, p);
-    convert(c, from, to, f, g, tile_of(c, p), fo, go);
+    if (from < to && c->cfg.lift_mode == 2)
+      /* a switching cell is lifted with the plain completion; the learned
+       * closure only serves collocation points of the band */
+      lat_lift_raw(c->lat[0], c->lat[1], th, c->cfg.cv, f, g, NULL, fo, go);
+    else
+      convert(c, from, to, f, g, tile_of(c, p), fo, go);
     for (int i = 0; i < c->lat[to]->Q; i++) {
       c->f[to][(int64_t)i * c->ncell + k] = store_round(c, fo[i], fscale(c, to, i));
       if (th) c->g[to][(int64_t)i * c->ncell + k] = store_round(c, go[i], gscale(c, to, i));

@@ -270,10 +270,11 @@ static void make_layout(const msl_config *cfg, Layout &L) {
         (size_t)L.mlpP * 4,                       // 4 adam m
         (size_t)L.mlpP * 4,                       // 5 adam v
         (size_t)L.mlpP * 4,                       // 6 grad
-        64,                                       // 7 loss
+        (size_t)MSL_MLP_LOSS_RING * 4,            // 7 loss history
         (size_t)L.nctile,                         // 8 flags
-        (size_t)L.nctile * 2 * 8,                 // 9 errors
-        0, 0};
+        (size_t)L.nctile * 2 * 8,                 // 9 per-tile errors
+        (size_t)MSL_MLP_MAXBLK * (L.mlpP + 1) * 4,  // 10 gradient / loss partials
+        (size_t)g.ncell * (L.mlpO * 4 + 16)};     // 11 check: targets, per-cell errors
     for (int k = 0; k < 12; ++k) {
       L.mlp_off[k] = off;
       off = align256(off + sizes[k]);
@@ -402,6 +403,9 @@ int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_
     c->mlp_loss = (float *)(base + L.mlp_off[7]);
     c->mlp_flag = (uint8_t *)(base + L.mlp_off[8]);
     c->mlp_err = (double *)(base + L.mlp_off[9]);
+    c->mlp_gpart = (float *)(base + L.mlp_off[10]);
+    c->mlp_tgt = (float *)(base + L.mlp_off[11]);
+    c->mlp_cerr = (double *)(base + L.mlp_off[11] + align256((size_t)L.geo.ncell * L.mlpO * 4));
     c->nctile = L.nctile;
     for (int a = 0; a < 3; ++a) c->nct[a] = L.nct[a];
   }

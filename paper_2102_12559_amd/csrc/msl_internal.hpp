@@ -13,6 +13,8 @@
 #define MSL_CHECK_TILE 64  // check tiles of the learned closure
 #define MSL_PROF_REC 512   // timed launches buffered between synchronisations
 #define MSL_PROF_K 6       // launch classes of msl_profile_read
+#define MSL_MLP_MAXBLK 256       // workgroups of one training step (64 rows each)
+#define MSL_MLP_LOSS_RING 65536  // device loss history of the training steps
 
 // Per velocity set: 1D nodes, weights, Hermite-weighted basis for the
 // equilibrium, and the 1D stencil (base offset and 3 Lagrange weights) of the
@@ -134,6 +136,10 @@ struct msl_ctx {
   float *mlp_loss;        // device scalars
   uint8_t *mlp_flag;      // per check tile
   double *mlp_err;        // per check tile: E_mlp, E_grad
+  float *mlp_gpart;       // per-block gradient partials [MSL_MLP_MAXBLK][P], then loss partials
+  float *mlp_tgt;         // check: true normalised targets of the high-order band cells
+  double *mlp_cerr;       // check: per-cell E_mlp, E_grad
+  long mlp_steps;         // Adam steps taken
   int nctile, nct[3];
   // per-kernel timing with HIP events (msl_profile)
   int prof;

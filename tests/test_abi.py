@@ -68,10 +68,13 @@ def test_workspace_too_small_is_enomem():
     assert rc == msl.MSL_ENOMEM
 
 
-def test_workspace_sizes_of_the_workloads():
-    w = inputs.jet_c2()
+@pytest.mark.parametrize("thermal,n_high", [(0, 6), (1, 4)])
+def test_workspace_sizes_of_the_workloads(thermal, n_high):
+    w = inputs.jet_c2(thermal=thermal, n_high=n_high)
     b = msl.workspace_bytes(w["cfg"])
-    # two buffers of f and g planes for D2Q9 and D2Q16 (fp32) plus bookkeeping
+    # two buffers of the population planes (f, and g when thermal) of both
+    # velocity sets in fp32, padded, plus per-cell bookkeeping
     cells = 1024 * 512
-    assert b > 2 * 2 * (9 + 16) * cells * 4
-    assert b < 1.3 * 2 * 2 * (9 + 16) * cells * 4 + 64 * cells
+    planes = (9 + n_high ** 2) * (2 if thermal else 1)
+    assert b > 2 * planes * cells * 4
+    assert b < 1.3 * 2 * planes * cells * 4 + 64 * cells

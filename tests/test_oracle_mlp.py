@@ -95,14 +95,21 @@ def test_nonzero_network_changes_only_lifted_values():
     cfg = inputs.base_config(nx=8, ny=8, n_low=3, n_high=4, lift_mode=inputs.LIFT_MLP)
     o = O.Oracle(cfg)
     o.set_mlp(H, p, np.zeros(F), np.ones(F), np.zeros(Od), np.ones(Od), manual_check=True)
-    fq = product_feq(2, 3, 1.0, np.array([0.1, 0.05, 0]), 1.0)
-    fQ = O.lift(2, 3, 4, fq)
-    rho, u, T = np.ones((1, 8, 8)), np.zeros((2, 1, 8, 8)), np.ones((1, 8, 8))
-    o.init(rho, u, T)
-    o.set_mask(np.ones((1, 8, 8), dtype=np.uint8))
-    got = o.get_pops(1)[:, 0]
-    feq = product_feq(2, 4, 1.0, np.zeros(3), 1.0)
+    u = np.array([0.1, 0.05, 0])
+    fq = product_feq(2, 3, 1.0, u, 1.0)
+    got = o.lift_cell(fq)
+    feq = product_feq(2, 4, 1.0, u, 1.0)
     assert np.max(np.abs(got - feq)) > 1e-4
     back = O.project(2, 4, 3, got)
-    assert np.max(np.abs(back - product_feq(2, 3, 1.0, np.zeros(3), 1.0))) < 1e-14
-    del fQ
+    assert np.max(np.abs(back - fq)) < 1e-14
+    # the raw moments the low-order set cannot hold moved by exactly rho T^{|p|/2} * 0.01
+    x, _ = O.gh_rule(4)
+    cx = np.array([x[i % 4] for i in range(16)])
+    cy = np.array([x[i // 4] for i in range(16)])
+    for j in range(16):
+        m, k = j % 4, j // 4
+        d = np.sum((got - feq) * cx ** m * cy ** k)
+        if m < 3 and k < 3:
+            assert abs(d) < 1e-13
+        else:
+            assert abs(d - 0.01) < 1e-12
