@@ -79,10 +79,13 @@ def collect_snapshots(cases, times, n_high=6, hidden=64):
     return np.concatenate(Xs), np.concatenate(Ys)
 
 
-def train(X, Y, *, epochs=50, batch=1024, lr=1e-3, hidden=64, seed=0, n_high=6, val_frac=0.1):
+def train(X, Y, *, epochs=50, batch=1024, lr=1e-3, hidden=64, seed=0, n_high=6, val_frac=0.1,
+          schedule=None):
     """Train the closure on the GPU.  Rows are shuffled with the seeded
-    generator and split into training and validation parts.  Returns a dict
-    with the parameters, standardisation statistics and loss history."""
+    generator and split into training and validation parts.  `schedule`, a
+    list of (epochs, learning rate) phases run one after the other with the
+    optimiser state carried over, replaces (epochs, lr).  Returns a dict with
+    the parameters, standardisation statistics and loss history."""
     import torch
     rows = X.shape[0]
     order = np.argsort(inputs.uniform_pm1(seed + 17, rows), kind="stable")
@@ -99,7 +102,8 @@ def train(X, Y, *, epochs=50, batch=1024, lr=1e-3, hidden=64, seed=0, n_high=6, 
     dev = s.device
     Xn = torch.as_tensor((Xt - xm) / xs, dtype=torch.float32, device=dev)
     Yn = torch.as_tensor((Yt - ym) / ys, dtype=torch.float32, device=dev)
-    log = s.mlp_train(Xn, Yn, batch=batch, epochs=epochs, lr=lr)
+    phases = schedule if schedule else [(epochs, lr)]
+    log = np.concatenate([s.mlp_train(Xn, Yn, batch=batch, epochs=e, lr=r) for e, r in phases])
     params = s.mlp_get_weights()
     val = None
     if nval:

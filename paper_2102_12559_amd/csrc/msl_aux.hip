@@ -6,7 +6,6 @@
 #include "msl_band.hpp"
 #include "msl_device.hpp"
 
-#define MSL_MAXQ 64
 #define AUX_BLOCK 256
 
 // ---------------------------------------------------------------------------
@@ -131,13 +130,6 @@ __device__ void project_cell(const Tab *tab, int dim, const double *fQ, const do
   if (tab->thermal) tensor_apply(tab->P, Lq.n, LQ.n, dim, gQ, gq);
 }
 
-__device__ __forceinline__ void cell_coords(const Geo &g, long long k, int &x, int &y, int &z) {
-  x = (int)(k % g.nx);
-  k /= g.nx;
-  y = (int)(k % g.ny);
-  z = (int)(k / g.ny);
-}
-
 // ---------------------------------------------------------------------------
 // initialisation: lattice equilibrium of each cell's own velocity set
 // ---------------------------------------------------------------------------
@@ -227,21 +219,14 @@ __global__ void k_bc_copy(const Tab *__restrict__ tab, Geo g, int ax, BCArgs b, 
   pl[g.idx(p[0], p[1], p[2])] = pl[g.idx(q[0], q[1], q[2])];
 }
 
-// fixed-equilibrium ghosts (constant: written once per buffer) and diffuse
-// walls (every step); `rules` selects which faces this launch fills
+// fixed-equilibrium ghosts: constant, written once per buffer when a state is
+// loaded
 template <typename S>
-__global__ void k_bc_pass(const Tab *__restrict__ tab, Geo g, int ax, BCArgs b, char *bl, char *bh,
-                          const uint8_t *__restrict__ cls, int rules) {
+__global__ void __launch_bounds__(AUX_BLOCK)
+k_bc_fixed(const Tab *__restrict__ tab, Geo g, int ax, BCArgs b, char *bl, char *bh) {
   const int N[3] = {g.nx, g.ny, g.nz};
-  // extent of the pass: lower axes with ghosts, higher axes interior
   int ext[3], lo[3];
-  for (int a = 0; a < 3; ++a) {
-    if (a >= g.dim) { ext[a] = 1; lo[a] = 0; continue; }
-    if (a < ax) { ext[a] = N[a] + 2 * MSL_G; lo[a] = -MSL_G; }
-    else if (a == ax) { ext[a] = 2 * MSL_G; lo[a] = 0; }
-    else { ext[a] = N[a]; lo[a] = 0; }
-  }
-  const long long tot = (long long)ext[0] * ext[1] * ext[2];
+  const long long tot = pass_cells(g, ax, ext, lo);
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= tot) return;
   int p[3];
@@ -250,86 +235,99 @@ __global__ void k_bc_pass(const Tab *__restrict__ tab, Geo g, int ax, BCArgs b, 
     p[a] = lo[a] + (int)(r % ext[a]);
     r /= ext[a];
   }
-  // ghost coordinate along ax
   const int gi = p[ax];
   const int side = gi < MSL_G ? 0 : 1;
   p[ax] = side ? N[ax] + (gi - MSL_G) : gi - MSL_G;
   const int face = 2 * ax + side;
-  const int rule = b.bc[face];
-  if (!(rules & (1 << rule))) return;
+  if (b.bc[face] != MSL_BC_FIXED_EQ) return;
   char *bases[2] = {bl, bh};
   const int dst = g.idx(p[0], p[1], p[2]);
-  if (rule == MSL_BC_PERIODIC || rule == MSL_BC_OUTFLOW_ZG) {
-    int q[3] = {p[0], p[1], p[2]};
-    if (rule == MSL_BC_PERIODIC) q[ax] = (q[ax] % N[ax] + N[ax]) % N[ax];
-    else q[ax] = side ? N[ax] - 1 : 0;
-    const int src = g.idx(q[0], q[1], q[2]);
-    for (int l = 0; l < tab->nlat; ++l) {
-      S *pl = (S *)bases[l];
-      const int np = tab->lat[l].Q * (tab->thermal ? 2 : 1);
-      for (int i = 0; i < np; ++i) pl[(long long)i * g.plane + dst] = pl[(long long)i * g.plane + src];
-    }
-    return;
+  double stb[5];
+  const double *st = in_slot(b, face, g.dim, p) ? b.slot_st[face] : b.st[face];
+  const int *s = b.slot[face];
+  const double w = b.slot_edge[face];
+  if (w > 0.0 && s[0] < s[1]) {
+    // smooth slot profile: tanh edges of width w
+    int t[2], nt = 0;
+    for (int a = 0; a < g.dim; ++a)
+      if (a != ax) t[nt++] = a;
+    double lam = 0.5 * (tanh((p[t[0]] - s[0] + 0.5) / w) - tanh((p[t[0]] - s[1] + 0.5) / w));
+    if (g.dim == 3 && s[2] < s[3])
+      lam *= 0.5 * (tanh((p[t[1]] - s[2] + 0.5) / w) - tanh((p[t[1]] - s[3] + 0.5) / w));
+    for (int m = 0; m < 5; ++m) stb[m] = b.st[face][m] + lam * (b.slot_st[face][m] - b.st[face][m]);
+    st = stb;
   }
-  if (rule == MSL_BC_FIXED_EQ) {
-    double stb[5];
-    const double *st = in_slot(b, face, g.dim, p) ? b.slot_st[face] : b.st[face];
-    const int *s = b.slot[face];
-    const double w = b.slot_edge[face];
-    if (w > 0.0 && s[0] < s[1]) {
-      // smooth slot profile: tanh edges of width w
-      int t[2], nt = 0;
-      for (int a = 0; a < g.dim; ++a)
-        if (a != ax) t[nt++] = a;
-      double lam = 0.5 * (tanh((p[t[0]] - s[0] + 0.5) / w) - tanh((p[t[0]] - s[1] + 0.5) / w));
-      if (g.dim == 3 && s[2] < s[3])
-        lam *= 0.5 * (tanh((p[t[1]] - s[2] + 0.5) / w) - tanh((p[t[1]] - s[3] + 0.5) / w));
-      for (int m = 0; m < 5; ++m) stb[m] = b.st[face][m] + lam * (b.slot_st[face][m] - b.st[face][m]);
-      st = stb;
-    }
-    for (int l = 0; l < tab->nlat; ++l) {
-      double f[MSL_MAXQ], gg[MSL_MAXQ];
-      cell_feq(tab->lat[l], g.dim, st[0], st + 1, st[4], f);
-      for (int i = 0; i < tab->lat[l].Q; ++i) gg[i] = tab->gfac * st[4] * f[i];
-      write_cell<S>(tab, g, bases[l], l, dst, f, gg);
-    }
-    return;
+  for (int l = 0; l < tab->nlat; ++l) {
+    double f[MSL_MAXQ], gg[MSL_MAXQ];
+    cell_feq(tab->lat[l], g.dim, st[0], st + 1, st[4], f);
+    for (int i = 0; i < tab->lat[l].Q; ++i) gg[i] = tab->gfac * st[4] * f[i];
+    write_cell<S>(tab, g, bases[l], l, dst, f, gg);
   }
-  // diffuse wall: zero net wall-normal mass flux through the wall
+}
+
+// diffuse walls (every step): the ghost holds the wall equilibrium scaled so
+// that as many particles leave the wall as arrive at it from the adjacent
+// fluid cell (zero net wall-normal mass flux).  The unit-density equilibrium
+// and its outgoing flux come from the tables; a thread reads only the arriving
+// populations of its adjacent cell and writes every plane of its ghost cell.
+template <typename S>
+__global__ void __launch_bounds__(AUX_BLOCK)
+k_bc_diffuse(const Tab *__restrict__ tab, Geo g, int ax, BCArgs b, char *bl, char *bh,
+             const uint8_t *__restrict__ cls) {
+  const int N[3] = {g.nx, g.ny, g.nz};
+  int ext[3], lo[3];
+  const long long tot = pass_cells(g, ax, ext, lo);
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tot) return;
+  int p[3];
+  long long r = t;
+  for (int a = 0; a < 3; ++a) {
+    p[a] = lo[a] + (int)(r % ext[a]);
+    r /= ext[a];
+  }
+  const int gi = p[ax];
+  const int side = gi < MSL_G ? 0 : 1;
+  p[ax] = side ? N[ax] + (gi - MSL_G) : gi - MSL_G;
+  const int face = 2 * ax + side;
+  if (b.bc[face] != MSL_BC_DIFFUSE_WALL) return;
+  // adjacent fluid point; lower-axis ghosts map through their own rule
   int q[3] = {p[0], p[1], p[2]};
   q[ax] = side ? N[ax] - 1 : 0;
-  // velocity set of the adjacent point: lower-axis ghosts map through their rule
-  int c[3] = {q[0], q[1], q[2]};
   int use_low = 0;
   for (int a = 0; a < ax; ++a) {
-    if (c[a] >= 0 && c[a] < N[a]) continue;
-    const int fr = b.bc[2 * a + (c[a] < 0 ? 0 : 1)];
-    if (fr == MSL_BC_PERIODIC) c[a] = (c[a] % N[a] + N[a]) % N[a];
-    else if (fr == MSL_BC_OUTFLOW_ZG) c[a] = c[a] < 0 ? 0 : N[a] - 1;
+    if (q[a] >= 0 && q[a] < N[a]) continue;
+    const int fr = b.bc[2 * a + (q[a] < 0 ? 0 : 1)];
+    if (fr == MSL_BC_PERIODIC) q[a] = (q[a] % N[a] + N[a]) % N[a];
+    else if (fr == MSL_BC_OUTFLOW_ZG) q[a] = q[a] < 0 ? 0 : N[a] - 1;
     else use_low = 1;
   }
-  const int m = use_low ? 0 : (cls[((long long)c[2] * g.ny + c[1]) * g.nx + c[0]] & 1);
+  const int m = use_low ? 0 : (cls[((long long)q[2] * g.ny + q[1]) * g.nx + q[0]] & 1);
   const LatTab &Lm = tab->lat[m];
-  double f[MSL_MAXQ], gg[MSL_MAXQ], weq[MSL_MAXQ];
-  read_cell<S>(tab, g, bases[m], m, g.idx(q[0], q[1], q[2]), f, gg);
-  const double *ws = b.st[face];
-  cell_feq(Lm, g.dim, 1.0, ws + 1, ws[4], weq);
-  double in = 0, out = 0;
+  const S *pm = (const S *)(m ? bh : bl);
+  const int src = g.idx(q[0], q[1], q[2]);
   const int n = Lm.n;
+  const int stride = ax == 0 ? 1 : (ax == 1 ? n : n * n);
+  // populations arriving at the wall: c_ax < 0 at the lower face, > 0 at the upper
+  double in = 0;
   for (int i = 0; i < Lm.Q; ++i) {
-    const int d = ax == 0 ? i % n : (ax == 1 ? (i / n) % n : i / (n * n));
-    const double cn = Lm.c[d];
-    if (side ? cn > 0 : cn < 0) in += fabs(cn) * f[i];
-    if (side ? cn < 0 : cn > 0) out += fabs(cn) * weq[i];
+    const double cn = Lm.c[(i / stride) % n];
+    if (side ? cn > 0 : cn < 0)
+      in += fabs(cn) * load_pop<S>(pm + (long long)i * g.plane, src, tab->rho0 * pop_weight(Lm, g.dim, i));
   }
-  const double rw = in / out;
+  const double rw = in / tab->wall_out[face][m];
+  const double Tw = b.st[face][4];
+  const int dst = g.idx(p[0], p[1], p[2]);
   for (int l = 0; l < tab->nlat; ++l) {
-    cell_feq(tab->lat[l], g.dim, 1.0, ws + 1, ws[4], f);
-    for (int i = 0; i < tab->lat[l].Q; ++i) {
-      f[i] *= rw;
-      gg[i] = tab->gfac * ws[4] * f[i];
+    const LatTab &L = tab->lat[l];
+    S *pl = (S *)(l ? bh : bl);
+    for (int i = 0; i < L.Q; ++i) {
+      const double W = pop_weight(L, g.dim, i);
+      const double f = rw * tab->wall_eq[face][l][i];
+      store_pop<S>(pl + (long long)i * g.plane, dst, f, tab->rho0 * W);
+      if (tab->thermal)
+        store_pop<S>(pl + (long long)(L.Q + i) * g.plane, dst, tab->gfac * Tw * f,
+                     tab->gfac * tab->rho0 * tab->T0 * W);
     }
-    write_cell<S>(tab, g, bases[l], l, dst, f, gg);
   }
 }
 
@@ -737,8 +735,8 @@ int msl_launch_bc(msl_ctx *c, char *bl, char *bh) {
       DISPATCH_STORE(c, k_bc_copy, dim3(nblocks(tot * (np0 + np1))), dim3(AUX_BLOCK), c->dtab, g, ax,
                      b, bl, bh, np0, np1);
     if (r0 == MSL_BC_DIFFUSE_WALL || r1 == MSL_BC_DIFFUSE_WALL)
-      DISPATCH_STORE(c, k_bc_pass, dim3(nblocks(tot)), dim3(AUX_BLOCK), c->dtab, g, ax, b, bl, bh,
-                     c->cls, 1 << MSL_BC_DIFFUSE_WALL);
+      DISPATCH_STORE(c, k_bc_diffuse, dim3(nblocks(tot)), dim3(AUX_BLOCK), c->dtab, g, ax, b, bl,
+                     bh, c->cls);
   }
   return last_err();
 }
@@ -752,15 +750,15 @@ int msl_launch_bc_fixed(msl_ctx *c) {
     char *bl = c->planes[0][buf], *bh = c->nlat > 1 ? c->planes[1][buf] : nullptr;
     for (int ax = 0; ax < c->D; ++ax) {
       if (b.bc[2 * ax] != MSL_BC_FIXED_EQ && b.bc[2 * ax + 1] != MSL_BC_FIXED_EQ) continue;
-      DISPATCH_STORE(c, k_bc_pass, dim3(nblocks(host_pass_cells(g, ax))), dim3(AUX_BLOCK), c->dtab,
-                     g, ax, b, bl, bh, c->cls, 1 << MSL_BC_FIXED_EQ);
+      DISPATCH_STORE(c, k_bc_fixed, dim3(nblocks(host_pass_cells(g, ax))), dim3(AUX_BLOCK), c->dtab,
+                     g, ax, b, bl, bh);
     }
   }
   return last_err();
 }
 
 // band conversion and switching with compile-time velocity-set sizes
-template <typename S, int D, int NL, int NH>
+template <typename S, int D, int NL, int NH, bool TH>
 __global__ void __launch_bounds__(AUX_BLOCK)
 k_band_convert_t(const Tab *__restrict__ tab, Geo g, char *bl, char *bh,
                  const int *__restrict__ list_lo, const int *__restrict__ list_hi,
@@ -776,20 +774,20 @@ k_band_convert_t(const Tab *__restrict__ tab, Geo g, char *bl, char *bh,
     cell_coords(g, k, x, y, z);
     const int off = g.idx(x, y, z);
     if (lift) {
-      double f[q], gg[q], fo[Q], go[Q];
-      read_cell_t<S, D, NL>(tab, g, bl, 0, off, f, gg);
-      lift_t<D, NL, NH>(tab, f, gg, nullptr, fo, go);
-      write_cell_t<S, D, NH>(tab, g, bh, 1, off, fo, go);
+      double f[q], gg[TH ? q : 1], fo[Q], go[TH ? Q : 1];
+      read_cell_t<S, D, NL, TH>(tab, g, bl, 0, off, f, gg);
+      lift_t<D, NL, NH, TH>(tab, f, gg, nullptr, fo, go);
+      write_cell_t<S, D, NH, TH>(tab, g, bh, 1, off, fo, go);
     } else {
-      double f[Q], gg[Q], fo[q], go[q];
-      read_cell_t<S, D, NH>(tab, g, bh, 1, off, f, gg);
-      project_t<D, NL, NH>(tab, f, gg, fo, go);
-      write_cell_t<S, D, NL>(tab, g, bl, 0, off, fo, go);
+      double f[Q], gg[TH ? Q : 1], fo[q], go[TH ? q : 1];
+      read_cell_t<S, D, NH, TH>(tab, g, bh, 1, off, f, gg);
+      project_t<D, NL, NH, TH>(tab, f, gg, fo, go);
+      write_cell_t<S, D, NL, TH>(tab, g, bl, 0, off, fo, go);
     }
   }
 }
 
-template <typename S, int D, int NL, int NH>
+template <typename S, int D, int NL, int NH, bool TH>
 __global__ void __launch_bounds__(AUX_BLOCK)
 k_switch_t(const Tab *__restrict__ tab, Geo g, char *bl, char *bh, uint8_t *__restrict__ cls,
            const uint8_t *__restrict__ newmask, int convert) {
@@ -802,15 +800,15 @@ k_switch_t(const Tab *__restrict__ tab, Geo g, char *bl, char *bh, uint8_t *__re
     cell_coords(g, k, x, y, z);
     const int off = g.idx(x, y, z);
     if (to == 1) {
-      double f[q], gg[q], fo[Q], go[Q];
-      read_cell_t<S, D, NL>(tab, g, bl, 0, off, f, gg);
-      lift_t<D, NL, NH>(tab, f, gg, nullptr, fo, go);
-      write_cell_t<S, D, NH>(tab, g, bh, 1, off, fo, go);
+      double f[q], gg[TH ? q : 1], fo[Q], go[TH ? Q : 1];
+      read_cell_t<S, D, NL, TH>(tab, g, bl, 0, off, f, gg);
+      lift_t<D, NL, NH, TH>(tab, f, gg, nullptr, fo, go);
+      write_cell_t<S, D, NH, TH>(tab, g, bh, 1, off, fo, go);
     } else {
-      double f[Q], gg[Q], fo[q], go[q];
-      read_cell_t<S, D, NH>(tab, g, bh, 1, off, f, gg);
-      project_t<D, NL, NH>(tab, f, gg, fo, go);
-      write_cell_t<S, D, NL>(tab, g, bl, 0, off, fo, go);
+      double f[Q], gg[TH ? Q : 1], fo[q], go[TH ? q : 1];
+      read_cell_t<S, D, NH, TH>(tab, g, bh, 1, off, f, gg);
+      project_t<D, NL, NH, TH>(tab, f, gg, fo, go);
+      write_cell_t<S, D, NL, TH>(tab, g, bl, 0, off, fo, go);
     }
   }
   cls[k] = (uint8_t)to;
@@ -819,8 +817,12 @@ k_switch_t(const Tab *__restrict__ tab, Geo g, char *bl, char *bh, uint8_t *__re
 template <typename S>
 static int band_convert_s(msl_ctx *c, char *bl, char *bh, int skip) {
   return msl_pair_dispatch(c->D, c->htab.lat[0].n, c->htab.lat[1].n, [&]<int D, int NL, int NH>() {
-    hipLaunchKernelGGL((k_band_convert_t<S, D, NL, NH>), dim3(512), dim3(AUX_BLOCK), 0, c->stream,
-                       c->dtab, c->geo, bl, bh, c->blist[0], c->blist[1], c->bcount, skip);
+    if (c->cfg.thermal)
+      hipLaunchKernelGGL((k_band_convert_t<S, D, NL, NH, true>), dim3(512), dim3(AUX_BLOCK), 0,
+                         c->stream, c->dtab, c->geo, bl, bh, c->blist[0], c->blist[1], c->bcount, skip);
+    else
+      hipLaunchKernelGGL((k_band_convert_t<S, D, NL, NH, false>), dim3(512), dim3(AUX_BLOCK), 0,
+                         c->stream, c->dtab, c->geo, bl, bh, c->blist[0], c->blist[1], c->bcount, skip);
     return last_err();
   });
 }
@@ -828,8 +830,12 @@ static int band_convert_s(msl_ctx *c, char *bl, char *bh, int skip) {
 template <typename S>
 static int switch_s(msl_ctx *c, char *bl, char *bh, const uint8_t *newmask, int convert) {
   return msl_pair_dispatch(c->D, c->htab.lat[0].n, c->htab.lat[1].n, [&]<int D, int NL, int NH>() {
-    hipLaunchKernelGGL((k_switch_t<S, D, NL, NH>), dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), 0,
-                       c->stream, c->dtab, c->geo, bl, bh, c->cls, newmask, convert);
+    if (c->cfg.thermal)
+      hipLaunchKernelGGL((k_switch_t<S, D, NL, NH, true>), dim3(nblocks(c->ncell)), dim3(AUX_BLOCK),
+                         0, c->stream, c->dtab, c->geo, bl, bh, c->cls, newmask, convert);
+    else
+      hipLaunchKernelGGL((k_switch_t<S, D, NL, NH, false>), dim3(nblocks(c->ncell)), dim3(AUX_BLOCK),
+                         0, c->stream, c->dtab, c->geo, bl, bh, c->cls, newmask, convert);
     return last_err();
   });
 }

@@ -106,14 +106,16 @@ __device__ __forceinline__ void feq_t(const LatTab &L, double rho, const double 
 
 // Lifting (Sec. III.B, App. C): f_Q = f^L_Q + (K x K) (f_q - f^L_q), K the
 // degree < n_q part of the high-order Lagrange basis at the low nodes (or the
-// Hermite completion matrix); the learned closure adds (Vi x Vi) dM.
-template <int D, int NL, int NH>
+// Hermite completion matrix); the learned closure adds (Vi x Vi) dM.  With
+// TH false the energy populations are known to be absent at compile time.
+template <int D, int NL, int NH, bool TH = true>
 __device__ __forceinline__ void lift_t(const Tab *tab, const double *fq, const double *gq,
                                        const double *dM, double *fQ, double *gQ) {
   const LatTab &Lq = tab->lat[0], &LQ = tab->lat[1];
   constexpr int q = Pow<D, NL>::v, Q = Pow<D, NH>::v;
   double rho, u[3], T;
-  macros_t<D, NL>(Lq, tab->thermal, tab->cv, fq, gq, rho, u, T);
+  const bool th = TH && tab->thermal;
+  macros_t<D, NL>(Lq, th, tab->cv, fq, gq, rho, u, T);
   double eq_q[q], eq_Q[Q], neq[q], corr[Q];
   feq_t<D, NL>(Lq, rho, u, T, eq_q);
   feq_t<D, NH>(LQ, rho, u, T, eq_Q);
@@ -128,7 +130,7 @@ __device__ __forceinline__ void lift_t(const Tab *tab, const double *fq, const d
 #pragma unroll
     for (int i = 0; i < Q; ++i) fQ[i] += corr[i];
   }
-  if (tab->thermal) {
+  if (th) {
     const double s = tab->gfac * T;
 #pragma unroll
     for (int i = 0; i < q; ++i) neq[i] = gq[i] - s * eq_q[i];
@@ -140,14 +142,14 @@ __device__ __forceinline__ void lift_t(const Tab *tab, const double *fq, const d
 
 // Projection (Sec. III.C, App. C): f_q = (P x P) f_Q, P the low-order
 // Lagrange basis evaluated at the high-order nodes.
-template <int D, int NL, int NH>
+template <int D, int NL, int NH, bool TH = true>
 __device__ __forceinline__ void project_t(const Tab *tab, const double *fQ, const double *gQ,
                                           double *fq, double *gq) {
   tensor_apply_t<D, NL, NH>(tab->P, fQ, fq);
-  if (tab->thermal) tensor_apply_t<D, NL, NH>(tab->P, gQ, gq);
+  if (TH && tab->thermal) tensor_apply_t<D, NL, NH>(tab->P, gQ, gq);
 }
 
-template <typename S, int D, int N>
+template <typename S, int D, int N, bool TH = true>
 __device__ __forceinline__ void read_cell_t(const Tab *tab, const Geo &g, const char *base, int l,
                                             int off, double *f, double *gg) {
   const LatTab &L = tab->lat[l];
@@ -159,11 +161,11 @@ __device__ __forceinline__ void read_cell_t(const Tab *tab, const Geo &g, const 
     double W = L.w[i % N] * L.w[(i / N) % N];
     if (D == 3) W *= L.w[i / (N * N)];
     f[i] = load_pop<S>(p + (long long)i * g.plane, off, tab->rho0 * W);
-    if (tab->thermal) gg[i] = load_pop<S>(p + (long long)(Q + i) * g.plane, off, gs * W);
+    if (TH && tab->thermal) gg[i] = load_pop<S>(p + (long long)(Q + i) * g.plane, off, gs * W);
   }
 }
 
-template <typename S, int D, int N>
+template <typename S, int D, int N, bool TH = true>
 __device__ __forceinline__ void write_cell_t(const Tab *tab, const Geo &g, char *base, int l,
                                              int off, const double *f, const double *gg) {
   const LatTab &L = tab->lat[l];
@@ -175,7 +177,7 @@ __device__ __forceinline__ void write_cell_t(const Tab *tab, const Geo &g, char 
     double W = L.w[i % N] * L.w[(i / N) % N];
     if (D == 3) W *= L.w[i / (N * N)];
     store_pop<S>(p + (long long)i * g.plane, off, f[i], tab->rho0 * W);
-    if (tab->thermal) store_pop<S>(p + (long long)(Q + i) * g.plane, off, gg[i], gs * W);
+    if (TH && tab->thermal) store_pop<S>(p + (long long)(Q + i) * g.plane, off, gg[i], gs * W);
   }
 }
 

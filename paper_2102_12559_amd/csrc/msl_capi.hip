@@ -375,6 +375,24 @@ int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_
   t.dim = cfg->dim;
   t.nlat = c->nlat;
   t.lift_mode = cfg->lift_mode;
+  // diffuse walls: the wall equilibrium does not change during a run, only its
+  // density (set per ghost cell from the flux arriving at the wall)
+  for (int f = 0; f < 2 * cfg->dim; ++f) {
+    if (cfg->bc[f] != MSL_BC_DIFFUSE_WALL) continue;
+    const int ax = f / 2, side = f % 2;
+    const double *ws = cfg->bc_state[f];
+    for (int l = 0; l < c->nlat; ++l) {
+      const LatTab &Lt = t.lat[l];
+      cell_feq(Lt, cfg->dim, 1.0, ws + 1, ws[4], t.wall_eq[f][l]);
+      double out = 0;
+      for (int i = 0; i < Lt.Q; ++i) {
+        const int d = ax == 0 ? i % Lt.n : (ax == 1 ? (i / Lt.n) % Lt.n : i / (Lt.n * Lt.n));
+        const double cn = Lt.c[d];
+        if (side ? cn < 0 : cn > 0) out += fabs(cn) * t.wall_eq[f][l][i];
+      }
+      t.wall_out[f][l] = out;
+    }
+  }
   // workspace
   c->dtab = (Tab *)(base + L.off_tab);
   for (int l = 0; l < c->nlat; ++l) {

@@ -38,8 +38,8 @@ __device__ __forceinline__ void eq_axis(const LatTab &L, C u, C theta, C *P) {
   }
 }
 
-// runtime-N variant (FP64), used by the auxiliary kernels
-__device__ __forceinline__ void eq_axis_rt(const LatTab &L, double u, double theta, double *P) {
+// runtime-N variant (FP64), used by the auxiliary kernels and the host tables
+__host__ __device__ __forceinline__ void eq_axis_rt(const LatTab &L, double u, double theta, double *P) {
   double b[MSL_MAXN];
   const int N = L.n;
   b[0] = 1.0;
@@ -52,9 +52,17 @@ __device__ __forceinline__ void eq_axis_rt(const LatTab &L, double u, double the
   }
 }
 
+// interior coordinates of cell k (x fastest)
+__device__ __forceinline__ void cell_coords(const Geo &g, long long k, int &x, int &y, int &z) {
+  x = (int)(k % g.nx);
+  k /= g.nx;
+  y = (int)(k % g.ny);
+  z = (int)(k / g.ny);
+}
+
 // decoded population scale of a 16-bit deviation: rho0 W_i (f) or
 // (cv - D/2) rho0 T0 W_i (g)
-__device__ __forceinline__ double pop_weight(const LatTab &L, int dim, int i) {
+__host__ __device__ __forceinline__ double pop_weight(const LatTab &L, int dim, int i) {
   const int n = L.n;
   double W = L.w[i % n] * L.w[(i / n) % n];
   if (dim == 3) W *= L.w[i / (n * n)];
@@ -100,7 +108,7 @@ __device__ __forceinline__ void cell_macros(const LatTab &L, int dim, int therma
 }
 
 // Lattice equilibrium of set L at (rho, u, T), FP64, all Q populations.
-__device__ __forceinline__ void cell_feq(const LatTab &L, int dim, double rho, const double *u,
+__host__ __device__ __forceinline__ void cell_feq(const LatTab &L, int dim, double rho, const double *u,
                                          double T, double *feq) {
   double P[3][MSL_MAXN];
   for (int a = 0; a < dim; ++a) eq_axis_rt(L, u[a], T, P[a]);

@@ -7,6 +7,7 @@
 #include "../../include/msl.h"
 
 #define MSL_MAXN 8
+#define MSL_MAXQ 64   // largest velocity set (D3Q64)
 #define MSL_G 2            // ghost layers (stencil reach of a 3-point stencil at CFL <= 1)
 #define MSL_TX 64          // tile width in x (one wavefront)
 #define MSL_MTY 4          // micro-tile height (rows) of the per-tile class flags
@@ -39,6 +40,10 @@ struct Tab {
   double dt, cv, gfac, tau, omega, mu_ref, mu_exp, tau_ref_T, rho0, T0;
   float omegaf;
   int tau_mode, thermal, dim, nlat, lift_mode;
+  // diffuse walls, per face and velocity set: the equilibrium at the wall state
+  // with unit density, and its flux of particles leaving the wall
+  double wall_eq[6][2][MSL_MAXQ];
+  double wall_out[6][2];
 };
 
 struct Geo {

@@ -39,70 +39,142 @@ __device__ __forceinline__ float silu_d(float z) {
 // features and targets (FP64)
 // ---------------------------------------------------------------------------
 
+// number of features (rho, u, T and the low-order moments of degree >= 2) and
+// of outputs (the raw moments the low-order set cannot hold)
+template <int D, int NL>
+constexpr int nfeat() {
+  int n = 2 + D;
+  for (int j = 0; j < Pow<D, NL>::v; ++j)
+    if (j % NL + (j / NL) % NL + (D == 3 ? j / (NL * NL) : 0) >= 2) ++n;
+  return n;
+}
+template <int D, int NL, int NH>
+constexpr int nout() { return Pow<D, NH>::v - Pow<D, NL>::v; }
+
+// M[p] = sum_i f_i prod_a (c_{i_a} - s_a)^{p_a} for every moment index p < N per
+// axis, by one contraction per axis of the tensor-product population array
+template <int D, int N>
+__device__ __forceinline__ void moments_sep(const double *c, const double *sft, const double *f,
+                                            double *M) {
+  double pw[D][N][N];   // pw[a][p][node]
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const double d = c[k] - sft[a];
+      double v = 1.0;
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+        pw[a][p][k] = v;
+        v *= d;
+      }
+    }
+  if constexpr (D == 2) {
+    double t[N][N];   // t[p0][b]
+#pragma unroll
+    for (int p0 = 0; p0 < N; ++p0)
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        double s = 0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) s += pw[0][p0][k] * f[k + N * b];
+        t[p0][b] = s;
+      }
+#pragma unroll
+    for (int p1 = 0; p1 < N; ++p1)
+#pragma unroll
+      for (int p0 = 0; p0 < N; ++p0) {
+        double s = 0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) s += pw[1][p1][b] * t[p0][b];
+        M[p0 + N * p1] = s;
+      }
+  } else {
+    double t1[N * N * N], t2[N * N * N];
+#pragma unroll
+    for (int p0 = 0; p0 < N; ++p0)
+#pragma unroll
+      for (int bc = 0; bc < N * N; ++bc) {
+        double s = 0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) s += pw[0][p0][k] * f[k + N * bc];
+        t1[p0 + N * bc] = s;   // [p0][b][c]
+      }
+#pragma unroll
+    for (int p1 = 0; p1 < N; ++p1)
+#pragma unroll
+      for (int p0 = 0; p0 < N; ++p0)
+#pragma unroll
+        for (int cc = 0; cc < N; ++cc) {
+          double s = 0;
+#pragma unroll
+          for (int k = 0; k < N; ++k) s += pw[1][p1][k] * t1[p0 + N * (k + N * cc)];
+          t2[p0 + N * (p1 + N * cc)] = s;
+        }
+#pragma unroll
+    for (int p2 = 0; p2 < N; ++p2)
+#pragma unroll
+      for (int p01 = 0; p01 < N * N; ++p01) {
+        double s = 0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) s += pw[2][p2][k] * t2[p01 + N * N * k];
+        M[p01 + N * N * p2] = s;
+      }
+  }
+}
+
 // rho, u/sqrt(T), T, then the normalised central moments
 // sum_i f_i prod_a (c_ia - u_a)^{p_a} / (rho T^{|p|/2}) of every low-order moment
 // index p with |p| >= 2, in ascending moment index
-template <int D, int NL>
+template <int D, int NL, bool TH = true>
 __device__ void features_t(const Tab *tab, const double *fq, const double *gq, double *feat) {
   const LatTab &L = tab->lat[0];
   double rho, u[3], T;
-  macros_t<D, NL>(L, tab->thermal, tab->cv, fq, gq, rho, u, T);
+  macros_t<D, NL>(L, TH && tab->thermal, tab->cv, fq, gq, rho, u, T);
   int k = 0;
   feat[k++] = rho;
   const double sT = sqrt(T);
   for (int a = 0; a < D; ++a) feat[k++] = u[a] / sT;
   feat[k++] = T;
   constexpr int q = Pow<D, NL>::v;
+  double M[q], den[D * (NL - 1) + 1];
+  moments_sep<D, NL>(L.c, u, fq, M);
+  den[0] = rho;
+#pragma unroll
+  for (int d = 1; d <= D * (NL - 1); ++d) den[d] = den[d - 1] * sT;
 #pragma unroll
   for (int j = 0; j < q; ++j) {
     const int p0 = j % NL, p1 = (j / NL) % NL, p2 = D == 3 ? j / (NL * NL) : 0;
     const int deg = p0 + p1 + p2;
     if (deg < 2) continue;
-    double s = 0;
-#pragma unroll
-    for (int i = 0; i < q; ++i) {
-      double v = fq[i];
-      const double dx = L.c[i % NL] - u[0], dy = L.c[(i / NL) % NL] - u[1];
-      for (int e = 0; e < p0; ++e) v *= dx;
-      for (int e = 0; e < p1; ++e) v *= dy;
-      if (D == 3) {
-        const double dz = L.c[i / (NL * NL)] - u[2];
-        for (int e = 0; e < p2; ++e) v *= dz;
-      }
-      s += v;
-    }
-    feat[k++] = s / (rho * pow(T, 0.5 * deg));
+    feat[k++] = M[j] / den[deg];
   }
 }
 
 // normalised non-equilibrium parts (M_p - M^eq_p) / (rho T^{|p|/2}) of the raw
 // moments the low-order set cannot hold, in ascending high-order moment index
-template <int D, int NL, int NH>
+template <int D, int NL, int NH, bool TH = true>
 __device__ void targets_t(const Tab *tab, const double *fQ, const double *gQ, double *t) {
   const LatTab &LQ = tab->lat[1];
   constexpr int Q = Pow<D, NH>::v;
-  double rho, u[3], T, feq[Q];
-  macros_t<D, NH>(LQ, tab->thermal, tab->cv, fQ, gQ, rho, u, T);
-  feq_t<D, NH>(LQ, rho, u, T, feq);
+  double rho, u[3], T, dv[Q], M[Q];
+  macros_t<D, NH>(LQ, TH && tab->thermal, tab->cv, fQ, gQ, rho, u, T);
+  feq_t<D, NH>(LQ, rho, u, T, dv);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) dv[i] = fQ[i] - dv[i];
+  const double zero[3] = {0.0, 0.0, 0.0};
+  moments_sep<D, NH>(LQ.c, zero, dv, M);
+  const double sT = sqrt(T);
+  double den[D * (NH - 1) + 1];
+  den[0] = rho;
+#pragma unroll
+  for (int d = 1; d <= D * (NH - 1); ++d) den[d] = den[d - 1] * sT;
   int k = 0;
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
     const int p0 = j % NH, p1 = (j / NH) % NH, p2 = D == 3 ? j / (NH * NH) : 0;
     if (p0 < NL && p1 < NL && p2 < NL) continue;
-    double s = 0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      double m = fQ[i] - feq[i];
-      const double cx = LQ.c[i % NH], cy = LQ.c[(i / NH) % NH];
-      for (int e = 0; e < p0; ++e) m *= cx;
-      for (int e = 0; e < p1; ++e) m *= cy;
-      if (D == 3) {
-        const double cz = LQ.c[i / (NH * NH)];
-        for (int e = 0; e < p2; ++e) m *= cz;
-      }
-      s += m;
-    }
-    t[k++] = s / (rho * pow(T, 0.5 * (p0 + p1 + p2)));
+    t[k++] = M[j] / den[p0 + p1 + p2];
   }
 }
 
@@ -169,6 +241,31 @@ k_mlp(const float *__restrict__ prm, int F, int O, const float *__restrict__ X,
     for (int b = 0; b < OP / 16; ++b) gb3[b] = 0.f;
   }
 
+  // forward only: the weight fragments stay in registers for every tile
+  s4 bw1[MODE == 0 ? FP / 16 : 1][MODE == 0 ? H / 16 : 1];
+  s4 bw2[MODE == 0 ? H / 16 : 1][MODE == 0 ? H / 16 : 1];
+  s4 bw3[MODE == 0 ? H / 16 : 1][MODE == 0 ? OP / 16 : 1];
+  if constexpr (MODE == 0) {
+#pragma unroll
+    for (int nt = 0; nt < H / 16; ++nt)
+#pragma unroll
+      for (int kc = 0; kc < FP / 16; ++kc)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bw1[kc][nt][i] = s.w1[(kc * 16 + 4 * lg + i) * H + nt * 16 + lr];
+#pragma unroll
+    for (int nt = 0; nt < H / 16; ++nt)
+#pragma unroll
+      for (int kc = 0; kc < H / 16; ++kc)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bw2[kc][nt][i] = s.w2[(kc * 16 + 4 * lg + i) * H + nt * 16 + lr];
+#pragma unroll
+    for (int nt = 0; nt < OP / 16; ++nt)
+#pragma unroll
+      for (int kc = 0; kc < H / 16; ++kc)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bw3[kc][nt][i] = s.w3[(kc * 16 + 4 * lg + i) * OP + nt * 16 + lr];
+  }
+
   const int tstride = MODE == 1 ? 1 << 30 : gridDim.x * 4;
   for (int tile = blockIdx.x * 4 + w; tile < ntiles; tile += tstride) {
     const int r0 = tile * 16;
@@ -187,7 +284,8 @@ k_mlp(const float *__restrict__ prm, int F, int O, const float *__restrict__ X,
         for (int i = 0; i < 4; ++i) {
           const int col = kc * 16 + 4 * lg + i;
           av[i] = f2bf(row < n && col < F ? X[(long long)row * F + col] : 0.f);
-          bv[i] = s.w1[(kc * 16 + 4 * lg + i) * H + nt * 16 + lr];
+          if constexpr (MODE == 0) bv[i] = bw1[kc][nt][i];
+          else bv[i] = s.w1[(kc * 16 + 4 * lg + i) * H + nt * 16 + lr];
         }
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
       }
@@ -205,8 +303,10 @@ k_mlp(const float *__restrict__ prm, int F, int O, const float *__restrict__ X,
       for (int kc = 0; kc < H / 16; ++kc) {
         const s4 av = *(const s4 *)&a1[lr * H + kc * 16 + 4 * lg];
         s4 bv;
+        if constexpr (MODE == 0) bv = bw2[kc][nt];
+        else
 #pragma unroll
-        for (int i = 0; i < 4; ++i) bv[i] = s.w2[(kc * 16 + 4 * lg + i) * H + nt * 16 + lr];
+          for (int i = 0; i < 4; ++i) bv[i] = s.w2[(kc * 16 + 4 * lg + i) * H + nt * 16 + lr];
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
       }
       z2[nt] = acc;
@@ -224,8 +324,10 @@ k_mlp(const float *__restrict__ prm, int F, int O, const float *__restrict__ X,
       for (int kc = 0; kc < H / 16; ++kc) {
         const s4 av = *(const s4 *)&a2[lr * H + kc * 16 + 4 * lg];
         s4 bv;
+        if constexpr (MODE == 0) bv = bw3[kc][nt];
+        else
 #pragma unroll
-        for (int i = 0; i < 4; ++i) bv[i] = s.w3[(kc * 16 + 4 * lg + i) * OP + nt * 16 + lr];
+          for (int i = 0; i < 4; ++i) bv[i] = s.w3[(kc * 16 + 4 * lg + i) * OP + nt * 16 + lr];
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
       }
       yv[nt] = acc;
@@ -452,22 +554,21 @@ __device__ __forceinline__ int check_tile(const Geo &g, int x, int y, int z, con
 }
 
 // standardised features of the low-order band cells (from the state in bl)
-template <typename S, int D, int NL>
-__global__ void k_band_features(const Tab *__restrict__ tab, Geo g, const char *bl,
-                                const int *__restrict__ list, const int *__restrict__ count,
-                                const float *__restrict__ stats, int F, float *__restrict__ feat) {
-  constexpr int q = Pow<D, NL>::v;
+template <typename S, int D, int NL, bool TH>
+__global__ void __launch_bounds__(64)
+k_band_features(const Tab *__restrict__ tab, Geo g, const char *bl, const int *__restrict__ list,
+                const int *__restrict__ count, const float *__restrict__ stats,
+                float *__restrict__ feat) {
+  constexpr int q = Pow<D, NL>::v, F = nfeat<D, NL>();
   const int n = *count;
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
        t += (long long)gridDim.x * blockDim.x) {
-    const long long k = list[t];
     int x, y, z;
-    x = (int)(k % g.nx);
-    y = (int)((k / g.nx) % g.ny);
-    z = (int)(k / ((long long)g.nx * g.ny));
-    double f[q], gg[q], ft[64];
-    read_cell_t<S, D, NL>(tab, g, bl, 0, g.idx(x, y, z), f, gg);
-    features_t<D, NL>(tab, f, gg, ft);
+    cell_coords(g, list[t], x, y, z);
+    double f[q], gg[TH ? q : 1], ft[F];
+    read_cell_t<S, D, NL, TH>(tab, g, bl, 0, g.idx(x, y, z), f, gg);
+    features_t<D, NL, TH>(tab, f, gg, ft);
+#pragma unroll
     for (int a = 0; a < F; ++a) feat[t * F + a] = (float)((ft[a] - stats[a]) / stats[F + a]);
   }
 }
@@ -475,64 +576,74 @@ __global__ void k_band_features(const Tab *__restrict__ tab, Geo g, const char *
 // the learned lift of the low-order band cells: completed moments
 // M^eq_{Q-q} + rho T^{|p|/2} t_p, t_p the de-standardised network output;
 // cells of check tiles that failed the error check get t = 0 (Grad lifting)
-template <typename S, int D, int NL, int NH>
-__global__ void k_band_lift_mlp(const Tab *__restrict__ tab, Geo g, const char *bl, char *bh,
-                                const int *__restrict__ list, const int *__restrict__ count,
-                                const float *__restrict__ stats, int F, int O,
-                                const float *__restrict__ yout, const uint8_t *__restrict__ flags,
-                                int nct0, int nct1) {
-  constexpr int q = Pow<D, NL>::v, Q = Pow<D, NH>::v;
+template <typename S, int D, int NL, int NH, bool TH>
+__global__ void __launch_bounds__(64)
+k_band_lift_mlp(const Tab *__restrict__ tab, Geo g, const char *bl, char *bh,
+                const int *__restrict__ list, const int *__restrict__ count,
+                const float *__restrict__ stats, const float *__restrict__ yout,
+                const uint8_t *__restrict__ flags, int nct0, int nct1) {
+  constexpr int q = Pow<D, NL>::v, Q = Pow<D, NH>::v, F = nfeat<D, NL>(), O = nout<D, NL, NH>();
   const int n = *count;
   const int nct[3] = {nct0, nct1, 1};
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
        t += (long long)gridDim.x * blockDim.x) {
-    const long long k = list[t];
-    int x = (int)(k % g.nx), y = (int)((k / g.nx) % g.ny), z = (int)(k / ((long long)g.nx * g.ny));
+    int x, y, z;
+    cell_coords(g, list[t], x, y, z);
     const int off = g.idx(x, y, z);
-    double f[q], gg[q], fo[Q], go[Q], dM[Q];
-    read_cell_t<S, D, NL>(tab, g, bl, 0, off, f, gg);
+    double f[q], gg[TH ? q : 1], fo[Q], go[TH ? Q : 1], dM[Q];
+    read_cell_t<S, D, NL, TH>(tab, g, bl, 0, off, f, gg);
     const bool use = flags[check_tile(g, x, y, z, nct)] != 0;
     double rho, u[3], T;
-    macros_t<D, NL>(tab->lat[0], tab->thermal, tab->cv, f, gg, rho, u, T);
+    macros_t<D, NL>(tab->lat[0], TH && tab->thermal, tab->cv, f, gg, rho, u, T);
+    // rho T^{|p|/2} for every degree
+    const double sT = sqrt(T);
+    double sc[D * (NH - 1) + 1];
+    sc[0] = use ? rho : 0.0;
+#pragma unroll
+    for (int d = 1; d <= D * (NH - 1); ++d) sc[d] = sc[d - 1] * sT;
+    const float *yo = yout + t * O;
     int o = 0;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
       const int p0 = j % NH, p1 = (j / NH) % NH, p2 = D == 3 ? j / (NH * NH) : 0;
       if (p0 < NL && p1 < NL && p2 < NL) { dM[j] = 0.0; continue; }
-      const double tn = (double)yout[t * O + o] * stats[2 * F + O + o] + stats[2 * F + o];
-      dM[j] = use ? rho * pow(T, 0.5 * (p0 + p1 + p2)) * tn : 0.0;
+      const double tn = (double)yo[o] * stats[2 * F + O + o] + stats[2 * F + o];
+      dM[j] = sc[p0 + p1 + p2] * tn;
       ++o;
     }
-    lift_t<D, NL, NH>(tab, f, gg, dM, fo, go);
-    write_cell_t<S, D, NH>(tab, g, bh, 1, off, fo, go);
+    lift_t<D, NL, NH, TH>(tab, f, gg, dM, fo, go);
+    write_cell_t<S, D, NH, TH>(tab, g, bh, 1, off, fo, go);
   }
 }
 
 // error check, stage 1: for the high-order band cells, the standardised
 // features of their projected state and their true normalised targets
-template <typename S, int D, int NL, int NH>
-__global__ void k_check_prepare(const Tab *__restrict__ tab, Geo g, const char *bh,
-                                const int *__restrict__ list, const int *__restrict__ count,
-                                const float *__restrict__ stats, int F, int O,
-                                float *__restrict__ feat, float *__restrict__ tgt) {
-  constexpr int q = Pow<D, NL>::v, Q = Pow<D, NH>::v;
+template <typename S, int D, int NL, int NH, bool TH>
+__global__ void __launch_bounds__(64)
+k_check_prepare(const Tab *__restrict__ tab, Geo g, const char *bh, const int *__restrict__ list,
+                const int *__restrict__ count, const float *__restrict__ stats,
+                float *__restrict__ feat, float *__restrict__ tgt) {
+  constexpr int q = Pow<D, NL>::v, Q = Pow<D, NH>::v, F = nfeat<D, NL>(), O = nout<D, NL, NH>();
   const int n = *count;
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
        t += (long long)gridDim.x * blockDim.x) {
-    const long long k = list[t];
-    int x = (int)(k % g.nx), y = (int)((k / g.nx) % g.ny), z = (int)(k / ((long long)g.nx * g.ny));
-    double fQ[Q], gQ[Q], fq[q], gq[q], ft[64], tt[Q];
-    read_cell_t<S, D, NH>(tab, g, bh, 1, g.idx(x, y, z), fQ, gQ);
-    project_t<D, NL, NH>(tab, fQ, gQ, fq, gq);
-    features_t<D, NL>(tab, fq, gq, ft);
-    targets_t<D, NL, NH>(tab, fQ, gQ, tt);
+    int x, y, z;
+    cell_coords(g, list[t], x, y, z);
+    double fQ[Q], gQ[TH ? Q : 1], fq[q], gq[TH ? q : 1], ft[F], tt[O];
+    read_cell_t<S, D, NH, TH>(tab, g, bh, 1, g.idx(x, y, z), fQ, gQ);
+    project_t<D, NL, NH, TH>(tab, fQ, gQ, fq, gq);
+    features_t<D, NL, TH>(tab, fq, gq, ft);
+    targets_t<D, NL, NH, TH>(tab, fQ, gQ, tt);
+#pragma unroll
     for (int a = 0; a < F; ++a) feat[t * F + a] = (float)((ft[a] - stats[a]) / stats[F + a]);
+#pragma unroll
     for (int a = 0; a < O; ++a) tgt[t * O + a] = (float)tt[a];
   }
 }
 
 // stage 2: per-cell squared errors of the network and of Grad (zero) lifting
-__global__ void k_check_cells(const int *__restrict__ count, const float *__restrict__ stats, int F,
+__global__ void __launch_bounds__(256)
+k_check_cells(const int *__restrict__ count, const float *__restrict__ stats, int F,
                               int O, const float *__restrict__ yout, const float *__restrict__ tgt,
                               double *__restrict__ cerr) {
   const int n = *count;
@@ -550,63 +661,112 @@ __global__ void k_check_cells(const int *__restrict__ count, const float *__rest
   }
 }
 
-// stage 3: per check tile sums (in list order) and the flags; tiles without
-// high-order band cells follow the total over the domain
-__global__ void k_check_tiles(Geo g, const int *__restrict__ list, const int *__restrict__ count,
-                              const double *__restrict__ cerr, int nct0, int nct1, int ntile,
-                              double *__restrict__ terr, uint8_t *__restrict__ flags) {
-  __shared__ double tot[2];
-  __shared__ int any_total;
-  const int n = *count;
+// stage 3: per check tile sums.  One block per tile.  The list is ascending in
+// cell index, so the cells of a tile lie in the slab of list entries whose
+// outermost coordinate falls in the tile's range; the block finds that slab by
+// bisection and sums the entries of its own tile in a fixed order (strided per
+// thread, then a fixed tree), so the sums do not depend on scheduling.
+__global__ void __launch_bounds__(256)
+k_check_tiles(Geo g, const int *__restrict__ list, const int *__restrict__ count,
+              const double *__restrict__ cerr, int nct0, int nct1, double *__restrict__ terr) {
+  __shared__ double rem[256], reg[256];
+  __shared__ int rhas[256];
+  __shared__ int range[2];
+  const int tl = blockIdx.x;
   const int nct[3] = {nct0, nct1, 1};
-  if (threadIdx.x == 0) { tot[0] = tot[1] = 0; any_total = 0; }
-  __syncthreads();
-  for (int tl = threadIdx.x; tl < ntile; tl += blockDim.x) {
-    double em = 0, eg = 0;
-    int has = 0;
-    for (int t = 0; t < n; ++t) {
-      const long long k = list[t];
-      const int x = (int)(k % g.nx), y = (int)((k / g.nx) % g.ny), z = (int)(k / ((long long)g.nx * g.ny));
-      if (check_tile(g, x, y, z, nct) != tl) continue;
-      em += cerr[2 * t];
-      eg += cerr[2 * t + 1];
-      has = 1;
+  if (threadIdx.x < 2) {
+    const int n = *count;
+    const int outer = g.dim == 3 ? tl / (nct0 * nct1) : tl / nct0;
+    const long long S = g.dim == 3 ? (long long)g.nx * g.ny : (long long)g.nx;
+    const int NO = g.dim == 3 ? g.nz : g.ny;
+    const int e = min((outer + threadIdx.x) * MSL_CHECK_TILE, NO);
+    const long long key = (long long)e * S;
+    int lo = 0, hi = n;           // first entry with list[t] >= key
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((long long)list[mid] < key) lo = mid + 1;
+      else hi = mid;
     }
-    terr[2 * tl] = em;
-    terr[2 * tl + 1] = has ? eg : -1.0;
+    range[threadIdx.x] = lo;
   }
   __syncthreads();
+  double em = 0, eg = 0;
+  int has = 0;
+  for (int t = range[0] + threadIdx.x; t < range[1]; t += blockDim.x) {
+    int x, y, z;
+    cell_coords(g, list[t], x, y, z);
+    if (check_tile(g, x, y, z, nct) != tl) continue;
+    em += cerr[2 * t];
+    eg += cerr[2 * t + 1];
+    has = 1;
+  }
+  rem[threadIdx.x] = em;
+  reg[threadIdx.x] = eg;
+  rhas[threadIdx.x] = has;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      rem[threadIdx.x] += rem[threadIdx.x + w];
+      reg[threadIdx.x] += reg[threadIdx.x + w];
+      rhas[threadIdx.x] |= rhas[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
-    double em = 0, eg = 0;
-    for (int tl = 0; tl < ntile; ++tl)
-      if (terr[2 * tl + 1] >= 0) { em += terr[2 * tl]; eg += terr[2 * tl + 1]; }
-    tot[0] = em;
-    tot[1] = eg;
+    terr[2 * tl] = rem[0];
+    terr[2 * tl + 1] = rhas[0] ? reg[0] : -1.0;
   }
+}
+
+// stage 4: the flags.  A tile uses the network where its summed error is below
+// the Grad completion's; tiles without high-order band cells follow the totals
+// over the domain.  One block, fixed-order sums.
+__global__ void __launch_bounds__(256)
+k_check_flags(int ntile, const double *__restrict__ terr, uint8_t *__restrict__ flags) {
+  __shared__ double rem[256], reg[256];
+  double em = 0, eg = 0;
+  for (int tl = threadIdx.x; tl < ntile; tl += blockDim.x)
+    if (terr[2 * tl + 1] >= 0) {
+      em += terr[2 * tl];
+      eg += terr[2 * tl + 1];
+    }
+  rem[threadIdx.x] = em;
+  reg[threadIdx.x] = eg;
   __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      rem[threadIdx.x] += rem[threadIdx.x + w];
+      reg[threadIdx.x] += reg[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  const double tm = rem[0], tg = reg[0];
   for (int tl = threadIdx.x; tl < ntile; tl += blockDim.x) {
     const bool has = terr[2 * tl + 1] >= 0;
-    flags[tl] = has ? (terr[2 * tl] < terr[2 * tl + 1]) : (tot[1] == 0.0 ? 1 : (tot[0] < tot[1]));
+    flags[tl] = has ? (terr[2 * tl] < terr[2 * tl + 1]) : (tg == 0.0 ? 1 : (tm < tg));
   }
-  (void)any_total;
 }
 
 // snapshots from a run on the high-order set: every cell's projected features
 // and true targets (rows in cell order)
-template <typename S, int D, int NL, int NH>
-__global__ void k_snapshots(const Tab *__restrict__ tab, Geo g, const char *bh, int F, int O,
-                            long long nmax, float *__restrict__ feat, float *__restrict__ tgt) {
-  constexpr int q = Pow<D, NL>::v, Q = Pow<D, NH>::v;
+template <typename S, int D, int NL, int NH, bool TH>
+__global__ void __launch_bounds__(64)
+k_snapshots(const Tab *__restrict__ tab, Geo g, const char *bh, long long nmax,
+            float *__restrict__ feat, float *__restrict__ tgt) {
+  constexpr int q = Pow<D, NL>::v, Q = Pow<D, NH>::v, F = nfeat<D, NL>(), O = nout<D, NL, NH>();
   const long long n = g.ncell < nmax ? g.ncell : nmax;
   for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
        k += (long long)gridDim.x * blockDim.x) {
-    int x = (int)(k % g.nx), y = (int)((k / g.nx) % g.ny), z = (int)(k / ((long long)g.nx * g.ny));
-    double fQ[Q], gQ[Q], fq[q], gq[q], ft[64], tt[Q];
-    read_cell_t<S, D, NH>(tab, g, bh, 1, g.idx(x, y, z), fQ, gQ);
-    project_t<D, NL, NH>(tab, fQ, gQ, fq, gq);
-    features_t<D, NL>(tab, fq, gq, ft);
-    targets_t<D, NL, NH>(tab, fQ, gQ, tt);
+    int x, y, z;
+    cell_coords(g, k, x, y, z);
+    double fQ[Q], gQ[TH ? Q : 1], fq[q], gq[TH ? q : 1], ft[F], tt[O];
+    read_cell_t<S, D, NH, TH>(tab, g, bh, 1, g.idx(x, y, z), fQ, gQ);
+    project_t<D, NL, NH, TH>(tab, fQ, gQ, fq, gq);
+    features_t<D, NL, TH>(tab, fq, gq, ft);
+    targets_t<D, NL, NH, TH>(tab, fQ, gQ, tt);
+#pragma unroll
     for (int a = 0; a < F; ++a) feat[k * F + a] = (float)ft[a];
+#pragma unroll
     for (int a = 0; a < O; ++a) tgt[k * O + a] = (float)tt[a];
   }
 }
@@ -651,24 +811,34 @@ static int store_dispatch(int store, F &&f) {
   return MSL_EINVAL;
 }
 
+template <typename F>
+static int thermal_dispatch(int thermal, F &&f) {
+  return thermal ? f.template operator()<true>() : f.template operator()<false>();
+}
+
 int msl_mlp_band_lift(msl_ctx *c, char *bl, char *bh) {
   if (!c->mlp_on) return MSL_OK;
   int rc = store_dispatch(c->cfg.store, [&]<typename S>() {
     return msl_pair_dispatch(c->D, c->htab.lat[0].n, c->htab.lat[1].n, [&]<int D, int NL, int NH>() {
-      hipLaunchKernelGGL((k_band_features<S, D, NL>), dim3(512), dim3(256), 0, c->stream, c->dtab,
-                         c->geo, bl, c->blist[0], c->bcount, c->mlp_stats, c->mlpF, c->mlp_feat);
-      return lerr();
+      if (nfeat<D, NL>() != c->mlpF || nout<D, NL, NH>() != c->mlpO) return (int)MSL_EINVAL;
+      return thermal_dispatch(c->cfg.thermal, [&]<bool TH>() {
+        hipLaunchKernelGGL((k_band_features<S, D, NL, TH>), dim3(2048), dim3(64), 0, c->stream,
+                           c->dtab, c->geo, bl, c->blist[0], c->bcount, c->mlp_stats, c->mlp_feat);
+        return lerr();
+      });
     });
   });
   if (rc) return rc;
-  rc = mlp_launch<0>(c, c->mlp_feat, nullptr, 0, c->bcount, c->mlp_out, 0.f, 256);
+  rc = mlp_launch<0>(c, c->mlp_feat, nullptr, 0, c->bcount, c->mlp_out, 0.f, 512);
   if (rc) return rc;
   return store_dispatch(c->cfg.store, [&]<typename S>() {
     return msl_pair_dispatch(c->D, c->htab.lat[0].n, c->htab.lat[1].n, [&]<int D, int NL, int NH>() {
-      hipLaunchKernelGGL((k_band_lift_mlp<S, D, NL, NH>), dim3(512), dim3(256), 0, c->stream,
-                         c->dtab, c->geo, bl, bh, c->blist[0], c->bcount, c->mlp_stats, c->mlpF,
-                         c->mlpO, c->mlp_out, c->mlp_flag, c->nct[0], c->nct[1]);
-      return lerr();
+      return thermal_dispatch(c->cfg.thermal, [&]<bool TH>() {
+        hipLaunchKernelGGL((k_band_lift_mlp<S, D, NL, NH, TH>), dim3(2048), dim3(64), 0, c->stream,
+                           c->dtab, c->geo, bl, bh, c->blist[0], c->bcount, c->mlp_stats,
+                           c->mlp_out, c->mlp_flag, c->nct[0], c->nct[1]);
+        return lerr();
+      });
     });
   });
 }
@@ -678,19 +848,23 @@ int msl_mlp_check_launch(msl_ctx *c) {
   char *bh = c->planes[1][c->cur];
   int rc = store_dispatch(c->cfg.store, [&]<typename S>() {
     return msl_pair_dispatch(c->D, c->htab.lat[0].n, c->htab.lat[1].n, [&]<int D, int NL, int NH>() {
-      hipLaunchKernelGGL((k_check_prepare<S, D, NL, NH>), dim3(512), dim3(256), 0, c->stream,
-                         c->dtab, c->geo, bh, c->blist[1], c->bcount + 1, c->mlp_stats, c->mlpF,
-                         c->mlpO, c->mlp_feat, c->mlp_tgt);
-      return lerr();
+      if (nfeat<D, NL>() != c->mlpF || nout<D, NL, NH>() != c->mlpO) return (int)MSL_EINVAL;
+      return thermal_dispatch(c->cfg.thermal, [&]<bool TH>() {
+        hipLaunchKernelGGL((k_check_prepare<S, D, NL, NH, TH>), dim3(2048), dim3(64), 0, c->stream,
+                           c->dtab, c->geo, bh, c->blist[1], c->bcount + 1, c->mlp_stats,
+                           c->mlp_feat, c->mlp_tgt);
+        return lerr();
+      });
     });
   });
   if (rc) return rc;
-  rc = mlp_launch<0>(c, c->mlp_feat, nullptr, 0, c->bcount + 1, c->mlp_out, 0.f, 256);
+  rc = mlp_launch<0>(c, c->mlp_feat, nullptr, 0, c->bcount + 1, c->mlp_out, 0.f, 512);
   if (rc) return rc;
   hipLaunchKernelGGL(k_check_cells, dim3(512), dim3(256), 0, c->stream, c->bcount + 1,
                      c->mlp_stats, c->mlpF, c->mlpO, c->mlp_out, c->mlp_tgt, c->mlp_cerr);
-  hipLaunchKernelGGL(k_check_tiles, dim3(1), dim3(256), 0, c->stream, c->geo, c->blist[1],
-                     c->bcount + 1, c->mlp_cerr, c->nct[0], c->nct[1], c->nctile, c->mlp_err,
+  hipLaunchKernelGGL(k_check_tiles, dim3(c->nctile), dim3(256), 0, c->stream, c->geo, c->blist[1],
+                     c->bcount + 1, c->mlp_cerr, c->nct[0], c->nct[1], c->mlp_err);
+  hipLaunchKernelGGL(k_check_flags, dim3(1), dim3(256), 0, c->stream, c->nctile, c->mlp_err,
                      c->mlp_flag);
   return lerr();
 }
@@ -716,9 +890,12 @@ int msl_collect_snapshots(msl_ctx *c, float *feats, float *targets, int max, int
   char *bh = c->planes[1][c->cur];
   int rc = store_dispatch(c->cfg.store, [&]<typename S>() {
     return msl_pair_dispatch(c->D, c->htab.lat[0].n, c->htab.lat[1].n, [&]<int D, int NL, int NH>() {
-      hipLaunchKernelGGL((k_snapshots<S, D, NL, NH>), dim3(1024), dim3(256), 0, c->stream, c->dtab,
-                         c->geo, bh, c->mlpF, c->mlpO, (long long)max, feats, targets);
-      return lerr();
+      if (nfeat<D, NL>() != c->mlpF || nout<D, NL, NH>() != c->mlpO) return (int)MSL_EINVAL;
+      return thermal_dispatch(c->cfg.thermal, [&]<bool TH>() {
+        hipLaunchKernelGGL((k_snapshots<S, D, NL, NH, TH>), dim3(4096), dim3(64), 0, c->stream,
+                           c->dtab, c->geo, bh, (long long)max, feats, targets);
+        return lerr();
+      });
     });
   });
   if (rc) return rc;
