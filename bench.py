@@ -1,17 +1,26 @@
 """Throughput benchmark of the multi-scale semi-Lagrangian LBM step on one GPU.
 
 A step is one pass of the whole hot path (criterion and switching every 20
-steps, ghost fill, stream-and-collide of both velocity sets, band conversion)
-over the workload's grid.  The default workload is the compressible slot jet:
-1024 x 512 cells, thermal two-population model, FP32 storage, D2Q9 with D2Q16
-where the local Mach number exceeds 0.4 (re-evaluated every 20 steps),
-tau = 0.52, 20000 steps.  Inputs are synthetic and resident in HBM before the
-timed region starts.
+steps, ghost fill, stream-and-collide of both velocity sets, band conversion,
+learned closure where configured) over the workload's grid.  The default
+workload is the slot jet: 1024 x 512 cells, a 32-cell slot at Mach 0.6 with
+tanh edges into gas at rest, athermal, FP32 storage, D2Q9 with D2Q36 where the
+local Mach number exceeds 0.4 (re-evaluated every 20 steps), tau = 0.52,
+20000 steps.  Inputs are synthetic and resident in HBM before the timed
+region starts.
 
 Prints one JSON line: MLUPS (million cell updates per second, each cell once
 per step whatever its velocity set), the HBM roofline of the dominant kernel
 (algorithmic bytes per launch / its HIP-event-timed average duration), and the
 FP64 CPU oracle timed on a bounded sample on the host cores.
+
+`--workload couette-equal-l2` runs the comparison of the learned form (network
+lift, FP16 deviation storage) with the plain form (Grad lift, FP32) at equal
+L2 error against full high-order runs of planar Couette flow: it trains the
+network on snapshots of those runs, sweeps the width of the high-order layer
+next to the walls for every form, takes as the common error the plain form's
+error at width 4, and reports each form's throughput at the cheapest width
+that reaches it.
 """
 import argparse
 import hashlib
@@ -58,7 +67,7 @@ def workload(name):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("msl_stream.hpp", "msl_device.hpp", "msl_internal.hpp"):
+    for f in ("msl_stream.hpp", "msl_stream2.hpp", "msl_device.hpp", "msl_internal.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2102_12559_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -103,6 +112,221 @@ def cpu_baseline(w, seconds_hint):
                        f"initial state, FP64, {dt:.1f} s")
 
 
+def timed_steps(s, steps, warmup):
+    """Warm up, then time `steps` steps with events on the library's stream and
+    the per-class kernel profile (HIP events around every launch class)."""
+    import torch
+    s.step(warmup)
+    torch.cuda.synchronize()
+    s.profile(True)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    s.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    prof = s.profile_read()
+    s.profile(False)
+    return ms, prof
+
+
+def roofline_of(prof, traffic_name):
+    """Roofline of the dominant kernel: the stream-collide class with the
+    largest total time; algorithmic bytes per launch over its average time."""
+    sc = {k: v for k, v in prof.items() if k.startswith("stream_collide") and v["launches"] > 0}
+    dom = max(sc, key=lambda k: sc[k]["ms"])
+    d = sc[dom]
+    avg_ms = d["ms"] / d["launches"]
+    bytes_per_launch = d["bytes"] / d["launches"]
+    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
+    return {
+        "bound": "hbm",
+        "kernel": dom,
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic_for(traffic_name, d),
+        "bytes_per_launch": round(bytes_per_launch),
+        "avg_launch_us": round(avg_ms * 1e3, 3),
+    }
+
+
+STORE_NAMES = {0: "f64", 1: "f32", 2: "fp16-dev", 3: "bf16-dev"}
+METRIC = "MLUPS & % HBM roofline; learned/FP16 form vs plain at equal L2 err"
+
+
+# ---------------------------------------------------------------------------
+# learned form vs plain form at equal L2 error (planar Couette flow)
+# ---------------------------------------------------------------------------
+EQ_CASES = [(N, kn) for N in (32, 64, 128) for kn in (0.1, 0.5, 1.0)]
+EQ_WIDTHS = [0, 1, 2, 3, 4, 6, 8]
+EQ_REF_WIDTH = 4
+
+
+def eq_forms():
+    from paper_2102_12559_amd import inputs
+    return {
+        "plain": (inputs.STORE_FP32, inputs.LIFT_GRAD),
+        "learned": (inputs.STORE_FP16_DEV, inputs.LIFT_MLP),
+        "learned_fp32": (inputs.STORE_FP32, inputs.LIFT_MLP),
+        "grad_hermite_fp32": (inputs.STORE_FP32, inputs.LIFT_GRAD_HERMITE),
+    }
+
+
+def steady_profile(w, net=None, full=False, chunk=1000, tol=1e-7, max_steps=30000):
+    """Run a Couette case to steady state: the x-averaged u_x profile once it
+    changes by less than `tol` over `chunk` steps."""
+    import numpy as np
+    from paper_2102_12559_amd import closure, msl
+    s = msl.Solver(w["cfg"])
+    if net is not None:
+        closure.install(s, net)
+    s.set_mask(np.ones_like(w["mask"]) if full else w["mask"])
+    s.init(w["rho"], w["u"], w["T"])
+    prev, done = None, 0
+    while done < max_steps:
+        s.step(chunk)
+        done += chunk
+        ux = s.macros()[1][0].mean(dim=(0, 2)).cpu().numpy()
+        if not np.all(np.isfinite(ux)):
+            break
+        if prev is not None and np.max(np.abs(ux - prev)) < tol:
+            break
+        prev = ux
+    s.close()
+    return ux, done
+
+
+def equal_l2(args):
+    import numpy as np
+    import torch
+    from paper_2102_12559_amd import closure, inputs, msl
+
+    def say(m):
+        print(m, file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    times = [int(x) for x in np.unique(np.round(np.geomspace(50, 8000, 19)))]
+    X, Y = closure.collect_snapshots(EQ_CASES, times)
+    net = closure.train(X, Y, batch=1024, hidden=64, seed=0,
+                        schedule=[(100, 1e-3), (60, 3e-4), (40, 1e-4)])
+    say(f"[equal-l2] {X.shape[0]} snapshots, trained in {time.time() - t0:.1f} s, "
+        f"validation mse {net['val_mse']:.4f}")
+    refs = {}
+    for (N, kn) in EQ_CASES:
+        w = closure.couette_case(N, kn, store=inputs.STORE_FP64, band=N // 2)
+        refs[(N, kn)], _ = steady_profile(w, full=True)
+    forms = eq_forms()
+    errs = {}
+    for f, (store, lift) in forms.items():
+        errs[f] = {}
+        for wd in EQ_WIDTHS:
+            e = []
+            for (N, kn) in EQ_CASES:
+                w = closure.couette_case(N, kn, store=store, band=wd, lift_mode=lift)
+                ux, _ = steady_profile(w, net if lift == inputs.LIFT_MLP else None)
+                r = refs[(N, kn)]
+                e.append(float(np.sqrt(np.sum((ux - r) ** 2) / np.sum(r ** 2))))
+            errs[f][wd] = float(np.mean(e))
+            say(f"[equal-l2] {f} w={wd}: mean L2 {errs[f][wd]:.4f}")
+    e_star = errs["plain"][EQ_REF_WIDTH]
+    # throughput: the x-extended channel 8192 x 128 at Kn 0.5
+    Nt, knt, nx = 128, 0.5, 8192
+    thr, rl = {}, {}
+    for f, (store, lift) in forms.items():
+        thr[f] = {}
+        for wd in EQ_WIDTHS:
+            w = closure.couette_case(Nt, knt, store=store, band=wd, lift_mode=lift, nx=nx)
+            s = msl.Solver(w["cfg"])
+            if lift == inputs.LIFT_MLP:
+                closure.install(s, net)
+            s.set_mask(w["mask"])
+            s.init(w["rho"], w["u"], w["T"])
+            ms, prof = timed_steps(s, args.steps or 400, 60)
+            n = args.steps or 400
+            thr[f][wd] = nx * Nt * n / (ms / 1e3) / 1e6
+            rl[(f, wd)] = (ms / n, prof)
+            s.close()
+    summary = {}
+    for f in forms:
+        ok = [wd for wd in EQ_WIDTHS if errs[f][wd] <= e_star]
+        best = max(ok, key=lambda wd: thr[f][wd]) if ok else None
+        summary[f] = {"width": best, "mlups": round(thr[f][best], 1) if best is not None else None,
+                      "l2": round(errs[f][best], 4) if best is not None else None,
+                      "min_l2": round(min(errs[f].values()), 4)}
+    lw = summary["learned"]["width"]
+    pick = ("learned", lw) if lw is not None else ("plain", summary["plain"]["width"])
+    ms_step, prof = rl[pick]
+    out = {
+        "metric": METRIC,
+        "value": summary["learned"]["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps or 400,
+        "warmup": 60,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "planar Couette flow, walls +-0.1, N in {32,64,128}, Kn in "
+                               "{0.1,0.5,1.0}; D2Q9 bulk, D2Q36 layers of width w at the walls; "
+                               "throughput on the x-extended 8192x128 channel at Kn 0.5",
+                   "reference": "full D2Q36 FP64 run of each case",
+                   "error": "mean over the 9 cases of the relative L2 error of the steady "
+                            "x-averaged u_x profile",
+                   "timed_run": f"{pick[0]} at width {pick[1]}"},
+        "equal_l2": {"target_l2": round(e_star, 4),
+                     "target": f"plain form's error at width {EQ_REF_WIDTH}",
+                     "forms": {f: {"storage": STORE_NAMES[forms[f][0]],
+                                   "lift": ["grad", "grad-hermite", "network"][forms[f][1]],
+                                   "l2_by_width": {str(k): round(v, 4) for k, v in errs[f].items()},
+                                   "mlups_by_width": {str(k): round(v, 1) for k, v in thr[f].items()},
+                                   **summary[f]} for f in forms},
+                     "snapshots": int(X.shape[0]), "validation_mse": net["val_mse"]},
+        "roofline": roofline_of(prof, "couette"),
+        "kernels_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
+    }
+    if not args.no_cpu:
+        w = closure.couette_case(32, 0.5, store=inputs.STORE_FP64, band=EQ_REF_WIDTH)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+def device_copy_rate(args):
+    """The library's plain copy kernel over 1 GiB: the measured bandwidth
+    ceiling, and the known byte count that calibrates the HBM counters."""
+    import torch
+    from paper_2102_12559_amd import msl
+    torch.cuda.set_device(0)
+    nbytes = 1 << 30
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0").fill_(1)
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    n = args.steps or 20
+    for _ in range(3):
+        msl.device_copy(b, a, stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(n):
+        msl.device_copy(b, a, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / n
+    gbs = 2 * nbytes / (ms / 1e3) / 1e9
+    print(json.dumps({"workload": "device copy", "bytes_read": nbytes, "bytes_written": nbytes,
+                      "launches": n + 3, "ms_per_copy": round(ms, 4), "GB_per_s": round(gbs, 1),
+                      "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,7 +341,13 @@ def main():
                                    "(the domain-decomposed multi-GPU step is a design only)"}))
         sys.exit(2)
 
-    import numpy as np
+    if args.workload == "couette-equal-l2":
+        equal_l2(args)
+        return
+    if args.workload == "device-copy":
+        device_copy_rate(args)
+        return
+
     import torch
     from paper_2102_12559_amd import msl
 
@@ -128,39 +358,17 @@ def main():
     s = msl.Solver(cfg, device="cuda:0")
     s.set_mask(w["mask"])
     s.init(w["rho"], w["u"], w["T"])
-    s.step(args.warmup)
-    torch.cuda.synchronize()
-    s.profile(True)
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    s.step(steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    prof = s.profile_read()
-    s.profile(False)
+    ms, prof = timed_steps(s, steps, args.warmup)
     ncell = s.ncell
     value = ncell * steps / (ms / 1e3) / 1e6
     stable = True
     try:
-        cons = s.conservation()
+        s.conservation()
     except msl.MslError:
-        stable, cons = False, None
+        stable = False
     nhigh = int(s.get_mask().sum().item())
-
-    # dominant kernel: the stream-collide class with the largest total time
-    sc = {k: v for k, v in prof.items() if k.startswith("stream_collide") and v["launches"] > 0}
-    dom = max(sc, key=lambda k: sc[k]["ms"])
-    d = sc[dom]
-    avg_ms = d["ms"] / d["launches"]
-    bytes_per_launch = d["bytes"] / d["launches"]
-    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
-    store_name = {0: "f64", 1: "f32", 2: "fp16-dev", 3: "bf16-dev"}[cfg["store"]]
     out = {
-        "metric": "MLUPS & % HBM roofline; learned/FP16 form vs plain at equal L2 err",
+        "metric": METRIC,
         "value": round(value, 2),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -175,18 +383,8 @@ def main():
         "config": {"workload": w["desc"], "grid": [cfg["nx"], cfg["ny"], cfg["nz"]],
                    "cells": ncell, "lattices": [cfg["n_low"] ** cfg["dim"],
                                                 cfg["n_high"] ** cfg["dim"] if cfg["n_high"] else 0],
-                   "storage": store_name, "parallelism": "single GPU"},
-        "roofline": {
-            "bound": "hbm",
-            "kernel": dom,
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_for(args.workload, d),
-            "bytes_per_launch": round(bytes_per_launch),
-            "avg_launch_us": round(avg_ms * 1e3, 3),
-        },
+                   "storage": STORE_NAMES[cfg["store"]], "parallelism": "single GPU"},
+        "roofline": roofline_of(prof, args.workload),
         "kernels_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
         "high_order_cells_end": nhigh,
         "stable": stable,
