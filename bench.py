@@ -49,15 +49,19 @@ def workload(name):
                      "D2Q9 + D2Q16 where Ma > 0.4 (every 20 steps), tau 0.52")
         return w
     if name.startswith("roofline"):
-        # single velocity set on 8192^2 periodic cells, smooth random flow
-        n = {"roofline-d2q9": 3, "roofline-d2q16": 4, "roofline-d2q36": 6}[name]
-        N = 8192
-        cfg = inputs.base_config(nx=N, ny=N, n_low=n, n_high=0, tau=0.6,
-                                 store=inputs.STORE_FP32)
-        rho, u, T = inputs.smooth_random_flow(N, N, umax=0.1, seed=0, modes=2)
+        # single velocity set on 8192^2 periodic cells, smooth random flow;
+        # roofline-d2q<Q>[-fp64|-fp16|-bf16] (default fp32)
         import numpy as np
+        parts = name.split("-")
+        n = {"d2q9": 3, "d2q16": 4, "d2q25": 5, "d2q36": 6}[parts[1]]
+        store = {"fp64": inputs.STORE_FP64, "fp32": inputs.STORE_FP32, "fp16": inputs.STORE_FP16_DEV,
+                 "bf16": inputs.STORE_BF16_DEV}[parts[2] if len(parts) > 2 else "fp32"]
+        N = 8192
+        cfg = inputs.base_config(nx=N, ny=N, n_low=n, n_high=0, tau=0.6, store=store)
+        rho, u, T = inputs.smooth_random_flow(N, N, umax=0.1, seed=0, modes=2)
         return dict(cfg=cfg, rho=rho, u=u, T=T, mask=np.zeros((1, N, N), np.uint8),
-                    steps=100, desc=f"single D2Q{n*n} lattice 8192x8192 periodic fp32")
+                    steps=100, desc=f"single D2Q{n*n} lattice 8192x8192 periodic "
+                                    f"{STORE_NAMES[store]}")
     if name == "vortex":
         w = inputs.vortex_c1()
         w["desc"] = "convected vortex 64x64, D2Q9 + D2Q16 disk, fp64"
@@ -112,13 +116,19 @@ def cpu_baseline(w, seconds_hint):
                        f"initial state, FP64, {dt:.1f} s")
 
 
+PROFILE_EVERY = 16
+
+
 def timed_steps(s, steps, warmup):
-    """Warm up, then time `steps` steps with events on the library's stream and
-    the per-class kernel profile (HIP events around every launch class)."""
+    """Warm up, then time `steps` steps with events on the library's stream.
+    Inside the same timed region the library times, with HIP events on its
+    stream, every launch of every 16th step: the per-class kernel profile
+    (event records cost the stream microseconds each, so timing every launch
+    of every step would slow the run it measures)."""
     import torch
     s.step(warmup)
     torch.cuda.synchronize()
-    s.profile(True)
+    s.profile(True, every=PROFILE_EVERY)
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)

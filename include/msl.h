@@ -184,10 +184,16 @@ int msl_num_check_tiles(const msl_ctx *ctx, int *n);
 /* ---- measurement ---- */
 
 /* Per-kernel timing of msl_step with HIP events recorded on the context's
- * stream around every launch (enable = 1).  While enabled the stream is
- * synchronised every 512 timed launches and after each criterion evaluation
- * (to read the number of high-order cells). */
-int msl_profile(msl_ctx *ctx, int enable);
+ * stream around the launches of every `every`-th step (every >= 1; 0
+ * disables; a second call changes the period).  Each event record costs the
+ * stream a few microseconds, so sampling keeps the timed run close to an
+ * untimed one.  The events form a ring of 2048 launches; when it is
+ * three-quarters full the host waits for the oldest half, which completed long
+ * before, so the stream never drains.  The number of high-order cells in force
+ * (which sets the bytes of a stream-collide launch) is written by the GPU into
+ * a small pinned host buffer that the first enable allocates (hipHostMalloc)
+ * and msl_destroy frees.  EINVAL for every < 0. */
+int msl_profile(msl_ctx *ctx, int every);
 /* stats[k][0..3] for launch class k = 0 ghost fill, 1 stream-collide of the
  * low-order set, 2 stream-collide of the high-order set, 3 band conversion,
  * 4 criterion and switching, 5 learned closure: number of launches, total

@@ -368,6 +368,7 @@ int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_
   t.mu_ref = (cfg->tau - 0.5) * cfg->tau_ref_rho * cfg->tau_ref_T * dt;
   t.mu_exp = cfg->mu_exp;
   t.tau_ref_T = cfg->tau_ref_T > 0 ? cfg->tau_ref_T : 1.0;
+  t.mu_T1 = t.mu_ref * pow(1.0 / t.tau_ref_T, t.mu_exp);
   t.rho0 = cfg->rho0 > 0 ? cfg->rho0 : 1.0;
   t.T0 = cfg->T0 > 0 ? cfg->T0 : 1.0;
   t.tau_mode = cfg->tau_mode;
@@ -447,6 +448,7 @@ int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_
 
 void msl_destroy(msl_ctx *c) {
   if (c && c->prof) msl_profile(c, 0);
+  if (c && c->prof_nh) hipHostFree(c->prof_nh);
   delete c;
 }
 
@@ -516,57 +518,85 @@ static int mask_step(msl_ctx *c) {
 }
 
 // ---- per-kernel timing ----
-static int prof_flush(msl_ctx *c) {
-  if (!c->nrec) return MSL_OK;
-  MSL_HIP(hipEventSynchronize(c->ev[2 * c->nrec - 1]));
-  for (int r = 0; r < c->nrec; ++r) {
+// Per-class launch timing without draining the stream: records live in a ring
+// of events; when the ring is three-quarters full the oldest half is read,
+// whose events completed long ago.  The number of high-order cells, which sets
+// the bytes of a stream-collide launch, is copied by the GPU itself into a
+// pinned host ring at every mask update and read with the records.
+__global__ void k_prof_snap(const int *__restrict__ src, int *__restrict__ dst) {
+  if (threadIdx.x == 0) dst[0] = src[0];
+}
+
+static int prof_read(msl_ctx *c, long long upto) {
+  if (upto <= c->ndone) return MSL_OK;
+  MSL_HIP(hipEventSynchronize(c->ev[2 * ((upto - 1) % MSL_PROF_REC) + 1]));
+  for (long long k = c->ndone; k < upto; ++k) {
+    const int r = (int)(k % MSL_PROF_REC);
     float ms = 0.f;
     MSL_HIP(hipEventElapsedTime(&ms, c->ev[2 * r], c->ev[2 * r + 1]));
+    double cells = c->rec_cells[r];
+    if (c->rec_lat[r] >= 0) {
+      const double nh = c->nlat > 1 ? (double)c->prof_nh[c->rec_slot[r]] : 0.0;
+      cells = c->nlat == 1 ? (double)c->ncell : (c->rec_lat[r] == 0 ? (double)c->ncell - nh : nh);
+    }
     double *st = c->pstat[c->rec_cls[r]];
     st[0] += 1.0;
     st[1] += ms;
-    st[2] += c->rec_bytes[r];
-    st[3] += c->rec_cells[r];
+    st[2] += cells * c->rec_bpc[r];
+    st[3] += cells;
   }
-  c->nrec = 0;
+  c->ndone = upto;
   return MSL_OK;
 }
+
+static void prof_snap(msl_ctx *c) {
+  if (!c->prof || c->nlat < 2) return;
+  const int slot = (int)(++c->nsnap % MSL_PROF_REC);
+  hipLaunchKernelGGL(k_prof_snap, dim3(1), dim3(64), 0, c->stream, c->bcount + 2, c->prof_nh + slot);
+}
+
+// launches of every prof-th step are timed
+static bool prof_on(const msl_ctx *c) { return c->prof && c->step % c->prof == 0; }
 
 static void prof_begin(msl_ctx *c) {
-  if (c->prof) hipEventRecord(c->ev[2 * c->nrec], c->stream);
+  if (prof_on(c)) hipEventRecord(c->ev[2 * (c->nrec % MSL_PROF_REC)], c->stream);
 }
 
-static int prof_end(msl_ctx *c, int cls, double bytes, double cells) {
-  if (!c->prof) return MSL_OK;
-  hipEventRecord(c->ev[2 * c->nrec + 1], c->stream);
-  c->rec_cls[c->nrec] = cls;
-  c->rec_bytes[c->nrec] = bytes;
-  c->rec_cells[c->nrec] = cells;
-  if (++c->nrec == MSL_PROF_REC) return prof_flush(c);
-  return MSL_OK;
-}
-
-static int read_nhigh(msl_ctx *c) {
-  int h = 0;
-  if (c->nlat > 1) {
-    MSL_HIP(hipMemcpyAsync(&h, c->bcount + 2, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    MSL_HIP(hipStreamSynchronize(c->stream));
-  }
-  c->nhigh = h;
+// lat >= 0: a stream-collide launch of that velocity set (cells from the
+// snapshot in force); otherwise `cells` as given
+static int prof_end(msl_ctx *c, int cls, int lat, double bytes_per_cell, double cells) {
+  if (!prof_on(c)) return MSL_OK;
+  const int r = (int)(c->nrec % MSL_PROF_REC);
+  hipEventRecord(c->ev[2 * r + 1], c->stream);
+  c->rec_cls[r] = cls;
+  c->rec_lat[r] = lat;
+  c->rec_slot[r] = (int)(c->nsnap % MSL_PROF_REC);
+  c->rec_bpc[r] = bytes_per_cell;
+  c->rec_cells[r] = cells;
+  ++c->nrec;
+  if (c->nrec - c->ndone >= 3 * MSL_PROF_REC / 4) return prof_read(c, c->ndone + MSL_PROF_REC / 2);
   return MSL_OK;
 }
 
 int msl_profile(msl_ctx *c, int enable) {
-  if (!c) return MSL_EINVAL;
+  if (!c || enable < 0) return MSL_EINVAL;
+  if (enable && c->prof) {
+    c->prof = enable;
+    return MSL_OK;
+  }
   if (enable && !c->prof) {
     for (int k = 0; k < 2 * MSL_PROF_REC; ++k) MSL_HIP(hipEventCreate(&c->ev[k]));
+    if (!c->prof_nh) MSL_HIP(hipHostMalloc((void **)&c->prof_nh, sizeof(int) * MSL_PROF_REC));
     memset(c->pstat, 0, sizeof(c->pstat));
-    c->nrec = 0;
-    c->prof = 1;
-    return read_nhigh(c);
+    c->nrec = c->ndone = 0;
+    c->nsnap = 0;
+    c->prof = enable;
+    if (c->nlat > 1)
+      hipLaunchKernelGGL(k_prof_snap, dim3(1), dim3(64), 0, c->stream, c->bcount + 2, c->prof_nh);
+    return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
   }
   if (!enable && c->prof) {
-    int rc = prof_flush(c);
+    int rc = prof_read(c, c->nrec);
     for (int k = 0; k < 2 * MSL_PROF_REC; ++k) hipEventDestroy(c->ev[k]);
     c->prof = 0;
     return rc;
@@ -577,7 +607,7 @@ int msl_profile(msl_ctx *c, int enable) {
 int msl_profile_read(msl_ctx *c, double *stats) {
   if (!c || !stats) return MSL_EINVAL;
   if (!c->prof) return MSL_ESTATE;
-  int rc = prof_flush(c);
+  int rc = prof_read(c, c->nrec);
   if (rc) return rc;
   memcpy(stats, c->pstat, sizeof(c->pstat));
   memset(c->pstat, 0, sizeof(c->pstat));
@@ -593,15 +623,15 @@ int msl_step(msl_ctx *c, int nsteps) {
       prof_begin(c);
       rc = mask_step(c);
       if (rc) { set_err(c, "criterion / switching failed"); return rc; }
-      if ((rc = prof_end(c, 4, 0, (double)c->ncell))) return rc;
-      if (c->prof && (rc = read_nhigh(c))) return rc;
+      prof_snap(c);
+      if ((rc = prof_end(c, 4, -1, 0.0, (double)c->ncell))) return rc;
     }
     if (c->cfg.lift_mode == MSL_LIFT_MLP && c->mlp_on && !c->mlp_manual) {
       const int every = c->cfg.mlp_check_every > 0 ? c->cfg.mlp_check_every : 20;
       if (c->step % every == 0) {
         prof_begin(c);
         if ((rc = msl_mlp_check_launch(c))) return rc;
-        if ((rc = prof_end(c, 5, 0, 0))) return rc;
+        if ((rc = prof_end(c, 5, -1, 0.0, 0.0))) return rc;
       }
     }
     const int cur = c->cur, nxt = cur ^ 1;
@@ -609,28 +639,26 @@ int msl_step(msl_ctx *c, int nsteps) {
     prof_begin(c);
     rc = msl_launch_bc(c, bl, bh);
     if (rc) { set_err(c, "ghost fill failed"); return rc; }
-    if ((rc = prof_end(c, 0, 0, 0))) return rc;
+    if ((rc = prof_end(c, 0, -1, 0.0, 0.0))) return rc;
     for (int l = 0; l < c->nlat; ++l) {
       // compulsory traffic: read and write every population plane of each native cell
-      const double cells = c->nlat == 1 ? (double)c->ncell
-                                        : (l == 0 ? (double)(c->ncell - c->nhigh) : (double)c->nhigh);
-      const double bytes = cells * 2.0 * c->Q[l] * (c->cfg.thermal ? 2 : 1) * (double)c->esz;
+      const double bpc = 2.0 * c->Q[l] * (c->cfg.thermal ? 2 : 1) * (double)c->esz;
       prof_begin(c);
       rc = msl_launch_stream_collide(c, l, c->planes[l][cur], c->planes[l][nxt]);
       if (rc) { set_err(c, "stream-collide launch failed"); return rc; }
-      if ((rc = prof_end(c, 1 + l, bytes, cells))) return rc;
+      if ((rc = prof_end(c, 1 + l, l, bpc, 0.0))) return rc;
     }
     if (c->nlat > 1) {
       char *nl = c->planes[0][nxt], *nh = c->planes[1][nxt];
       prof_begin(c);
       rc = msl_launch_band_convert(c, nl, nh);
       if (rc) { set_err(c, "band conversion failed"); return rc; }
-      if ((rc = prof_end(c, 3, 0, 0))) return rc;
+      if ((rc = prof_end(c, 3, -1, 0.0, 0.0))) return rc;
       if (c->cfg.lift_mode == MSL_LIFT_MLP && c->mlp_on) {
         prof_begin(c);
         rc = msl_mlp_band_lift(c, nl, nh);
         if (rc) { set_err(c, "learned lifting failed"); return rc; }
-        if ((rc = prof_end(c, 5, 0, 0))) return rc;
+        if ((rc = prof_end(c, 5, -1, 0.0, 0.0))) return rc;
       }
     }
     c->cur = nxt;

@@ -12,7 +12,7 @@
 #define MSL_TX 64          // tile width in x (one wavefront)
 #define MSL_MTY 4          // micro-tile height (rows) of the per-tile class flags
 #define MSL_CHECK_TILE 64  // check tiles of the learned closure
-#define MSL_PROF_REC 512   // timed launches buffered between synchronisations
+#define MSL_PROF_REC 2048  // ring of timed launches (the oldest half is read while the rest run)
 #define MSL_PROF_K 6       // launch classes of msl_profile_read
 #define MSL_MLP_MAXBLK 256       // workgroups of one training step (64 rows each)
 #define MSL_MLP_LOSS_RING 65536  // device loss history of the training steps
@@ -38,6 +38,7 @@ struct Tab {
   double P[MSL_MAXN][MSL_MAXN];    // project: P[a'][a] = l^low_{a'}(C_a)
   double Vi[MSL_MAXN][MSL_MAXN];   // inverse Vandermonde of the high nodes: Vi[a][m]
   double dt, cv, gfac, tau, omega, mu_ref, mu_exp, tau_ref_T, rho0, T0;
+  double mu_T1;   // mu_ref (1 / tau_ref_T)^mu_exp: the viscosity at T = 1
   float omegaf;
   int tau_mode, thermal, dim, nlat, lift_mode;
   // diffuse walls, per face and velocity set: the equilibrium at the wall state
@@ -149,11 +150,15 @@ struct msl_ctx {
   // per-kernel timing with HIP events (msl_profile)
   int prof;
   hipEvent_t ev[2 * MSL_PROF_REC];
-  int nrec;
+  long long nrec, ndone;  // records issued / read
   int rec_cls[MSL_PROF_REC];
-  double rec_bytes[MSL_PROF_REC], rec_cells[MSL_PROF_REC];
+  int rec_lat[MSL_PROF_REC];      // stream-collide: velocity set; else -1
+  int rec_slot[MSL_PROF_REC];     // high-order cell count snapshot in force
+  double rec_bpc[MSL_PROF_REC];   // algorithmic bytes per cell update
+  double rec_cells[MSL_PROF_REC];
   double pstat[MSL_PROF_K][4];
-  long long nhigh;        // high-order cells (host copy, refreshed while profiling)
+  int *prof_nh;           // pinned host ring of high-order cell counts, written by the GPU
+  long long nsnap;
 };
 
 // launch helpers implemented in the .hip files

@@ -95,7 +95,7 @@ __device__ __forceinline__ void collide_store(const Tab *__restrict__ tab, int l
     if (TH) Tm = ((double)e - 0.5 * rd * (ux * ux + uy * uy + uz * uz)) / (tab->cv * rd);
     C om = tsel<C>(tab->omega, tab->omegaf);
     if (tab->tau_mode == 1) {
-      const double mu = tab->mu_ref * pow(Tm / tab->tau_ref_T, tab->mu_exp);
+      const double mu = TH ? tab->mu_ref * pow(Tm / tab->tau_ref_T, tab->mu_exp) : tab->mu_T1;
       om = (C)(1.0 / (mu / (rd * Tm * tab->dt) + 0.5));
     }
     double Px[N], Py[N], Pz[N];

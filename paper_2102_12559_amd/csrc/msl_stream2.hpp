@@ -7,15 +7,18 @@
 // offset x - c_i dt is the same for all cells of a plane, so the window is
 // the tile shifted by the plane's base offset).  All windows are in flight at
 // once -- tens of KB per workgroup -- and no VGPR stages them.  After one wait
-// and one barrier, two passes over the resident windows follow:
-//   pass 1: separable 3-point Lagrange reconstruction of every population
-//           (eq. reconstructionPond), accumulating rho, rho u (, rho E);
-//   pass 2: the reconstruction again, BGK relaxation towards the Hermite
-//           product-form lattice equilibrium (eqs. Pond_f/g, feqL, geqL) and
-//           the store, with buffer stores whose out-of-range offset drops the
-//           writes of foreign or outside cells.
-// Reconstructing twice costs LDS reads but keeps only the moments and the
-// per-axis equilibrium factors in registers.
+// and one barrier follow:
+//   1. separable 3-point Lagrange reconstruction of every population
+//      (eq. reconstructionPond) into registers, accumulating rho, rho u
+//      (, rho E);
+//   2. the per-axis equilibrium factors of each cell (FP64);
+//   3. BGK relaxation of the reconstructed values towards the Hermite
+//      product-form lattice equilibrium (eqs. Pond_f/g, feqL, geqL) and the
+//      store, with buffer stores whose out-of-range offset drops the writes of
+//      foreign or outside cells.
+// A wave owns R rows of 64 cells, so the reconstructed values take NP * R
+// registers per lane; every window element is read from LDS (R + 2) / R
+// times per population instead of 3.
 #pragma once
 #include <utility>
 
@@ -36,8 +39,14 @@ struct SC2Traits {
   static constexpr int LWD = (66 * SZ + 3) / 4 + (SZ < 4 ? 1 : 0);
   static constexpr int dwords_per_plane(int ty) { return ((ty + 2) * LWD + 255) / 256 * 256; }
   static constexpr int LDS_BUDGET = 72 * 1024;
-  static constexpr int TY = NP * dwords_per_plane(16) * 4 <= LDS_BUDGET ? 16
-                          : (NP * dwords_per_plane(8) * 4 <= LDS_BUDGET ? 8 : 4);
+  // tile height: the tallest of 16 / 8 / 4 rows whose windows fit the LDS
+  // budget and whose reconstructed values (NP x TY/4 per lane) fit a register
+  // budget of 48
+  static constexpr int REGW = SZ == 8 ? 2 : 1;
+  static constexpr bool tile_ok(int ty) {
+    return NP * dwords_per_plane(ty) * 4 <= LDS_BUDGET && NP * (ty / 4) * REGW <= 48;
+  }
+  static constexpr int TY = tile_ok(16) ? 16 : (tile_ok(8) ? 8 : 4);
   static constexpr int R = TY / 4;
   static constexpr int PD = dwords_per_plane(TY);     // LDS dwords per plane window
   static constexpr int M = PD / 256;                    // DMA instructions per wave per plane
@@ -157,33 +166,30 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
 
   const C rho0 = (C)tab->rho0;
   const C gsc0 = (C)(tab->gfac * tab->rho0 * tab->T0);
-  // 2. moments
+  // 2. reconstruction and moments
   C rho[R], jx[R], jy[R], en[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) { rho[r] = C(0); jx[r] = C(0); jy[r] = C(0); en[r] = C(0); }
+  C ftk[NP][R];   // reconstructed populations (storage domain)
   auto pass1 = [&]<int K>() {
     constexpr int i = K % Q, a = i % N, b = i / N;
-    C ft[R];
-    recon.template operator()<K>(ft);
+    recon.template operator()<K>(ftk[K]);
     const C W = tsel<C>(L.w[a], L.wf[a]) * tsel<C>(L.w[b], L.wf[b]);
     const C cx = tsel<C>(L.c[a], L.cf[a]), cy = tsel<C>(L.c[b], L.cf[b]);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if constexpr (K < Q) {
-        const C f = T::dev ? rho0 * W * (C(1) + ft[r]) : ft[r];
+        const C f = T::dev ? rho0 * W * (C(1) + ftk[K][r]) : ftk[K][r];
         rho[r] += f;
         jx[r] += cx * f;
         jy[r] += cy * f;
         if (TH) en[r] += C(0.5) * (cx * cx + cy * cy) * f;
       } else {
-        en[r] += T::dev ? gsc0 * W * (C(1) + ft[r]) : ft[r];
+        en[r] += T::dev ? gsc0 * W * (C(1) + ftk[K][r]) : ftk[K][r];
       }
     }
   };
   msl_for_planes<NP>(pass1);
-  // LDS is re-read in pass 2: without this barrier the compiler would keep
-  // every reconstructed value of pass 1 in registers to reuse it
-  __syncthreads();
 
   // 3. equilibrium factors per cell, in FP64 (no rounding bias in the
   //    equilibrium's mass and momentum), kept in the compute precision
@@ -203,8 +209,10 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
       Py[r][q] = (C)py[q];
     }
     om[r] = tsel<C>(tab->omega, tab->omegaf);
+    // temperature-dependent viscosity mu = mu_ref (T / T_ref)^s, tau = mu / (rho T dt)
+    // + 1/2 (athermal: T = 1, the power is a table constant)
     if (tab->tau_mode == 1) {
-      const double mu = tab->mu_ref * pow(Tm / tab->tau_ref_T, tab->mu_exp);
+      const double mu = TH ? tab->mu_ref * pow(Tm / tab->tau_ref_T, tab->mu_exp) : tab->mu_T1;
       om[r] = (C)(1.0 / (mu / (rd * Tm * tab->dt) + 0.5));
     }
     gf[r] = (C)(tab->gfac * Tm);
@@ -218,24 +226,20 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   }
   auto pass2 = [&]<int K>() {
     constexpr int i = K % Q, a = i % N, b = i / N;
-    C ft[R];
-    recon.template operator()<K>(ft);
     const C W = tsel<C>(L.w[a], L.wf[a]) * tsel<C>(L.w[b], L.wf[b]);
+    // decoded scale of a 16-bit deviation and its reciprocal (one per plane)
+    const C sc = K < Q ? rho0 * W : gsc0 * W;
+    const C isc = T::dev ? C(1) / sc : C(1);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(out + (long long)K * g.plane), (short)0, (int)plane_b, MSL_RSRC_WORD3);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const C feq = Px[r][a] * Py[r][b];
-      C o;
-      if constexpr (K < Q) {
-        const C f = T::dev ? rho0 * W * (C(1) + ft[r]) : ft[r];
-        const C fo = f + om[r] * (feq - f);
-        o = T::dev ? fo / (rho0 * W) - C(1) : fo;
-      } else {
-        const C gv = T::dev ? gsc0 * W * (C(1) + ft[r]) : ft[r];
-        const C go = gv + om[r] * (gf[r] * feq - gv);
-        o = T::dev ? go / (gsc0 * W) - C(1) : go;
-      }
+      const C v = T::dev ? sc * (C(1) + ftk[K][r]) : ftk[K][r];
+      C vo;
+      if constexpr (K < Q) vo = v + om[r] * (feq - v);
+      else vo = v + om[r] * (gf[r] * feq - v);
+      const C o = T::dev ? vo * isc - C(1) : vo;
       const S sv = T::store(o);
       if constexpr (SZ == 8) {
         typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));

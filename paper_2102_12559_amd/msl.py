@@ -263,8 +263,9 @@ class Solver:
     PROFILE_CLASSES = ("ghost_fill", "stream_collide_low", "stream_collide_high",
                        "band_convert", "criterion_switch", "closure")
 
-    def profile(self, enable=True):
-        self._check(lib().msl_profile(self._ctx, int(enable)), "msl_profile")
+    def profile(self, enable=True, every=1):
+        """Time the launches of every `every`-th step (HIP events)."""
+        self._check(lib().msl_profile(self._ctx, int(every) if enable else 0), "msl_profile")
 
     def profile_read(self):
         st = (C.c_double * 24)()

@@ -61,7 +61,8 @@ def compare_pops(s, o, tol, fg=0, rho0=1.0):
         n = s.cfg["n_low"] if which == 0 else s.cfg["n_high"]
         W = weights(s.dim, n)[:, None]
         scale = np.maximum(np.abs(r), rho0 * W * (1.0 if fg == 0 else 0.5))
-        err = np.max(np.abs(g - r) / scale)
+        assert np.all(np.isfinite(g)) and np.all(np.isfinite(r)), "non-finite populations"
+        err = float(np.max(np.abs(g - r) / scale))
         say(f"  set {which} fg {fg}: max rel err {err:.3e} over {sel.sum()} cells")
         worst = max(worst, err)
     assert worst <= tol, f"population parity {worst:.3e} > {tol:.1e}"
@@ -71,6 +72,7 @@ def compare_pops(s, o, tol, fg=0, rho0=1.0):
 def compare_macros(s, o, tol, uscale):
     rg, ug, Tg = [a.cpu().numpy() for a in s.macros()]
     ro, uo, To = o.macros()
+    assert all(np.all(np.isfinite(a)) for a in (rg, ug, Tg, ro, uo, To)), "non-finite macros"
     e_rho = np.max(np.abs(rg - ro))
     e_u = np.max(np.abs(ug - uo)) / uscale
     e_T = np.max(np.abs(Tg - To))
