@@ -62,6 +62,15 @@ def workload(name):
         return dict(cfg=cfg, rho=rho, u=u, T=T, mask=np.zeros((1, N, N), np.uint8),
                     steps=100, desc=f"single D2Q{n*n} lattice 8192x8192 periodic "
                                     f"{STORE_NAMES[store]}")
+    if name.startswith("vortex3d"):
+        # 3D convected vortex + shear slab, 256^3, FP16 deviations, D3Q27 + D3Q64
+        # where Ma > 0.4 (every 20 steps); vortex3d-fp32 for FP32 storage
+        store = inputs.STORE_FP32 if name.endswith("fp32") else inputs.STORE_FP16_DEV
+        w = inputs.vortex_shear_3d(n=256, store=store)
+        w["desc"] = (f"3D vortex (eps 0.05, core 16) + shear slab at Ma 0.6, 256^3 periodic, "
+                     f"{STORE_NAMES[store]}, D3Q27 + D3Q64 where Ma > 0.4 (every 20 steps), "
+                     f"tau 0.6, 2000 steps")
+        return w
     if name == "vortex":
         w = inputs.vortex_c1()
         w["desc"] = "convected vortex 64x64, D2Q9 + D2Q16 disk, fp64"

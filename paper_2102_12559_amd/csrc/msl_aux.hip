@@ -190,17 +190,34 @@ __device__ __forceinline__ long long pass_cells(const Geo &g, int ax, int *ext, 
   return tot;
 }
 
-// periodic and zero-gradient ghosts: one thread per (ghost cell, plane)
+// periodic and zero-gradient ghosts of every axis in one launch: one thread
+// per (ghost cell, plane).  A ghost cell belongs to the pass of its highest
+// out-of-range axis (that axis' ghost layers, lower axes with their ghosts,
+// higher axes interior), so the passes partition the ghost cells.  A cell
+// whose owning face is a copy rule takes the value at the point where every
+// out-of-range coordinate is mapped by its own face's rule (wrap, clamp),
+// except fixed and diffuse faces of lower axes, whose ghost coordinate is
+// kept (constant ghosts, or diffuse ghosts filled earlier in the step): the
+// same values as filling the axes one after the other.
 template <typename S>
-__global__ void k_bc_copy(const Tab *__restrict__ tab, Geo g, int ax, BCArgs b, char *bl, char *bh,
-                          int np0, int np1) {
+__global__ void __launch_bounds__(AUX_BLOCK)
+k_bc_copy(const Tab *__restrict__ tab, Geo g, BCArgs b, char *bl, char *bh, int np0, int np1) {
   const int N[3] = {g.nx, g.ny, g.nz};
-  int ext[3], lo[3];
-  const long long tot = pass_cells(g, ax, ext, lo);
+  long long cnt[3];
+  long long tot = 0;
+  for (int a = 0; a < 3; ++a) {
+    int ext[3], lo[3];
+    cnt[a] = a < g.dim ? pass_cells(g, a, ext, lo) : 0;
+    tot += cnt[a];
+  }
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= tot * (np0 + np1)) return;
-  const long long cellid = t % tot;
+  long long cellid = t % tot;
   const int plane = (int)(t / tot);
+  int ax = 0;
+  while (cellid >= cnt[ax]) cellid -= cnt[ax++];
+  int ext[3], lo[3];
+  pass_cells(g, ax, ext, lo);
   int p[3];
   long long r = cellid;
   for (int a = 0; a < 3; ++a) {
@@ -213,8 +230,12 @@ __global__ void k_bc_copy(const Tab *__restrict__ tab, Geo g, int ax, BCArgs b, 
   const int rule = b.bc[2 * ax + side];
   if (rule != MSL_BC_PERIODIC && rule != MSL_BC_OUTFLOW_ZG) return;
   int q[3] = {p[0], p[1], p[2]};
-  if (rule == MSL_BC_PERIODIC) q[ax] = (q[ax] % N[ax] + N[ax]) % N[ax];
-  else q[ax] = side ? N[ax] - 1 : 0;
+  for (int a = 0; a <= ax; ++a) {
+    if (q[a] >= 0 && q[a] < N[a]) continue;
+    const int ra = b.bc[2 * a + (q[a] < 0 ? 0 : 1)];
+    if (ra == MSL_BC_PERIODIC) q[a] = (q[a] % N[a] + N[a]) % N[a];
+    else if (ra == MSL_BC_OUTFLOW_ZG) q[a] = q[a] < 0 ? 0 : N[a] - 1;
+  }
   S *pl = plane < np0 ? (S *)bl + (long long)plane * g.plane : (S *)bh + (long long)(plane - np0) * g.plane;
   pl[g.idx(p[0], p[1], p[2])] = pl[g.idx(q[0], q[1], q[2])];
 }
@@ -719,25 +740,28 @@ static long long host_pass_cells(const Geo &g, int ax) {
   return tot;
 }
 
-// per step: periodic / zero-gradient copies and diffuse walls, axis by axis
+// per step: diffuse walls (from interior cells), then the periodic and
+// zero-gradient copies of every axis in one launch
 int msl_launch_bc(msl_ctx *c, char *bl, char *bh) {
   BCArgs b;
   bc_args(c, b);
   const Geo &g = c->geo;
   const int np0 = c->Q[0] * (c->cfg.thermal ? 2 : 1);
   const int np1 = c->nlat > 1 ? c->Q[1] * (c->cfg.thermal ? 2 : 1) : 0;
+  long long tot = 0;
+  bool copy = false;
   for (int ax = 0; ax < c->D; ++ax) {
     const int r0 = b.bc[2 * ax], r1 = b.bc[2 * ax + 1];
-    const long long tot = host_pass_cells(g, ax);
-    const bool copy = r0 == MSL_BC_PERIODIC || r0 == MSL_BC_OUTFLOW_ZG || r1 == MSL_BC_PERIODIC ||
-                      r1 == MSL_BC_OUTFLOW_ZG;
-    if (copy)
-      DISPATCH_STORE(c, k_bc_copy, dim3(nblocks(tot * (np0 + np1))), dim3(AUX_BLOCK), c->dtab, g, ax,
-                     b, bl, bh, np0, np1);
+    tot += host_pass_cells(g, ax);
+    copy = copy || r0 == MSL_BC_PERIODIC || r0 == MSL_BC_OUTFLOW_ZG || r1 == MSL_BC_PERIODIC ||
+           r1 == MSL_BC_OUTFLOW_ZG;
     if (r0 == MSL_BC_DIFFUSE_WALL || r1 == MSL_BC_DIFFUSE_WALL)
-      DISPATCH_STORE(c, k_bc_diffuse, dim3(nblocks(tot)), dim3(AUX_BLOCK), c->dtab, g, ax, b, bl,
-                     bh, c->cls);
+      DISPATCH_STORE(c, k_bc_diffuse, dim3(nblocks(host_pass_cells(g, ax))), dim3(AUX_BLOCK), c->dtab,
+                     g, ax, b, bl, bh, c->cls);
   }
+  if (copy)
+    DISPATCH_STORE(c, k_bc_copy, dim3(nblocks(tot * (np0 + np1))), dim3(AUX_BLOCK), c->dtab, g, b, bl,
+                   bh, np0, np1);
   return last_err();
 }
 

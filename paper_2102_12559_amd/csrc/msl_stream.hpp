@@ -1,7 +1,11 @@
 // msl_stream.hpp -- the fused stream-and-collide kernel, one instantiation per
 // (dimension, velocity-set order, storage precision, thermal model).
 //
-// One workgroup owns a tile of 64 x TY cells (2D) or 64 x 4 x TZ cells (3D).
+// This file holds the register-staged 2D kernel used where the LDS-resident
+// one (msl_stream2.hpp) does not fit, and the launcher; 3D runs use the
+// chunked kernel of msl_stream3.hpp.
+//
+// One workgroup owns a tile of 64 x TY cells.
 // For each population plane (f_0..f_{Q-1}, then g_0..g_{Q-1}) the workgroup
 // stages the plane's (64+2) x (TY+2) neighbourhood of the departure points into
 // LDS -- the departure offset x - c_i dt is the same for every cell of a plane,
@@ -19,6 +23,7 @@
 
 #include "msl_device.hpp"
 #include "msl_stream2.hpp"
+#include "msl_stream3.hpp"
 
 template <typename S, bool TH, int N, int D>
 struct SCTraits {
@@ -220,93 +225,6 @@ k_sc2d(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in, S 
   collide_store<S, TH, N, 2, R, NP>(tab, lat, g, ft, out, cls, x0 + tx, y0 + ty * R, 0, 1, 0);
 }
 
-// 3D: tile 64 x 4 x TZ; each thread owns one (x, y) column of TZ cells.
-template <typename S, bool TH, int N>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCTraits<S, TH, N, 3>::WAVES)))
-k_sc3d(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in, S *__restrict__ out,
-       const uint8_t *__restrict__ cls, const uint8_t *__restrict__ tflag) {
-  using Tr = SCTraits<S, TH, N, 3>;
-  using T = typename Tr::T;
-  using C = typename Tr::C;
-  constexpr int Q = Tr::Q, NP = Tr::NP, R = Tr::R;
-  constexpr int TZ = R;
-  constexpr int LW = MSL_TX + 2, LY = MSL_MTY + 2, LZ = TZ + 2;
-  constexpr int NE = LW * LY * LZ, NLD = (NE + 255) / 256;
-  __shared__ C sm[2][NE];
-  const LatTab &L = tab->lat[lat];
-  const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
-  const int x0 = bx * MSL_TX, y0 = by * MSL_MTY, z0 = bz * TZ;
-  {
-    uint8_t any = 0;
-#pragma unroll
-    for (int r = 0; r < TZ; ++r) {
-      const int mz = z0 + r;
-      if (mz < g.ntz) any |= tflag[((long long)mz * g.nty + by) * g.ntx + bx];
-    }
-    if (!(any & (1 << lat))) return;
-  }
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  int eoff[NLD];
-#pragma unroll
-  for (int m = 0; m < NLD; ++m) {
-    int e = threadIdx.x + 256 * m;
-    e = e < NE ? e : NE - 1;
-    const int rz = e / (LW * LY), rem = e - rz * (LW * LY);
-    const int ry = rem / LW, rx = rem - ry * LW;
-    eoff[m] = ((rz * g.rows + ry) * g.pitch + rx) * (int)sizeof(S);   // byte offset
-  }
-  C ft[NP][R];
-  C reg[NLD];
-  auto gload = [&]<int K>() {
-    constexpr int i = K % Q, a = i % N, b = (i / N) % N, cc = i / (N * N);
-    const int ox = L.n0[a] - 1, oy = L.n0[b] - 1, oz = L.n0[cc] - 1;
-    const S *base = in + (long long)K * g.plane + g.idx(x0 + ox, y0 + oy, z0 + oz);
-#pragma unroll
-    for (int m = 0; m < NLD; ++m)
-      reg[m] = (C)T::load(*(const S *)((const char *)base + (unsigned)eoff[m]));
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int m = 0; m < NLD; ++m) {
-      const int e = threadIdx.x + 256 * m;
-      if (NE % 256 == 0 || m + 1 < NLD || e < NE) sm[buf][e] = reg[m];
-    }
-  };
-  auto step = [&]<int K>() {
-    if constexpr (K + 1 < NP) gload.template operator()<K + 1>();
-    constexpr int i = K % Q, a = i % N, b = (i / N) % N, cc = i / (N * N);
-    constexpr int buf = K & 1;
-    C wx[3], wy[3], wz[3];
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      wx[s] = tsel<C>(L.a[a][s], L.af[a][s]);
-      wy[s] = tsel<C>(L.a[b][s], L.af[b][s]);
-      wz[s] = tsel<C>(L.a[cc][s], L.af[cc][s]);
-    }
-    // differenced form along each axis (centre weight 1 - w0 - w2 exactly)
-    C hz[R + 2];
-#pragma unroll
-    for (int rz = 0; rz < R + 2; ++rz) {
-      C hy[3];
-#pragma unroll
-      for (int sy = 0; sy < 3; ++sy) {
-        const C *row = &sm[buf][(rz * LY + ty + sy) * LW + tx];
-        hy[sy] = row[1] + wx[0] * (row[0] - row[1]) + wx[2] * (row[2] - row[1]);
-      }
-      hz[rz] = hy[1] + wy[0] * (hy[0] - hy[1]) + wy[2] * (hy[2] - hy[1]);
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) ft[K][r] = hz[r + 1] + wz[0] * (hz[r] - hz[r + 1]) + wz[2] * (hz[r + 2] - hz[r + 1]);
-    if constexpr (K + 1 < NP) lstore((K + 1) & 1);
-    __syncthreads();
-  };
-  gload.template operator()<0>();
-  lstore(0);
-  __syncthreads();
-  for_planes<NP>(step);
-  collide_store<S, TH, N, 3, R, NP>(tab, lat, g, ft, out, cls, x0 + tx, y0 + ty, z0, 0, 1);
-}
-
 template <typename S, bool TH, int N, int D>
 static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
   using Tr = SCTraits<S, TH, N, D>;
@@ -323,9 +241,9 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
     hipLaunchKernelGGL((k_sc2d<S, TH, N>), grid, block, 0, c->stream, c->dtab, lat, g,
                        (const S *)in, (S *)out, c->cls, c->tflag);
   } else {
-    dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + MSL_MTY - 1) / MSL_MTY,
-              (g.nz + Tr::R - 1) / Tr::R);
-    hipLaunchKernelGGL((k_sc3d<S, TH, N>), grid, block, 0, c->stream, c->dtab, lat, g,
+    // 3D: planes streamed through LDS in chunks
+    dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + MSL_MTY - 1) / MSL_MTY, g.nz);
+    hipLaunchKernelGGL((k_sc3d_res<S, TH, N>), grid, block, 0, c->stream, c->dtab, lat, g,
                        (const S *)in, (S *)out, c->cls, c->tflag);
   }
   return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
