@@ -674,7 +674,12 @@ static void mlp_predict(const or_ctx *c, const double *fq, const double *gq, dou
   const lat_t *Lq = c->lat[0], *LQ = c->lat[1];
   double feat[64], x[64], y[256];
   mlp_features_lat(Lq, c->cfg.thermal, c->cfg.cv, fq, gq, feat);
-  for (int k = 0; k < c->mlp_F; k++) x[k] = (feat[k] - c->xm[k]) / c->xs[k];
+  /* standardised features, limited to +-8 standard deviations: a state far
+   * outside the training data gets a bounded input instead of an arbitrary one */
+  for (int k = 0; k < c->mlp_F; k++) {
+    double v = (feat[k] - c->xm[k]) / c->xs[k];
+    x[k] = v > 8.0 ? 8.0 : (v < -8.0 ? -8.0 : v);
+  }
   mlp_forward_one(c->mlp_p, c->mlp_F, c->mlp_H, c->mlp_O, x, y, c->mlp_bf16 & 1);
   double rho, u[3], T;
   lat_macros(Lq, c->cfg.thermal, c->cfg.cv, fq, gq, &rho, u, &T);
@@ -723,7 +728,8 @@ int or_lift_cell(const or_ctx *c, const double *fq, const double *gq, int tile,
  * missing moments from their projected low-order state; per check tile, the
  * network is kept only if its squared error is below that of Grad lifting
  * (which predicts no non-equilibrium part).  Tiles without such cells follow
- * the total over the domain. */
+ * the total over the domain.  Ties, including an exactly equilibrium state
+ * where both errors vanish, go to Grad lifting. */
 int or_mlp_check(or_ctx *c) {
   if (!c->mlp_on) return -1;
   const int D = c->D, R = c->reach, O = c->mlp_O;
@@ -764,7 +770,7 @@ int or_mlp_check(or_ctx *c) {
   double em = 0, eg = 0;
   for (int t = 0; t < c->ntiles; t++) { em += c->emlp[t]; eg += c->egrad[t]; }
   for (int t = 0; t < c->ntiles; t++)
-    c->flags[t] = has[t] ? (c->emlp[t] < c->egrad[t]) : (eg == 0.0 ? 1 : (em < eg));
+    c->flags[t] = has[t] ? (c->emlp[t] < c->egrad[t]) : (em < eg);
   free(has);
   return 0;
 }

@@ -34,13 +34,19 @@ def init_params(F, H, O, seed=0):
     return np.concatenate(out).astype(np.float32)
 
 
+XSTD_FLOOR = 1e-3   # features are dimensionless, of order 0.01 to 1
+XCLIP = 8.0         # standardised features are limited to +-8 (as in the library)
+
+
 def standardize(X, Y):
-    """Column means and standard deviations (zero spread -> 1)."""
+    """Column means and standard deviations.  A feature that hardly varies in
+    the training data (u_z of a columnar flow) gets a spread of at least
+    XSTD_FLOOR, so that a small change of it in use does not become a huge
+    network input; targets with no spread get 1."""
     xm = X.mean(axis=0)
-    xs = X.std(axis=0)
+    xs = np.maximum(X.std(axis=0), XSTD_FLOOR)
     ym = Y.mean(axis=0)
     ys = Y.std(axis=0)
-    xs[xs < 1e-12] = 1.0
     ys[ys < 1e-12] = 1.0
     return (xm.astype(np.float32), xs.astype(np.float32), ym.astype(np.float32),
             ys.astype(np.float32))
@@ -79,13 +85,41 @@ def collect_snapshots(cases, times, n_high=6, hidden=64):
     return np.concatenate(Xs), np.concatenate(Ys)
 
 
+def snapshots_of_run(w, times, max_rows=None):
+    """Snapshots of a run of workload `w` on the high-order set everywhere
+    (its mask is replaced by all ones and its criterion switched off; the
+    configuration must use the learned lift so that the closure buffers
+    exist): features and targets of every
+    cell after each number of steps in `times` (ascending), at most
+    `max_rows` per time (every k-th cell in cell order).  Host float32."""
+    s = msl.Solver(dict(w["cfg"], crit_kind=inputs.CRIT_NONE))   # stays on the high-order set
+    s.set_mask(np.ones_like(w["mask"]))
+    s.init(w["rho"], w["u"], w["T"])
+    Xs, Ys = [], []
+    done = 0
+    for t in times:
+        s.step(t - done)
+        done = t
+        X, Y = s.collect_snapshots(s.ncell)
+        X, Y = X.cpu().numpy(), Y.cpu().numpy()
+        if max_rows and X.shape[0] > max_rows:
+            k = -(-X.shape[0] // max_rows)
+            X, Y = X[::k], Y[::k]
+        Xs.append(X)
+        Ys.append(Y)
+    s.close()
+    return np.concatenate(Xs), np.concatenate(Ys)
+
+
 def train(X, Y, *, epochs=50, batch=1024, lr=1e-3, hidden=64, seed=0, n_high=6, val_frac=0.1,
-          schedule=None):
+          schedule=None, cfg=None):
     """Train the closure on the GPU.  Rows are shuffled with the seeded
     generator and split into training and validation parts.  `schedule`, a
     list of (epochs, learning rate) phases run one after the other with the
-    optimiser state carried over, replaces (epochs, lr).  Returns a dict with
-    the parameters, standardisation statistics and loss history."""
+    optimiser state carried over, replaces (epochs, lr).  `cfg` is the
+    configuration whose network shape is trained (default: the 2D D2Q9/D2Q36
+    Couette case).  Returns a dict with the parameters, standardisation
+    statistics and loss history."""
     import torch
     rows = X.shape[0]
     order = np.argsort(inputs.uniform_pm1(seed + 17, rows), kind="stable")
@@ -94,20 +128,21 @@ def train(X, Y, *, epochs=50, batch=1024, lr=1e-3, hidden=64, seed=0, n_high=6, 
     nval = int(round(val_frac * rows))
     Xt, Yt, Xv, Yv = X[nval:], Y[nval:], X[:nval], Y[:nval]
     xm, xs, ym, ys = standardize(Xt.astype(np.float64), Yt.astype(np.float64))
-    w = couette_case(32, 0.1, n_high=n_high, lift_mode=inputs.LIFT_MLP, hidden=hidden)
-    s = msl.Solver(w["cfg"])
+    if cfg is None:
+        cfg = couette_case(32, 0.1, n_high=n_high, lift_mode=inputs.LIFT_MLP, hidden=hidden)["cfg"]
+    s = msl.Solver(cfg)
     F, O, H, P = s.mlp_dims()
     p0 = init_params(F, H, O, seed=seed)
     s.mlp_set_weights(p0, xm, xs, ym, ys)
     dev = s.device
-    Xn = torch.as_tensor((Xt - xm) / xs, dtype=torch.float32, device=dev)
+    Xn = torch.as_tensor(np.clip((Xt - xm) / xs, -XCLIP, XCLIP), dtype=torch.float32, device=dev)
     Yn = torch.as_tensor((Yt - ym) / ys, dtype=torch.float32, device=dev)
     phases = schedule if schedule else [(epochs, lr)]
     log = np.concatenate([s.mlp_train(Xn, Yn, batch=batch, epochs=e, lr=r) for e, r in phases])
     params = s.mlp_get_weights()
     val = None
     if nval:
-        Xvn = torch.as_tensor((Xv - xm) / xs, dtype=torch.float32, device=dev)
+        Xvn = torch.as_tensor(np.clip((Xv - xm) / xs, -XCLIP, XCLIP), dtype=torch.float32, device=dev)
         pred = s.mlp_forward(Xvn).cpu().numpy()
         val = float(np.mean((pred - (Yv - ym) / ys) ** 2))
     s.close()

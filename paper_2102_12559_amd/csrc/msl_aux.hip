@@ -201,28 +201,31 @@ __device__ __forceinline__ long long pass_cells(const Geo &g, int ax, int *ext, 
 // same values as filling the axes one after the other.
 template <typename S>
 __global__ void __launch_bounds__(AUX_BLOCK)
-k_bc_copy(const Tab *__restrict__ tab, Geo g, BCArgs b, char *bl, char *bh, int np0, int np1) {
+k_bc_copy(const Tab *__restrict__ tab, Geo g, BCArgs b, char *bl, char *bh, int np0) {
+  // blockIdx.y: plane; x: ghost cell, passes in axis order (32-bit indexing:
+  // the ghost layers of any admissible grid hold fewer than 2^31 cells)
   const int N[3] = {g.nx, g.ny, g.nz};
-  long long cnt[3];
-  long long tot = 0;
-  for (int a = 0; a < 3; ++a) {
-    int ext[3], lo[3];
-    cnt[a] = a < g.dim ? pass_cells(g, a, ext, lo) : 0;
-    tot += cnt[a];
+  int ext[3][3], lo[3][3], cnt[3] = {0, 0, 0};
+  for (int a = 0; a < g.dim; ++a) {
+    cnt[a] = 1;
+    for (int e = 0; e < 3; ++e) {
+      if (e >= g.dim) { ext[a][e] = 1; lo[a][e] = 0; }
+      else if (e < a) { ext[a][e] = N[e] + 2 * MSL_G; lo[a][e] = -MSL_G; }
+      else if (e == a) { ext[a][e] = 2 * MSL_G; lo[a][e] = 0; }
+      else { ext[a][e] = N[e]; lo[a][e] = 0; }
+      cnt[a] *= ext[a][e];
+    }
   }
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= tot * (np0 + np1)) return;
-  long long cellid = t % tot;
-  const int plane = (int)(t / tot);
+  int cellid = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (cellid >= cnt[0] + cnt[1] + cnt[2]) return;
+  const int plane = (int)blockIdx.y;
   int ax = 0;
   while (cellid >= cnt[ax]) cellid -= cnt[ax++];
-  int ext[3], lo[3];
-  pass_cells(g, ax, ext, lo);
   int p[3];
-  long long r = cellid;
-  for (int a = 0; a < 3; ++a) {
-    p[a] = lo[a] + (int)(r % ext[a]);
-    r /= ext[a];
+  int r = cellid;
+  for (int e = 0; e < 3; ++e) {
+    p[e] = lo[ax][e] + r % ext[ax][e];
+    r /= ext[ax][e];
   }
   const int gi = p[ax];
   const int side = gi < MSL_G ? 0 : 1;
@@ -233,7 +236,7 @@ k_bc_copy(const Tab *__restrict__ tab, Geo g, BCArgs b, char *bl, char *bh, int 
   for (int a = 0; a <= ax; ++a) {
     if (q[a] >= 0 && q[a] < N[a]) continue;
     const int ra = b.bc[2 * a + (q[a] < 0 ? 0 : 1)];
-    if (ra == MSL_BC_PERIODIC) q[a] = (q[a] % N[a] + N[a]) % N[a];
+    if (ra == MSL_BC_PERIODIC) q[a] = q[a] < 0 ? q[a] + N[a] : q[a] - N[a];
     else if (ra == MSL_BC_OUTFLOW_ZG) q[a] = q[a] < 0 ? 0 : N[a] - 1;
   }
   S *pl = plane < np0 ? (S *)bl + (long long)plane * g.plane : (S *)bh + (long long)(plane - np0) * g.plane;
@@ -386,43 +389,57 @@ __global__ void k_band_convert(const Tab *__restrict__ tab, Geo g, char *bl, cha
 // ---------------------------------------------------------------------------
 // refinement criterion, switching, classes, tiles, band compaction
 // ---------------------------------------------------------------------------
-template <typename S>
-__global__ void k_criterion(const Tab *__restrict__ tab, Geo g, const char *bl, const char *bh,
-                            const uint8_t *__restrict__ cls, uint8_t *__restrict__ newmask,
-                            int kind, double thr) {
+// criterion value of one cell of order N: local Mach number |u| / c_s, or the
+// Frobenius norm of the non-equilibrium central second moment over p = rho T
+template <typename S, int D, int N, bool TH>
+__device__ __forceinline__ double crit_value(const Tab *tab, const Geo &g, const char *base, int l,
+                                             int off, int kind) {
+  constexpr int Q = Pow<D, N>::v;
+  const LatTab &L = tab->lat[l];
+  double f[Q], gg[TH ? Q : 1], rho, u[3], T;
+  read_cell_t<S, D, N, TH>(tab, g, base, l, off, f, gg);
+  macros_t<D, N>(L, TH && tab->thermal, tab->cv, f, gg, rho, u, T);
+  if (kind == MSL_CRIT_MA) {
+    const double gam = (tab->cv + 1.0) / tab->cv;
+    const double cs = TH && tab->thermal ? sqrt(gam * T) : 1.0;
+    return sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / cs;
+  }
+  double P[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double c[3] = {L.c[i % N], L.c[(i / N) % N], D == 3 ? L.c[i / (N * N)] : 0.0};
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int bb = 0; bb < D; ++bb) P[a][bb] += (c[a] - u[a]) * (c[bb] - u[bb]) * f[i];
+  }
+  const double p = rho * T;
+  double s = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int bb = 0; bb < D; ++bb) {
+      const double d = P[a][bb] - (a == bb ? p : 0.0);
+      s += d * d;
+    }
+  return sqrt(s) / p;
+}
+
+// refinement criterion of every cell (Sec. III.A), from its own populations
+template <typename S, int D, int NL, int NH, bool TH>
+__global__ void __launch_bounds__(AUX_BLOCK)
+k_criterion_t(const Tab *__restrict__ tab, Geo g, const char *bl, const char *bh,
+              const uint8_t *__restrict__ cls, uint8_t *__restrict__ newmask, int kind, double thr) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= g.ncell) return;
   int x, y, z;
   cell_coords(g, k, x, y, z);
-  const int l = cls[k] & 1;
-  const LatTab &L = tab->lat[l];
-  double f[MSL_MAXQ], gg[MSL_MAXQ], rho, u[3], T;
-  read_cell<S>(tab, g, l ? bh : bl, l, g.idx(x, y, z), f, gg);
-  cell_macros(L, g.dim, tab->thermal, tab->cv, f, gg, rho, u, T);
-  double v = 0;
-  if (kind == MSL_CRIT_MA) {
-    const double gam = (tab->cv + 1.0) / tab->cv;
-    const double cs = tab->thermal ? sqrt(gam * T) : 1.0;
-    v = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / cs;
-  } else {
-    double P[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    const int n = L.n;
-    for (int i = 0; i < L.Q; ++i) {
-      const double c[3] = {L.c[i % n], L.c[(i / n) % n], g.dim == 3 ? L.c[i / (n * n)] : 0.0};
-      for (int a = 0; a < g.dim; ++a)
-        for (int bb = 0; bb < g.dim; ++bb) P[a][bb] += (c[a] - u[a]) * (c[bb] - u[bb]) * f[i];
-    }
-    const double p = rho * T;
-    double s = 0;
-    for (int a = 0; a < g.dim; ++a)
-      for (int bb = 0; bb < g.dim; ++bb) {
-        const double d = P[a][bb] - (a == bb ? p : 0.0);
-        s += d * d;
-      }
-    v = sqrt(s) / p;
-  }
+  const int off = g.idx(x, y, z);
+  const double v = (cls[k] & 1) ? crit_value<S, D, NH, TH>(tab, g, bh, 1, off, kind)
+                                : crit_value<S, D, NL, TH>(tab, g, bl, 0, off, kind);
   newmask[k] = v > thr ? 1 : 0;
 }
+
 
 __global__ void k_mask_out(const uint8_t *__restrict__ cls, long long n, uint8_t *__restrict__ m) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -462,32 +479,41 @@ __global__ void k_switch(const Tab *__restrict__ tab, Geo g, char *bl, char *bh,
   cls[k] = (uint8_t)to;
 }
 
-// band bit: a cell of one order within the stencil reach (Chebyshev distance
-// <= G, through periodic wrap, clamped at other faces) of a cell of the other
+// class bytes of a run with one velocity set: no band cells
 __global__ void k_classify(Geo g, int bc_periodic_mask, uint8_t *__restrict__ cls) {
+  (void)bc_periodic_mask;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < g.ncell) cls[k] = (uint8_t)(cls[k] & 1);
+}
+
+// Band classification by separable box extrema: a cell is a band cell when a
+// cell of the other order lies within Chebyshev distance MSL_G (the stencil
+// reach), i.e. when the maximum and the minimum of the order bit over the box
+// of +-MSL_G cells differ.  One pass per axis (periodic faces wrap, the others
+// clamp to the boundary cell); a pass writes code = max << 1 | min, the last
+// one sets bit 1 of the class byte.
+__global__ void k_order_extrema(Geo g, int ax, int bc_periodic_mask, const uint8_t *__restrict__ in,
+                                int from_cls, uint8_t *__restrict__ out, int last) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= g.ncell) return;
-  int x, y, z;
-  cell_coords(g, k, x, y, z);
-  const int o = cls[k] & 1;
+  int p[3];
+  cell_coords(g, k, p[0], p[1], p[2]);
   const int N[3] = {g.nx, g.ny, g.nz};
-  int band = 0;
-  const int R = MSL_G;
-  const int zr = g.dim == 3 ? R : 0;
-  for (int dz = -zr; dz <= zr && !band; ++dz)
-    for (int dy = -R; dy <= R && !band; ++dy)
-      for (int dx = -R; dx <= R && !band; ++dx) {
-        int q[3] = {x + dx, y + dy, z + dz};
-        for (int a = 0; a < g.dim; ++a) {
-          if (q[a] >= 0 && q[a] < N[a]) continue;
-          const int side = q[a] < 0 ? 0 : 1;
-          if (bc_periodic_mask & (1 << (2 * a + side))) q[a] = (q[a] % N[a] + N[a]) % N[a];
-          else q[a] = side ? N[a] - 1 : 0;
-        }
-        const long long kk = ((long long)q[2] * g.ny + q[1]) * g.nx + q[0];
-        if ((cls[kk] & 1) != o) band = 1;
-      }
-  cls[k] = (uint8_t)(o | (band << 1));
+  const long long stride = ax == 0 ? 1 : (ax == 1 ? (long long)g.nx : (long long)g.nx * g.ny);
+  int mx = 0, mn = 1;
+  for (int d = -MSL_G; d <= MSL_G; ++d) {
+    int q = p[ax] + d;
+    if (q < 0 || q >= N[ax]) {
+      const int side = q < 0 ? 0 : 1;
+      if (bc_periodic_mask & (1 << (2 * ax + side))) q = (q % N[ax] + N[ax]) % N[ax];
+      else q = side ? N[ax] - 1 : 0;
+    }
+    const uint8_t v = in[k + (long long)(q - p[ax]) * stride];
+    mx |= from_cls ? (v & 1) : ((v >> 1) & 1);
+    mn &= v & 1;
+  }
+  if (last) out[k] = (uint8_t)((out[k] & 1) | ((mx != mn) << 1));
+  else out[k] = (uint8_t)((mx << 1) | mn);
 }
 
 // per micro-tile (64 x 4 (x 1)) presence of each order
@@ -760,8 +786,8 @@ int msl_launch_bc(msl_ctx *c, char *bl, char *bh) {
                      g, ax, b, bl, bh, c->cls);
   }
   if (copy)
-    DISPATCH_STORE(c, k_bc_copy, dim3(nblocks(tot * (np0 + np1))), dim3(AUX_BLOCK), c->dtab, g, b, bl,
-                   bh, np0, np1);
+    DISPATCH_STORE(c, k_bc_copy, dim3(nblocks(tot), np0 + np1), dim3(AUX_BLOCK), c->dtab, g, b, bl, bh,
+                   np0);
   return last_err();
 }
 
@@ -876,11 +902,31 @@ int msl_launch_band_convert(msl_ctx *c, char *bl, char *bh) {
   return MSL_EINVAL;
 }
 
+template <typename S>
+static int criterion_s(msl_ctx *c) {
+  return msl_pair_dispatch(c->D, c->htab.lat[0].n, c->htab.lat[1].n, [&]<int D, int NL, int NH>() {
+    const char *bl = c->planes[0][c->cur], *bh = c->planes[1][c->cur];
+    if (c->cfg.thermal)
+      hipLaunchKernelGGL((k_criterion_t<S, D, NL, NH, true>), dim3(nblocks(c->ncell)), dim3(AUX_BLOCK),
+                         0, c->stream, c->dtab, c->geo, bl, bh, c->cls, c->newmask,
+                         c->cfg.crit_kind, c->cfg.crit_thr);
+    else
+      hipLaunchKernelGGL((k_criterion_t<S, D, NL, NH, false>), dim3(nblocks(c->ncell)),
+                         dim3(AUX_BLOCK), 0, c->stream, c->dtab, c->geo, bl, bh, c->cls, c->newmask,
+                         c->cfg.crit_kind, c->cfg.crit_thr);
+    return last_err();
+  });
+}
+
 int msl_launch_criterion(msl_ctx *c) {
-  DISPATCH_STORE(c, k_criterion, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), c->dtab, c->geo,
-                 c->planes[0][c->cur], c->nlat > 1 ? c->planes[1][c->cur] : nullptr, c->cls,
-                 c->newmask, c->cfg.crit_kind, c->cfg.crit_thr);
-  return last_err();
+  if (c->nlat < 2) return MSL_OK;   // nothing to switch to
+  switch (c->cfg.store) {
+    case MSL_FP64: return criterion_s<double>(c);
+    case MSL_FP32: return criterion_s<float>(c);
+    case MSL_FP16_DEV: return criterion_s<_Float16>(c);
+    case MSL_BF16_DEV: return criterion_s<bf16_t>(c);
+  }
+  return MSL_EINVAL;
 }
 
 int msl_launch_check_mask(msl_ctx *c, const uint8_t *mask) {
@@ -916,8 +962,23 @@ int msl_launch_classify(msl_ctx *c) {
   int pm = 0;
   for (int f = 0; f < 2 * c->D; ++f)
     if (c->cfg.bc[f] == MSL_BC_PERIODIC) pm |= 1 << f;
-  hipLaunchKernelGGL(k_classify, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), 0, c->stream, c->geo, pm,
-                     c->cls);
+  if (c->nlat < 2) {
+    hipLaunchKernelGGL(k_classify, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), 0, c->stream, c->geo, pm,
+                       c->cls);
+  } else {
+    // separable passes through two byte buffers that are free at this point
+    // (the criterion's new mask has been applied; the band lists are rebuilt
+    // below)
+    uint8_t *t[2] = {c->newmask, (uint8_t *)c->blist[0]};
+    const uint8_t *src = c->cls;
+    for (int ax = 0; ax < c->D; ++ax) {
+      const int last = ax == c->D - 1;
+      uint8_t *dst = last ? c->cls : t[ax & 1];
+      hipLaunchKernelGGL(k_order_extrema, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), 0, c->stream,
+                         c->geo, ax, pm, src, ax == 0, dst, last);
+      src = dst;
+    }
+  }
   const Geo &g = c->geo;
   const long long nt = (long long)g.ntx * g.nty * g.ntz;
   hipLaunchKernelGGL(k_tileflags, dim3((unsigned)nt), dim3(64), 0, c->stream, g, c->cls, c->tflag);

@@ -39,6 +39,14 @@ __device__ __forceinline__ float silu_d(float z) {
 // features and targets (FP64)
 // ---------------------------------------------------------------------------
 
+// standardised feature, limited to +-8 standard deviations: a state far
+// outside the training data gets a bounded input instead of an arbitrary one
+#define MSL_MLP_XCLIP 8.0
+__device__ __forceinline__ double std_feature(double v, float mean, float sd) {
+  const double z = (v - mean) / sd;
+  return z > MSL_MLP_XCLIP ? MSL_MLP_XCLIP : (z < -MSL_MLP_XCLIP ? -MSL_MLP_XCLIP : z);
+}
+
 // number of features (rho, u, T and the low-order moments of degree >= 2) and
 // of outputs (the raw moments the low-order set cannot hold)
 template <int D, int NL>
@@ -569,7 +577,7 @@ k_band_features(const Tab *__restrict__ tab, Geo g, const char *bl, const int *_
     read_cell_t<S, D, NL, TH>(tab, g, bl, 0, g.idx(x, y, z), f, gg);
     features_t<D, NL, TH>(tab, f, gg, ft);
 #pragma unroll
-    for (int a = 0; a < F; ++a) feat[t * F + a] = (float)((ft[a] - stats[a]) / stats[F + a]);
+    for (int a = 0; a < F; ++a) feat[t * F + a] = (float)std_feature(ft[a], stats[a], stats[F + a]);
   }
 }
 
@@ -635,7 +643,7 @@ k_check_prepare(const Tab *__restrict__ tab, Geo g, const char *bh, const int *_
     features_t<D, NL, TH>(tab, fq, gq, ft);
     targets_t<D, NL, NH, TH>(tab, fQ, gQ, tt);
 #pragma unroll
-    for (int a = 0; a < F; ++a) feat[t * F + a] = (float)((ft[a] - stats[a]) / stats[F + a]);
+    for (int a = 0; a < F; ++a) feat[t * F + a] = (float)std_feature(ft[a], stats[a], stats[F + a]);
 #pragma unroll
     for (int a = 0; a < O; ++a) tgt[t * O + a] = (float)tt[a];
   }
@@ -720,7 +728,8 @@ k_check_tiles(Geo g, const int *__restrict__ list, const int *__restrict__ count
 
 // stage 4: the flags.  A tile uses the network where its summed error is below
 // the Grad completion's; tiles without high-order band cells follow the totals
-// over the domain.  One block, fixed-order sums.
+// over the domain; ties (an equilibrium state, where both vanish) go to Grad.
+// One block, fixed-order sums.
 __global__ void __launch_bounds__(256)
 k_check_flags(int ntile, const double *__restrict__ terr, uint8_t *__restrict__ flags) {
   __shared__ double rem[256], reg[256];
@@ -743,7 +752,7 @@ k_check_flags(int ntile, const double *__restrict__ terr, uint8_t *__restrict__ 
   const double tm = rem[0], tg = reg[0];
   for (int tl = threadIdx.x; tl < ntile; tl += blockDim.x) {
     const bool has = terr[2 * tl + 1] >= 0;
-    flags[tl] = has ? (terr[2 * tl] < terr[2 * tl + 1]) : (tg == 0.0 ? 1 : (tm < tg));
+    flags[tl] = has ? (terr[2 * tl] < terr[2 * tl + 1]) : (tm < tg);
   }
 }
 

@@ -210,3 +210,49 @@ def test_error_check_flags_match_oracle():
     decisive = np.abs(em - eg) > 0.05 * np.maximum(eg, 1e-300)
     say(f"  flags gpu {fg.tolist()} oracle {fo.tolist()} decisive {decisive.sum()}/{fo.size}")
     assert np.array_equal(fg[decisive], fo[decisive])
+
+
+def test_learned_lift_3d_matches_oracle():
+    """3D (D3Q27 / D3Q64) run with the learned lift on every tile against the
+    oracle running the same network with BF16 operands."""
+    from paper_2102_12559_amd import msl
+    from oracle.oracle import Oracle
+    n = 14
+    cfg = inputs.base_config(dim=3, nx=n, ny=n, nz=n, n_low=3, n_high=4, lift_mode=inputs.LIFT_MLP,
+                             store=inputs.STORE_FP64, tau=0.7)
+    rho, u, T = inputs.smooth_random_flow(n, n, n, umax=0.2, seed=13, drho=0.02)
+    mask = np.zeros((n, n, n), np.uint8)
+    mask[:, 4:9, :] = 1
+    say("[case] learned lift 3D run")
+    s = msl.Solver(cfg)
+    F, Od, H, P = s.mlp_dims()
+    assert (F, Od) == (28, 37)
+    p = (closure.init_params(F, H, Od, seed=17) * 0.5).astype(np.float32)
+    xm = np.zeros(F, np.float32); xm[0] = 1.0
+    xs = np.full(F, 0.5, np.float32)
+    tm = np.zeros(Od, np.float32)
+    ts = np.full(Od, 1e-3, np.float32)
+    s.mlp_set_weights(p, xm, xs, tm, ts)
+    flags = np.ones(s.num_check_tiles(), np.uint8)
+    s.mlp_set_flags(flags)
+    s.set_mask(mask)
+    s.init(rho, u, T)
+    s.step(6)
+    o = Oracle(cfg)
+    o.set_mlp(H, p.astype(np.float64), xm.astype(np.float64), xs.astype(np.float64),
+              tm.astype(np.float64), ts.astype(np.float64), bf16=True, manual_check=True)
+    o.set_mlp_flags(flags)
+    o.set_mask(mask, convert=False)
+    o.init(rho, u, T)
+    o.step(6)
+    m = s.get_mask().cpu().numpy().reshape(-1)
+    worst = 0.0
+    for which in (0, 1):
+        sel = m == which
+        g = s.get_populations(which).cpu().numpy()[:, sel]
+        r = o.get_pops(which)[:, sel]
+        W = weights(3, 3 if which == 0 else 4)[:, None]
+        e = np.max(np.abs(g - r) / np.maximum(np.abs(r), W))
+        say(f"  set {which}: max rel err {e:.3e}")
+        worst = max(worst, e)
+    assert worst < 1e-4
