@@ -52,6 +52,17 @@ __host__ __device__ __forceinline__ void eq_axis_rt(const LatTab &L, double u, d
   }
 }
 
+// XCD-aware tile order.  Workgroups are handed to the 8 XCDs in turn (linear
+// workgroup id modulo 8), and each XCD has its own L2.  Mapping the workgroups
+// an XCD receives onto one contiguous range of tiles (row-major) keeps the
+// halo rows and columns that neighbouring tiles share inside one L2.
+#define MSL_NXCD 8
+__device__ __forceinline__ int msl_xcd_tile(int b, int nb) {
+  const int per = nb / MSL_NXCD, rem = nb % MSL_NXCD;
+  const int xcd = b % MSL_NXCD, slot = b / MSL_NXCD;
+  return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+}
+
 // interior coordinates of cell k (x fastest)
 __device__ __forceinline__ void cell_coords(const Geo &g, long long k, int &x, int &y, int &z) {
   x = (int)(k % g.nx);

@@ -235,7 +235,7 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
     using T2 = SC2Traits<S, TH, N>;
     dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + T2::TY - 1) / T2::TY);
     hipLaunchKernelGGL((k_sc2d_res<S, TH, N>), grid, block, 0, c->stream, c->dtab, lat, g,
-                       (const S *)in, (S *)out, c->cls, c->tflag);
+                       (const S *)in, (S *)out, c->cls, c->tflag, lat == 0);
   } else if constexpr (D == 2) {
     dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + MSL_MTY * Tr::R - 1) / (MSL_MTY * Tr::R));
     hipLaunchKernelGGL((k_sc2d<S, TH, N>), grid, block, 0, c->stream, c->dtab, lat, g,
@@ -244,7 +244,7 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
     // 3D: planes streamed through LDS in chunks
     dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + MSL_MTY - 1) / MSL_MTY, g.nz);
     hipLaunchKernelGGL((k_sc3d_res<S, TH, N>), grid, block, 0, c->stream, c->dtab, lat, g,
-                       (const S *)in, (S *)out, c->cls, c->tflag);
+                       (const S *)in, (S *)out, c->cls, c->tflag, lat == 0);
   }
   return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
 }

@@ -82,7 +82,7 @@ template <typename S, bool TH, int N>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SC2Traits<S, TH, N>::WAVES)))
 k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
            S *__restrict__ out, const uint8_t *__restrict__ cls,
-           const uint8_t *__restrict__ tflag) {
+           const uint8_t *__restrict__ tflag, int remap) {
   using Tr = SC2Traits<S, TH, N>;
   using T = typename Tr::T;
   using C = typename Tr::C;
@@ -91,7 +91,12 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   constexpr int LR = TY + 2;
   __shared__ uint32_t sm[NP * PD];
   const LatTab &L = tab->lat[lat];
-  const int bx = blockIdx.x, by = blockIdx.y;
+  // dense launches take the XCD-aware tile order; sparse ones (the high-order
+  // set of a mixed run) keep the linear order, which spreads their few active
+  // tiles over all XCDs
+  const int lin = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+  const int tile = remap ? msl_xcd_tile(lin, (int)(gridDim.x * gridDim.y)) : lin;
+  const int bx = tile % (int)gridDim.x, by = tile / (int)gridDim.x;
   const int x0 = bx * MSL_TX, y0 = by * TY;
   {
     uint8_t any = 0;

@@ -53,7 +53,7 @@ template <typename S, bool TH, int N>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SC3Traits<S, TH, N>::WAVES)))
 k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
            S *__restrict__ out, const uint8_t *__restrict__ cls,
-           const uint8_t *__restrict__ tflag) {
+           const uint8_t *__restrict__ tflag, int remap) {
   using Tr = SC3Traits<S, TH, N>;
   using T = typename Tr::T;
   using C = typename Tr::C;
@@ -61,7 +61,10 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   constexpr int LWD = Tr::LWD, SZ = Tr::SZ, ROWS = Tr::ROWS;
   __shared__ uint32_t sm[CH * PD];
   const LatTab &L = tab->lat[lat];
-  const int bx = blockIdx.x, by = blockIdx.y, z0 = blockIdx.z;
+  const int lin = (int)((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
+  const int tile = remap ? msl_xcd_tile(lin, (int)(gridDim.x * gridDim.y * gridDim.z)) : lin;
+  const int bx = tile % (int)gridDim.x, by = (tile / (int)gridDim.x) % (int)gridDim.y;
+  const int z0 = tile / (int)(gridDim.x * gridDim.y);
   const int x0 = bx * MSL_TX, y0 = by * MSL_MTY;
   if (!(tflag[((long long)z0 * g.nty + by) * g.ntx + bx] & (1 << lat))) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
