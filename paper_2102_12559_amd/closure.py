@@ -34,7 +34,7 @@ def init_params(F, H, O, seed=0):
     return np.concatenate(out).astype(np.float32)
 
 
-XSTD_FLOOR = 1e-3   # features are dimensionless, of order 0.01 to 1
+XSTD_FLOOR = 1e-6   # spread below which a feature counts as constant
 XCLIP = 8.0         # standardised features are limited to +-8 (as in the library)
 
 
