@@ -34,10 +34,13 @@ struct SC2Traits {
   static constexpr int Q = N * N;
   static constexpr int NP = TH ? 2 * Q : Q;
   static constexpr int SZ = (int)sizeof(S);
-  // dwords per window row: 66 elements plus one dword of slack for 16-bit
-  // windows that start at an odd element
-  static constexpr int LWD = (66 * SZ + 3) / 4 + (SZ < 4 ? 1 : 0);
-  static constexpr int dwords_per_plane(int ty) { return ((ty + 2) * LWD + 255) / 256 * 256; }
+  // a window row is loaded in 16-byte chunks (one per lane and DMA
+  // instruction): 66 elements plus the misalignment of the row start (its
+  // address is only 4-byte aligned), rounded up to whole chunks
+  static constexpr int CPR = (66 * SZ + 3 + 15) / 16;   // chunks per row
+  static constexpr int LWD = 4 * CPR;                    // dwords per row
+  static constexpr int chunks_per_plane(int ty) { return (ty + 2) * CPR; }
+  static constexpr int dwords_per_plane(int ty) { return 4 * chunks_per_plane(ty); }
   static constexpr int LDS_BUDGET = 72 * 1024;
   // tile height: the tallest of 16 / 8 / 4 rows whose windows fit the LDS
   // budget and whose reconstructed values (NP x TY/4 per lane) fit a register
@@ -49,7 +52,8 @@ struct SC2Traits {
   static constexpr int TY = tile_ok(16) ? 16 : (tile_ok(8) ? 8 : 4);
   static constexpr int R = TY / 4;
   static constexpr int PD = dwords_per_plane(TY);     // LDS dwords per plane window
-  static constexpr int M = PD / 256;                    // DMA instructions per wave per plane
+  static constexpr int CP = chunks_per_plane(TY);      // 16-byte chunks per plane window
+  static constexpr int M = (CP + 255) / 256;           // DMA instructions per wave per plane
   static constexpr int LDS_BYTES = NP * PD * 4;
   static constexpr bool fits = LDS_BYTES <= 150 * 1024;
   // workgroups per CU allowed by LDS (160 KB); with 4 waves per workgroup that
@@ -111,14 +115,15 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   const int tx = lane, ty = w;
   const unsigned pitch_b = (unsigned)g.pitch * SZ;
   const unsigned plane_b = (unsigned)g.plane * SZ;
-  // plane-independent byte offsets of this lane's window dwords
+  // plane-independent byte offsets of this lane's window chunks (16 bytes)
+  constexpr int CPR = Tr::CPR, CP = Tr::CP;
   unsigned voff[M];
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     int d = lane + 64 * (w + 4 * m);
-    d = d < LR * LWD ? d : LR * LWD - 1;
-    const int row = d / LWD, col = d - row * LWD;
-    voff[m] = (unsigned)row * pitch_b + (unsigned)col * 4u;
+    d = d < CP ? d : CP - 1;
+    const int row = d / CPR, col = d - row * CPR;
+    voff[m] = (unsigned)row * pitch_b + (unsigned)col * 16u;
   }
   // 1. every plane's window in flight at once (direct-to-LDS loads)
   auto issue = [&]<int K>() {
@@ -130,8 +135,9 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     const int soff = (int)(org & ~3u);
 #pragma unroll
     for (int m = 0; m < M; ++m)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          rs, (msl_lds_t *)(sm + K * PD + 64 * (w + 4 * m)), 4, (int)voff[m], soff, 0, 0);
+      if ((m + 1) * 256 <= CP || lane + 64 * (w + 4 * m) < CP)   // chunk of the window
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (msl_lds_t *)(sm + K * PD + 256 * (w + 4 * m)), 16, (int)voff[m], soff, 0, 0);
   };
   msl_for_planes<NP>(issue);
   // my cells: inside the domain and of this velocity set
