@@ -1,0 +1,43 @@
+"""Host-side logic that needs no GPU: the benchmark's command-line contract
+and the closure's input standardisation."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+from paper_2102_12559_amd import closure
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
+
+
+def test_standardize_floors_constant_features():
+    rng = np.random.default_rng(0)
+    X = np.stack([rng.normal(1.0, 0.1, 1000), np.full(1000, 1.0),
+                  1e-9 * rng.normal(size=1000)], axis=1)
+    Y = rng.normal(size=(1000, 2))
+    xm, xs, ym, ys = closure.standardize(X, Y)
+    assert abs(xs[0] - 0.1) < 0.01
+    assert xs[1] == closure.XSTD_FLOOR and xs[2] == closure.XSTD_FLOOR
+    # a change of 1e-3 in a feature that never varied in training stays bounded
+    z = np.clip((np.array([1.0, 1.0 + 1e-3, 1e-3]) - xm) / xs, -closure.XCLIP, closure.XCLIP)
+    assert np.all(np.abs(z) <= closure.XCLIP)
+
+
+def test_init_params_glorot_range():
+    p = closure.init_params(10, 64, 27, seed=3)
+    F, H, O = 10, 64, 27
+    w1 = p[:F * H]
+    assert np.max(np.abs(w1)) <= np.sqrt(6.0 / (F + H)) + 1e-7
+    b1 = p[F * H:F * H + H]
+    assert np.all(b1 == 0)
+    assert p.size == F * H + H + H * H + H + H * O + O
