@@ -190,8 +190,9 @@ __device__ __forceinline__ long long pass_cells(const Geo &g, int ax, int *ext, 
   return tot;
 }
 
-// periodic and zero-gradient ghosts of every axis in one launch: one thread
-// per (ghost cell, plane).  A ghost cell belongs to the pass of its highest
+// 2D: periodic and zero-gradient ghosts of every axis in one launch (the
+// step of a small 2D grid is latency-bound: one launch instead of two); one
+// thread per (ghost cell, plane).  A ghost cell belongs to the pass of its highest
 // out-of-range axis (that axis' ghost layers, lower axes with their ghosts,
 // higher axes interior), so the passes partition the ghost cells.  A cell
 // whose owning face is a copy rule takes the value at the point where every
@@ -241,6 +242,70 @@ k_bc_copy(const Tab *__restrict__ tab, Geo g, BCArgs b, char *bl, char *bh, int 
   }
   S *pl = plane < np0 ? (S *)bl + (long long)plane * g.plane : (S *)bh + (long long)(plane - np0) * g.plane;
   pl[g.idx(p[0], p[1], p[2])] = pl[g.idx(q[0], q[1], q[2])];
+}
+
+// 3D: periodic and zero-gradient ghosts, one axis after the other: x, then y,
+// then z.  A ghost takes the value at the point where its out-of-range
+// coordinate is mapped by its face's rule (wrap, clamp).  The x pass covers
+// the interior rows; the y pass then copies whole rows (x ghosts included)
+// and the z pass whole slabs (y ghost rows included), so edges and corners
+// get every axis' rule in turn.  Fixed and diffuse faces keep their own
+// ghosts, which later passes copy like any other value.
+
+// x faces: one thread per (ghost cell of an interior row, plane)
+template <typename S>
+__global__ void __launch_bounds__(AUX_BLOCK)
+k_bc_xcopy(Geo g, BCArgs b, char *bl, char *bh, int np0) {
+  const int nz = g.dim == 3 ? g.nz : 1;
+  const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);   // < 4 ny nz < 2^31
+  if (t >= 2 * MSL_G * g.ny * nz) return;
+  const int gi = t % (2 * MSL_G), r = t / (2 * MSL_G);
+  const int y = r % g.ny, z = r / g.ny;
+  const int side = gi < MSL_G ? 0 : 1;
+  const int rule = b.bc[side];
+  if (rule != MSL_BC_PERIODIC && rule != MSL_BC_OUTFLOW_ZG) return;
+  const int x = side ? g.nx + (gi - MSL_G) : gi - MSL_G;
+  const int xs = rule == MSL_BC_PERIODIC ? (side ? x - g.nx : x + g.nx) : (side ? g.nx - 1 : 0);
+  const int plane = (int)blockIdx.y;
+  S *pl = plane < np0 ? (S *)bl + (long long)plane * g.plane : (S *)bh + (long long)(plane - np0) * g.plane;
+  pl[g.idx(x, y, z)] = pl[g.idx(xs, y, z)];
+}
+
+// y faces (A = 1: whole rows of interior slabs) and z faces (A = 2: whole
+// slabs): 16-byte chunks, one per thread.  Rows and slabs span the full pitch
+// and row count, so the padding beyond the ghost layers is copied too (it
+// holds no value any cell reads).
+template <int A>
+__global__ void __launch_bounds__(AUX_BLOCK)
+k_bc_blocks(Geo g, BCArgs b, char *bl, char *bh, int np0, int esz) {
+  const long long blk16 = A == 1 ? (long long)g.pitch * esz / 16 : (long long)g.rows * g.pitch * esz / 16;
+  const int nblk = A == 1 ? 2 * MSL_G * (g.dim == 3 ? g.nz : 1) : 2 * MSL_G;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= blk16 * nblk) return;
+  const int blk = (int)(t / blk16);
+  const long long ch = t - (long long)blk * blk16;
+  const int gi = blk % (2 * MSL_G), zz = blk / (2 * MSL_G);
+  const int n = A == 1 ? g.ny : g.nz;
+  const int side = gi < MSL_G ? 0 : 1;
+  const int rule = b.bc[2 * A + side];
+  if (rule != MSL_BC_PERIODIC && rule != MSL_BC_OUTFLOW_ZG) return;
+  const int c = side ? n + (gi - MSL_G) : gi - MSL_G;
+  const int cs = rule == MSL_BC_PERIODIC ? (side ? c - n : c + n) : (side ? n - 1 : 0);
+  // element offsets of the ghost block and of its source
+  long long dst, src;
+  if (A == 1) {
+    const long long zoff = g.dim == 3 ? (long long)(zz + MSL_G) * g.rows : 0;
+    dst = (zoff + c + MSL_G) * g.pitch;
+    src = (zoff + cs + MSL_G) * g.pitch;
+  } else {
+    dst = (long long)(c + MSL_G) * g.rows * g.pitch;
+    src = (long long)(cs + MSL_G) * g.rows * g.pitch;
+  }
+  const int plane = (int)blockIdx.y;
+  char *pl = plane < np0 ? bl + (long long)plane * g.plane * esz : bh + (long long)(plane - np0) * g.plane * esz;
+  uint4 *d = (uint4 *)(pl + dst * esz) + ch;
+  const uint4 *s = (const uint4 *)(pl + src * esz) + ch;
+  *d = *s;
 }
 
 // fixed-equilibrium ghosts: constant, written once per buffer when a state is
@@ -767,27 +832,48 @@ static long long host_pass_cells(const Geo &g, int ax) {
 }
 
 // per step: diffuse walls (from interior cells), then the periodic and
-// zero-gradient copies of every axis in one launch
+// zero-gradient copies: 2D in one launch; 3D x (unless the previous step
+// wrote them), y, z
 int msl_launch_bc(msl_ctx *c, char *bl, char *bh) {
   BCArgs b;
   bc_args(c, b);
   const Geo &g = c->geo;
   const int np0 = c->Q[0] * (c->cfg.thermal ? 2 : 1);
   const int np1 = c->nlat > 1 ? c->Q[1] * (c->cfg.thermal ? 2 : 1) : 0;
-  long long tot = 0;
-  bool copy = false;
+  const int esz = (int)c->esz;
+  auto copies = [&](int ax) {
+    const int r0 = b.bc[2 * ax], r1 = b.bc[2 * ax + 1];
+    return r0 == MSL_BC_PERIODIC || r0 == MSL_BC_OUTFLOW_ZG || r1 == MSL_BC_PERIODIC ||
+           r1 == MSL_BC_OUTFLOW_ZG;
+  };
   for (int ax = 0; ax < c->D; ++ax) {
     const int r0 = b.bc[2 * ax], r1 = b.bc[2 * ax + 1];
-    tot += host_pass_cells(g, ax);
-    copy = copy || r0 == MSL_BC_PERIODIC || r0 == MSL_BC_OUTFLOW_ZG || r1 == MSL_BC_PERIODIC ||
-           r1 == MSL_BC_OUTFLOW_ZG;
     if (r0 == MSL_BC_DIFFUSE_WALL || r1 == MSL_BC_DIFFUSE_WALL)
       DISPATCH_STORE(c, k_bc_diffuse, dim3(nblocks(host_pass_cells(g, ax))), dim3(AUX_BLOCK), c->dtab,
                      g, ax, b, bl, bh, c->cls);
   }
-  if (copy)
-    DISPATCH_STORE(c, k_bc_copy, dim3(nblocks(tot), np0 + np1), dim3(AUX_BLOCK), c->dtab, g, b, bl, bh,
-                   np0);
+  const dim3 blk(AUX_BLOCK);
+  if (c->D == 2) {
+    long long tot = 0;
+    for (int ax = 0; ax < 2; ++ax) tot += host_pass_cells(g, ax);
+    if (copies(0) || copies(1))
+      DISPATCH_STORE(c, k_bc_copy, dim3(nblocks(tot), np0 + np1), blk, c->dtab, g, b, bl, bh, np0);
+    return last_err();
+  }
+  const int nz = g.nz;
+  if (copies(0) && !c->xg_ok)
+    DISPATCH_STORE(c, k_bc_xcopy, dim3(nblocks((long long)2 * MSL_G * g.ny * nz), np0 + np1), blk, g, b,
+                   bl, bh, np0);
+  if (copies(1)) {
+    const long long n = (long long)g.pitch * esz / 16 * 2 * MSL_G * nz;
+    hipLaunchKernelGGL(k_bc_blocks<1>, dim3(nblocks(n), np0 + np1), blk, 0, c->stream, g, b, bl, bh, np0,
+                       esz);
+  }
+  if (copies(2)) {
+    const long long n = (long long)g.rows * g.pitch * esz / 16 * 2 * MSL_G;
+    hipLaunchKernelGGL(k_bc_blocks<2>, dim3(nblocks(n), np0 + np1), blk, 0, c->stream, g, b, bl, bh, np0,
+                       esz);
+  }
   return last_err();
 }
 
@@ -812,7 +898,7 @@ template <typename S, int D, int NL, int NH, bool TH>
 __global__ void __launch_bounds__(AUX_BLOCK)
 k_band_convert_t(const Tab *__restrict__ tab, Geo g, char *bl, char *bh,
                  const int *__restrict__ list_lo, const int *__restrict__ list_hi,
-                 const int *__restrict__ counts, int skip_lift) {
+                 const int *__restrict__ counts, int skip_lift, int xmir) {
   constexpr int q = Pow<D, NL>::v, Q = Pow<D, NH>::v;
   const int nlo = counts[0], nhi = counts[1];
   const long long stride = (long long)gridDim.x * blockDim.x;
@@ -823,16 +909,24 @@ k_band_convert_t(const Tab *__restrict__ tab, Geo g, char *bl, char *bh,
     int x, y, z;
     cell_coords(g, k, x, y, z);
     const int off = g.idx(x, y, z);
+    // periodic-x image of the cell in the ghost columns (3D; cells x < 2 and
+    // x >= nx - 2; xmir is set only for nx >= 4)
+    const bool img = D == 3 && xmir && (x < MSL_G || x >= g.nx - MSL_G);
+    const int ioff = x < MSL_G ? off + g.nx : off - g.nx;
     if (lift) {
       double f[q], gg[TH ? q : 1], fo[Q], go[TH ? Q : 1];
       read_cell_t<S, D, NL, TH>(tab, g, bl, 0, off, f, gg);
       lift_t<D, NL, NH, TH>(tab, f, gg, nullptr, fo, go);
       write_cell_t<S, D, NH, TH>(tab, g, bh, 1, off, fo, go);
+      if constexpr (D == 3)
+        if (img) write_cell_t<S, D, NH, TH>(tab, g, bh, 1, ioff, fo, go);
     } else {
       double f[Q], gg[TH ? Q : 1], fo[q], go[TH ? q : 1];
       read_cell_t<S, D, NH, TH>(tab, g, bh, 1, off, f, gg);
       project_t<D, NL, NH, TH>(tab, f, gg, fo, go);
       write_cell_t<S, D, NL, TH>(tab, g, bl, 0, off, fo, go);
+      if constexpr (D == 3)
+        if (img) write_cell_t<S, D, NL, TH>(tab, g, bl, 0, ioff, fo, go);
     }
   }
 }
@@ -869,10 +963,12 @@ static int band_convert_s(msl_ctx *c, char *bl, char *bh, int skip) {
   return msl_pair_dispatch(c->D, c->htab.lat[0].n, c->htab.lat[1].n, [&]<int D, int NL, int NH>() {
     if (c->cfg.thermal)
       hipLaunchKernelGGL((k_band_convert_t<S, D, NL, NH, true>), dim3(512), dim3(AUX_BLOCK), 0,
-                         c->stream, c->dtab, c->geo, bl, bh, c->blist[0], c->blist[1], c->bcount, skip);
+                         c->stream, c->dtab, c->geo, bl, bh, c->blist[0], c->blist[1], c->bcount, skip,
+                         c->xmir);
     else
       hipLaunchKernelGGL((k_band_convert_t<S, D, NL, NH, false>), dim3(512), dim3(AUX_BLOCK), 0,
-                         c->stream, c->dtab, c->geo, bl, bh, c->blist[0], c->blist[1], c->bcount, skip);
+                         c->stream, c->dtab, c->geo, bl, bh, c->blist[0], c->blist[1], c->bcount, skip,
+                         c->xmir);
     return last_err();
   });
 }

@@ -617,10 +617,14 @@ int msl_profile_read(msl_ctx *c, double *stats) {
 int msl_step(msl_ctx *c, int nsteps) {
   if (!c || nsteps < 0) return MSL_EINVAL;
   if (!c->initialized) { set_err(c, "msl_step before msl_init"); return MSL_ESTATE; }
+  // the x ghost columns of the current buffer are taken as stale on entry
+  // (the state may have been set since the last step) and after switching
+  c->xg_ok = 0;
   for (int s = 0; s < nsteps; ++s) {
     int rc;
     if (c->cfg.crit_kind && c->cfg.crit_every > 0 && c->nlat > 1 && c->step % c->cfg.crit_every == 0) {
       prof_begin(c);
+      c->xg_ok = 0;
       rc = mask_step(c);
       if (rc) { set_err(c, "criterion / switching failed"); return rc; }
       prof_snap(c);
@@ -640,6 +644,11 @@ int msl_step(msl_ctx *c, int nsteps) {
     rc = msl_launch_bc(c, bl, bh);
     if (rc) { set_err(c, "ghost fill failed"); return rc; }
     if ((rc = prof_end(c, 0, -1, 0.0, 0.0))) return rc;
+    // 3D with x periodic on both faces: the new buffer's x ghosts are written
+    // by the step itself (not with the learned lift, whose kernel writes the
+    // lifted band cells without their images)
+    c->xmir = c->D == 3 && c->cfg.bc[0] == MSL_BC_PERIODIC && c->cfg.bc[1] == MSL_BC_PERIODIC &&
+              c->geo.nx >= 2 * MSL_G && !(c->cfg.lift_mode == MSL_LIFT_MLP && c->mlp_on);
     for (int l = 0; l < c->nlat; ++l) {
       // compulsory traffic: read and write every population plane of each native cell
       const double bpc = 2.0 * c->Q[l] * (c->cfg.thermal ? 2 : 1) * (double)c->esz;
@@ -661,6 +670,8 @@ int msl_step(msl_ctx *c, int nsteps) {
         if ((rc = prof_end(c, 5, -1, 0.0, 0.0))) return rc;
       }
     }
+    c->xg_ok = c->xmir;
+    c->xmir = 0;
     c->cur = nxt;
     ++c->step;
     if (c->cfg.check_every > 0 && c->step % c->cfg.check_every == 0) {

@@ -132,6 +132,10 @@ struct msl_ctx {
   double *wall_rho;       // diffuse wall densities
   long step;
   int initialized;
+  // 3D, x periodic: the step's stream-collide and band conversion also write
+  // the x ghost columns of the new buffer (xmir), so the next ghost fill
+  // leaves out the x faces while xg_ok says they hold the current values
+  int xmir, xg_ok;
   // learned closure
   int mlpF, mlpO, mlpH, mlpP, mlp_on, mlp_manual;
   float *mlp_w;           // fp32 master parameters [P]

@@ -231,11 +231,30 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
   const Geo &g = c->geo;
   dim3 block(256);
   if constexpr (D == 2 && SC2Traits<S, TH, N>::fits) {
-    // every plane resident in LDS
-    using T2 = SC2Traits<S, TH, N>;
-    dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + T2::TY - 1) / T2::TY);
-    hipLaunchKernelGGL((k_sc2d_res<S, TH, N>), grid, block, 0, c->stream, c->dtab, lat, g,
-                       (const S *)in, (S *)out, c->cls, c->tflag, lat == 0);
+    // every plane resident in LDS; non-temporal stores for FP32 / FP64 D2Q9
+    // planes when the set's buffer exceeds the 256 MB last-level cache
+    const int nt = N == 3 && sizeof(S) >= 4 &&
+                   (double)g.plane * sizeof(S) * c->Q[lat] * (c->cfg.thermal ? 2 : 1) > 256.0 * (1 << 20);
+    const long long tiles8 = (long long)((g.nx + MSL_TX - 1) / MSL_TX) * ((g.ny + 7) / 8);
+    bool small = false;
+    if constexpr (N == 3) {
+      // D2Q9 on a grid of fewer than 8 tiles of 8 rows per CU: 4-row tiles,
+      // twice as many workgroups
+      using T2 = SC2Traits<S, TH, N, true>;
+      static_assert(T2::fits && T2::TY == 4, "4-row D2Q9 tile");
+      small = tiles8 < 2048;
+      if (small) {
+        dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + T2::TY - 1) / T2::TY);
+        hipLaunchKernelGGL((k_sc2d_res<S, TH, N, true>), grid, block, 0, c->stream, c->dtab, lat, g,
+                           (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, nt);
+      }
+    }
+    if (!small) {
+      using T2 = SC2Traits<S, TH, N>;
+      dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + T2::TY - 1) / T2::TY);
+      hipLaunchKernelGGL((k_sc2d_res<S, TH, N, false>), grid, block, 0, c->stream, c->dtab, lat, g,
+                         (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, nt);
+    }
   } else if constexpr (D == 2) {
     dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + MSL_MTY * Tr::R - 1) / (MSL_MTY * Tr::R));
     hipLaunchKernelGGL((k_sc2d<S, TH, N>), grid, block, 0, c->stream, c->dtab, lat, g,
@@ -244,7 +263,7 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
     // 3D: planes streamed through LDS in chunks
     dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + MSL_MTY - 1) / MSL_MTY, g.nz);
     hipLaunchKernelGGL((k_sc3d_res<S, TH, N>), grid, block, 0, c->stream, c->dtab, lat, g,
-                       (const S *)in, (S *)out, c->cls, c->tflag, lat == 0);
+                       (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, c->xmir);
   }
   return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
 }

@@ -27,7 +27,7 @@
 typedef __attribute__((address_space(3))) void msl_lds_t;
 #define MSL_RSRC_WORD3 0x00020000   // raw buffer, gfx9-family descriptor word 3
 
-template <typename S, bool TH, int N>
+template <typename S, bool TH, int N, bool SMALL = false>
 struct SC2Traits {
   using T = StoreTraits<S>;
   using C = typename T::C;
@@ -44,12 +44,14 @@ struct SC2Traits {
   static constexpr int LDS_BUDGET = 72 * 1024;
   // tile height: the tallest of 16 / 8 / 4 rows whose windows fit the LDS
   // budget and whose reconstructed values (NP x TY/4 per lane) fit a register
-  // budget of 48
+  // budget of 48; D2Q9 takes at most 8 rows (smaller workgroups, more of them
+  // resident per CU: measured faster at every storage type), and 4 on grids
+  // too small to give every CU several tiles of 8 rows (SMALL)
   static constexpr int REGW = SZ == 8 ? 2 : 1;
   static constexpr bool tile_ok(int ty) {
     return NP * dwords_per_plane(ty) * 4 <= LDS_BUDGET && NP * (ty / 4) * REGW <= 48;
   }
-  static constexpr int TY = tile_ok(16) ? 16 : (tile_ok(8) ? 8 : 4);
+  static constexpr int TY = SMALL ? 4 : (N == 3 && tile_ok(8)) ? 8 : (tile_ok(16) ? 16 : (tile_ok(8) ? 8 : 4));
   static constexpr int R = TY / 4;
   static constexpr int PD = dwords_per_plane(TY);     // LDS dwords per plane window
   static constexpr int CP = chunks_per_plane(TY);      // 16-byte chunks per plane window
@@ -57,9 +59,12 @@ struct SC2Traits {
   static constexpr int LDS_BYTES = NP * PD * 4;
   static constexpr bool fits = LDS_BYTES <= 150 * 1024;
   // workgroups per CU allowed by LDS (160 KB); with 4 waves per workgroup that
-  // is also the waves per SIMD the register budget has to allow
+  // is also the waves per SIMD the register budget has to allow (capped where
+  // a tighter register budget would spill: 3 in general, 4 for athermal
+  // D2Q9, 8 for the 4-row D2Q9 tile)
   static constexpr int WGS = (160 * 1024) / LDS_BYTES;
-  static constexpr int WAVES = WGS >= 3 ? 3 : (WGS < 1 ? 1 : WGS);
+  static constexpr int WCAP = SMALL ? 8 : (N == 3 && !TH ? 4 : 3);
+  static constexpr int WAVES = WGS >= WCAP ? WCAP : (WGS < 1 ? 1 : WGS);
 };
 
 template <int NP, typename F>
@@ -82,12 +87,12 @@ __device__ __forceinline__ float lds_elem<bf16_t>(const char *p) {
 template <typename S>
 __device__ __forceinline__ double lds_elem_d(const char *p) { return *(const double *)p; }
 
-template <typename S, bool TH, int N>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SC2Traits<S, TH, N>::WAVES)))
+template <typename S, bool TH, int N, bool SMALL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SC2Traits<S, TH, N, SMALL>::WAVES)))
 k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
            S *__restrict__ out, const uint8_t *__restrict__ cls,
-           const uint8_t *__restrict__ tflag, int remap) {
-  using Tr = SC2Traits<S, TH, N>;
+           const uint8_t *__restrict__ tflag, int remap, int nt) {
+  using Tr = SC2Traits<S, TH, N, SMALL>;
   using T = typename Tr::T;
   using C = typename Tr::C;
   constexpr int Q = Tr::Q, NP = Tr::NP, R = Tr::R, TY = Tr::TY, PD = Tr::PD, M = Tr::M;
@@ -252,11 +257,17 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
       else vo = v + om[r] * (gf[r] * feq - v);
       const C o = T::dev ? vo * isc - C(1) : vo;
       const S sv = T::store(o);
+      // nt: non-temporal stores (cache policy bit 1) when the output buffer is
+      // far larger than the caches and is read back only in the next step
+      // (D2Q9 in FP32 / FP64 on large grids; the test is compiled out elsewhere)
+      constexpr bool NTOK = N == 3 && !SMALL && SZ >= 4;
       if constexpr (SZ == 8) {
         typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, sv), rs, (int)soff_cell[r], 0, 0);
+        if (NTOK && nt) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, sv), rs, (int)soff_cell[r], 0, 2);
+        else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, sv), rs, (int)soff_cell[r], 0, 0);
       } else if constexpr (SZ == 4) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, sv), rs, (int)soff_cell[r], 0, 0);
+        if (NTOK && nt) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, sv), rs, (int)soff_cell[r], 0, 2);
+        else __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, sv), rs, (int)soff_cell[r], 0, 0);
       } else {
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, sv), rs, (int)soff_cell[r], 0, 0);
       }

@@ -53,7 +53,7 @@ template <typename S, bool TH, int N>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SC3Traits<S, TH, N>::WAVES)))
 k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
            S *__restrict__ out, const uint8_t *__restrict__ cls,
-           const uint8_t *__restrict__ tflag, int remap) {
+           const uint8_t *__restrict__ tflag, int remap, int xmir) {
   using Tr = SC3Traits<S, TH, N>;
   using T = typename Tr::T;
   using C = typename Tr::C;
@@ -204,6 +204,12 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   }
   const C gf = (C)(tab->gfac * Tm);
   const unsigned soff = mine ? (unsigned)g.idx(x, y, z) * SZ : 0x80000000u;
+  // periodic x (xmir, nx >= 4): the cells x < 2 and x >= nx - 2 are also
+  // stored into the ghost columns of the other side, which the next step's
+  // windows read; only the tiles at the two x ends take the second store
+  const bool xedge = xmir && (x0 < MSL_G || x0 + MSL_TX > g.nx - MSL_G);
+  const unsigned ioff = (mine && x < MSL_G) ? soff + (unsigned)g.nx * SZ
+                        : (mine && x >= g.nx - MSL_G) ? soff - (unsigned)g.nx * SZ : 0x80000000u;
   // collide and store
   auto store = [&]<int K>() {
     constexpr int i = K % Q, a = i % N, b = (i / N) % N, cc = i / (N * N);
@@ -218,14 +224,18 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     const S sv = T::store(T::dev ? vo * isc - C(1) : vo);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(out + (long long)K * g.plane), (short)0, (int)plane_b, MSL_RSRC_WORD3);
-    if constexpr (SZ == 8) {
-      typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, sv), rs, (int)soff, 0, 0);
-    } else if constexpr (SZ == 4) {
-      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, sv), rs, (int)soff, 0, 0);
-    } else {
-      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, sv), rs, (int)soff, 0, 0);
-    }
+    auto put = [&](unsigned o) {
+      if constexpr (SZ == 8) {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, sv), rs, (int)o, 0, 0);
+      } else if constexpr (SZ == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, sv), rs, (int)o, 0, 0);
+      } else {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, sv), rs, (int)o, 0, 0);
+      }
+    };
+    put(soff);
+    if (xedge) put(ioff);
   };
   msl_for_planes<NP>(store);
 }

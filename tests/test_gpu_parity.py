@@ -149,6 +149,42 @@ def test_3d_small_fp64():
     compare_pops(s, o, 1e-12)
 
 
+P, ZG = inputs.BC_PERIODIC, inputs.BC_OUTFLOW_ZG
+
+
+@pytest.mark.parametrize("n_high,split,bc", [
+    (4, (4, 5), [P] * 6), (0, (3, 4), [P] * 6),
+    (4, (4, 5), [P, P, ZG, ZG, P, P]), (4, (4, 5), [P, P, P, P, ZG, ZG])])
+def test_3d_periodic_x_images_fp64(n_high, split, bc):
+    """3D, x periodic: from the second step of a step call on, the x ghost
+    columns come from the previous step itself (the stream-collide and band
+    conversion kernels also store the cells x < 2 and x >= nx - 2 into the
+    ghost columns of the other side) instead of the ghost-fill copy.  Ragged
+    70 x 12 x 10 grid (two tiles in x, the second partial), random flow up to
+    |u| = 0.45 with the Mach criterion at 0.3 every 3 steps (about 200 cells
+    of the four x-end columns switch at step 3), the steps split over two
+    calls (each call starts from a full ghost fill); FP64, 1e-12 per
+    population.  With zero-gradient y or z faces the y and z ghost passes
+    (whole rows, then whole slabs) carry the x images into the edges."""
+    nx, ny, nz = 70, 12, 10
+    rho, u, T = inputs.smooth_random_flow(nx, ny, nz, umax=0.45, modes=2, seed=5, drho=0.02)
+    crit = dict(crit_kind=inputs.CRIT_MA, crit_thr=0.3, crit_every=3) if n_high else {}
+    cfg = inputs.base_config(dim=3, nx=nx, ny=ny, nz=nz, n_low=3, n_high=n_high, tau=0.7, bc=bc,
+                             **crit)
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    if n_high:
+        mask[:, :, :3] = 1
+        mask[:, :, -2:] = 1
+    s, o = run_pair(cfg, rho, u, T, mask, split[0], tag=f"3D x images n_high={n_high} bc={bc}")
+    s.step(split[1])
+    o.step(split[1])
+    if n_high:
+        nh = int(s.get_mask().sum())
+        say(f"  high-order cells {nh}")
+        assert nh < nx * ny * nz
+    compare_pops(s, o, 1e-12)
+
+
 def test_checkpoint_resume_bitwise():
     from paper_2102_12559_amd import msl
     w = inputs.vortex_c1()
