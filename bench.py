@@ -20,7 +20,12 @@ L2 error against full high-order runs of planar Couette flow: it trains the
 network on snapshots of those runs, sweeps the width of the high-order layer
 next to the walls for every form, takes as the common error the plain form's
 error at width 4, and reports each form's throughput at the cheapest width
-that reaches it.
+that reaches it.  `--workload vortex3d-equal-l2` makes the same comparison on
+the 3D vortex and shear slab, sweeping the Mach threshold.
+
+`--workload efficiency-d2q25` runs the paper's computational-efficiency
+layout (N x N, D2Q25 on 10 % of the cells, D2Q9 elsewhere) for N from 128 to
+8192 and reports the hybrid speed-up over an all-D2Q25 run per N.
 """
 import argparse
 import hashlib
@@ -460,6 +465,78 @@ def device_copy_rate(args):
                       "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}))
 
 
+def efficiency(args):
+    """The computational-efficiency experiment of Sec. V (Fig. 13 layout): an
+    N x N periodic box split into two rectangles, D2Q25 on a band of 10 % of
+    the columns and D2Q9 elsewhere (fixed mask, no criterion), against the
+    same box all D2Q9 and all D2Q25.  Reported per N: the step times, t25/t9,
+    the hybrid speed-up t25/t_hyb and its bound 1 / (0.1 + 0.9 t9/t25) (the
+    cost of the interface conversions is what keeps the speed-up below it).
+    FP32 storage, smooth random flow with |u| <= 0.1, tau 0.6; each time is
+    taken over enough steps for ~20 ms or more after 10 warm-up steps."""
+    import numpy as np
+    import torch
+    from paper_2102_12559_amd import inputs, msl
+    torch.cuda.set_device(0)
+    sizes = [128, 256, 512, 1024, 2048, 4096, 8192]
+
+    def step_ms(cfg, mask, rho, u, T, steps):
+        s = msl.Solver(cfg, device="cuda:0")
+        s.set_mask(mask)
+        s.init(rho, u, T)
+        s.step(10)
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        s.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        s.conservation()
+        s.close()
+        torch.cuda.empty_cache()
+        return ms
+
+    pts = []
+    for N in sizes:
+        steps = max(20, min(2000, int(1.6e9 / (N * N))))
+        rho, u, T = inputs.smooth_random_flow(N, N, umax=0.1, seed=0, modes=2)
+        zero = np.zeros((1, N, N), np.uint8)
+        hyb = zero.copy()
+        w = max(1, round(0.1 * N))
+        x0 = (N - w) // 2
+        hyb[:, :, x0:x0 + w] = 1
+        base = dict(nx=N, ny=N, tau=0.6, store=inputs.STORE_FP32)
+        t9 = step_ms(inputs.base_config(n_low=3, n_high=0, **base), zero, rho, u, T, steps)
+        t25 = step_ms(inputs.base_config(n_low=5, n_high=0, **base), zero, rho, u, T, steps)
+        th = step_ms(inputs.base_config(n_low=3, n_high=5, **base), hyb, rho, u, T, steps)
+        r = t25 / t9
+        pts.append({"N": N, "steps": steps, "high_fraction": round(w / N, 4),
+                    "t9_ms": round(t9, 5), "t25_ms": round(t25, 5), "thyb_ms": round(th, 5),
+                    "t25_over_t9": round(r, 3), "speedup_t25_over_thyb": round(t25 / th, 3),
+                    "speedup_bound": round(1.0 / (w / N + (1 - w / N) / r), 3),
+                    "hyb_mlups": round(N * N / (th / 1e3) / 1e6, 1)})
+        print(json.dumps(pts[-1]), file=sys.stderr, flush=True)
+    big = pts[-1]
+    print(json.dumps({
+        "metric": "speed-up t_D2Q25 / t_hybrid (10 % D2Q25)",
+        "value": big["speedup_t25_over_thyb"],
+        "unit": "x",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "efficiency layout: N x N periodic, D2Q25 band of 10 % of the columns, "
+                               "D2Q9 elsewhere, fixed mask; all-D2Q9 and all-D2Q25 runs beside it",
+                   "sizes": sizes, "storage": "f32"},
+        "paper_cpu_8_cores": {"t25_over_t9": 2.9, "max_speedup": 2.43},
+        "points": pts,
+    }))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -482,6 +559,9 @@ def main():
         return
     if args.workload == "device-copy":
         device_copy_rate(args)
+        return
+    if args.workload == "efficiency-d2q25":
+        efficiency(args)
         return
 
     import torch

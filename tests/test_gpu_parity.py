@@ -185,6 +185,48 @@ def test_3d_periodic_x_images_fp64(n_high, split, bc):
     compare_pops(s, o, 1e-12)
 
 
+FX = inputs.BC_FIXED_EQ
+
+
+@pytest.mark.parametrize("bc", [[ZG] * 4 + [P, P], [P, P, ZG, ZG, P, P], [FX, ZG, P, P, P, P],
+                                [FX, ZG, ZG, ZG, P, P]])
+def test_2d_ghost_images_fp64(bc):
+    """2D: from the second step of a step call on, no ghost-fill launch runs;
+    the stream-collide and band conversion kernels store every cell next to
+    a periodic or zero-gradient face into the ghost cells that copy it (edges
+    and corners included), fixed-equilibrium ghosts stay as loaded.  Ragged
+    70 x 37 grid, D2Q9 + D2Q16 with a blob mask touching every face, random
+    flow up to |u| = 0.45 and the Mach criterion at 0.3 every 3 steps, the
+    steps split over two calls; FP64, 1e-12 per population."""
+    nx, ny = 70, 37
+    rho, u, T = inputs.smooth_random_flow(nx, ny, umax=0.45, modes=2, seed=7, drho=0.02)
+    cfg = inputs.base_config(nx=nx, ny=ny, n_low=3, n_high=4, tau=0.7, bc=bc,
+                             crit_kind=inputs.CRIT_MA, crit_thr=0.3, crit_every=3)
+    mask = np.zeros((1, ny, nx), np.uint8)
+    mask[0, :3, :] = 1
+    mask[0, -2:, :] = 1
+    mask[0, :, :2] = 1
+    mask[0, :, -3:] = 1
+    s, o = run_pair(cfg, rho, u, T, mask, 4, tag=f"2D ghost images bc={bc}")
+    s.step(5)
+    o.step(5)
+    compare_pops(s, o, 1e-12)
+
+
+def test_efficiency_layout_d2q9_d2q25_fp32():
+    """The efficiency layout (a D2Q25 band of 10 % of the columns in a D2Q9
+    box, fixed mask) at 100 x 100 in FP32 against the FP64 oracle after 30
+    steps: 1e-5 on rho and u."""
+    N = 100
+    rho, u, T = inputs.smooth_random_flow(N, N, umax=0.1, seed=0, modes=2)
+    cfg = inputs.base_config(nx=N, ny=N, n_low=3, n_high=5, tau=0.6, store=inputs.STORE_FP32)
+    mask = np.zeros((1, N, N), np.uint8)
+    mask[:, :, 45:55] = 1
+    s, o = run_pair(cfg, rho, u, T, mask, 30, oracle_cfg=dict(cfg, store=inputs.STORE_FP64),
+                    tag="efficiency layout 100^2 fp32")
+    compare_macros(s, o, 1e-5, uscale=1.0)
+
+
 def test_checkpoint_resume_bitwise():
     from paper_2102_12559_amd import msl
     w = inputs.vortex_c1()
