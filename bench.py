@@ -481,6 +481,8 @@ def efficiency(args):
     sizes = [128, 256, 512, 1024, 2048, 4096, 8192]
 
     def step_ms(cfg, mask, rho, u, T, steps):
+        """Step time, and the per-class kernel time per step (HIP events
+        around every launch of a few further steps)."""
         s = msl.Solver(cfg, device="cuda:0")
         s.set_mask(mask)
         s.init(rho, u, T)
@@ -494,10 +496,15 @@ def efficiency(args):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
+        nprof = max(5, steps // 10)
+        s.profile(True, every=1)
+        s.step(nprof)
+        prof = s.profile_read()
+        s.profile(False)
         s.conservation()
         s.close()
         torch.cuda.empty_cache()
-        return ms
+        return ms, {k: round(v["ms"] / nprof * 1e3, 2) for k, v in prof.items() if v["launches"]}
 
     pts = []
     for N in sizes:
@@ -509,15 +516,15 @@ def efficiency(args):
         x0 = (N - w) // 2
         hyb[:, :, x0:x0 + w] = 1
         base = dict(nx=N, ny=N, tau=0.6, store=inputs.STORE_FP32)
-        t9 = step_ms(inputs.base_config(n_low=3, n_high=0, **base), zero, rho, u, T, steps)
-        t25 = step_ms(inputs.base_config(n_low=5, n_high=0, **base), zero, rho, u, T, steps)
-        th = step_ms(inputs.base_config(n_low=3, n_high=5, **base), hyb, rho, u, T, steps)
+        t9, _ = step_ms(inputs.base_config(n_low=3, n_high=0, **base), zero, rho, u, T, steps)
+        t25, _ = step_ms(inputs.base_config(n_low=5, n_high=0, **base), zero, rho, u, T, steps)
+        th, kh = step_ms(inputs.base_config(n_low=3, n_high=5, **base), hyb, rho, u, T, steps)
         r = t25 / t9
         pts.append({"N": N, "steps": steps, "high_fraction": round(w / N, 4),
                     "t9_ms": round(t9, 5), "t25_ms": round(t25, 5), "thyb_ms": round(th, 5),
                     "t25_over_t9": round(r, 3), "speedup_t25_over_thyb": round(t25 / th, 3),
                     "speedup_bound": round(1.0 / (w / N + (1 - w / N) / r), 3),
-                    "hyb_mlups": round(N * N / (th / 1e3) / 1e6, 1)})
+                    "hyb_mlups": round(N * N / (th / 1e3) / 1e6, 1), "hyb_kernels_us_per_step": kh})
         print(json.dumps(pts[-1]), file=sys.stderr, flush=True)
     big = pts[-1]
     print(json.dumps({

@@ -581,6 +581,57 @@ __global__ void k_order_extrema(Geo g, int ax, int bc_periodic_mask, const uint8
   else out[k] = (uint8_t)((mx << 1) | mn);
 }
 
+// The live tiles of velocity set `lat` in ascending order: a launch tile is
+// 64 x 4R cells (2D) or one 64 x 4 micro-tile of a z plane (3D, R = 1) and
+// live when one of its micro-tiles holds a cell of the set.  One workgroup
+// compacts the tile grid in chunks of 1024 (wave ballots, then the wave
+// totals in LDS); the list holds (z * rows + by) * ntx + bx.
+__global__ void __launch_bounds__(1024)
+k_tile_list(Geo g, const uint8_t *__restrict__ tflag, int lat, int R, int *__restrict__ list,
+            int *__restrict__ count) {
+  __shared__ int wsum[16];
+  __shared__ int base;
+  const int rows = (g.nty + R - 1) / R;
+  const int ntiles = g.ntx * rows * g.ntz;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < ntiles; c0 += 1024) {
+    const int t = c0 + (int)threadIdx.x;
+    bool live = false;
+    if (t < ntiles) {
+      const int bx = t % g.ntx, rest = t / g.ntx, by = rest % rows, bz = rest / rows;
+      uint8_t any = 0;
+      for (int r = 0; r < R; ++r) {
+        const int my = by * R + r;
+        if (my < g.nty) any |= tflag[((long long)bz * g.nty + my) * g.ntx + bx];
+      }
+      live = (any >> lat) & 1;
+    }
+    const unsigned long long b = __ballot(live);
+    const int before = __popcll(b & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wv] = __popcll(b);
+    __syncthreads();
+    int off = base;
+    for (int k = 0; k < wv; ++k) off += wsum[k];
+    if (live) list[off + before] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int k = 0; k < 16; ++k) tot += wsum[k];
+      base += tot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *count = base;
+}
+
+int msl_launch_tile_list(msl_ctx *c, int lat, int rows_per_tile) {
+  hipLaunchKernelGGL(k_tile_list, dim3(1), dim3(1024), 0, c->stream, c->geo, c->tflag, lat, rows_per_tile,
+                     c->tlist, c->tcount);
+  return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
+}
+
 // per micro-tile (64 x 4 (x 1)) presence of each order
 __global__ void k_tileflags(Geo g, const uint8_t *__restrict__ cls, uint8_t *__restrict__ tflag) {
   const long long t = blockIdx.x;   // one 64-thread block per micro-tile
@@ -1078,6 +1129,7 @@ int msl_launch_classify(msl_ctx *c) {
   const Geo &g = c->geo;
   const long long nt = (long long)g.ntx * g.nty * g.ntz;
   hipLaunchKernelGGL(k_tileflags, dim3((unsigned)nt), dim3(64), 0, c->stream, g, c->cls, c->tflag);
+  c->tl_ok = 0;
   hipLaunchKernelGGL(k_band_count, dim3(c->nblk), dim3(AUX_BLOCK), 0, c->stream, g, c->cls, c->blk,
                      c->nblk);
   hipLaunchKernelGGL(k_band_scan, dim3(1), dim3(64), 0, c->stream, c->blk, c->nblk, c->bcount);

@@ -187,7 +187,7 @@ struct Layout {
   Geo geo;
   size_t esz;
   size_t off_tab, off_planes[2], off_cls, off_newmask, off_tflag, off_blist[2], off_bcount, off_blk,
-      off_red, off_flag, off_mlp, total;
+      off_red, off_flag, off_tlist, off_mlp, total;
   int nblk, Q[2], np[2];
   long long plane_bytes;
   int mlpF, mlpO, mlpH, mlpP, nctile, nct[3];
@@ -250,6 +250,8 @@ static void make_layout(const msl_config *cfg, Layout &L) {
   off = align256(off + (size_t)1024 * 6 * 8 + 64);
   L.off_flag = off;
   off = align256(off + 64);
+  L.off_tlist = off;   // live-tile list of the high-order set, then its count
+  off = align256(off + ((size_t)g.ntx * g.nty * g.ntz + 16) * 4);
   // learned closure
   if (cfg->lift_mode == MSL_LIFT_MLP && nl > 1) {
     const int q = L.Q[0], Q = L.Q[1];
@@ -410,6 +412,8 @@ int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_
   c->nblk = L.nblk;
   c->red = (double *)(base + L.off_red);
   c->flag = (int *)(base + L.off_flag);
+  c->tlist = (int *)(base + L.off_tlist);
+  c->tcount = c->tlist + (size_t)L.geo.ntx * L.geo.nty * L.geo.ntz;
   if (L.mlpP) {
     c->mlpF = L.mlpF; c->mlpO = L.mlpO; c->mlpH = L.mlpH; c->mlpP = L.mlpP;
     c->mlp_w = (float *)(base + L.mlp_off[0]);
@@ -618,8 +622,10 @@ int msl_step(msl_ctx *c, int nsteps) {
   if (!c || nsteps < 0) return MSL_EINVAL;
   if (!c->initialized) { set_err(c, "msl_step before msl_init"); return MSL_ESTATE; }
   // the x ghost columns of the current buffer are taken as stale on entry
-  // (the state may have been set since the last step) and after switching
+  // (the state may have been set since the last step) and after switching;
+  // the live-tile list is rebuilt on first use
   c->xg_ok = 0;
+  c->tl_ok = 0;
   for (int s = 0; s < nsteps; ++s) {
     int rc;
     if (c->cfg.crit_kind && c->cfg.crit_every > 0 && c->nlat > 1 && c->step % c->cfg.crit_every == 0) {

@@ -136,6 +136,11 @@ struct msl_ctx {
   // the x ghost columns of the new buffer (xmir), so the next ghost fill
   // leaves out the x faces while xg_ok says they hold the current values
   int xmir, xg_ok;
+  // live tiles of the high-order set, ascending (sparse stream-collide
+  // launches walk this list instead of the whole tile grid); tl_ok: the list
+  // matches the current tile flags
+  int *tlist, *tcount;
+  int tl_ok;
   // learned closure
   int mlpF, mlpO, mlpH, mlpP, mlp_on, mlp_manual;
   float *mlp_w;           // fp32 master parameters [P]
@@ -167,6 +172,7 @@ struct msl_ctx {
 
 // launch helpers implemented in the .hip files
 int msl_launch_stream_collide(msl_ctx *c, int lat, const char *in, char *out);
+int msl_launch_tile_list(msl_ctx *c, int lat, int rows_per_tile);
 int msl_launch_bc(msl_ctx *c, char *buf_low, char *buf_high);
 int msl_launch_bc_fixed(msl_ctx *c);
 int msl_launch_band_convert(msl_ctx *c, char *buf_low, char *buf_high);

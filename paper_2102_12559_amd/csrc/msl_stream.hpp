@@ -246,14 +246,32 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
       if (small) {
         dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + T2::TY - 1) / T2::TY);
         hipLaunchKernelGGL((k_sc2d_res<S, TH, N, true>), grid, block, 0, c->stream, c->dtab, lat, g,
-                           (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, nt);
+                           (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, nt, nullptr, nullptr);
+      }
+    }
+    if constexpr (N > 3) {
+      using T2 = SC2Traits<S, TH, N>;
+      const long long tiles = (long long)g.ntx * ((g.ny + T2::TY - 1) / T2::TY);
+      const long long fit = 256LL * (T2::WGS < 1 ? 1 : T2::WGS);
+      if (!small && lat != 0 && tiles > 4 * fit) {
+        // the high-order set on a large grid: as many workgroups as fit the
+        // GPU at once, each walking the list of live tiles (on smaller grids
+        // the one-tile-per-workgroup grid is faster)
+        if (!c->tl_ok) {
+          if (msl_launch_tile_list(c, lat, T2::R)) return MSL_EHIP;
+          c->tl_ok = 1;
+        }
+        dim3 grid((unsigned)fit);
+        hipLaunchKernelGGL((k_sc2d_res<S, TH, N, false, true>), grid, block, 0, c->stream, c->dtab, lat,
+                           g, (const S *)in, (S *)out, c->cls, c->tflag, 0, nt, c->tlist, c->tcount);
+        return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
       }
     }
     if (!small) {
       using T2 = SC2Traits<S, TH, N>;
       dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + T2::TY - 1) / T2::TY);
       hipLaunchKernelGGL((k_sc2d_res<S, TH, N, false>), grid, block, 0, c->stream, c->dtab, lat, g,
-                         (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, nt);
+                         (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, nt, nullptr, nullptr);
     }
   } else if constexpr (D == 2) {
     dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + MSL_MTY * Tr::R - 1) / (MSL_MTY * Tr::R));

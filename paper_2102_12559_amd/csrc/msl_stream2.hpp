@@ -87,11 +87,12 @@ __device__ __forceinline__ float lds_elem<bf16_t>(const char *p) {
 template <typename S>
 __device__ __forceinline__ double lds_elem_d(const char *p) { return *(const double *)p; }
 
-template <typename S, bool TH, int N, bool SMALL>
+template <typename S, bool TH, int N, bool SMALL, bool LIST = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SC2Traits<S, TH, N, SMALL>::WAVES)))
 k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
            S *__restrict__ out, const uint8_t *__restrict__ cls,
-           const uint8_t *__restrict__ tflag, int remap, int nt) {
+           const uint8_t *__restrict__ tflag, int remap, int nt, const int *__restrict__ tlist,
+           const int *__restrict__ tcount) {
   using Tr = SC2Traits<S, TH, N, SMALL>;
   using T = typename Tr::T;
   using C = typename Tr::C;
@@ -100,12 +101,7 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   constexpr int LR = TY + 2;
   __shared__ uint32_t sm[NP * PD];
   const LatTab &L = tab->lat[lat];
-  // dense launches take the XCD-aware tile order; sparse ones (the high-order
-  // set of a mixed run) keep the linear order, which spreads their few active
-  // tiles over all XCDs
-  const int lin = (int)(blockIdx.y * gridDim.x + blockIdx.x);
-  const int tile = remap ? msl_xcd_tile(lin, (int)(gridDim.x * gridDim.y)) : lin;
-  const int bx = tile % (int)gridDim.x, by = tile / (int)gridDim.x;
+  auto tile_body = [&](const int bx, const int by) {
   const int x0 = bx * MSL_TX, y0 = by * TY;
   {
     uint8_t any = 0;
@@ -274,4 +270,25 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     }
   };
   msl_for_planes<NP>(pass2);
+  };
+  if constexpr (LIST) {
+    // sparse launch: the workgroups take the live tiles of a compact list
+    // (ascending tile order) in turn, so no workgroup is spent on a tile
+    // without cells of this set (a contiguous eighth of the list per XCD
+    // measured slower than this interleaved order); the barrier keeps the
+    // next tile's loads out of the LDS until every wave has read the current
+    // windows
+    const int n = *tcount;
+    for (int t = (int)blockIdx.x; t < n; t += (int)gridDim.x) {
+      const int tile = tlist[t];
+      tile_body(tile % g.ntx, tile / g.ntx);
+      __syncthreads();
+    }
+  } else {
+    // dense launches take the XCD-aware tile order; the others the linear
+    // order, which spreads their active tiles over all XCDs
+    const int lin = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    const int tile = remap ? msl_xcd_tile(lin, (int)(gridDim.x * gridDim.y)) : lin;
+    tile_body(tile % (int)gridDim.x, tile / (int)gridDim.x);
+  }
 }

@@ -227,6 +227,25 @@ def test_efficiency_layout_d2q9_d2q25_fp32():
     compare_macros(s, o, 1e-5, uscale=1.0)
 
 
+def test_live_tile_list_large_grid_fp64():
+    """A grid with more than four times as many D2Q25 tiles as fit the GPU at
+    once (1024 x 800: 3200 tiles of 64 x 4 against 768) takes the list-walking
+    launch for the high-order set; the Mach criterion (threshold 0.1, flow up
+    to 0.12, every 3 steps) changes the live tiles, and the steps are split
+    over two calls, so the list is rebuilt within and between calls.  FP64,
+    1e-12 per population."""
+    nx, ny = 1024, 800
+    rho, u, T = inputs.smooth_random_flow(nx, ny, umax=0.12, seed=3, modes=2)
+    cfg = inputs.base_config(nx=nx, ny=ny, n_low=3, n_high=5, tau=0.6, crit_kind=inputs.CRIT_MA,
+                             crit_thr=0.1, crit_every=3)
+    mask = np.zeros((1, ny, nx), np.uint8)
+    mask[:, :, 461:563] = 1
+    s, o = run_pair(cfg, rho, u, T, mask, 4, tag="live-tile list 1024x800 D2Q9/D2Q25")
+    s.step(4)
+    o.step(4)
+    compare_pops(s, o, 1e-12)
+
+
 def test_checkpoint_resume_bitwise():
     from paper_2102_12559_amd import msl
     w = inputs.vortex_c1()
