@@ -140,7 +140,7 @@ struct msl_ctx {
   // launches walk this list instead of the whole tile grid); tl_ok: the list
   // matches the current tile flags
   int *tlist, *tcount;
-  int tl_ok;
+  int tl_ok, tl_n;        // tl_n: host copy of the count, read when the list is built
   // learned closure
   int mlpF, mlpO, mlpH, mlpP, mlp_on, mlp_manual;
   float *mlp_w;           // fp32 master parameters [P]

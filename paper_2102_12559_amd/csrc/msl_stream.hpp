@@ -254,14 +254,22 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
       const long long tiles = (long long)g.ntx * ((g.ny + T2::TY - 1) / T2::TY);
       const long long fit = 256LL * (T2::WGS < 1 ? 1 : T2::WGS);
       if (!small && lat != 0 && tiles > 4 * fit) {
-        // the high-order set on a large grid: as many workgroups as fit the
-        // GPU at once, each walking the list of live tiles (on smaller grids
-        // the one-tile-per-workgroup grid is faster)
+        // the high-order set on a large grid: one workgroup per live tile of
+        // the compact list, whose length is read back (one stream
+        // synchronisation each time the tile flags change, i.e. once per
+        // criterion pass); smaller grids launch the whole tile grid, where
+        // tiles without cells of the set exit at once
         if (!c->tl_ok) {
           if (msl_launch_tile_list(c, lat, T2::R)) return MSL_EHIP;
+          int n = 0;
+          if (hipMemcpyAsync(&n, c->tcount, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+              hipStreamSynchronize(c->stream) != hipSuccess)
+            return MSL_EHIP;
+          c->tl_n = n;
           c->tl_ok = 1;
         }
-        dim3 grid((unsigned)fit);
+        if (c->tl_n == 0) return MSL_OK;
+        dim3 grid((unsigned)c->tl_n);
         hipLaunchKernelGGL((k_sc2d_res<S, TH, N, false, true>), grid, block, 0, c->stream, c->dtab, lat,
                            g, (const S *)in, (S *)out, c->cls, c->tflag, 0, nt, c->tlist, c->tcount);
         return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;

@@ -272,17 +272,15 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   msl_for_planes<NP>(pass2);
   };
   if constexpr (LIST) {
-    // sparse launch: the workgroups take the live tiles of a compact list
-    // (ascending tile order) in turn, so no workgroup is spent on a tile
-    // without cells of this set (a contiguous eighth of the list per XCD
-    // measured slower than this interleaved order); the barrier keeps the
-    // next tile's loads out of the LDS until every wave has read the current
-    // windows
+    // sparse launch: one workgroup per entry of the compact list of live
+    // tiles (ascending tile order), so no workgroup is spent on a tile
+    // without cells of this set; the XCD-aware order over the list gives
+    // each XCD a contiguous run of it (vertically adjacent tiles, whose
+    // windows overlap, share that XCD's L2)
     const int n = *tcount;
-    for (int t = (int)blockIdx.x; t < n; t += (int)gridDim.x) {
-      const int tile = tlist[t];
+    if ((int)blockIdx.x < n) {
+      const int tile = tlist[msl_xcd_tile((int)blockIdx.x, n)];
       tile_body(tile % g.ntx, tile / g.ntx);
-      __syncthreads();
     }
   } else {
     // dense launches take the XCD-aware tile order; the others the linear
