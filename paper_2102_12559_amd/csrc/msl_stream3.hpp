@@ -49,11 +49,12 @@ __device__ __forceinline__ void msl_for_range(F &&f) {
   }(std::make_integer_sequence<int, K1 - K0>{});
 }
 
-template <typename S, bool TH, int N>
+template <typename S, bool TH, int N, bool LIST = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SC3Traits<S, TH, N>::WAVES)))
 k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
            S *__restrict__ out, const uint8_t *__restrict__ cls,
-           const uint8_t *__restrict__ tflag, int remap, int xmir) {
+           const uint8_t *__restrict__ tflag, int remap, int xmir, const int *__restrict__ tlist,
+           const int *__restrict__ tcount) {
   using Tr = SC3Traits<S, TH, N>;
   using T = typename Tr::T;
   using C = typename Tr::C;
@@ -61,10 +62,20 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   constexpr int LWD = Tr::LWD, SZ = Tr::SZ, ROWS = Tr::ROWS;
   __shared__ uint32_t sm[CH * PD];
   const LatTab &L = tab->lat[lat];
-  const int lin = (int)((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
-  const int tile = remap ? msl_xcd_tile(lin, (int)(gridDim.x * gridDim.y * gridDim.z)) : lin;
-  const int bx = tile % (int)gridDim.x, by = (tile / (int)gridDim.x) % (int)gridDim.y;
-  const int z0 = tile / (int)(gridDim.x * gridDim.y);
+  // the tile: from the grid (XCD-aware order for dense launches), or (LIST:
+  // sparse launches on large grids) one workgroup per entry of the compact
+  // list of live tiles, in XCD-aware order over the list
+  int tile;
+  if constexpr (LIST) {
+    const int n = *tcount;
+    if ((int)blockIdx.x >= n) return;
+    tile = tlist[msl_xcd_tile((int)blockIdx.x, n)];
+  } else {
+    const int lin = (int)((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
+    tile = remap ? msl_xcd_tile(lin, (int)(gridDim.x * gridDim.y * gridDim.z)) : lin;
+  }
+  const int bx = tile % g.ntx, by = (tile / g.ntx) % g.nty;
+  const int z0 = tile / (g.ntx * g.nty);
   const int x0 = bx * MSL_TX, y0 = by * MSL_MTY;
   if (!(tflag[((long long)z0 * g.nty + by) * g.ntx + bx] & (1 << lat))) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
