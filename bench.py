@@ -130,19 +130,24 @@ def cpu_baseline(w, seconds_hint):
                        f"initial state, FP64, {dt:.1f} s")
 
 
-PROFILE_EVERY = 16
+def profile_every(steps):
+    """Sampling period of the in-run kernel profile: about 20 sampled steps on
+    short runs, every 100th step on long ones.  Each sampled step records two
+    events per launch from the host, which on a step of ~35 us (the jet) costs
+    more host time than the GPU needs for the step; sampling every 16th step
+    cost the jet 15 % of its throughput, every 100th costs ~2 %."""
+    return max(1, min(100, steps // 20))
 
 
 def timed_steps(s, steps, warmup):
     """Warm up, then time `steps` steps with events on the library's stream.
     Inside the same timed region the library times, with HIP events on its
-    stream, every launch of every 16th step: the per-class kernel profile
-    (event records cost the stream microseconds each, so timing every launch
-    of every step would slow the run it measures)."""
+    stream, every launch of a sample of the steps: the per-class kernel
+    profile."""
     import torch
     s.step(warmup)
     torch.cuda.synchronize()
-    s.profile(True, every=PROFILE_EVERY)
+    s.profile(True, every=profile_every(steps))
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
