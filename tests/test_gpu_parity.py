@@ -149,6 +149,22 @@ def test_3d_small_fp64():
     compare_pops(s, o, 1e-12)
 
 
+@pytest.mark.parametrize("store,tol", [(inputs.STORE_FP32, 1e-5), (inputs.STORE_FP16_DEV, 2e-3)])
+def test_3d_small_reduced_storage(store, tol):
+    """3D D3Q27 + D3Q64 with FP32 storage (1e-5 on rho, u against the FP64
+    oracle) and FP16 deviations (2e-3, the oracle storing the same FP16
+    deviations): 66 x 20 x 12 (a second, partial tile in x), vortex and a
+    D3Q64 slab, 12 steps."""
+    nx, ny, nz = 66, 20, 12
+    rho, u, T = inputs.vortex_fields(nx, ny, nz, eps=0.05, rc=4.0, u0=0.2)
+    cfg = inputs.base_config(dim=3, nx=nx, ny=ny, nz=nz, n_low=3, n_high=4, tau=0.7, store=store)
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    mask[:, 6:13, :] = 1
+    ocfg = dict(cfg, store=inputs.STORE_FP64) if store == inputs.STORE_FP32 else cfg
+    s, o = run_pair(cfg, rho, u, T, mask, 12, oracle_cfg=ocfg, tag=f"3D store={store}")
+    compare_macros(s, o, tol, uscale=1.0)
+
+
 P, ZG = inputs.BC_PERIODIC, inputs.BC_OUTFLOW_ZG
 
 
