@@ -20,8 +20,11 @@
  *  - the caller owns every buffer it passes (workspace, inputs, outputs); the
  *    library allocates no device memory and never frees caller memory;
  *  - all work is enqueued on the HIP stream given to msl_create, in order;
- *    only msl_conservation, msl_get_state/msl_set_state, msl_mlp_train and a
- *    msl_step with check_every > 0 synchronise that stream;
+ *    only msl_conservation, msl_get_state/msl_set_state, msl_mlp_train, a
+ *    msl_step with check_every > 0, and on grids with more tiles than four
+ *    times what the GPU holds at once the first step after each change of the
+ *    velocity-set mask (it reads back the number of live tiles), synchronise
+ *    that stream;
  *  - a context is not thread-safe; use one context per stream;
  *  - cell index = x + nx*(y + ny*z); population index i = a + n*b (+ n*n*c),
  *    a, b, c the ascending 1D node indices along x, y, z; population arrays
