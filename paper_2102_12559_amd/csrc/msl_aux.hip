@@ -690,18 +690,40 @@ __global__ void k_band_count(Geo g, const uint8_t *__restrict__ cls, int *__rest
   }
 }
 
-__global__ void k_band_scan(int *__restrict__ blk, int nblk, int *__restrict__ counts) {
-  // single thread per list: nblk is at most a few thousand
-  const int l = threadIdx.x;
-  if (l > 2) return;
-  int *b = blk + (long long)l * nblk;
-  int run = 0;
-  for (int i = 0; i < nblk; ++i) {
-    const int v = b[i];
-    b[i] = run;
-    run += v;
+__global__ void __launch_bounds__(1024) k_band_scan(int *__restrict__ blk, int nblk, int *__restrict__ counts) {
+  // one workgroup per list (blockIdx.x): exclusive prefix sum of the
+  // per-block counts in chunks of 1024 (shuffle scan within each wave, the
+  // wave totals in LDS, a running carry between chunks); the list length
+  // goes to counts[list]
+  __shared__ int wsum[16];
+  __shared__ int carry;
+  int *b = blk + (long long)blockIdx.x * nblk;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < nblk; c0 += 1024) {
+    const int i = c0 + (int)threadIdx.x;
+    const int v = i < nblk ? b[i] : 0;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(x, d);
+      if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int before = carry;
+    for (int k = 0; k < wv; ++k) before += wsum[k];
+    if (i < nblk) b[i] = before + x - v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int t = 0;
+      for (int k = 0; k < 16; ++k) t += wsum[k];
+      carry += t;
+    }
+    __syncthreads();
   }
-  counts[l] = run;
+  if (threadIdx.x == 0) counts[blockIdx.x] = carry;
 }
 
 __global__ void k_band_scatter(Geo g, const uint8_t *__restrict__ cls, const int *__restrict__ blk,
@@ -1132,7 +1154,7 @@ int msl_launch_classify(msl_ctx *c) {
   c->tl_ok = 0;
   hipLaunchKernelGGL(k_band_count, dim3(c->nblk), dim3(AUX_BLOCK), 0, c->stream, g, c->cls, c->blk,
                      c->nblk);
-  hipLaunchKernelGGL(k_band_scan, dim3(1), dim3(64), 0, c->stream, c->blk, c->nblk, c->bcount);
+  hipLaunchKernelGGL(k_band_scan, dim3(3), dim3(1024), 0, c->stream, c->blk, c->nblk, c->bcount);
   hipLaunchKernelGGL(k_band_scatter, dim3(c->nblk), dim3(64), 0, c->stream, g, c->cls, c->blk,
                      c->nblk, c->blist[0], c->blist[1]);
   return last_err();
