@@ -726,18 +726,39 @@ __global__ void __launch_bounds__(1024) k_band_scan(int *__restrict__ blk, int n
   if (threadIdx.x == 0) counts[blockIdx.x] = carry;
 }
 
-__global__ void k_band_scatter(Geo g, const uint8_t *__restrict__ cls, const int *__restrict__ blk,
-                               int nblk, int *__restrict__ lo, int *__restrict__ hi) {
-  // one wavefront per block walks its 4096 cells in 64-cell chunks, in order
-  const long long base = (long long)blockIdx.x * CMP_CELLS;
-  int off0 = blk[blockIdx.x], off1 = blk[nblk + blockIdx.x];
-  const int lane = threadIdx.x;
-  for (int j = 0; j < CMP_CELLS; j += 64) {
+__global__ void __launch_bounds__(256) k_band_scatter(Geo g, const uint8_t *__restrict__ cls,
+                                                      const int *__restrict__ blk, int nblk,
+                                                      int *__restrict__ lo, int *__restrict__ hi) {
+  // four waves per block, each owning a quarter of its 4096 cells: count the
+  // quarter's band cells, offset each wave by the counts of the waves before
+  // it, then walk the quarter again in 64-cell chunks, in order
+  constexpr int QC = CMP_CELLS / 4;
+  __shared__ int wc[2][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const long long base = (long long)blockIdx.x * CMP_CELLS + (long long)wv * QC;
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  int n0 = 0, n1 = 0;
+  for (int j = 0; j < QC; j += 64) {
     const long long k = base + j + lane;
-    uint8_t v = k < g.ncell ? cls[k] : 0;
+    const uint8_t v = k < g.ncell ? cls[k] : 0;
+    n0 += __popcll(__ballot((v & 2) && !(v & 1)));
+    n1 += __popcll(__ballot((v & 2) && (v & 1)));
+  }
+  if (lane == 0) {
+    wc[0][wv] = n0;
+    wc[1][wv] = n1;
+  }
+  __syncthreads();
+  int off0 = blk[blockIdx.x], off1 = blk[nblk + blockIdx.x];
+  for (int k = 0; k < wv; ++k) {
+    off0 += wc[0][k];
+    off1 += wc[1][k];
+  }
+  for (int j = 0; j < QC; j += 64) {
+    const long long k = base + j + lane;
+    const uint8_t v = k < g.ncell ? cls[k] : 0;
     const bool p0 = (v & 2) && !(v & 1), p1 = (v & 2) && (v & 1);
     const unsigned long long m0 = __ballot(p0), m1 = __ballot(p1);
-    const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
     if (p0) lo[off0 + __popcll(m0 & below)] = (int)k;
     if (p1) hi[off1 + __popcll(m1 & below)] = (int)k;
     off0 += __popcll(m0);
@@ -1155,7 +1176,7 @@ int msl_launch_classify(msl_ctx *c) {
   hipLaunchKernelGGL(k_band_count, dim3(c->nblk), dim3(AUX_BLOCK), 0, c->stream, g, c->cls, c->blk,
                      c->nblk);
   hipLaunchKernelGGL(k_band_scan, dim3(3), dim3(1024), 0, c->stream, c->blk, c->nblk, c->bcount);
-  hipLaunchKernelGGL(k_band_scatter, dim3(c->nblk), dim3(64), 0, c->stream, g, c->cls, c->blk,
+  hipLaunchKernelGGL(k_band_scatter, dim3(c->nblk), dim3(256), 0, c->stream, g, c->cls, c->blk,
                      c->nblk, c->blist[0], c->blist[1]);
   return last_err();
 }
