@@ -30,7 +30,10 @@ struct SC3Traits {
   static constexpr int ROWS = 6 * 3;                                  // (4 + 2) y rows x 3 z slabs
   static constexpr int PD = (ROWS * LWD + 255) / 256 * 256;           // dwords per plane window
   static constexpr int M = PD / 256;                                  // DMA instructions per wave
-  static constexpr int CHMAX = (40 * 1024) / (PD * 4) < 1 ? 1 : (40 * 1024) / (PD * 4);
+  // LDS budget of a chunk: 24 KB for D3Q27 (more workgroups per CU), 40 KB
+  // for D3Q64 (fewer chunks per tile); both measured best on the 256^3 run
+  static constexpr int BUDGET = (N == 3 ? 24 : 40) * 1024;
+  static constexpr int CHMAX = BUDGET / (PD * 4) < 1 ? 1 : BUDGET / (PD * 4);
   static constexpr int NCH = (NP + CHMAX - 1) / CHMAX;                // chunks
   static constexpr int CH = (NP + NCH - 1) / NCH;                     // planes per chunk
   static constexpr int LDS_BYTES = CH * PD * 4;
