@@ -651,10 +651,10 @@ int msl_step(msl_ctx *c, int nsteps) {
     if (rc) { set_err(c, "ghost fill failed"); return rc; }
     if ((rc = prof_end(c, 0, -1, 0.0, 0.0))) return rc;
     // 3D with x periodic on both faces: the new buffer's x ghosts are written
-    // by the step itself (not with the learned lift, whose kernel writes the
-    // lifted band cells without their images)
+    // by the step itself (stream-collide, band conversion and learned lift
+    // store the images of the cells x < 2 and x >= nx - 2)
     c->xmir = c->D == 3 && c->cfg.bc[0] == MSL_BC_PERIODIC && c->cfg.bc[1] == MSL_BC_PERIODIC &&
-              c->geo.nx >= 2 * MSL_G && !(c->cfg.lift_mode == MSL_LIFT_MLP && c->mlp_on);
+              c->geo.nx >= 2 * MSL_G;
     for (int l = 0; l < c->nlat; ++l) {
       // compulsory traffic: read and write every population plane of each native cell
       const double bpc = 2.0 * c->Q[l] * (c->cfg.thermal ? 2 : 1) * (double)c->esz;

@@ -589,7 +589,7 @@ __global__ void __launch_bounds__(64)
 k_band_lift_mlp(const Tab *__restrict__ tab, Geo g, const char *bl, char *bh,
                 const int *__restrict__ list, const int *__restrict__ count,
                 const float *__restrict__ stats, const float *__restrict__ yout,
-                const uint8_t *__restrict__ flags, int nct0, int nct1) {
+                const uint8_t *__restrict__ flags, int nct0, int nct1, int xmir) {
   constexpr int q = Pow<D, NL>::v, Q = Pow<D, NH>::v, F = nfeat<D, NL>(), O = nout<D, NL, NH>();
   const int n = *count;
   const int nct[3] = {nct0, nct1, 1};
@@ -621,6 +621,10 @@ k_band_lift_mlp(const Tab *__restrict__ tab, Geo g, const char *bl, char *bh,
     }
     lift_t<D, NL, NH, TH>(tab, f, gg, dM, fo, go);
     write_cell_t<S, D, NH, TH>(tab, g, bh, 1, off, fo, go);
+    // 3D, x periodic: the image in the ghost column on the other side
+    if constexpr (D == 3)
+      if (xmir && (x < MSL_G || x >= g.nx - MSL_G))
+        write_cell_t<S, D, NH, TH>(tab, g, bh, 1, x < MSL_G ? off + g.nx : off - g.nx, fo, go);
   }
 }
 
@@ -845,7 +849,7 @@ int msl_mlp_band_lift(msl_ctx *c, char *bl, char *bh) {
       return thermal_dispatch(c->cfg.thermal, [&]<bool TH>() {
         hipLaunchKernelGGL((k_band_lift_mlp<S, D, NL, NH, TH>), dim3(2048), dim3(64), 0, c->stream,
                            c->dtab, c->geo, bl, bh, c->blist[0], c->bcount, c->mlp_stats,
-                           c->mlp_out, c->mlp_flag, c->nct[0], c->nct[1]);
+                           c->mlp_out, c->mlp_flag, c->nct[0], c->nct[1], c->xmir);
         return lerr();
       });
     });
