@@ -132,11 +132,18 @@ def cpu_baseline(w, seconds_hint):
 
 def profile_every(steps):
     """Sampling period of the in-run kernel profile: about 20 sampled steps on
-    short runs, every 100th step on long ones.  Each sampled step records two
+    short runs, every 99th step on long ones.  Each sampled step records two
     events per launch from the host, which on a step of ~35 us (the jet) costs
     more host time than the GPU needs for the step; sampling every 16th step
-    cost the jet 15 % of its throughput, every 100th costs ~2 %."""
-    return max(1, min(100, steps // 20))
+    cost the jet 15 % of its throughput, every 99th costs ~2 %.  The period is
+    odd and not a multiple of 5, so that it is coprime with the criterion and
+    check periods (20): the samples see every phase of that cycle."""
+    p = max(1, min(99, steps // 20))
+    if p > 1 and p % 2 == 0:
+        p -= 1
+    if p > 1 and p % 5 == 0:
+        p -= 2
+    return p
 
 
 def timed_steps(s, steps, warmup):
