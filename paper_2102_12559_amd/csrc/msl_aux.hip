@@ -1028,7 +1028,7 @@ k_band_convert_t(const Tab *__restrict__ tab, Geo g, char *bl, char *bh,
 template <typename S, int D, int NL, int NH, bool TH>
 __global__ void __launch_bounds__(AUX_BLOCK)
 k_switch_t(const Tab *__restrict__ tab, Geo g, char *bl, char *bh, uint8_t *__restrict__ cls,
-           const uint8_t *__restrict__ newmask, int convert) {
+           const uint8_t *__restrict__ newmask, int convert, int xmir) {
   constexpr int q = Pow<D, NL>::v, Q = Pow<D, NH>::v;
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= g.ncell) return;
@@ -1037,16 +1037,24 @@ k_switch_t(const Tab *__restrict__ tab, Geo g, char *bl, char *bh, uint8_t *__re
     int x, y, z;
     cell_coords(g, k, x, y, z);
     const int off = g.idx(x, y, z);
+    // 3D, x periodic: the converted cell's image in the ghost column on the
+    // other side (the x ghosts of the current buffer stay current)
+    const bool img = D == 3 && xmir && (x < MSL_G || x >= g.nx - MSL_G);
+    const int ioff = x < MSL_G ? off + g.nx : off - g.nx;
     if (to == 1) {
       double f[q], gg[TH ? q : 1], fo[Q], go[TH ? Q : 1];
       read_cell_t<S, D, NL, TH>(tab, g, bl, 0, off, f, gg);
       lift_t<D, NL, NH, TH>(tab, f, gg, nullptr, fo, go);
       write_cell_t<S, D, NH, TH>(tab, g, bh, 1, off, fo, go);
+      if constexpr (D == 3)
+        if (img) write_cell_t<S, D, NH, TH>(tab, g, bh, 1, ioff, fo, go);
     } else {
       double f[Q], gg[TH ? Q : 1], fo[q], go[TH ? q : 1];
       read_cell_t<S, D, NH, TH>(tab, g, bh, 1, off, f, gg);
       project_t<D, NL, NH, TH>(tab, f, gg, fo, go);
       write_cell_t<S, D, NL, TH>(tab, g, bl, 0, off, fo, go);
+      if constexpr (D == 3)
+        if (img) write_cell_t<S, D, NL, TH>(tab, g, bl, 0, ioff, fo, go);
     }
   }
   cls[k] = (uint8_t)to;
@@ -1072,10 +1080,10 @@ static int switch_s(msl_ctx *c, char *bl, char *bh, const uint8_t *newmask, int 
   return msl_pair_dispatch(c->D, c->htab.lat[0].n, c->htab.lat[1].n, [&]<int D, int NL, int NH>() {
     if (c->cfg.thermal)
       hipLaunchKernelGGL((k_switch_t<S, D, NL, NH, true>), dim3(nblocks(c->ncell)), dim3(AUX_BLOCK),
-                         0, c->stream, c->dtab, c->geo, bl, bh, c->cls, newmask, convert);
+                         0, c->stream, c->dtab, c->geo, bl, bh, c->cls, newmask, convert, c->xmir);
     else
       hipLaunchKernelGGL((k_switch_t<S, D, NL, NH, false>), dim3(nblocks(c->ncell)), dim3(AUX_BLOCK),
-                         0, c->stream, c->dtab, c->geo, bl, bh, c->cls, newmask, convert);
+                         0, c->stream, c->dtab, c->geo, bl, bh, c->cls, newmask, convert, c->xmir);
     return last_err();
   });
 }

@@ -622,15 +622,19 @@ int msl_step(msl_ctx *c, int nsteps) {
   if (!c || nsteps < 0) return MSL_EINVAL;
   if (!c->initialized) { set_err(c, "msl_step before msl_init"); return MSL_ESTATE; }
   // the x ghost columns of the current buffer are taken as stale on entry
-  // (the state may have been set since the last step) and after switching;
-  // the live-tile list is rebuilt on first use
+  // (the state may have been set since the last step); the live-tile list is
+  // rebuilt on first use
   c->xg_ok = 0;
   c->tl_ok = 0;
   for (int s = 0; s < nsteps; ++s) {
     int rc;
+    // 3D with x periodic on both faces: the x ghosts are kept current by the
+    // kernels that write cells (switching, stream-collide, band conversion and
+    // learned lift store the images of the cells x < 2 and x >= nx - 2)
+    c->xmir = c->D == 3 && c->cfg.bc[0] == MSL_BC_PERIODIC && c->cfg.bc[1] == MSL_BC_PERIODIC &&
+              c->geo.nx >= 2 * MSL_G;
     if (c->cfg.crit_kind && c->cfg.crit_every > 0 && c->nlat > 1 && c->step % c->cfg.crit_every == 0) {
       prof_begin(c);
-      c->xg_ok = 0;
       rc = mask_step(c);
       if (rc) { set_err(c, "criterion / switching failed"); return rc; }
       prof_snap(c);
@@ -650,11 +654,6 @@ int msl_step(msl_ctx *c, int nsteps) {
     rc = msl_launch_bc(c, bl, bh);
     if (rc) { set_err(c, "ghost fill failed"); return rc; }
     if ((rc = prof_end(c, 0, -1, 0.0, 0.0))) return rc;
-    // 3D with x periodic on both faces: the new buffer's x ghosts are written
-    // by the step itself (stream-collide, band conversion and learned lift
-    // store the images of the cells x < 2 and x >= nx - 2)
-    c->xmir = c->D == 3 && c->cfg.bc[0] == MSL_BC_PERIODIC && c->cfg.bc[1] == MSL_BC_PERIODIC &&
-              c->geo.nx >= 2 * MSL_G;
     for (int l = 0; l < c->nlat; ++l) {
       // compulsory traffic: read and write every population plane of each native cell
       const double bpc = 2.0 * c->Q[l] * (c->cfg.thermal ? 2 : 1) * (double)c->esz;
