@@ -291,25 +291,27 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
     using T3 = SC3Traits<S, TH, N>;
     const long long tiles = (long long)g.ntx * g.nty * g.ntz;
     const long long fit = 256LL * ((160 * 1024) / T3::LDS_BYTES);
-    if (lat != 0 && tiles > 4 * fit) {
-      if (!c->tl_ok) {
-        if (msl_launch_tile_list(c, lat, 1)) return MSL_EHIP;
-        int n = 0;
-        if (hipMemcpyAsync(&n, c->tcount, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-            hipStreamSynchronize(c->stream) != hipSuccess)
-          return MSL_EHIP;
-        c->tl_n = n;
-        c->tl_ok = 1;
+    if constexpr (T3::RZ == 1) {
+      if (lat != 0 && tiles > 4 * fit) {
+        if (!c->tl_ok) {
+          if (msl_launch_tile_list(c, lat, 1)) return MSL_EHIP;
+          int n = 0;
+          if (hipMemcpyAsync(&n, c->tcount, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+              hipStreamSynchronize(c->stream) != hipSuccess)
+            return MSL_EHIP;
+          c->tl_n = n;
+          c->tl_ok = 1;
+        }
+        if (c->tl_n == 0) return MSL_OK;
+        hipLaunchKernelGGL((k_sc3d_res<S, TH, N, true>), dim3((unsigned)c->tl_n), block, 0, c->stream,
+                           c->dtab, lat, g, (const S *)in, (S *)out, c->cls, c->tflag, 0, c->xmir,
+                           c->tlist, c->tcount);
+        return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
       }
-      if (c->tl_n == 0) return MSL_OK;
-      hipLaunchKernelGGL((k_sc3d_res<S, TH, N, true>), dim3((unsigned)c->tl_n), block, 0, c->stream,
-                         c->dtab, lat, g, (const S *)in, (S *)out, c->cls, c->tflag, 0, c->xmir,
-                         c->tlist, c->tcount);
-    } else {
-      dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + MSL_MTY - 1) / MSL_MTY, g.nz);
-      hipLaunchKernelGGL((k_sc3d_res<S, TH, N>), grid, block, 0, c->stream, c->dtab, lat, g,
-                         (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, c->xmir, nullptr, nullptr);
     }
+    dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + MSL_MTY - 1) / MSL_MTY, (g.nz + T3::RZ - 1) / T3::RZ);
+    hipLaunchKernelGGL((k_sc3d_res<S, TH, N>), grid, block, 0, c->stream, c->dtab, lat, g,
+                       (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, c->xmir, nullptr, nullptr);
   }
   return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
 }

@@ -1,9 +1,10 @@
 // msl_stream3.hpp -- the 3D stream-and-collide kernel: population planes
 // streamed through LDS in chunks, the reconstructed values held in registers.
 //
-// A workgroup owns 64 x 4 x 1 cells, one cell per lane.  The planes
+// A workgroup owns 64 x 4 x RZ cells, RZ cells per lane along z (2 for D3Q27,
+// 1 for D3Q64).  The planes
 // (f_0..f_{Q-1}, then g_0..g_{Q-1}) are taken CH at a time: direct-to-LDS
-// buffer loads of every plane's 66 x 6 x 3 window around the departure points
+// buffer loads of every plane's 66 x 6 x (RZ + 2) window around the departure points
 // of the tile (the departure offset x - c_i dt is the same for every cell of a
 // plane), one wait and barrier, the separable 3-point Lagrange reconstruction
 // (eq. reconstructionPond: along x on nine rows, then y, then z) of each
@@ -27,18 +28,23 @@ struct SC3Traits {
   static constexpr int NP = TH ? 2 * Q : Q;
   static constexpr int SZ = (int)sizeof(S);
   static constexpr int LWD = (66 * SZ + 3) / 4 + (SZ < 4 ? 1 : 0);   // dwords per window row
-  static constexpr int ROWS = 6 * 3;                                  // (4 + 2) y rows x 3 z slabs
+  // z cells per lane: D3Q27 tiles are 64 x 4 x 2 (the four z slabs of the
+  // window serve two cells, where a 64 x 4 x 1 tile reads three slabs for
+  // one: a third fewer window reads); D3Q64 keeps one cell per lane (its
+  // reconstructed values would not fit the registers twice)
+  static constexpr int RZ = N == 3 ? 2 : 1;
+  static constexpr int ROWS = 6 * (RZ + 2);                           // (4 + 2) y rows x (RZ + 2) z slabs
   static constexpr int PD = (ROWS * LWD + 255) / 256 * 256;           // dwords per plane window
   static constexpr int M = PD / 256;                                  // DMA instructions per wave
-  // LDS budget of a chunk: 24 KB for D3Q27 (more workgroups per CU), 40 KB
-  // for D3Q64 (fewer chunks per tile); both measured best on the 256^3 run
+  // LDS budget of a chunk: 24 KB for D3Q27, 40 KB for D3Q64 (measured on the
+  // 256^3 run; D3Q27 with two cells per lane is insensitive to 24-48 KB)
   static constexpr int BUDGET = (N == 3 ? 24 : 40) * 1024;
   static constexpr int CHMAX = BUDGET / (PD * 4) < 1 ? 1 : BUDGET / (PD * 4);
   static constexpr int NCH = (NP + CHMAX - 1) / CHMAX;                // chunks
   static constexpr int CH = (NP + NCH - 1) / NCH;                     // planes per chunk
   static constexpr int LDS_BYTES = CH * PD * 4;
   static constexpr int REGW = SZ == 8 ? 2 : 1;
-  static constexpr int VREG = NP * REGW + 80;
+  static constexpr int VREG = NP * REGW * RZ + 80;
   static constexpr int WG_LDS = (160 * 1024) / LDS_BYTES;
   static constexpr int W_REG = 512 / VREG;
   static constexpr int WAVES0 = WG_LDS < W_REG ? WG_LDS : W_REG;
@@ -62,7 +68,8 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   using T = typename Tr::T;
   using C = typename Tr::C;
   constexpr int Q = Tr::Q, NP = Tr::NP, PD = Tr::PD, M = Tr::M, CH = Tr::CH, NCH = Tr::NCH;
-  constexpr int LWD = Tr::LWD, SZ = Tr::SZ, ROWS = Tr::ROWS;
+  constexpr int LWD = Tr::LWD, SZ = Tr::SZ, ROWS = Tr::ROWS, RZ = Tr::RZ;
+  static_assert(!LIST || RZ == 1, "the live-tile list holds one-plane tiles");
   __shared__ uint32_t sm[CH * PD];
   const LatTab &L = tab->lat[lat];
   // the tile: from the grid (XCD-aware order for dense launches), or (LIST:
@@ -78,9 +85,15 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     tile = remap ? msl_xcd_tile(lin, (int)(gridDim.x * gridDim.y * gridDim.z)) : lin;
   }
   const int bx = tile % g.ntx, by = (tile / g.ntx) % g.nty;
-  const int z0 = tile / (g.ntx * g.nty);
+  const int z0 = tile / (g.ntx * g.nty) * RZ;
   const int x0 = bx * MSL_TX, y0 = by * MSL_MTY;
-  if (!(tflag[((long long)z0 * g.nty + by) * g.ntx + bx] & (1 << lat))) return;
+  {
+    uint8_t any = 0;
+#pragma unroll
+    for (int rz = 0; rz < RZ; ++rz)
+      if (z0 + rz < g.nz) any |= tflag[((long long)(z0 + rz) * g.nty + by) * g.ntx + bx];
+    if (!(any & (1 << lat))) return;
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const unsigned pitch_b = (unsigned)g.pitch * SZ;
   const unsigned plane_b = (unsigned)g.plane * SZ;
@@ -94,9 +107,14 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     const int rz = row / 6, ry = row - 6 * rz;
     voff[m] = ((unsigned)rz * (unsigned)g.rows + (unsigned)ry) * pitch_b + (unsigned)col * 4u;
   }
-  const int x = x0 + lane, y = y0 + w, z = z0;
-  const bool inside = x < g.nx && y < g.ny;
-  const bool mine = inside && (cls[inside ? ((long long)z * g.ny + y) * g.nx + x : 0] & 1) == lat;
+  const int x = x0 + lane, y = y0 + w;
+  bool mine[RZ];
+#pragma unroll
+  for (int rz = 0; rz < RZ; ++rz) {
+    const int z = z0 + rz;
+    const bool inside = x < g.nx && y < g.ny && z < g.nz;
+    mine[rz] = inside && (cls[inside ? ((long long)z * g.ny + y) * g.nx + x : 0] & 1) == lat;
+  }
 
   // per-node tables shared by the three axes: interpolation weights and the
   // window offset of the departure stencil along each axis
@@ -129,7 +147,7 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
             (int)(org & ~3u), 0, 0);
     }
   };
-  C ftk[NP];   // reconstructed populations (storage domain)
+  C ftk[NP][RZ];   // reconstructed populations (storage domain)
   auto recon = [&]<int K>() {
     constexpr int i = K % Q, a = i % N, b = (i / N) % N, cc = i / (N * N);
     const unsigned org = (unsigned)(org0 + offx[a] + offy[b] + offz[cc]) * SZ;
@@ -139,9 +157,9 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     asm volatile("" : "+v"(lofs));
     const char *base = (const char *)sm + lofs;
     const C wx0 = wlo[a], wx2 = whi[a], wy0 = wlo[b], wy2 = whi[b], wz0 = wlo[cc], wz2 = whi[cc];
-    C hz[3];
+    C hz[RZ + 2];   // x- then y-interpolated values of the window's z slabs
 #pragma unroll
-    for (int dz = 0; dz < 3; ++dz) {
+    for (int dz = 0; dz < RZ + 2; ++dz) {
       C hy[3];
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy) {
@@ -157,11 +175,14 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
       }
       hz[dz] = hy[1] + wy0 * (hy[0] - hy[1]) + wy2 * (hy[2] - hy[1]);
     }
-    ftk[K] = hz[1] + wz0 * (hz[0] - hz[1]) + wz2 * (hz[2] - hz[1]);
-    // the value is final here: without this the interpolation would be sunk
-    // to its first use after the last chunk, keeping every window value of
-    // every plane alive until then
-    asm volatile("" : "+v"(ftk[K]));
+#pragma unroll
+    for (int rz = 0; rz < RZ; ++rz) {
+      ftk[K][rz] = hz[rz + 1] + wz0 * (hz[rz] - hz[rz + 1]) + wz2 * (hz[rz + 2] - hz[rz + 1]);
+      // the value is final here: without this the interpolation would be sunk
+      // to its first use after the last chunk, keeping every window value of
+      // every plane alive until then
+      asm volatile("" : "+v"(ftk[K][rz]));
+    }
   };
   auto chunk = [&]<int CI>() {
     constexpr int k0 = CI * CH, k1 = k0 + CH < NP ? k0 + CH : NP;
@@ -172,23 +193,30 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   };
   msl_for_planes<NCH>(chunk);
 
-  // moments (Sec. II.B)
   const C rho0 = (C)tab->rho0;
   const C gsc0 = (C)(tab->gfac * tab->rho0 * tab->T0);
+  // periodic x (xmir, nx >= 4): the cells x < 2 and x >= nx - 2 are also
+  // stored into the ghost columns of the other side, which the next step's
+  // windows read; only the tiles at the two x ends take the second store
+  const bool xedge = xmir && (x0 < MSL_G || x0 + MSL_TX > g.nx - MSL_G);
+  // moments, equilibrium, collision and stores of the lane's cell z0 + rz
+  auto finish = [&]<int rz>() {
+  const int z = z0 + rz;
+  // moments (Sec. II.B)
   C rho = C(0), jx = C(0), jy = C(0), jz = C(0), en = C(0);
   auto moments = [&]<int K>() {
     constexpr int i = K % Q, a = i % N, b = (i / N) % N, cc = i / (N * N);
     const C W = tsel<C>(L.w[a], L.wf[a]) * tsel<C>(L.w[b], L.wf[b]) * tsel<C>(L.w[cc], L.wf[cc]);
     if constexpr (K < Q) {
       const C cx = tsel<C>(L.c[a], L.cf[a]), cy = tsel<C>(L.c[b], L.cf[b]), cz = tsel<C>(L.c[cc], L.cf[cc]);
-      const C f = T::dev ? rho0 * W * (C(1) + ftk[K]) : ftk[K];
+      const C f = T::dev ? rho0 * W * (C(1) + ftk[K][rz]) : ftk[K][rz];
       rho += f;
       jx += cx * f;
       jy += cy * f;
       jz += cz * f;
       if (TH) en += C(0.5) * (cx * cx + cy * cy + cz * cz) * f;
     } else {
-      en += T::dev ? gsc0 * W * (C(1) + ftk[K]) : ftk[K];
+      en += T::dev ? gsc0 * W * (C(1) + ftk[K][rz]) : ftk[K][rz];
     }
   };
   msl_for_planes<NP>(moments);
@@ -217,13 +245,9 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     }
   }
   const C gf = (C)(tab->gfac * Tm);
-  const unsigned soff = mine ? (unsigned)g.idx(x, y, z) * SZ : 0x80000000u;
-  // periodic x (xmir, nx >= 4): the cells x < 2 and x >= nx - 2 are also
-  // stored into the ghost columns of the other side, which the next step's
-  // windows read; only the tiles at the two x ends take the second store
-  const bool xedge = xmir && (x0 < MSL_G || x0 + MSL_TX > g.nx - MSL_G);
-  const unsigned ioff = (mine && x < MSL_G) ? soff + (unsigned)g.nx * SZ
-                        : (mine && x >= g.nx - MSL_G) ? soff - (unsigned)g.nx * SZ : 0x80000000u;
+  const unsigned soff = mine[rz] ? (unsigned)g.idx(x, y, z) * SZ : 0x80000000u;
+  const unsigned ioff = (mine[rz] && x < MSL_G) ? soff + (unsigned)g.nx * SZ
+                        : (mine[rz] && x >= g.nx - MSL_G) ? soff - (unsigned)g.nx * SZ : 0x80000000u;
   // collide and store
   auto store = [&]<int K>() {
     constexpr int i = K % Q, a = i % N, b = (i / N) % N, cc = i / (N * N);
@@ -231,7 +255,7 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     const C sc = K < Q ? rho0 * W : gsc0 * W;
     const C isc = T::dev ? C(1) / sc : C(1);
     const C feq = Px[a] * Py[b] * Pz[cc];
-    const C v = T::dev ? sc * (C(1) + ftk[K]) : ftk[K];
+    const C v = T::dev ? sc * (C(1) + ftk[K][rz]) : ftk[K][rz];
     C vo;
     if constexpr (K < Q) vo = v + om * (feq - v);
     else vo = v + om * (gf * feq - v);
@@ -252,4 +276,6 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     if (xedge) put(ioff);
   };
   msl_for_planes<NP>(store);
+  };
+  msl_for_planes<RZ>(finish);
 }
