@@ -28,11 +28,13 @@ struct SC3Traits {
   static constexpr int NP = TH ? 2 * Q : Q;
   static constexpr int SZ = (int)sizeof(S);
   static constexpr int LWD = (66 * SZ + 3) / 4 + (SZ < 4 ? 1 : 0);   // dwords per window row
-  // z cells per lane: D3Q27 tiles are 64 x 4 x 2 (the four z slabs of the
-  // window serve two cells, where a 64 x 4 x 1 tile reads three slabs for
-  // one: a third fewer window reads); D3Q64 keeps one cell per lane (its
-  // reconstructed values would not fit the registers twice)
-  static constexpr int RZ = N == 3 ? 2 : 1;
+  // z cells per lane: a D3Q27 tile is 64 x 4 x RZ cells, whose window's
+  // RZ + 2 z slabs serve RZ cells (a 64 x 4 x 1 tile reads three slabs for
+  // one cell); RZ = 3 for 16-bit storage, 4 for FP32, 2 for FP64 (measured
+  // on the 256^3 run; the register budget bounds it), and 2 (1 in FP64) with
+  // the g populations.  D3Q64 keeps one cell per lane: its reconstructed
+  // values would not fit the registers twice.
+  static constexpr int RZ = N != 3 ? 1 : TH ? (SZ == 8 ? 1 : 2) : (SZ == 2 ? 3 : (SZ == 4 ? 4 : 2));
   static constexpr int ROWS = 6 * (RZ + 2);                           // (4 + 2) y rows x (RZ + 2) z slabs
   static constexpr int PD = (ROWS * LWD + 255) / 256 * 256;           // dwords per plane window
   static constexpr int M = PD / 256;                                  // DMA instructions per wave
