@@ -582,17 +582,17 @@ __global__ void k_order_extrema(Geo g, int ax, int bc_periodic_mask, const uint8
 }
 
 // The live tiles of velocity set `lat` in ascending order: a launch tile is
-// 64 x 4R cells (2D) or one 64 x 4 micro-tile of a z plane (3D, R = 1) and
-// live when one of its micro-tiles holds a cell of the set.  One workgroup
-// compacts the tile grid in chunks of 1024 (wave ballots, then the wave
-// totals in LDS); the list holds (z * rows + by) * ntx + bx.
+// 64 x 4R cells (2D) or 64 x 4 x RZ cells (3D, R = 1) and live when one of
+// its micro-tiles holds a cell of the set.  One workgroup compacts the tile
+// grid in chunks of 1024 (wave ballots, then the wave totals in LDS); the
+// list holds (bz * rows + by) * ntx + bx.
 __global__ void __launch_bounds__(1024)
-k_tile_list(Geo g, const uint8_t *__restrict__ tflag, int lat, int R, int *__restrict__ list,
+k_tile_list(Geo g, const uint8_t *__restrict__ tflag, int lat, int R, int RZ, int *__restrict__ list,
             int *__restrict__ count) {
   __shared__ int wsum[16];
   __shared__ int base;
   const int rows = (g.nty + R - 1) / R;
-  const int ntiles = g.ntx * rows * g.ntz;
+  const int ntiles = g.ntx * rows * ((g.ntz + RZ - 1) / RZ);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (threadIdx.x == 0) base = 0;
   __syncthreads();
@@ -602,9 +602,13 @@ k_tile_list(Geo g, const uint8_t *__restrict__ tflag, int lat, int R, int *__res
     if (t < ntiles) {
       const int bx = t % g.ntx, rest = t / g.ntx, by = rest % rows, bz = rest / rows;
       uint8_t any = 0;
-      for (int r = 0; r < R; ++r) {
-        const int my = by * R + r;
-        if (my < g.nty) any |= tflag[((long long)bz * g.nty + my) * g.ntx + bx];
+      for (int rz = 0; rz < RZ; ++rz) {
+        const int mz = bz * RZ + rz;
+        if (mz < g.ntz)
+          for (int r = 0; r < R; ++r) {
+            const int my = by * R + r;
+            if (my < g.nty) any |= tflag[((long long)mz * g.nty + my) * g.ntx + bx];
+          }
       }
       live = (any >> lat) & 1;
     }
@@ -626,9 +630,9 @@ k_tile_list(Geo g, const uint8_t *__restrict__ tflag, int lat, int R, int *__res
   if (threadIdx.x == 0) *count = base;
 }
 
-int msl_launch_tile_list(msl_ctx *c, int lat, int rows_per_tile) {
+int msl_launch_tile_list(msl_ctx *c, int lat, int rows_per_tile, int planes_per_tile) {
   hipLaunchKernelGGL(k_tile_list, dim3(1), dim3(1024), 0, c->stream, c->geo, c->tflag, lat, rows_per_tile,
-                     c->tlist, c->tcount);
+                     planes_per_tile, c->tlist, c->tcount);
   return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
 }
 

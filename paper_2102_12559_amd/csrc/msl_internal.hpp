@@ -172,7 +172,7 @@ struct msl_ctx {
 
 // launch helpers implemented in the .hip files
 int msl_launch_stream_collide(msl_ctx *c, int lat, const char *in, char *out);
-int msl_launch_tile_list(msl_ctx *c, int lat, int rows_per_tile);
+int msl_launch_tile_list(msl_ctx *c, int lat, int rows_per_tile, int planes_per_tile);
 int msl_launch_bc(msl_ctx *c, char *buf_low, char *buf_high);
 int msl_launch_bc_fixed(msl_ctx *c);
 int msl_launch_band_convert(msl_ctx *c, char *buf_low, char *buf_high);

@@ -260,7 +260,7 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
         // criterion pass); smaller grids launch the whole tile grid, where
         // tiles without cells of the set exit at once
         if (!c->tl_ok) {
-          if (msl_launch_tile_list(c, lat, T2::R)) return MSL_EHIP;
+          if (msl_launch_tile_list(c, lat, T2::R, 1)) return MSL_EHIP;
           int n = 0;
           if (hipMemcpyAsync(&n, c->tcount, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
               hipStreamSynchronize(c->stream) != hipSuccess)
@@ -289,12 +289,12 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
     // 3D: planes streamed through LDS in chunks; the high-order set of a
     // large grid runs over the compact list of its live tiles (as in 2D)
     using T3 = SC3Traits<S, TH, N>;
-    const long long tiles = (long long)g.ntx * g.nty * g.ntz;
+    const long long tiles = (long long)g.ntx * g.nty * ((g.ntz + T3::RZ - 1) / T3::RZ);
     const long long fit = 256LL * ((160 * 1024) / T3::LDS_BYTES);
-    if constexpr (T3::RZ == 1) {
+    {
       if (lat != 0 && tiles > 4 * fit) {
         if (!c->tl_ok) {
-          if (msl_launch_tile_list(c, lat, 1)) return MSL_EHIP;
+          if (msl_launch_tile_list(c, lat, 1, T3::RZ)) return MSL_EHIP;
           int n = 0;
           if (hipMemcpyAsync(&n, c->tcount, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
               hipStreamSynchronize(c->stream) != hipSuccess)

@@ -32,9 +32,10 @@ struct SC3Traits {
   // RZ + 2 z slabs serve RZ cells (a 64 x 4 x 1 tile reads three slabs for
   // one cell); RZ = 3 for 16-bit storage, 4 for FP32, 2 for FP64 (measured
   // on the 256^3 run; the register budget bounds it), and 2 (1 in FP64) with
-  // the g populations.  D3Q64 keeps one cell per lane: its reconstructed
-  // values would not fit the registers twice.
-  static constexpr int RZ = N != 3 ? 1 : TH ? (SZ == 8 ? 1 : 2) : (SZ == 2 ? 3 : (SZ == 4 ? 4 : 2));
+  // the g populations.  D3Q64: two cells per lane in FP32, one otherwise
+  // (measured; with 16-bit storage the extra registers cost more than the
+  // saved reads).
+  static constexpr int RZ = N != 3 ? (!TH && SZ == 4 ? 2 : 1) : TH ? (SZ == 8 ? 1 : 2) : (SZ == 2 ? 3 : (SZ == 4 ? 4 : 2));
   static constexpr int ROWS = 6 * (RZ + 2);                           // (4 + 2) y rows x (RZ + 2) z slabs
   static constexpr int PD = (ROWS * LWD + 255) / 256 * 256;           // dwords per plane window
   static constexpr int M = PD / 256;                                  // DMA instructions per wave
@@ -71,7 +72,6 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   using C = typename Tr::C;
   constexpr int Q = Tr::Q, NP = Tr::NP, PD = Tr::PD, M = Tr::M, CH = Tr::CH, NCH = Tr::NCH;
   constexpr int LWD = Tr::LWD, SZ = Tr::SZ, ROWS = Tr::ROWS, RZ = Tr::RZ;
-  static_assert(!LIST || RZ == 1, "the live-tile list holds one-plane tiles");
   __shared__ uint32_t sm[CH * PD];
   const LatTab &L = tab->lat[lat];
   // the tile: from the grid (XCD-aware order for dense launches), or (LIST:
