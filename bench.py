@@ -566,7 +566,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus above 1 is not supported "
                                    "(the domain-decomposed multi-GPU step is a design only)"}))
         sys.exit(2)
 

@@ -61,7 +61,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"libmsl.so not built at {LIB_PATH}; run __graft_entry__.build()")
+            raise ImportError(f"libmsl.so not built at {LIB_PATH}; run python paper_2102_12559_amd/build.py")
         L = C.CDLL(LIB_PATH)
         vp, sz = C.c_void_p, C.c_size_t
         L.msl_workspace_bytes.argtypes = [C.POINTER(MslConfig), C.POINTER(sz)]
