@@ -159,6 +159,7 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     const char *base = (const char *)(sm + K * PD) + (org & 3u);
     const C wx0 = tsel<C>(L.a[a][0], L.af[a][0]), wx2 = tsel<C>(L.a[a][2], L.af[a][2]);
     const C wy0 = tsel<C>(L.a[b][0], L.af[b][0]), wy2 = tsel<C>(L.a[b][2], L.af[b][2]);
+    const C wx1 = tsel<C>(L.a[a][1], L.af[a][1]), wy1 = tsel<C>(L.a[b][1], L.af[b][1]);
     C h[R + 2];
 #pragma unroll
     for (int r = 0; r < R + 2; ++r) {
@@ -169,11 +170,18 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
       } else {
         v0 = (C)lds_elem<S>(row); v1 = (C)lds_elem<S>(row + SZ); v2 = (C)lds_elem<S>(row + 2 * SZ);
       }
-      // differenced form: centre weight 1 - w0 - w2 exactly
-      h[r] = v1 + wx0 * (v0 - v1) + wx2 * (v2 - v1);
+      // FP32 / FP64: the differenced form, centre weight 1 - w0 - w2 exactly;
+      // 16-bit deviations: the three weights (one operation fewer per row on
+      // the arithmetic-bound 16-bit path; the difference is below the storage
+      // rounding)
+      if constexpr (SZ == 2) h[r] = wx0 * v0 + wx1 * v1 + wx2 * v2;
+      else h[r] = v1 + wx0 * (v0 - v1) + wx2 * (v2 - v1);
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) ft[r] = h[r + 1] + wy0 * (h[r] - h[r + 1]) + wy2 * (h[r + 2] - h[r + 1]);
+    for (int r = 0; r < R; ++r) {
+      if constexpr (SZ == 2) ft[r] = wy0 * h[r] + wy1 * h[r + 1] + wy2 * h[r + 2];
+      else ft[r] = h[r + 1] + wy0 * (h[r] - h[r + 1]) + wy2 * (h[r + 2] - h[r + 1]);
+    }
   };
 
   const C rho0 = (C)tab->rho0;
