@@ -120,11 +120,12 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
 
   // per-node tables shared by the three axes: interpolation weights and the
   // window offset of the departure stencil along each axis
-  C wlo[N], whi[N];
+  C wlo[N], wmid[N], whi[N];
   int offx[N], offy[N], offz[N];
 #pragma unroll
   for (int a = 0; a < N; ++a) {
     wlo[a] = tsel<C>(L.a[a][0], L.af[a][0]);
+    wmid[a] = tsel<C>(L.a[a][1], L.af[a][1]);
     whi[a] = tsel<C>(L.a[a][2], L.af[a][2]);
     offx[a] = L.n0[a] - 1;
     offy[a] = (L.n0[a] - 1) * g.pitch;
@@ -172,14 +173,18 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
         } else {
           v0 = (C)lds_elem<S>(row); v1 = (C)lds_elem<S>(row + SZ); v2 = (C)lds_elem<S>(row + 2 * SZ);
         }
-        // differenced form: centre weight 1 - w0 - w2 exactly
-        hy[dy] = v1 + wx0 * (v0 - v1) + wx2 * (v2 - v1);
+        // FP32 / FP64: differenced form, centre weight 1 - w0 - w2 exactly;
+        // 16-bit deviations: the three weights (one operation fewer)
+        if constexpr (SZ == 2) hy[dy] = wx0 * v0 + wmid[a] * v1 + wx2 * v2;
+        else hy[dy] = v1 + wx0 * (v0 - v1) + wx2 * (v2 - v1);
       }
-      hz[dz] = hy[1] + wy0 * (hy[0] - hy[1]) + wy2 * (hy[2] - hy[1]);
+      if constexpr (SZ == 2) hz[dz] = wy0 * hy[0] + wmid[b] * hy[1] + wy2 * hy[2];
+      else hz[dz] = hy[1] + wy0 * (hy[0] - hy[1]) + wy2 * (hy[2] - hy[1]);
     }
 #pragma unroll
     for (int rz = 0; rz < RZ; ++rz) {
-      ftk[K][rz] = hz[rz + 1] + wz0 * (hz[rz] - hz[rz + 1]) + wz2 * (hz[rz + 2] - hz[rz + 1]);
+      if constexpr (SZ == 2) ftk[K][rz] = wz0 * hz[rz] + wmid[cc] * hz[rz + 1] + wz2 * hz[rz + 2];
+      else ftk[K][rz] = hz[rz + 1] + wz0 * (hz[rz] - hz[rz + 1]) + wz2 * (hz[rz + 2] - hz[rz + 1]);
       // the value is final here: without this the interpolation would be sunk
       // to its first use after the last chunk, keeping every window value of
       // every plane alive until then
