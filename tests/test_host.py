@@ -41,3 +41,30 @@ def test_init_params_glorot_range():
     b1 = p[F * H:F * H + H]
     assert np.all(b1 == 0)
     assert p.size == F * H + H + H * H + H + H * O + O
+
+
+def test_profile_period_is_coprime_with_the_criterion_period():
+    import bench
+    for steps in (100, 200, 400, 2000, 20000):
+        p = bench.profile_every(steps)
+        assert p >= 1
+        if p > 1:
+            assert p % 2 == 1 and p % 5 != 0   # coprime with 20
+        assert steps // p >= 15 or p == 1   # enough sampled steps
+
+
+def test_roofline_of_takes_the_dominant_stream_collide_class():
+    import bench
+    prof = {
+        "ghost_fill": dict(launches=10, ms=5.0, bytes=0.0, cells=0.0),
+        "stream_collide_low": dict(launches=10, ms=2.0, bytes=10 * 72e6, cells=1e7),
+        "stream_collide_high": dict(launches=10, ms=3.0, bytes=10 * 288e5, cells=1e5),
+        "band_convert": dict(launches=10, ms=1.0, bytes=0.0, cells=0.0),
+    }
+    r = bench.roofline_of(prof, "no-such-workload")
+    assert r["kernel"] == "stream_collide_high"          # largest stream-collide time
+    assert abs(r["avg_launch_us"] - 300.0) < 1e-9
+    assert abs(r["achieved"] - 288e5 / 300e-6 / 1e9) < 0.1
+    assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-4
+    assert r["traffic"] is None                          # no counter summary for it
+
