@@ -262,6 +262,26 @@ def test_live_tile_list_large_grid_fp64():
     compare_pops(s, o, 1e-12)
 
 
+def test_live_tile_list_thermal_fp64():
+    """The list-walking launch with two populations per velocity (f and g):
+    thermal D2Q9 + D2Q16 in FP64 on 1024 x 800 (3200 tiles of 64 x 4 against
+    the 256 workgroups of 104 KB that fit the GPU at once), a band of D2Q16
+    and a temperature field, the Mach criterion (0.06: about a quarter of the
+    cells high order) every 3 steps, steps split over two calls; 1e-12 per population of
+    f and of g."""
+    nx, ny = 1024, 800
+    rho, u, T = inputs.smooth_random_flow(nx, ny, umax=0.12, seed=9, modes=2, dT=0.05)
+    cfg = inputs.base_config(nx=nx, ny=ny, n_low=3, n_high=4, tau=0.6, thermal=1,
+                             crit_kind=inputs.CRIT_MA, crit_thr=0.06, crit_every=3)
+    mask = np.zeros((1, ny, nx), np.uint8)
+    mask[:, :, 300:420] = 1
+    s, o = run_pair(cfg, rho, u, T, mask, 3, tag="live-tile list thermal 1024x800 D2Q9/D2Q16")
+    s.step(3)
+    o.step(3)
+    compare_pops(s, o, 1e-12)
+    compare_pops(s, o, 1e-12, fg=1)
+
+
 @pytest.mark.parametrize("store", [inputs.STORE_FP64, inputs.STORE_FP32])
 def test_live_tile_list_3d(store):
     """3D list-walking launch of the high-order set: 8 x 4 x 4160 periodic
