@@ -149,12 +149,14 @@ def test_3d_small_fp64():
     compare_pops(s, o, 1e-12)
 
 
-@pytest.mark.parametrize("store,tol", [(inputs.STORE_FP32, 1e-5), (inputs.STORE_FP16_DEV, 2e-3)])
+@pytest.mark.parametrize("store,tol", [(inputs.STORE_FP32, 1e-5), (inputs.STORE_FP16_DEV, 2e-3),
+                                       (inputs.STORE_BF16_DEV, 5e-3)])
 def test_3d_small_reduced_storage(store, tol):
     """3D D3Q27 + D3Q64 with FP32 storage (1e-5 on rho, u against the FP64
-    oracle) and FP16 deviations (2e-3, the oracle storing the same FP16
-    deviations): 66 x 20 x 12 (a second, partial tile in x), vortex and a
-    D3Q64 slab, 12 steps."""
+    oracle), FP16 deviations (2e-3) and BF16 deviations (5e-3, the bound of
+    the 2D BF16 tests), the oracle storing the same 16-bit deviations:
+    66 x 20 x 12 (a second, partial tile in x; 12 planes, four z tiles of
+    three), vortex and a D3Q64 slab, 12 steps."""
     nx, ny, nz = 66, 20, 12
     rho, u, T = inputs.vortex_fields(nx, ny, nz, eps=0.05, rc=4.0, u0=0.2)
     cfg = inputs.base_config(dim=3, nx=nx, ny=ny, nz=nz, n_low=3, n_high=4, tau=0.7, store=store)
