@@ -309,6 +309,36 @@ def test_live_tile_list_3d(store):
         compare_macros(s, o, 1e-5, uscale=1.0)
 
 
+@pytest.mark.parametrize("dim,n_high,fill,thermal", [
+    (2, 4, 1, 0), (2, 6, 1, 0), (2, 0, 0, 0), (2, 4, 1, 1), (3, 4, 1, 0), (3, 0, 0, 0)])
+def test_smallest_grid_one_velocity_set_fp64(dim, n_high, fill, thermal):
+    """4 cells per axis, the smallest grid a 3-point stencil with two ghost
+    layers admits, periodic, with every cell in one velocity set (all high
+    order, or a single lattice): each ghost is then an image of a cell two
+    positions away and no band cell exists."""
+    n = 4
+    nz = n if dim == 3 else 1
+    rho, u, T = inputs.vortex_fields(n, n, nz, eps=0.03, rc=1.5, u0=0.1, seed=dim + n_high)
+    if thermal:
+        T = T + 0.02 * np.cos(2 * np.pi * np.arange(n) / n)[None, None, :]
+    cfg = inputs.base_config(dim=dim, nx=n, ny=n, nz=nz, n_low=3, n_high=n_high, tau=0.7,
+                             thermal=thermal)
+    mask = np.full((nz, n, n), fill, np.uint8)
+    s, o = run_pair(cfg, rho, u, T, mask, 12, tag=f"smallest grid dim={dim} fill={fill}")
+    compare_pops(s, o, 1e-12)
+    if thermal:
+        compare_pops(s, o, 1e-12, fg=1)
+
+
+def test_zero_steps_leaves_the_initial_state():
+    """A call for zero steps is valid and changes nothing: the populations
+    equal the oracle's initial equilibrium and the step counter stays 0."""
+    w = inputs.vortex_c1()
+    s, o = run_pair(w["cfg"], w["rho"], w["u"], w["T"], w["mask"], 0, tag="zero steps")
+    assert s.step_count == 0
+    compare_pops(s, o, 1e-12)
+
+
 def test_checkpoint_resume_bitwise():
     from paper_2102_12559_amd import msl
     w = inputs.vortex_c1()
