@@ -491,6 +491,8 @@ def efficiency(args):
     from paper_2102_12559_amd import inputs, msl
     torch.cuda.set_device(0)
     sizes = [128, 256, 512, 1024, 2048, 4096, 8192]
+    if args.sizes:
+        sizes = [int(v) for v in args.sizes.split(",")]
 
     def step_ms(cfg, mask, rho, u, T, steps):
         """Step time, and the per-class kernel time per step (HIP events
@@ -564,6 +566,8 @@ def main():
     ap.add_argument("--workload", default="jet")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sizes", default=None,
+                    help="efficiency workload: comma-separated box sizes N (default 128 ... 8192)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus above 1 is not supported "

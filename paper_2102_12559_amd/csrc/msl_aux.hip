@@ -584,8 +584,11 @@ __global__ void k_order_extrema(Geo g, int ax, int bc_periodic_mask, const uint8
 // The live tiles of velocity set `lat` in ascending order: a launch tile is
 // 64 x 4R cells (2D) or 64 x 4 x RZ cells (3D, R = 1) and live when one of
 // its micro-tiles holds a cell of the set.  One workgroup compacts the tile
-// grid in chunks of 1024 (wave ballots, then the wave totals in LDS); the
-// list holds (bz * rows + by) * ntx + bx.
+// grid in chunks of 1024 x TL_TPT tiles: each thread takes TL_TPT consecutive
+// tiles (their flag loads in flight together), an exclusive scan of the
+// per-thread counts (wave shuffles, then the wave totals in LDS) gives each
+// thread its place; the list holds (bz * rows + by) * ntx + bx.
+#define TL_TPT 16
 __global__ void __launch_bounds__(1024)
 k_tile_list(Geo g, const uint8_t *__restrict__ tflag, int lat, int R, int RZ, int *__restrict__ list,
             int *__restrict__ count) {
@@ -596,29 +599,44 @@ k_tile_list(Geo g, const uint8_t *__restrict__ tflag, int lat, int R, int RZ, in
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (threadIdx.x == 0) base = 0;
   __syncthreads();
-  for (int c0 = 0; c0 < ntiles; c0 += 1024) {
-    const int t = c0 + (int)threadIdx.x;
-    bool live = false;
-    if (t < ntiles) {
-      const int bx = t % g.ntx, rest = t / g.ntx, by = rest % rows, bz = rest / rows;
-      uint8_t any = 0;
-      for (int rz = 0; rz < RZ; ++rz) {
-        const int mz = bz * RZ + rz;
-        if (mz < g.ntz)
-          for (int r = 0; r < R; ++r) {
-            const int my = by * R + r;
-            if (my < g.nty) any |= tflag[((long long)mz * g.nty + my) * g.ntx + bx];
-          }
+  for (int c0 = 0; c0 < ntiles; c0 += 1024 * TL_TPT) {
+    const int t0 = c0 + (int)threadIdx.x * TL_TPT;
+    unsigned live = 0;   // bit j: tile t0 + j is live
+    // coordinates of tile t0, then stepped along x (no division per tile)
+    int bx = t0 % g.ntx, by = (t0 / g.ntx) % rows, bz = t0 / g.ntx / rows;
+#pragma unroll
+    for (int j = 0; j < TL_TPT; ++j) {
+      const int t = t0 + j;
+      if (t < ntiles) {
+        uint8_t any = 0;
+        for (int rz = 0; rz < RZ; ++rz) {
+          const int mz = bz * RZ + rz;
+          if (mz < g.ntz)
+            for (int r = 0; r < R; ++r) {
+              const int my = by * R + r;
+              if (my < g.nty) any |= tflag[((long long)mz * g.nty + my) * g.ntx + bx];
+            }
+        }
+        live |= (unsigned)((any >> lat) & 1) << j;
       }
-      live = (any >> lat) & 1;
+      if (++bx == g.ntx) {
+        bx = 0;
+        if (++by == rows) { by = 0; ++bz; }
+      }
     }
-    const unsigned long long b = __ballot(live);
-    const int before = __popcll(b & ((1ull << lane) - 1ull));
-    if (lane == 0) wsum[wv] = __popcll(b);
+    const int n = __popc(live);
+    int incl = n;   // inclusive scan of the counts over the wave
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int v = __shfl_up(incl, d);
+      if (lane >= d) incl += v;
+    }
+    if (lane == 63) wsum[wv] = incl;
     __syncthreads();
-    int off = base;
+    int off = base + incl - n;
     for (int k = 0; k < wv; ++k) off += wsum[k];
-    if (live) list[off + before] = t;
+    for (int j = 0; j < TL_TPT; ++j)
+      if ((live >> j) & 1u) list[off++] = t0 + j;
     __syncthreads();
     if (threadIdx.x == 0) {
       int tot = 0;
