@@ -89,7 +89,10 @@ typedef struct msl_config {
 
 typedef struct msl_ctx msl_ctx;
 
-/* Device workspace size (bytes) that msl_create needs for `cfg`. */
+/* Device workspace size (bytes) that msl_create needs for `cfg`.  MSL_EINVAL
+ * for an invalid configuration, including a grid of 2^31 cells or more, or one
+ * whose padded population plane (ghosts included) reaches 2^31 elements (cells
+ * and planes are indexed with 32 bits inside the kernels). */
 int msl_workspace_bytes(const msl_config *cfg, size_t *bytes);
 
 /* Validates `cfg`, builds the velocity-set tables (Gauss-Hermite rules,
@@ -100,7 +103,8 @@ int msl_workspace_bytes(const msl_config *cfg, size_t *bytes);
  * low order; the state is undefined until msl_init.  Errors: MSL_EINVAL
  * (n_low >= n_high, tau <= 1/2, unsupported order/dim, stencil reach beyond
  * the ghost layers, diffuse walls on non-y/z faces, grid smaller than the
- * stencil), MSL_ENOMEM (bytes too small), MSL_EHIP. */
+ * stencil, grid or padded plane of 2^31 cells or more), MSL_ENOMEM (bytes
+ * too small), MSL_EHIP. */
 int msl_create(const msl_config *cfg, void *workspace, size_t bytes, void *hip_stream,
                msl_ctx **out);
 void msl_destroy(msl_ctx *ctx);   /* frees the host-side context only */

@@ -48,6 +48,10 @@ def test_config_struct_matches_header():
     dict(cfl=1.5), dict(store=9), dict(lift_mode=2, n_high=0),
     dict(bc=[3, 3, 0, 0, 0, 0]), dict(bc=[0, 2, 0, 0, 0, 0]),
     dict(dim=3, nz=8, n_low=3, n_high=5), dict(thermal=1, cv=1.0),
+    # 2^31 cells: the largest grid the 32-bit cell indexing admits is one cell less
+    dict(nx=65536, ny=32768), dict(dim=3, nx=2048, ny=1024, nz=1024),
+    # fewer cells than 2^31, but the padded plane (ghost layers) reaches it
+    dict(nx=65535, ny=32768),
 ])
 def test_invalid_configs_rejected(bad):
     cfg = inputs.base_config(nx=16, ny=16, n_low=3, n_high=4)
@@ -78,3 +82,11 @@ def test_workspace_sizes_of_the_workloads(thermal, n_high):
     planes = (9 + n_high ** 2) * (2 if thermal else 1)
     assert b > 2 * planes * cells * 4
     assert b < 1.3 * 2 * planes * cells * 4 + 64 * cells
+
+
+def test_largest_admitted_grid_has_a_workspace():
+    """A 2D grid whose padded plane stays under 2^31 elements is admitted; its
+    workspace holds both buffers of the nine FP16 planes."""
+    cfg = inputs.base_config(nx=32768, ny=32768, n_low=3, n_high=0, store=inputs.STORE_FP16_DEV)
+    b = msl.workspace_bytes(cfg)
+    assert b > 2 * 9 * 32768 * 32768 * 2
