@@ -3,7 +3,7 @@
 - the reconstruction weights interpolate quadratics exactly;
 - with D2Q9 alone and CFL = 1 every departure point is a lattice node, so the
   step must equal a standard on-lattice stream-and-collide LBM, written out
-  below from scratch with its own equilibrium;
+  below from scratch with its own equilibrium (and D3Q27 in 3D);
 - a single velocity set on a periodic box conserves mass and momentum (and
   energy in the thermal model) to rounding;
 - a uniform equilibrium is a fixed point of the coupled step for any mask;
@@ -91,6 +91,50 @@ def test_d2q9_cfl1_equals_standard_lbm():
     o.step(steps)
     ref = standard_d2q9(rho[0], u[0, 0], u[1, 0], tau, steps)
     got = o.get_pops(0).reshape(9, ny, nx)
+    assert np.max(np.abs(got - ref)) < 1e-13
+
+
+def standard_d3q27(rho, u, tau, steps):
+    """Textbook D3Q27 stream-and-collide on integer velocities e in {-1,0,1}^3:
+    the same 1D equilibrium factors as the D2Q9 reference above, one per axis;
+    population index a + 3 b + 9 c for the x, y, z components (a, b, c)."""
+    e = [-1, 0, 1]
+
+    def feq1d(k, v):
+        cs2 = 1.0 / 3.0
+        if k == 0:
+            return 1.0 - cs2 - v * v
+        return 0.5 * (cs2 + v * v + k * v)
+
+    def equilibrium(r, v):
+        f = np.zeros((27,) + r.shape)
+        for i in range(27):
+            a, b, c = i % 3, (i // 3) % 3, i // 9
+            f[i] = r * feq1d(e[a], v[0]) * feq1d(e[b], v[1]) * feq1d(e[c], v[2])
+        return f
+
+    f = equilibrium(rho, u / math.sqrt(3))
+    for _ in range(steps):
+        for i in range(27):
+            a, b, c = i % 3, (i // 3) % 3, i // 9
+            f[i] = np.roll(f[i], (e[c], e[b], e[a]), axis=(0, 1, 2))
+        r = f.sum(axis=0)
+        v = np.stack([sum(e[(i // 3 ** ax) % 3] * f[i] for i in range(27)) / r for ax in range(3)])
+        f = f + (equilibrium(r, v) - f) / tau
+    return f
+
+
+def test_d3q27_cfl1_equals_standard_lbm():
+    """3D counterpart: D3Q27 alone at CFL 1 on a ragged periodic box."""
+    nx, ny, nz, tau, steps = 10, 7, 6, 0.8, 12
+    rho, u, T = inputs.smooth_random_flow(nx, ny, nz, umax=0.15, seed=5, drho=0.02)
+    cfg = inputs.base_config(dim=3, nx=nx, ny=ny, nz=nz, n_low=3, n_high=0, tau=tau)
+    o = O.Oracle(cfg)
+    assert abs(o.dt - 1 / math.sqrt(3)) < 1e-15
+    o.init(rho, u, T)
+    o.step(steps)
+    ref = standard_d3q27(rho, u, tau, steps)
+    got = o.get_pops(0).reshape(27, nz, ny, nx)
     assert np.max(np.abs(got - ref)) < 1e-13
 
 
