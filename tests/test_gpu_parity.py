@@ -45,6 +45,21 @@ def test_integer_offsets_single_lattice():
     compare_pops(s, o, 1e-12)
 
 
+@pytest.mark.parametrize("store,tol", [(inputs.STORE_FP64, 1e-12), (inputs.STORE_FP32, 1e-5)])
+def test_integer_offsets_single_lattice_3d(store, tol):
+    """D3Q27 alone on a ragged periodic box (two x tiles, y and z not
+    multiples of the tile's 4 rows or its z depth)."""
+    nx, ny, nz = 70, 9, 7
+    cfg = inputs.base_config(dim=3, nx=nx, ny=ny, nz=nz, n_low=3, n_high=0, tau=0.8, store=store)
+    rho, u, T = inputs.smooth_random_flow(nx, ny, nz, umax=0.15, seed=5, drho=0.02)
+    s, o = run_pair(cfg, rho, u, T, np.zeros((nz, ny, nx), np.uint8), 15,
+                    oracle_cfg=dict(cfg, store=inputs.STORE_FP64), tag=f"D3Q27 3D store={store}")
+    if store == inputs.STORE_FP64:
+        compare_pops(s, o, tol)
+    else:
+        compare_macros(s, o, tol, uscale=1.0)
+
+
 @pytest.mark.parametrize("nq,nQ", [(3, 4), (3, 5), (3, 6), (4, 6)])
 def test_random_mask_ragged_fp64(nq, nQ):
     nx, ny = 131, 45
