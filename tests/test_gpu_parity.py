@@ -164,6 +164,25 @@ def test_3d_small_fp64():
     compare_pops(s, o, 1e-12)
 
 
+@pytest.mark.parametrize("store,tol", [(inputs.STORE_FP64, 1e-12), (inputs.STORE_FP32, 1e-5)])
+def test_3d_thermal(store, tol):
+    """Thermal 3D: D3Q27 with a D3Q64 slab, f and g populations (cv = 5/2),
+    a temperature field varying by 3 %, on a ragged 20 x 12 x 10 box."""
+    nx, ny, nz = 20, 12, 10
+    rho, u, T = inputs.smooth_random_flow(nx, ny, nz, umax=0.12, seed=7, drho=0.02, dT=0.03)
+    cfg = inputs.base_config(dim=3, nx=nx, ny=ny, nz=nz, n_low=3, n_high=4, tau=0.8, thermal=1,
+                             cv=2.5, store=store)
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    mask[:, 4:9, :] = 1
+    s, o = run_pair(cfg, rho, u, T, mask, 6, oracle_cfg=dict(cfg, store=inputs.STORE_FP64),
+                    tag=f"3D thermal D3Q27/D3Q64 store={store}")
+    if store == inputs.STORE_FP64:
+        compare_pops(s, o, tol)
+        compare_pops(s, o, tol, fg=1)
+    else:
+        compare_macros(s, o, tol, uscale=1.0)
+
+
 @pytest.mark.parametrize("store,tol", [(inputs.STORE_FP32, 1e-5), (inputs.STORE_FP16_DEV, 2e-3),
                                        (inputs.STORE_BF16_DEV, 5e-3)])
 def test_3d_small_reduced_storage(store, tol):
