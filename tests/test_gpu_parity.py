@@ -242,12 +242,11 @@ FX = inputs.BC_FIXED_EQ
 
 @pytest.mark.parametrize("bc", [[ZG] * 4 + [P, P], [P, P, ZG, ZG, P, P], [FX, ZG, P, P, P, P],
                                 [FX, ZG, ZG, ZG, P, P]])
-def test_2d_ghost_images_fp64(bc):
-    """2D: from the second step of a step call on, no ghost-fill launch runs;
-    the stream-collide and band conversion kernels store every cell next to
-    a periodic or zero-gradient face into the ghost cells that copy it (edges
-    and corners included), fixed-equilibrium ghosts stay as loaded.  Ragged
-    70 x 37 grid, D2Q9 + D2Q16 with a blob mask touching every face, random
+def test_2d_ghost_fill_faces_fp64(bc):
+    """2D ghosts of every face rule combination: the single ghost-fill launch
+    wraps or clamps each periodic or zero-gradient ghost (edges and corners
+    taking the rule of each out-of-range axis), fixed-equilibrium ghosts stay
+    as loaded.  Ragged 70 x 37 grid, D2Q9 + D2Q16 with a blob mask touching every face, random
     flow up to |u| = 0.45 and the Mach criterion at 0.3 every 3 steps, the
     steps split over two calls; FP64, 1e-12 per population."""
     nx, ny = 70, 37
@@ -259,7 +258,7 @@ def test_2d_ghost_images_fp64(bc):
     mask[0, -2:, :] = 1
     mask[0, :, :2] = 1
     mask[0, :, -3:] = 1
-    s, o = run_pair(cfg, rho, u, T, mask, 4, tag=f"2D ghost images bc={bc}")
+    s, o = run_pair(cfg, rho, u, T, mask, 4, tag=f"2D ghost fill bc={bc}")
     s.step(5)
     o.step(5)
     compare_pops(s, o, 1e-12)
