@@ -60,7 +60,7 @@ def test_integer_offsets_single_lattice_3d(store, tol):
         compare_macros(s, o, tol, uscale=1.0)
 
 
-@pytest.mark.parametrize("nq,nQ", [(3, 4), (3, 5), (3, 6), (4, 6)])
+@pytest.mark.parametrize("nq,nQ", [(3, 4), (3, 5), (3, 6), (4, 5), (4, 6), (5, 6)])
 def test_random_mask_ragged_fp64(nq, nQ):
     nx, ny = 131, 45
     cfg = inputs.base_config(nx=nx, ny=ny, n_low=nq, n_high=nQ, tau=0.65)
