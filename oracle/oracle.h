@@ -22,11 +22,15 @@
  * exactness, the printed diagonal moments (eqs. QxxxL, RxxL, QxxxPonD, RxxPond)
  * and Fig. 1's 3 %, the closed Hermite product form of f^L, lifting/projection
  * moment properties and round trips, exact equality with a textbook D2Q9 LBM
- * at CFL 1, conservation, fixed points, the shear-wave viscosity, vortex
- * translation, Couette symmetry, finite-difference gradients of the MLP.
- * Parity unpinned: the per-tile error check of the learned closure
- * (or_mlp_check) is a rule of this implementation with no closed form to test
- * against; only its consistency with the GPU path is checked.
+ * at CFL 1 (also in a frame moving by one cell per step, as a Galilean shift),
+ * conservation, fixed points, the shear-wave viscosity, vortex translation,
+ * Couette symmetry, the second-order Taylor-Green convergence of App. A, the
+ * |Pi_neq|/p criterion on a hand-set stress, the closure's per-tile error
+ * check against hand-computed errors, finite-difference gradients of the MLP.
+ *
+ * The run may use a global constant reference frame {u_ref, T_ref} (eq. veli):
+ * particle velocities, moments, equilibria, lifting and projection are then
+ * taken in that frame's velocities v_i = sqrt(T_ref) c_i + u_ref.
  *
  * Conventions: cell index = x + nx*(y + ny*z); population index
  * i = a + n*b (+ n*n*c) with a, b, c the ascending 1D node indices along x, y, z;
@@ -59,6 +63,12 @@ typedef struct or_config {
   int crit_kind;              /* 0 none, 1 Mach, 2 |Pi_neq|/p */
   double crit_thr;
   int crit_every;
+  double u_ref[3], T_ref;     /* global constant reference frame (eq. veli): particle
+                                 velocities v_i = sqrt(T_ref) c_i + u_ref; T_ref <= 0: 1 */
+  double store_u[3];          /* velocity of the reduced-precision storage reference: the
+                                 deviation scale of population i is
+                                 rho0 prod_a w_a exp(c_a s_a - s_a^2 / 2),
+                                 s = (store_u - u_ref) / sqrt(T_ref) */
 } or_config;
 
 typedef struct or_ctx or_ctx;
@@ -77,6 +87,9 @@ int or_lagrange3(double xi, double *a);
 /* round-to-nearest-even conversions used by the deviation-storage emulation */
 double or_round_fp16(double v);
 double or_round_bf16(double v);
+
+/* OpenMP threads of the stepper (n >= 1); returns the previous count */
+int or_set_threads(int n);
 
 /* ---- stepper ---- */
 int or_create(const or_config *cfg, or_ctx **out);

@@ -27,7 +27,11 @@ class OrConfig(C.Structure):
         ("slot_state", (C.c_double * 5) * 6), ("slot", (C.c_int * 4) * 6),
         ("slot_edge", C.c_double * 6),
         ("crit_kind", C.c_int), ("crit_thr", C.c_double), ("crit_every", C.c_int),
+        ("u_ref", C.c_double * 3), ("T_ref", C.c_double), ("store_u", C.c_double * 3),
     ]
+
+# fields of the run configuration that default when a workload leaves them out
+_DEFAULTS = {"u_ref": (0.0, 0.0, 0.0), "T_ref": 1.0, "store_u": (0.0, 0.0, 0.0)}
 
 
 def lib():
@@ -49,6 +53,8 @@ def lib():
                                  dp, dp, dp, dp]
         _lib.or_project.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, dp]
         _lib.or_step_count.restype = C.c_long
+        _lib.or_set_threads.argtypes = [C.c_int]
+        _lib.or_set_threads.restype = C.c_int
         _lib.or_adam.argtypes = [dp, dp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_double,
                                  C.c_double, C.c_double]
         _lib.or_mlp_features.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, dp, dp, dp]
@@ -71,7 +77,7 @@ def _check(rc, what):
 def make_config(cfg: dict) -> OrConfig:
     c = OrConfig()
     for name, _ in OrConfig._fields_:
-        v = cfg[name]
+        v = cfg.get(name, _DEFAULTS.get(name)) if name in _DEFAULTS else cfg[name]
         if name in ("bc",):
             for k in range(6):
                 c.bc[k] = int(v[k])
@@ -87,6 +93,10 @@ def make_config(cfg: dict) -> OrConfig:
         elif name == "slot_edge":
             for k in range(6):
                 c.slot_edge[k] = float(v[k])
+        elif name in ("u_ref", "store_u"):
+            arr = getattr(c, name)
+            for k in range(3):
+                arr[k] = float(v[k]) if k < len(v) else 0.0
         else:
             setattr(c, name, v)
     return c
@@ -95,6 +105,11 @@ def make_config(cfg: dict) -> OrConfig:
 # ---------------------------------------------------------------------------
 # lattice-level helpers
 # ---------------------------------------------------------------------------
+
+def set_threads(n):
+    """OpenMP threads of the oracle's stepper; returns the previous count."""
+    return lib().or_set_threads(int(n))
+
 
 def gh_rule(n):
     x = np.zeros(n)

@@ -19,12 +19,19 @@ typedef struct lat_t {
   double W[OR_MAXQ];
   int pw[OR_MAXQ][3];          /* base-n digits of the population / moment index */
   ld *M, *Minv;                /* Q x Q moment matrix and its inverse */
+  /* reference frame of the run (eq. veli): v_ia = sqrt(T_ref) c_ia + u_ref,a */
+  ld ur[3], Tr;
+  ld vl[OR_MAXQ][3];
+  double v[OR_MAXQ][3];
+  ld *Mf, *Mfinv;              /* moment matrix at the particle velocities v and its inverse */
 } lat_t;
 
 int gh_rule_ld(int n, ld *x, ld *w);
 lat_t *lat_build(int dim, int n);
 void lat_free(lat_t *L);
-double lat_cmax(const lat_t *L);
+int lat_set_frame(lat_t *L, const double *u_ref, double T_ref);
+int lat_frame_trivial(const lat_t *L);
+double lat_vmax(const lat_t *L, int axis);
 void lat_feq(const lat_t *L, double rho, const double *u, double theta, double *out);
 void lat_moments(const lat_t *L, const double *f, ld *m);
 void lat_macros(const lat_t *L, int thermal, double cv, const double *f, const double *g,

@@ -147,6 +147,10 @@ lat_t *lat_build(int dim, int n) {
       L->M[j * Q + i] = v;
     }
   if (invert_ld(Q, L->M, L->Minv)) { lat_free(L); return NULL; }
+  L->Mf = (ld *)malloc(sizeof(ld) * Q * Q);
+  L->Mfinv = (ld *)malloc(sizeof(ld) * Q * Q);
+  const double zero[3] = {0.0, 0.0, 0.0};
+  if (lat_set_frame(L, zero, 1.0)) { lat_free(L); return NULL; }
   return L;
 }
 
@@ -154,19 +158,51 @@ void lat_free(lat_t *L) {
   if (!L) return;
   free(L->M);
   free(L->Minv);
+  free(L->Mf);
+  free(L->Mfinv);
   free(L);
 }
 
-double lat_cmax(const lat_t *L) {
+/* The run's reference frame lambda_ref = {u_ref, T_ref} (eq. veli with R = 1,
+ * T_L = 1): particle velocities v_i = sqrt(T_ref) c_i + u_ref, and the moment
+ * matrix of eq. momf evaluated at them, M_f[j][i] = prod_a v_ia^{p_a(j)}, with
+ * its inverse.  The lattice frame is u_ref = 0, T_ref = 1. */
+int lat_set_frame(lat_t *L, const double *u_ref, double T_ref) {
+  if (!(T_ref > 0.0)) return -1;
+  const int Q = L->Q, D = L->D;
+  ld st = sqrtl((ld)T_ref);
+  L->Tr = (ld)T_ref;
+  for (int a = 0; a < 3; a++) L->ur[a] = a < D ? (ld)u_ref[a] : 0.0L;
+  for (int i = 0; i < Q; i++)
+    for (int a = 0; a < 3; a++) {
+      L->vl[i][a] = a < D ? st * L->cl[i][a] + L->ur[a] : 0.0L;
+      L->v[i][a] = (double)L->vl[i][a];
+    }
+  for (int j = 0; j < Q; j++)
+    for (int i = 0; i < Q; i++) {
+      ld v = 1.0L;
+      for (int a = 0; a < D; a++) v *= ipow_ld(L->vl[i][a], L->pw[j][a]);
+      L->Mf[j * Q + i] = v;
+    }
+  return invert_ld(Q, L->Mf, L->Mfinv);
+}
+
+int lat_frame_trivial(const lat_t *L) {
+  return L->Tr == 1.0L && L->ur[0] == 0.0L && L->ur[1] == 0.0L && L->ur[2] == 0.0L;
+}
+
+/* largest particle speed along one axis */
+double lat_vmax(const lat_t *L, int axis) {
   double m = 0;
-  for (int k = 0; k < L->n; k++) if (fabs((double)L->x[k]) > m) m = fabs((double)L->x[k]);
+  for (int i = 0; i < L->Q; i++) if (fabs(L->v[i][axis]) > m) m = fabs(L->v[i][axis]);
   return m;
 }
 
-/* Lattice-frame equilibrium f^L = M_L^{-1} M_{u,theta} (rho W) (eqs. feqL,
- * feqL0): the moments of the co-moving equilibrium rho W_i evaluated with the
- * particle velocities sqrt(theta) c_i + u (eqs. vi, momf), mapped back to the
- * lattice frame by the inverse lattice moment matrix. */
+/* Equilibrium in the run's frame, f^ref = M_ref^{-1} M_{u,theta} (rho W)
+ * (eqs. fll, feqL, feqL0 with the target frame lambda_ref): the moments of the
+ * co-moving equilibrium rho W_i evaluated with the particle velocities
+ * sqrt(theta) c_i + u (eqs. vi, momf), mapped to the run's frame by the inverse
+ * of its moment matrix.  In the lattice frame this is f^L. */
 void lat_feq(const lat_t *L, double rho, const double *u, double theta, double *out) {
   const int Q = L->Q, D = L->D;
   ld st = sqrtl((ld)theta);
@@ -185,7 +221,7 @@ void lat_feq(const lat_t *L, double rho, const double *u, double theta, double *
   }
   for (int i = 0; i < Q; i++) {
     ld s = 0.0L;
-    for (int j = 0; j < Q; j++) s += L->Minv[i * Q + j] * mom[j];
+    for (int j = 0; j < Q; j++) s += L->Mfinv[i * Q + j] * mom[j];
     out[i] = (double)s;
   }
 }
@@ -201,20 +237,22 @@ void lat_moments(const lat_t *L, const double *f, ld *m) {
   }
 }
 
-/* moment of lattice H (digits in base H->n) with powers p, evaluated on populations f */
+/* raw moment with powers p of populations f of lattice L, taken with the
+ * particle velocities of the run's frame (eq. momf) */
 static ld moment_pows(const lat_t *L, const double *f, const int *p) {
   ld s = 0.0L;
   for (int i = 0; i < L->Q; i++) {
     ld v = (ld)f[i];
-    for (int a = 0; a < L->D; a++) v *= ipow_ld(L->cl[i][a], p[a]);
+    for (int a = 0; a < L->D; a++) v *= ipow_ld(L->vl[i][a], p[a]);
     s += v;
   }
   return s;
 }
 
 /* Density, velocity and temperature of one cell (conservation laws of Sec.
- * II.B): rho = sum f, rho u = sum c f, rho E = sum |c|^2/2 f + sum g, and the
- * ideal-gas energy rho E = cv rho T + rho u^2/2 (eq. E).  Athermal: T = T_L = 1. */
+ * II.B): rho = sum f, rho u = sum v f, rho E = sum |v|^2/2 f + sum g with the
+ * particle velocities v of the run's frame, and the ideal-gas energy
+ * rho E = cv rho T + rho u^2/2 (eq. E).  Athermal: T = T_L = 1. */
 void lat_macros(const lat_t *L, int thermal, double cv, const double *f, const double *g,
                 double *rho, double *u, double *T) {
   ld r = 0.0L, j[3] = {0, 0, 0}, e = 0.0L;
@@ -223,8 +261,8 @@ void lat_macros(const lat_t *L, int thermal, double cv, const double *f, const d
     r += fi;
     ld c2 = 0.0L;
     for (int a = 0; a < L->D; a++) {
-      j[a] += L->cl[i][a] * fi;
-      c2 += L->cl[i][a] * L->cl[i][a];
+      j[a] += L->vl[i][a] * fi;
+      c2 += L->vl[i][a] * L->vl[i][a];
     }
     e += 0.5L * c2 * fi;
     if (thermal) e += (ld)g[i];
@@ -277,7 +315,7 @@ void lat_lift_raw(const lat_t *Lq, const lat_t *LQ, int thermal, double cv,
   }
   for (int i = 0; i < Q; i++) {
     ld s = 0.0L;
-    for (int j = 0; j < Q; j++) s += LQ->Minv[i * Q + j] * Mf[j];
+    for (int j = 0; j < Q; j++) s += LQ->Mfinv[i * Q + j] * Mf[j];
     fQ[i] = (double)s;
   }
   if (thermal && gq && gQ) {
@@ -289,7 +327,7 @@ void lat_lift_raw(const lat_t *Lq, const lat_t *LQ, int thermal, double cv,
     }
     for (int i = 0; i < Q; i++) {
       ld s = 0.0L;
-      for (int j = 0; j < Q; j++) s += LQ->Minv[i * Q + j] * Mg[j];
+      for (int j = 0; j < Q; j++) s += LQ->Mfinv[i * Q + j] * Mg[j];
       gQ[i] = (double)s;
     }
   }
@@ -354,14 +392,14 @@ void lat_project(const lat_t *LQ, const lat_t *Lq, int thermal, const double *fQ
   for (int j = 0; j < q; j++) m[j] = moment_pows(LQ, fQ, Lq->pw[j]);
   for (int i = 0; i < q; i++) {
     ld s = 0.0L;
-    for (int j = 0; j < q; j++) s += Lq->Minv[i * q + j] * m[j];
+    for (int j = 0; j < q; j++) s += Lq->Mfinv[i * q + j] * m[j];
     fq[i] = (double)s;
   }
   if (thermal && gQ && gq) {
     for (int j = 0; j < q; j++) m[j] = moment_pows(LQ, gQ, Lq->pw[j]);
     for (int i = 0; i < q; i++) {
       ld s = 0.0L;
-      for (int j = 0; j < q; j++) s += Lq->Minv[i * q + j] * m[j];
+      for (int j = 0; j < q; j++) s += Lq->Mfinv[i * q + j] * m[j];
       gq[i] = (double)s;
     }
   }

@@ -3,15 +3,18 @@
  * TEST INFRASTRUCTURE ONLY (see oracle.h).
  *
  * One step, for every cell x with velocity-set order l (Sec. III.D):
- *   1. for each population i of order l, the departure point x - c_i dt and the
- *      3-point-per-axis collocation points around the nearest node;
+ *   1. for each population i of order l, the departure point x - v_i dt and the
+ *      3-point-per-axis collocation points around the nearest node, with the
+ *      particle velocities v_i = sqrt(T_ref) c_i + u_ref of the run's global
+ *      constant frame (eq. veli; the lattice frame is u_ref = 0, T_ref = 1);
  *   2. every collocation point of another order is converted to order l by
  *      lifting (lower order) or projection (higher order), on the fly; points
  *      outside the domain resolve through the boundary rule of their face;
  *   3. Lagrange reconstruction at the departure point (eqs. reconstructionPond,
- *      advectionPond with the identity frame transfer of the lattice frame);
- *   4. BGK collision towards the lattice equilibrium (eqs. Pond_f, Pond_g with
- *      omega1 = omega2 = 1/tau; eqs. feqL, geqL).
+ *      advectionPond; every point shares the one frame, so the transfer matrix
+ *      is the identity);
+ *   4. BGK collision towards the equilibrium in that frame (eqs. Pond_f, Pond_g
+ *      with omega1 = omega2 = 1/tau; eqs. feqL, geqL with the frame as target).
  * The stored state is the post-collision population vector of each cell.
  */
 #include "oracle_internal.h"
@@ -37,6 +40,7 @@ struct or_ctx {
   int n0[2][OR_MAXQ][3];
   double a[2][OR_MAXQ][3][3];
   double *f[2], *g[2], *fn[2], *gn[2];
+  double sW[2][OR_MAXQ];   /* reduced-precision storage scale of each f population */
   uint8_t *order;
   long step;
   /* learned closure */
@@ -66,8 +70,9 @@ static int tile_of(const or_ctx *c, const int *p) {
   return t0 + c->ntile[0] * (t1 + c->ntile[1] * t2);
 }
 
-/* storage rounding of the configured precision (Sec. on reduced-precision
- * storage: deviations h = f/(rho0 W_i) - 1 kept in 16 bits) */
+/* storage rounding of the configured precision: FP32, or deviations
+ * h = f / scale_i - 1 kept in 16 bits (scale_i = rho0 W_i unless a storage
+ * reference velocity tilts it) */
 static double store_round(const or_ctx *c, double v, double scale) {
   switch (c->cfg.store) {
     case 1: return (double)(float)v;
@@ -77,9 +82,9 @@ static double store_round(const or_ctx *c, double v, double scale) {
   }
 }
 
-static double fscale(const or_ctx *c, int l, int i) { return c->cfg.rho0 * c->lat[l]->W[i]; }
+static double fscale(const or_ctx *c, int l, int i) { return c->sW[l][i]; }
 static double gscale(const or_ctx *c, int l, int i) {
-  return (c->cfg.cv - 0.5 * c->D) * c->cfg.rho0 * c->cfg.T0 * c->lat[l]->W[i];
+  return (c->cfg.cv - 0.5 * c->D) * c->cfg.T0 * c->sW[l][i];
 }
 
 /* ---- conversion of one cell's state between the two orders ---- */
@@ -185,7 +190,7 @@ static void resolve(const or_ctx *c, const int *pin, src_t *out) {
         lat_feq(L, 1.0, ws + 1, ws[4], weq);
         ld in = 0.0L, outf = 0.0L;
         for (int i = 0; i < L->Q; i++) {
-          double cn = L->c[i][ax];
+          double cn = L->v[i][ax];
           int towall = side ? (cn > 0) : (cn < 0);
           int fromwall = side ? (cn < 0) : (cn > 0);
           if (towall) in += fabsl((ld)cn) * (ld)f[i];
@@ -334,16 +339,38 @@ int or_create(const or_config *cfg, or_ctx **out) {
   c->lat[0] = lat_build(c->D, cfg->n_low);
   c->lat[1] = cfg->n_high ? lat_build(c->D, cfg->n_high) : NULL;
   if (!c->lat[0] || (cfg->n_high && !c->lat[1])) { or_destroy(c); return -2; }
-  /* time step from CFL = max|c_i| dt / dx over every configured velocity set */
-  double cmax = lat_cmax(c->lat[0]);
-  if (c->lat[1] && lat_cmax(c->lat[1]) > cmax) cmax = lat_cmax(c->lat[1]);
-  c->dt = cfg->cfl / cmax;
+  /* the run's reference frame (eq. veli); T_ref <= 0 stands for 1 */
+  const double Tref = cfg->T_ref > 0.0 ? cfg->T_ref : 1.0;
+  for (int l = 0; l < c->nlat; l++)
+    if (lat_set_frame(c->lat[l], cfg->u_ref, Tref)) { or_destroy(c); return -2; }
+  if (cfg->lift_mode == 2 && !lat_frame_trivial(c->lat[0])) { or_destroy(c); return -1; }
+  /* time step from CFL = max|v_ia| dt / dx, the largest particle speed along any
+   * axis over every configured velocity set */
+  double vmax = 0.0;
+  for (int l = 0; l < c->nlat; l++)
+    for (int a = 0; a < c->D; a++)
+      if (lat_vmax(c->lat[l], a) > vmax) vmax = lat_vmax(c->lat[l], a);
+  c->dt = cfg->cfl / vmax;
+  /* storage scale: rho0 W_i tilted to the storage reference velocity,
+   * rho0 prod_a w_a exp(c_a s_a - s_a^2/2) with s = (store_u - u_ref)/sqrt(T_ref)
+   * (the Gaussian density ratio of N(s, 1) to N(0, 1) at the node) */
+  for (int l = 0; l < c->nlat; l++) {
+    const lat_t *L = c->lat[l];
+    for (int i = 0; i < L->Q; i++) {
+      double sc = cfg->rho0;
+      for (int a = 0; a < c->D; a++) {
+        const double sa = (cfg->store_u[a] - cfg->u_ref[a]) / sqrt(Tref);
+        sc *= (double)L->w[L->pw[i][a]] * exp(L->c[i][a] * sa - 0.5 * sa * sa);
+      }
+      c->sW[l][i] = sc;
+    }
+  }
   c->reach = 0;
   for (int l = 0; l < c->nlat; l++) {
     const lat_t *L = c->lat[l];
     for (int i = 0; i < L->Q; i++)
       for (int a = 0; a < c->D; a++) {
-        double d = -L->c[i][a] * c->dt;     /* departure point offset */
+        double d = -L->v[i][a] * c->dt;     /* departure point offset x - v_i dt */
         int n0 = (int)floor(d + 0.5);       /* nearest node */
         c->n0[l][i][a] = n0;
         or_lagrange3(d - n0, c->a[l][i][a]);
@@ -382,6 +409,17 @@ void or_destroy(or_ctx *c) {
   free(c->flags); free(c->emlp); free(c->egrad);
   free(c->mlp_p); free(c->xm); free(c->xs); free(c->tm); free(c->ts);
   free(c);
+}
+
+int or_set_threads(int n) {
+#ifdef _OPENMP
+  int prev = omp_get_max_threads();
+  if (n >= 1) omp_set_num_threads(n);
+  return prev;
+#else
+  (void)n;
+  return 1;
+#endif
 }
 
 double or_dt(const or_ctx *c) { return c->dt; }
@@ -462,7 +500,7 @@ static double criterion_value(const or_ctx *c, int64_t k) {
     for (int i = 0; i < L->Q; i++)
       for (int a = 0; a < c->D; a++)
         for (int b = 0; b < c->D; b++)
-          P[a][b] += (L->c[i][a] - u[a]) * (L->c[i][b] - u[b]) * f[i];
+          P[a][b] += (L->v[i][a] - u[a]) * (L->v[i][b] - u[b]) * f[i];
     double p = rho * T, s = 0;
     for (int a = 0; a < c->D; a++)
       for (int b = 0; b < c->D; b++) {
@@ -615,8 +653,8 @@ int or_conservation(const or_ctx *c, double *out) {
       ld fi = (ld)f[i], c2 = 0.0L;
       s[0] += fi;
       for (int a = 0; a < c->D; a++) {
-        s[1 + a] += (ld)L->c[i][a] * fi;
-        c2 += (ld)L->c[i][a] * (ld)L->c[i][a];
+        s[1 + a] += (ld)L->v[i][a] * fi;
+        c2 += (ld)L->v[i][a] * (ld)L->v[i][a];
       }
       s[4] += 0.5L * c2 * fi;
       if (c->cfg.thermal) s[4] += (ld)g[i];
@@ -632,7 +670,7 @@ int or_conservation(const or_ctx *c, double *out) {
 
 int or_set_mlp(or_ctx *c, int H, const double *params, const double *xmean,
                const double *xstd, const double *tmean, const double *tstd, int bf16) {
-  if (c->nlat < 2) return -1;
+  if (c->nlat < 2 || !lat_frame_trivial(c->lat[0])) return -1;
   int F, O;
   or_mlp_dims(c->D, c->lat[0]->n, c->lat[1]->n, &F, &O);
   int np = or_mlp_nparams(F, H, O);
