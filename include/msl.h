@@ -85,14 +85,30 @@ typedef struct msl_config {
   int check_every;            /* conservation sentinel every k steps (synchronises); 0: never */
   int mlp_hidden;             /* hidden width of the closure (lift_mode MLP); 0 -> 64 */
   int mlp_check_every;        /* closure error check every k steps; 0 -> 20 */
+  double u_ref[3], T_ref;     /* global constant reference frame (eq. veli, Sec. II.A): every
+                                 population moves with v_i = sqrt(T_ref) c_i + u_ref, and
+                                 moments, equilibria (eqs. feqL, geqL with this frame as the
+                                 target of eq. fll), lifting and projection are taken in these
+                                 velocities; u_ref = 0, T_ref = 1 is the lattice frame of
+                                 Sec. II.C.2.  T_ref <= 0 stands for 1.  The learned closure
+                                 needs the lattice frame. */
+  double store_u[3];          /* velocity of the 16-bit storage reference state
+                                 (rho0, store_u, T0): population f_i is stored as
+                                 h = f_i / s_i - 1 (g_i: scale (cv - D/2) T0 s_i) with
+                                 s_i = rho0 prod_a w_a r(c_a), r the density ratio of the
+                                 Gaussian N(z_a, T0/T_ref) to N(0, 1) at the node and
+                                 z = (store_u - u_ref) / sqrt(T_ref); s_i = rho0 W_i when
+                                 the storage reference is the frame's rest state */
 } msl_config;
 
 typedef struct msl_ctx msl_ctx;
 
 /* Device workspace size (bytes) that msl_create needs for `cfg`.  MSL_EINVAL
  * for an invalid configuration, including a grid of 2^31 cells or more, or one
- * whose padded population plane (ghosts included) reaches 2^31 elements (cells
- * and planes are indexed with 32 bits inside the kernels). */
+ * whose padded population plane (ghosts included) takes 2^31 bytes or more in
+ * the storage precision: the kernels address a plane with 32-bit byte offsets
+ * and drop the stores of foreign cells at offset 2^31, which must lie beyond
+ * the plane. */
 int msl_workspace_bytes(const msl_config *cfg, size_t *bytes);
 
 /* Validates `cfg`, builds the velocity-set tables (Gauss-Hermite rules,
@@ -103,8 +119,9 @@ int msl_workspace_bytes(const msl_config *cfg, size_t *bytes);
  * low order; the state is undefined until msl_init.  Errors: MSL_EINVAL
  * (n_low >= n_high, tau <= 1/2, unsupported order/dim, stencil reach beyond
  * the ghost layers, diffuse walls on non-y/z faces, grid smaller than the
- * stencil, grid or padded plane of 2^31 cells or more), MSL_ENOMEM (bytes
- * too small), MSL_EHIP. */
+ * stencil, grid of 2^31 cells or more, padded plane of 2^31 bytes or more,
+ * learned lifting outside the lattice frame), MSL_ENOMEM (bytes too small),
+ * MSL_EHIP. */
 int msl_create(const msl_config *cfg, void *workspace, size_t bytes, void *hip_stream,
                msl_ctx **out);
 void msl_destroy(msl_ctx *ctx);   /* frees the host-side context only */

@@ -65,10 +65,10 @@ typedef struct or_config {
   int crit_every;
   double u_ref[3], T_ref;     /* global constant reference frame (eq. veli): particle
                                  velocities v_i = sqrt(T_ref) c_i + u_ref; T_ref <= 0: 1 */
-  double store_u[3];          /* velocity of the reduced-precision storage reference: the
-                                 deviation scale of population i is
-                                 rho0 prod_a w_a exp(c_a s_a - s_a^2 / 2),
-                                 s = (store_u - u_ref) / sqrt(T_ref) */
+  double store_u[3];          /* velocity of the reduced-precision storage reference state
+                                 (rho0, store_u, T0): the deviation scale of population i
+                                 is rho0 prod_a w_a r(c_a), r the density ratio of
+                                 N(s, T0/T_ref) to N(0, 1), s = (store_u - u_ref)/sqrt(T_ref) */
 } or_config;
 
 typedef struct or_ctx or_ctx;

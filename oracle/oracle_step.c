@@ -351,16 +351,20 @@ int or_create(const or_config *cfg, or_ctx **out) {
     for (int a = 0; a < c->D; a++)
       if (lat_vmax(c->lat[l], a) > vmax) vmax = lat_vmax(c->lat[l], a);
   c->dt = cfg->cfl / vmax;
-  /* storage scale: rho0 W_i tilted to the storage reference velocity,
-   * rho0 prod_a w_a exp(c_a s_a - s_a^2/2) with s = (store_u - u_ref)/sqrt(T_ref)
-   * (the Gaussian density ratio of N(s, 1) to N(0, 1) at the node) */
+  /* storage scale: rho0 W_i carried over to the storage reference state
+   * (store_u, T0): rho0 prod_a w_a r(c_a) with r the density ratio of the
+   * Gaussian N(s_a, th) to N(0, 1) at the node, s = (store_u - u_ref)/sqrt(T_ref),
+   * th = T0 / T_ref; rho0 W_i when store_u = u_ref and T0 = T_ref */
+  const double ths = cfg->T0 / Tref;
   for (int l = 0; l < c->nlat; l++) {
     const lat_t *L = c->lat[l];
     for (int i = 0; i < L->Q; i++) {
       double sc = cfg->rho0;
       for (int a = 0; a < c->D; a++) {
         const double sa = (cfg->store_u[a] - cfg->u_ref[a]) / sqrt(Tref);
-        sc *= (double)L->w[L->pw[i][a]] * exp(L->c[i][a] * sa - 0.5 * sa * sa);
+        const double ca = L->c[i][a];
+        sc *= (double)L->w[L->pw[i][a]] *
+              exp(0.5 * ca * ca - 0.5 * (ca - sa) * (ca - sa) / ths) / sqrt(ths);
       }
       c->sW[l][i] = sc;
     }

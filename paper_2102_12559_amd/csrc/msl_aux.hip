@@ -11,22 +11,15 @@
 // ---------------------------------------------------------------------------
 // per-cell state access (FP64 view of the stored planes)
 // ---------------------------------------------------------------------------
-struct StateView {
-  char *f[2];        // base of lattice l's planes in the chosen buffer
-  int Q[2], nplanes[2];
-};
-
 template <typename S>
 __device__ __forceinline__ void read_cell(const Tab *tab, const Geo &g, const char *base, int l,
                                           int off, double *f, double *gg) {
   const LatTab &L = tab->lat[l];
   const S *p = (const S *)base;
+  const double gs = tab->gfac * tab->T0;
   for (int i = 0; i < L.Q; ++i) {
-    const double W = pop_weight(L, g.dim, i);
-    f[i] = load_pop<S>(p + (long long)i * g.plane, off, tab->rho0 * W);
-    if (tab->thermal)
-      gg[i] = load_pop<S>(p + (long long)(L.Q + i) * g.plane, off,
-                          tab->gfac * tab->rho0 * tab->T0 * W);
+    f[i] = load_pop<S>(p + (long long)i * g.plane, off, L.sc[i]);
+    if (tab->thermal) gg[i] = load_pop<S>(p + (long long)(L.Q + i) * g.plane, off, gs * L.sc[i]);
   }
 }
 
@@ -35,99 +28,11 @@ __device__ __forceinline__ void write_cell(const Tab *tab, const Geo &g, char *b
                                            const double *f, const double *gg) {
   const LatTab &L = tab->lat[l];
   S *p = (S *)base;
+  const double gs = tab->gfac * tab->T0;
   for (int i = 0; i < L.Q; ++i) {
-    const double W = pop_weight(L, g.dim, i);
-    store_pop<S>(p + (long long)i * g.plane, off, f[i], tab->rho0 * W);
-    if (tab->thermal)
-      store_pop<S>(p + (long long)(L.Q + i) * g.plane, off, gg[i],
-                   tab->gfac * tab->rho0 * tab->T0 * W);
+    store_pop<S>(p + (long long)i * g.plane, off, f[i], L.sc[i]);
+    if (tab->thermal) store_pop<S>(p + (long long)(L.Q + i) * g.plane, off, gg[i], gs * L.sc[i]);
   }
-}
-
-// Apply a 1D matrix A[nout][nin] (row stride MSL_MAXN) along every axis of a
-// tensor-product population array: out = (A x A (x A)) in.
-__device__ void tensor_apply(const double (*A)[MSL_MAXN], int nout, int nin, int dim,
-                             const double *in, double *out) {
-  double t1[MSL_MAXQ], t2[MSL_MAXQ];
-  if (dim == 2) {
-    // contract y: t1[a'][b] = sum_b' A[b][b'] in[a' + nin b']
-    for (int b = 0; b < nout; ++b)
-      for (int ap = 0; ap < nin; ++ap) {
-        double s = 0;
-        for (int bp = 0; bp < nin; ++bp) s += A[b][bp] * in[ap + nin * bp];
-        t1[ap + nin * b] = s;
-      }
-    for (int b = 0; b < nout; ++b)
-      for (int a = 0; a < nout; ++a) {
-        double s = 0;
-        for (int ap = 0; ap < nin; ++ap) s += A[a][ap] * t1[ap + nin * b];
-        out[a + nout * b] = s;
-      }
-  } else {
-    // z, then y, then x
-    for (int c = 0; c < nout; ++c)
-      for (int bp = 0; bp < nin; ++bp)
-        for (int ap = 0; ap < nin; ++ap) {
-          double s = 0;
-          for (int cp = 0; cp < nin; ++cp) s += A[c][cp] * in[ap + nin * (bp + nin * cp)];
-          t1[ap + nin * (bp + nin * c)] = s;
-        }
-    for (int c = 0; c < nout; ++c)
-      for (int b = 0; b < nout; ++b)
-        for (int ap = 0; ap < nin; ++ap) {
-          double s = 0;
-          for (int bp = 0; bp < nin; ++bp) s += A[b][bp] * t1[ap + nin * (bp + nin * c)];
-          t2[ap + nin * (b + nout * c)] = s;
-        }
-    for (int c = 0; c < nout; ++c)
-      for (int b = 0; b < nout; ++b)
-        for (int a = 0; a < nout; ++a) {
-          double s = 0;
-          for (int ap = 0; ap < nin; ++ap) s += A[a][ap] * t2[ap + nin * (b + nout * c)];
-          out[a + nout * (b + nout * c)] = s;
-        }
-  }
-}
-
-// Lifting (Sec. III.B, App. C).  With the completion M_{q->Q} = m_q (+)
-// M^eq_{Q-q}, and both velocity sets reproducing the equilibrium moments below
-// their order, f_Q = f^L_Q + M_Q^{-1} ((M_q (f_q - f^L_q)) (+) 0).  In tensor
-// form the second term is (K x K) (f_q - f^L_q) with K[a][a'] the degree < n_q
-// part of the high-order Lagrange basis polynomial l_a evaluated at the
-// low-order node c_a' (raw completion), or w_a sum_{j<n_q} He_j(C_a) He_j(c_a')/j!
-// (Hermite completion).  The learned closure adds (Vi x Vi) dM with dM the
-// predicted non-equilibrium parts of the missing raw moments.
-__device__ void lift_cell(const Tab *tab, int dim, const double *fq, const double *gq,
-                          const double *dM, double *fQ, double *gQ) {
-  const LatTab &Lq = tab->lat[0], &LQ = tab->lat[1];
-  double rho, u[3], T;
-  cell_macros(Lq, dim, tab->thermal, tab->cv, fq, gq, rho, u, T);
-  double eq_q[MSL_MAXQ], eq_Q[MSL_MAXQ], neq[MSL_MAXQ], corr[MSL_MAXQ];
-  cell_feq(Lq, dim, rho, u, T, eq_q);
-  cell_feq(LQ, dim, rho, u, T, eq_Q);
-  const double (*K)[MSL_MAXN] = tab->lift_mode == MSL_LIFT_GRAD_HERMITE ? tab->KH : tab->K;
-  for (int i = 0; i < Lq.Q; ++i) neq[i] = fq[i] - eq_q[i];
-  tensor_apply(K, LQ.n, Lq.n, dim, neq, corr);
-  for (int i = 0; i < LQ.Q; ++i) fQ[i] = eq_Q[i] + corr[i];
-  if (dM) {
-    tensor_apply(tab->Vi, LQ.n, LQ.n, dim, dM, corr);
-    for (int i = 0; i < LQ.Q; ++i) fQ[i] += corr[i];
-  }
-  if (tab->thermal) {
-    const double s = tab->gfac * T;
-    for (int i = 0; i < Lq.Q; ++i) neq[i] = gq[i] - s * eq_q[i];
-    tensor_apply(K, LQ.n, Lq.n, dim, neq, corr);
-    for (int i = 0; i < LQ.Q; ++i) gQ[i] = s * eq_Q[i] + corr[i];
-  }
-}
-
-// Projection (Sec. III.C, App. C): f_q = M_q^{-1} M_q f_Q, i.e. (P x P) f_Q with
-// P[a'][a] = l^low_{a'}(C_a), the low-order Lagrange basis at the high nodes.
-__device__ void project_cell(const Tab *tab, int dim, const double *fQ, const double *gQ,
-                             double *fq, double *gq) {
-  const LatTab &Lq = tab->lat[0], &LQ = tab->lat[1];
-  tensor_apply(tab->P, Lq.n, LQ.n, dim, fQ, fq);
-  if (tab->thermal) tensor_apply(tab->P, Lq.n, LQ.n, dim, gQ, gq);
 }
 
 // ---------------------------------------------------------------------------
@@ -396,12 +301,12 @@ k_bc_diffuse(const Tab *__restrict__ tab, Geo g, int ax, BCArgs b, char *bl, cha
   const int src = g.idx(q[0], q[1], q[2]);
   const int n = Lm.n;
   const int stride = ax == 0 ? 1 : (ax == 1 ? n : n * n);
-  // populations arriving at the wall: c_ax < 0 at the lower face, > 0 at the upper
+  // populations arriving at the wall: v_ax < 0 at the lower face, > 0 at the upper
   double in = 0;
   for (int i = 0; i < Lm.Q; ++i) {
-    const double cn = Lm.c[(i / stride) % n];
+    const double cn = Lm.v[ax][(i / stride) % n];
     if (side ? cn > 0 : cn < 0)
-      in += fabs(cn) * load_pop<S>(pm + (long long)i * g.plane, src, tab->rho0 * pop_weight(Lm, g.dim, i));
+      in += fabs(cn) * load_pop<S>(pm + (long long)i * g.plane, src, Lm.sc[i]);
   }
   const double rw = in / tab->wall_out[face][m];
   const double Tw = b.st[face][4];
@@ -410,43 +315,11 @@ k_bc_diffuse(const Tab *__restrict__ tab, Geo g, int ax, BCArgs b, char *bl, cha
     const LatTab &L = tab->lat[l];
     S *pl = (S *)(l ? bh : bl);
     for (int i = 0; i < L.Q; ++i) {
-      const double W = pop_weight(L, g.dim, i);
       const double f = rw * tab->wall_eq[face][l][i];
-      store_pop<S>(pl + (long long)i * g.plane, dst, f, tab->rho0 * W);
+      store_pop<S>(pl + (long long)i * g.plane, dst, f, L.sc[i]);
       if (tab->thermal)
         store_pop<S>(pl + (long long)(L.Q + i) * g.plane, dst, tab->gfac * Tw * f,
-                     tab->gfac * tab->rho0 * tab->T0 * W);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// band conversion: low-order band cells are lifted into the high-order planes,
-// high-order band cells projected into the low-order planes
-// ---------------------------------------------------------------------------
-template <typename S>
-__global__ void k_band_convert(const Tab *__restrict__ tab, Geo g, char *bl, char *bh,
-                               const int *__restrict__ list_lo, const int *__restrict__ list_hi,
-                               const int *__restrict__ counts, int grad_only_mlp) {
-  const int nlo = counts[0], nhi = counts[1];
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < nlo + nhi; t += stride) {
-    const int lift = t < nlo;
-    const long long k = lift ? list_lo[t] : list_hi[t - nlo];
-    // with the learned closure, lifted band cells are written by the closure kernels
-    if (lift && grad_only_mlp) continue;
-    int x, y, z;
-    cell_coords(g, k, x, y, z);
-    const int off = g.idx(x, y, z);
-    double f[MSL_MAXQ], gg[MSL_MAXQ], fo[MSL_MAXQ], go[MSL_MAXQ];
-    if (lift) {
-      read_cell<S>(tab, g, bl, 0, off, f, gg);
-      lift_cell(tab, g.dim, f, gg, nullptr, fo, go);
-      write_cell<S>(tab, g, bh, 1, off, fo, go);
-    } else {
-      read_cell<S>(tab, g, bh, 1, off, f, gg);
-      project_cell(tab, g.dim, f, gg, fo, go);
-      write_cell<S>(tab, g, bl, 0, off, fo, go);
+                     tab->gfac * tab->T0 * L.sc[i]);
     }
   }
 }
@@ -472,7 +345,7 @@ __device__ __forceinline__ double crit_value(const Tab *tab, const Geo &g, const
   double P[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const double c[3] = {L.c[i % N], L.c[(i / N) % N], D == 3 ? L.c[i / (N * N)] : 0.0};
+    const double c[3] = {L.v[0][i % N], L.v[1][(i / N) % N], D == 3 ? L.v[2][i / (N * N)] : 0.0};
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -518,30 +391,10 @@ __global__ void k_check_mask(const uint8_t *__restrict__ m, long long n, int all
   if (m[k] > 1 || (m[k] == 1 && !allow_high)) atomicOr(flag, 1);
 }
 
-// switching: cells whose order changes lift / project their own state
-template <typename S>
-__global__ void k_switch(const Tab *__restrict__ tab, Geo g, char *bl, char *bh,
-                         uint8_t *__restrict__ cls, const uint8_t *__restrict__ newmask,
-                         int convert) {
+// one velocity set: the class bytes take the new mask (every value is 0)
+__global__ void k_switch_one(uint8_t *__restrict__ cls, const uint8_t *__restrict__ newmask, long long n) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= g.ncell) return;
-  const int from = cls[k] & 1, to = newmask[k] & 1;
-  if (from != to && convert) {
-    int x, y, z;
-    cell_coords(g, k, x, y, z);
-    const int off = g.idx(x, y, z);
-    double f[MSL_MAXQ], gg[MSL_MAXQ], fo[MSL_MAXQ], go[MSL_MAXQ];
-    if (to == 1) {
-      read_cell<S>(tab, g, bl, 0, off, f, gg);
-      lift_cell(tab, g.dim, f, gg, nullptr, fo, go);
-      write_cell<S>(tab, g, bh, 1, off, fo, go);
-    } else {
-      read_cell<S>(tab, g, bh, 1, off, f, gg);
-      project_cell(tab, g.dim, f, gg, fo, go);
-      write_cell<S>(tab, g, bl, 0, off, fo, go);
-    }
-  }
-  cls[k] = (uint8_t)to;
+  if (k < n) cls[k] = (uint8_t)(newmask[k] & 1);
 }
 
 // class bytes of a run with one velocity set: no band cells
@@ -819,8 +672,7 @@ __global__ void k_pops(const Tab *__restrict__ tab, Geo g, char *base, int l, in
   const LatTab &L = tab->lat[l];
   S *p = (S *)base;
   for (int i = 0; i < L.Q; ++i) {
-    const double W = pop_weight(L, g.dim, i);
-    const double sc = fg ? tab->gfac * tab->rho0 * tab->T0 * W : tab->rho0 * W;
+    const double sc = fg ? tab->gfac * tab->T0 * L.sc[i] : L.sc[i];
     S *pl = p + (long long)(fg * L.Q + i) * g.plane;
     if (out) out[(long long)i * g.ncell + k] = load_pop<S>(pl, off, sc);
     else if ((cls[k] & 1) == l) store_pop<S>(pl, off, in[(long long)i * g.ncell + k], sc);
@@ -848,7 +700,7 @@ k_conserve_partial(const Tab *__restrict__ tab, Geo g, const char *bl, const cha
     const int n = L.n;
     double r = 0;
     for (int i = 0; i < L.Q; ++i) {
-      const double c[3] = {L.c[i % n], L.c[(i / n) % n], g.dim == 3 ? L.c[i / (n * n)] : 0.0};
+      const double c[3] = {L.v[0][i % n], L.v[1][(i / n) % n], g.dim == 3 ? L.v[2][i / (n * n)] : 0.0};
       r += f[i];
       acc[1] += c[0] * f[i];
       acc[2] += c[1] * f[i];
@@ -1164,8 +1016,8 @@ int msl_launch_get_mask(msl_ctx *c, uint8_t *mask) {
 int msl_launch_switch(msl_ctx *c, const uint8_t *newmask) {
   char *bl = c->planes[0][c->cur], *bh = c->nlat > 1 ? c->planes[1][c->cur] : nullptr;
   if (c->nlat < 2) {
-    DISPATCH_STORE(c, k_switch, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), c->dtab, c->geo, bl, bh,
-                   c->cls, newmask, 0);
+    hipLaunchKernelGGL(k_switch_one, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), 0, c->stream, c->cls,
+                       newmask, c->ncell);
     return last_err();
   }
   const int conv = c->initialized;

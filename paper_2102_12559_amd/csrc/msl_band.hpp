@@ -6,9 +6,11 @@
 
 template <int D, int N> struct Pow { static constexpr int v = D == 2 ? N * N : N * N * N; };
 
-// (A x A (x A)) applied to a tensor-product array: out[NO^D] = A[NO][NI] in[NI^D]
+// (Ax x Ay (x Az)) applied to a tensor-product array: out[NO^D] = A_a[NO][NI]
+// along each axis a of in[NI^D]
 template <int D, int NO, int NI>
-__device__ __forceinline__ void tensor_apply_t(const double (*A)[MSL_MAXN], const double *in,
+__device__ __forceinline__ void tensor_apply_t(const double (*Ax)[MSL_MAXN], const double (*Ay)[MSL_MAXN],
+                                               const double (*Az)[MSL_MAXN], const double *in,
                                                double *out) {
   if constexpr (D == 2) {
     double t[NI * NO];
@@ -18,7 +20,7 @@ __device__ __forceinline__ void tensor_apply_t(const double (*A)[MSL_MAXN], cons
       for (int ap = 0; ap < NI; ++ap) {
         double s = 0;
 #pragma unroll
-        for (int bp = 0; bp < NI; ++bp) s += A[b][bp] * in[ap + NI * bp];
+        for (int bp = 0; bp < NI; ++bp) s += Ay[b][bp] * in[ap + NI * bp];
         t[ap + NI * b] = s;
       }
 #pragma unroll
@@ -27,7 +29,7 @@ __device__ __forceinline__ void tensor_apply_t(const double (*A)[MSL_MAXN], cons
       for (int a = 0; a < NO; ++a) {
         double s = 0;
 #pragma unroll
-        for (int ap = 0; ap < NI; ++ap) s += A[a][ap] * t[ap + NI * b];
+        for (int ap = 0; ap < NI; ++ap) s += Ax[a][ap] * t[ap + NI * b];
         out[a + NO * b] = s;
       }
   } else {
@@ -40,7 +42,7 @@ __device__ __forceinline__ void tensor_apply_t(const double (*A)[MSL_MAXN], cons
         for (int ap = 0; ap < NI; ++ap) {
           double s = 0;
 #pragma unroll
-          for (int cp = 0; cp < NI; ++cp) s += A[c][cp] * in[ap + NI * (bp + NI * cp)];
+          for (int cp = 0; cp < NI; ++cp) s += Az[c][cp] * in[ap + NI * (bp + NI * cp)];
           t1[ap + NI * (bp + NI * c)] = s;
         }
 #pragma unroll
@@ -51,7 +53,7 @@ __device__ __forceinline__ void tensor_apply_t(const double (*A)[MSL_MAXN], cons
         for (int ap = 0; ap < NI; ++ap) {
           double s = 0;
 #pragma unroll
-          for (int bp = 0; bp < NI; ++bp) s += A[b][bp] * t1[ap + NI * (bp + NI * c)];
+          for (int bp = 0; bp < NI; ++bp) s += Ay[b][bp] * t1[ap + NI * (bp + NI * c)];
           t2[ap + NI * (b + NO * c)] = s;
         }
 #pragma unroll
@@ -62,7 +64,7 @@ __device__ __forceinline__ void tensor_apply_t(const double (*A)[MSL_MAXN], cons
         for (int a = 0; a < NO; ++a) {
           double s = 0;
 #pragma unroll
-          for (int ap = 0; ap < NI; ++ap) s += A[a][ap] * t2[ap + NI * (b + NO * c)];
+          for (int ap = 0; ap < NI; ++ap) s += Ax[a][ap] * t2[ap + NI * (b + NO * c)];
           out[a + NO * (b + NO * c)] = s;
         }
   }
@@ -75,7 +77,7 @@ __device__ __forceinline__ void macros_t(const LatTab &L, bool thermal, double c
 #pragma unroll
   for (int i = 0; i < Pow<D, N>::v; ++i) {
     const int a = i % N, b = (i / N) % N, c = D == 3 ? i / (N * N) : 0;
-    const double cx = L.c[a], cy = L.c[b], cz = D == 3 ? L.c[c] : 0.0;
+    const double cx = L.v[0][a], cy = L.v[1][b], cz = D == 3 ? L.v[2][c] : 0.0;
     r += f[i];
     j[0] += cx * f[i];
     j[1] += cy * f[i];
@@ -95,7 +97,7 @@ __device__ __forceinline__ void feq_t(const LatTab &L, double rho, const double 
                                       double *feq) {
   double P[3][N];
 #pragma unroll
-  for (int a = 0; a < D; ++a) eq_axis<double, N>(L, u[a], T, P[a]);
+  for (int a = 0; a < D; ++a) eq_axis<double, N>(L, (u[a] - L.ur[a]) * L.isq, T * L.iTr, P[a]);
 #pragma unroll
   for (int i = 0; i < Pow<D, N>::v; ++i) {
     double v = rho * P[0][i % N] * P[1][(i / N) % N];
@@ -104,10 +106,11 @@ __device__ __forceinline__ void feq_t(const LatTab &L, double rho, const double 
   }
 }
 
-// Lifting (Sec. III.B, App. C): f_Q = f^L_Q + (K x K) (f_q - f^L_q), K the
-// degree < n_q part of the high-order Lagrange basis at the low nodes (or the
-// Hermite completion matrix); the learned closure adds (Vi x Vi) dM.  With
-// TH false the energy populations are known to be absent at compile time.
+// Lifting (Sec. III.B, App. C): f_Q = f^L_Q + (Kx x Ky (x Kz)) (f_q - f^L_q),
+// K_a the degree < n_q part of the high-order Lagrange basis in the particle
+// velocities along axis a, evaluated at the low nodes (or the Hermite
+// completion matrix); the learned closure adds (Vi x Vi) dM.  With TH false
+// the energy populations are known to be absent at compile time.
 template <int D, int NL, int NH, bool TH = true>
 __device__ __forceinline__ void lift_t(const Tab *tab, const double *fq, const double *gq,
                                        const double *dM, double *fQ, double *gQ) {
@@ -119,14 +122,17 @@ __device__ __forceinline__ void lift_t(const Tab *tab, const double *fq, const d
   double eq_q[q], eq_Q[Q], neq[q], corr[Q];
   feq_t<D, NL>(Lq, rho, u, T, eq_q);
   feq_t<D, NH>(LQ, rho, u, T, eq_Q);
-  const double (*K)[MSL_MAXN] = tab->lift_mode == MSL_LIFT_GRAD_HERMITE ? tab->KH : tab->K;
+  const bool herm = tab->lift_mode == MSL_LIFT_GRAD_HERMITE;
+  const double (*Kx)[MSL_MAXN] = herm ? tab->KH : tab->K[0];
+  const double (*Ky)[MSL_MAXN] = herm ? tab->KH : tab->K[1];
+  const double (*Kz)[MSL_MAXN] = herm ? tab->KH : tab->K[2];
 #pragma unroll
   for (int i = 0; i < q; ++i) neq[i] = fq[i] - eq_q[i];
-  tensor_apply_t<D, NH, NL>(K, neq, corr);
+  tensor_apply_t<D, NH, NL>(Kx, Ky, Kz, neq, corr);
 #pragma unroll
   for (int i = 0; i < Q; ++i) fQ[i] = eq_Q[i] + corr[i];
   if (dM) {
-    tensor_apply_t<D, NH, NH>(tab->Vi, dM, corr);
+    tensor_apply_t<D, NH, NH>(tab->Vi, tab->Vi, tab->Vi, dM, corr);
 #pragma unroll
     for (int i = 0; i < Q; ++i) fQ[i] += corr[i];
   }
@@ -134,7 +140,7 @@ __device__ __forceinline__ void lift_t(const Tab *tab, const double *fq, const d
     const double s = tab->gfac * T;
 #pragma unroll
     for (int i = 0; i < q; ++i) neq[i] = gq[i] - s * eq_q[i];
-    tensor_apply_t<D, NH, NL>(K, neq, corr);
+    tensor_apply_t<D, NH, NL>(Kx, Ky, Kz, neq, corr);
 #pragma unroll
     for (int i = 0; i < Q; ++i) gQ[i] = s * eq_Q[i] + corr[i];
   }
@@ -145,8 +151,8 @@ __device__ __forceinline__ void lift_t(const Tab *tab, const double *fq, const d
 template <int D, int NL, int NH, bool TH = true>
 __device__ __forceinline__ void project_t(const Tab *tab, const double *fQ, const double *gQ,
                                           double *fq, double *gq) {
-  tensor_apply_t<D, NL, NH>(tab->P, fQ, fq);
-  if (TH && tab->thermal) tensor_apply_t<D, NL, NH>(tab->P, gQ, gq);
+  tensor_apply_t<D, NL, NH>(tab->P, tab->P, tab->P, fQ, fq);
+  if (TH && tab->thermal) tensor_apply_t<D, NL, NH>(tab->P, tab->P, tab->P, gQ, gq);
 }
 
 template <typename S, int D, int N, bool TH = true>
@@ -155,13 +161,11 @@ __device__ __forceinline__ void read_cell_t(const Tab *tab, const Geo &g, const 
   const LatTab &L = tab->lat[l];
   constexpr int Q = Pow<D, N>::v;
   const S *p = (const S *)base;
-  const double gs = tab->gfac * tab->rho0 * tab->T0;
+  const double gs = tab->gfac * tab->T0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    double W = L.w[i % N] * L.w[(i / N) % N];
-    if (D == 3) W *= L.w[i / (N * N)];
-    f[i] = load_pop<S>(p + (long long)i * g.plane, off, tab->rho0 * W);
-    if (TH && tab->thermal) gg[i] = load_pop<S>(p + (long long)(Q + i) * g.plane, off, gs * W);
+    f[i] = load_pop<S>(p + (long long)i * g.plane, off, L.sc[i]);
+    if (TH && tab->thermal) gg[i] = load_pop<S>(p + (long long)(Q + i) * g.plane, off, gs * L.sc[i]);
   }
 }
 
@@ -171,13 +175,11 @@ __device__ __forceinline__ void write_cell_t(const Tab *tab, const Geo &g, char 
   const LatTab &L = tab->lat[l];
   constexpr int Q = Pow<D, N>::v;
   S *p = (S *)base;
-  const double gs = tab->gfac * tab->rho0 * tab->T0;
+  const double gs = tab->gfac * tab->T0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    double W = L.w[i % N] * L.w[(i / N) % N];
-    if (D == 3) W *= L.w[i / (N * N)];
-    store_pop<S>(p + (long long)i * g.plane, off, f[i], tab->rho0 * W);
-    if (TH && tab->thermal) store_pop<S>(p + (long long)(Q + i) * g.plane, off, gg[i], gs * W);
+    store_pop<S>(p + (long long)i * g.plane, off, f[i], L.sc[i]);
+    if (TH && tab->thermal) store_pop<S>(p + (long long)(Q + i) * g.plane, off, gg[i], gs * L.sc[i]);
   }
 }
 

@@ -106,14 +106,23 @@ static ld lagrange_eval(int n, const ld *nodes, int a, ld x) {
   return v;
 }
 
-static void build_lat(LatTab &L, int n, int dim, const ld *x, const ld *w, double dt) {
+// One velocity set of 1D order n in the run's frame {u_ref, T_ref} (eq. veli):
+// Gauss-Hermite nodes c_a and weights (Tab. I), the Hermite-weighted basis of
+// the equilibrium, the particle velocity v = sqrt(T_ref) c_a + u_ref of every
+// node along each axis with the 3-point stencil of its departure point
+// x - v dt, and the 16-bit storage scale of every population: the weight
+// rho0 W_i carried over to the storage reference state (rho0, store_u, T0),
+// rho0 prod_a w_a r(c_a) with r the density ratio of the Gaussian N(z_a, th)
+// to N(0, 1), z = (store_u - u_ref)/sqrt(T_ref), th = T0/T_ref.
+static void build_lat(LatTab &L, int n, int dim, const ld *x, const ld *w, double dt,
+                      const double *ur, double Tr, const double *su, double rho0, double T0) {
   memset(&L, 0, sizeof(L));
   L.n = n;
   L.Q = dim == 2 ? n * n : n * n * n;
+  const ld sq = sqrtl((ld)Tr);
   for (int a = 0; a < n; ++a) {
-    L.c[a] = (double)x[a];
+    L.cr[a] = (double)x[a];
     L.w[a] = (double)w[a];
-    L.cf[a] = (float)x[a];
     L.wf[a] = (float)w[a];
     ld fact = 1.0L;
     for (int j = 0; j < n; ++j) {
@@ -122,16 +131,37 @@ static void build_lat(LatTab &L, int n, int dim, const ld *x, const ld *w, doubl
       L.hw[a][j] = (double)v;
       L.hwf[a][j] = (float)v;
     }
-    // departure point x - c dt: base node n0 = nearest integer offset, xi in [-1/2, 1/2)
-    const ld d = -x[a] * (ld)dt;
-    const int n0 = (int)floorl(d + 0.5L);
-    const ld xi = d - (ld)n0;
-    const ld wts[3] = {0.5L * xi * (xi - 1.0L), 1.0L - xi * xi, 0.5L * xi * (xi + 1.0L)};
-    L.n0[a] = n0;
-    for (int s = 0; s < 3; ++s) {
-      L.a[a][s] = (double)wts[s];
-      L.af[a][s] = (float)wts[s];
+  }
+  for (int ax = 0; ax < 3; ++ax) {
+    const ld u = ax < dim ? (ld)ur[ax] : 0.0L;
+    L.ur[ax] = (double)u;
+    for (int a = 0; a < n; ++a) {
+      const ld v = sq * x[a] + u;
+      L.v[ax][a] = (double)v;
+      L.vf[ax][a] = (float)v;
+      // departure point x - v dt: base node n0 = nearest integer offset, xi in [-1/2, 1/2)
+      const ld d = -v * (ld)dt;
+      const int n0 = (int)floorl(d + 0.5L);
+      const ld xi = d - (ld)n0;
+      const ld wts[3] = {0.5L * xi * (xi - 1.0L), 1.0L - xi * xi, 0.5L * xi * (xi + 1.0L)};
+      L.n0[ax][a] = n0;
+      for (int s = 0; s < 3; ++s) {
+        L.a[ax][a][s] = (double)wts[s];
+        L.af[ax][a][s] = (float)wts[s];
+      }
     }
+  }
+  L.isq = (double)(1.0L / sq);
+  L.iTr = (double)(1.0L / (ld)Tr);
+  const ld th = (ld)T0 / (ld)Tr;
+  for (int i = 0; i < L.Q; ++i) {
+    ld s = (ld)rho0;
+    for (int ax = 0, r = i; ax < dim; ++ax, r /= n) {
+      const ld z = ((ld)su[ax] - (ld)ur[ax]) / sq, c = x[r % n];
+      s *= w[r % n] * expl(0.5L * c * c - 0.5L * (c - z) * (c - z) / th) / sqrtl(th);
+    }
+    L.sc[i] = (double)s;
+    L.scf[i] = (float)s;
   }
 }
 
@@ -168,6 +198,12 @@ static const char *check_config(const msl_config *cfg) {
   if (cfg->lift_mode == MSL_LIFT_MLP && !cfg->n_high) return "learned lifting needs two velocity sets";
   if (cfg->crit_kind < 0 || cfg->crit_kind > 2) return "unknown criterion";
   if (cfg->store >= MSL_FP16_DEV && !(cfg->rho0 > 0.0 && cfg->T0 > 0.0)) return "deviation storage needs rho0, T0 > 0";
+  for (int a = 0; a < 3; ++a)
+    if (!isfinite(cfg->u_ref[a]) || !isfinite(cfg->store_u[a])) return "frame and storage velocities must be finite";
+  if (isnan(cfg->T_ref) || isinf(cfg->T_ref)) return "T_ref must be finite";
+  const bool trivial_frame = cfg->u_ref[0] == 0.0 && cfg->u_ref[1] == 0.0 &&
+                             (cfg->dim == 2 || cfg->u_ref[2] == 0.0) && (cfg->T_ref <= 0.0 || cfg->T_ref == 1.0);
+  if (cfg->lift_mode == MSL_LIFT_MLP && !trivial_frame) return "learned lifting needs the lattice frame";
   const long long cells = (long long)cfg->nx * cfg->ny * (cfg->dim == 3 ? cfg->nz : 1);
   if (cells >= (1ll << 31)) return "grid too large";
   for (int f = 0; f < 2 * cfg->dim; ++f) {
@@ -295,7 +331,7 @@ int msl_workspace_bytes(const msl_config *cfg, size_t *bytes) {
   if (!bytes || check_config(cfg)) return MSL_EINVAL;
   Layout L;
   make_layout(cfg, L);
-  if (L.geo.plane >= (1ll << 31)) return MSL_EINVAL;
+  if (L.plane_bytes >= (1ll << 31)) return MSL_EINVAL;
   *bytes = L.total;
   return MSL_OK;
 }
@@ -309,7 +345,9 @@ int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_
   if (why) return MSL_EINVAL;
   Layout L;
   make_layout(cfg, L);
-  if (L.geo.plane >= (1ll << 31)) return MSL_EINVAL;
+  // planes are addressed with 32-bit byte offsets, and the stores of foreign
+  // cells go to offset 2^31, which has to lie outside the plane
+  if (L.plane_bytes >= (1ll << 31)) return MSL_EINVAL;
   if (!ws || bytes < L.total) return MSL_ENOMEM;
   msl_ctx *c = new (std::nothrow) msl_ctx;
   if (!c) return MSL_ENOMEM;
@@ -327,20 +365,31 @@ int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_
   // tables
   ld xs[2][MSL_MAXN], wsl[2][MSL_MAXN];
   const int ns[2] = {cfg->n_low, cfg->n_high};
-  ld cmax = 0;
-  for (int l = 0; l < c->nlat; ++l) {
+  for (int l = 0; l < c->nlat; ++l)
     if (gauss_hermite(ns[l], xs[l], wsl[l])) { delete c; return MSL_EINVAL; }
-    for (int a = 0; a < ns[l]; ++a)
-      if (fabsl(xs[l][a]) > cmax) cmax = fabsl(xs[l][a]);
-  }
   Tab &t = c->htab;
   memset(&t, 0, sizeof(t));
-  // CFL = max|c_i| dt / dx over every configured velocity set (Sec. IV)
-  const double dt = (double)((ld)cfg->cfl / cmax);
-  for (int l = 0; l < c->nlat; ++l) build_lat(t.lat[l], ns[l], cfg->dim, xs[l], wsl[l], dt);
+  // the run's frame (eq. veli); T_ref <= 0 stands for the lattice temperature 1
+  const double Tref = cfg->T_ref > 0.0 ? cfg->T_ref : 1.0;
+  const ld sqT = sqrtl((ld)Tref);
+  double ur[3] = {0, 0, 0}, su[3] = {0, 0, 0};
+  for (int a = 0; a < cfg->dim; ++a) { ur[a] = cfg->u_ref[a]; su[a] = cfg->store_u[a]; }
+  // CFL = max |v_ia| dt / dx over every configured velocity set and axis (Sec. IV)
+  ld vmax = 0;
   for (int l = 0; l < c->nlat; ++l)
-    for (int a = 0; a < ns[l]; ++a)
-      if (abs(t.lat[l].n0[a]) + 1 > MSL_G) { delete c; return MSL_EINVAL; }
+    for (int ax = 0; ax < cfg->dim; ++ax)
+      for (int a = 0; a < ns[l]; ++a) {
+        const ld v = fabsl(sqT * xs[l][a] + (ld)ur[ax]);
+        if (v > vmax) vmax = v;
+      }
+  const double dt = (double)((ld)cfg->cfl / vmax);
+  const double rho0 = cfg->rho0 > 0 ? cfg->rho0 : 1.0, T0 = cfg->T0 > 0 ? cfg->T0 : 1.0;
+  for (int l = 0; l < c->nlat; ++l)
+    build_lat(t.lat[l], ns[l], cfg->dim, xs[l], wsl[l], dt, ur, Tref, su, rho0, T0);
+  for (int l = 0; l < c->nlat; ++l)
+    for (int ax = 0; ax < cfg->dim; ++ax)
+      for (int a = 0; a < ns[l]; ++a)
+        if (abs(t.lat[l].n0[ax][a]) + 1 > MSL_G) { delete c; return MSL_EINVAL; }
   if (c->nlat > 1) {
     const int nq = ns[0], nQ = ns[1];
     for (int a = 0; a < nQ; ++a) {
@@ -348,14 +397,30 @@ int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_
       lagrange_coeffs(nQ, xs[1], a, coef);
       for (int m = 0; m < nQ; ++m) t.Vi[a][m] = (double)coef[m];
       for (int ap = 0; ap < nq; ++ap) {
-        ld s = 0, sh = 0, fact = 1;
-        for (int m = 0; m < nq; ++m) s += coef[m] * powl(xs[0][ap], m);
+        ld sh = 0, fact = 1;
         for (int j = 0; j < nq; ++j) {
           if (j > 0) fact *= (ld)j;
           sh += hermite_he(j, xs[1][a]) * hermite_he(j, xs[0][ap]) / fact;
         }
-        t.K[a][ap] = (double)s;
         t.KH[a][ap] = (double)(wsl[1][a] * sh);
+      }
+    }
+    // raw completion per axis, in the particle velocities of that axis: the
+    // degree < n_q part of the high-order Lagrange basis polynomial in v,
+    // evaluated at the low-order velocities
+    for (int ax = 0; ax < 3; ++ax) {
+      const ld u = ax < cfg->dim ? (ld)ur[ax] : 0.0L;
+      ld vh[MSL_MAXN], vl[MSL_MAXN];
+      for (int a = 0; a < nQ; ++a) vh[a] = sqT * xs[1][a] + u;
+      for (int a = 0; a < nq; ++a) vl[a] = sqT * xs[0][a] + u;
+      for (int a = 0; a < nQ; ++a) {
+        ld coef[MSL_MAXN];
+        lagrange_coeffs(nQ, vh, a, coef);
+        for (int ap = 0; ap < nq; ++ap) {
+          ld s = 0;
+          for (int m = 0; m < nq; ++m) s += coef[m] * powl(vl[ap], m);
+          t.K[ax][a][ap] = (double)s;
+        }
       }
     }
     for (int ap = 0; ap < nq; ++ap)
@@ -390,7 +455,7 @@ int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_
       double out = 0;
       for (int i = 0; i < Lt.Q; ++i) {
         const int d = ax == 0 ? i % Lt.n : (ax == 1 ? (i / Lt.n) % Lt.n : i / (Lt.n * Lt.n));
-        const double cn = Lt.c[d];
+        const double cn = Lt.v[ax][d];
         if (side ? cn < 0 : cn > 0) out += fabs(cn) * t.wall_eq[f][l][i];
       }
       t.wall_out[f][l] = out;

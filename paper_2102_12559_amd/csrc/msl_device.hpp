@@ -71,15 +71,6 @@ __device__ __forceinline__ void cell_coords(const Geo &g, long long k, int &x, i
   z = (int)(k / g.ny);
 }
 
-// decoded population scale of a 16-bit deviation: rho0 W_i (f) or
-// (cv - D/2) rho0 T0 W_i (g)
-__host__ __device__ __forceinline__ double pop_weight(const LatTab &L, int dim, int i) {
-  const int n = L.n;
-  double W = L.w[i % n] * L.w[(i / n) % n];
-  if (dim == 3) W *= L.w[i / (n * n)];
-  return W;
-}
-
 template <typename S>
 __device__ __forceinline__ double load_pop(const S *p, long long k, double scale) {
   using T = StoreTraits<S>;
@@ -95,14 +86,15 @@ __device__ __forceinline__ void store_pop(S *p, long long k, double v, double sc
 }
 
 // Moments of one cell's populations of set L in FP64: rho, u, T (conservation
-// laws of Sec. II.B; T from rho E = cv rho T + rho u^2/2, eq. E; athermal T = 1).
+// laws of Sec. II.B with the particle velocities v of the run's frame; T from
+// rho E = cv rho T + rho u^2/2, eq. E; athermal T = 1).
 __device__ __forceinline__ void cell_macros(const LatTab &L, int dim, int thermal, double cv,
                                             const double *f, const double *g, double &rho,
                                             double *u, double &T) {
   const int n = L.n, Q = L.Q;
   double r = 0, j[3] = {0, 0, 0}, e = 0;
   for (int i = 0; i < Q; ++i) {
-    const double cx = L.c[i % n], cy = L.c[(i / n) % n], cz = dim == 3 ? L.c[i / (n * n)] : 0.0;
+    const double cx = L.v[0][i % n], cy = L.v[1][(i / n) % n], cz = dim == 3 ? L.v[2][i / (n * n)] : 0.0;
     r += f[i];
     j[0] += cx * f[i];
     j[1] += cy * f[i];
@@ -118,11 +110,13 @@ __device__ __forceinline__ void cell_macros(const LatTab &L, int dim, int therma
   T = thermal ? (e - 0.5 * r * u2) / (cv * r) : 1.0;
 }
 
-// Lattice equilibrium of set L at (rho, u, T), FP64, all Q populations.
+// Equilibrium of set L at (rho, u, T) in the run's frame, FP64, all Q
+// populations: per axis the 1D factor at the frame-relative velocity
+// (u - u_ref) / sqrt(T_ref) and reduced temperature T / T_ref.
 __host__ __device__ __forceinline__ void cell_feq(const LatTab &L, int dim, double rho, const double *u,
                                          double T, double *feq) {
   double P[3][MSL_MAXN];
-  for (int a = 0; a < dim; ++a) eq_axis_rt(L, u[a], T, P[a]);
+  for (int a = 0; a < dim; ++a) eq_axis_rt(L, (u[a] - L.ur[a]) * L.isq, T * L.iTr, P[a]);
   const int n = L.n;
   for (int i = 0; i < L.Q; ++i) {
     double v = rho * P[0][i % n] * P[1][(i / n) % n];

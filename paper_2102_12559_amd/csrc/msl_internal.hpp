@@ -17,23 +17,35 @@
 #define MSL_MLP_MAXBLK 256       // workgroups of one training step (64 rows each)
 #define MSL_MLP_LOSS_RING 65536  // device loss history of the training steps
 
-// Per velocity set: 1D nodes, weights, Hermite-weighted basis for the
-// equilibrium, and the 1D stencil (base offset and 3 Lagrange weights) of the
-// departure point of each node.
+// Per velocity set: 1D Gauss-Hermite nodes c_a (in the units of the run's
+// reference frame) and weights, the Hermite-weighted basis of the
+// equilibrium, the particle velocity of every node along each axis
+// (v = sqrt(T_ref) c + u_ref, eq. veli), the 1D stencil (base offset and 3
+// Lagrange weights) of each node's departure point along each axis, the
+// frame's map of (u, T) to the equilibrium arguments, and the storage scale of
+// every f population.
 struct LatTab {
   int n, Q;
-  double c[MSL_MAXN], w[MSL_MAXN];
+  double cr[MSL_MAXN], w[MSL_MAXN];
   double hw[MSL_MAXN][MSL_MAXN];   // w_a He_j(c_a) / j!
-  int n0[MSL_MAXN];
-  double a[MSL_MAXN][3];
-  float cf[MSL_MAXN], wf[MSL_MAXN];
+  double v[3][MSL_MAXN];           // particle velocity of node a along axis
+  int n0[3][MSL_MAXN];
+  double a[3][MSL_MAXN][3];
+  // equilibrium in the frame: per-axis factors at (u - ur) isq with reduced
+  // temperature T iTr (isq = 1/sqrt(T_ref), iTr = 1/T_ref)
+  double ur[3], isq, iTr;
+  double sc[MSL_MAXQ];             // 16-bit storage scale of f_i (g_i: gfac T0 sc[i])
+  float vf[3][MSL_MAXN], wf[MSL_MAXN];
   float hwf[MSL_MAXN][MSL_MAXN];
-  float af[MSL_MAXN][3];
+  float af[3][MSL_MAXN][3];
+  float scf[MSL_MAXQ];
 };
 
 struct Tab {
   LatTab lat[2];
-  double K[MSL_MAXN][MSL_MAXN];    // lift, raw completion: K[a][a'] (high node a, low node a')
+  // lift, raw completion in the frame's velocities, per axis: K[ax][a][a']
+  // (high node a, low node a')
+  double K[3][MSL_MAXN][MSL_MAXN];
   double KH[MSL_MAXN][MSL_MAXN];   // lift, Hermite completion
   double P[MSL_MAXN][MSL_MAXN];    // project: P[a'][a] = l^low_{a'}(C_a)
   double Vi[MSL_MAXN][MSL_MAXN];   // inverse Vandermonde of the high nodes: Vi[a][m]

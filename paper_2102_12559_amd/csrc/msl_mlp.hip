@@ -146,7 +146,7 @@ __device__ void features_t(const Tab *tab, const double *fq, const double *gq, d
   feat[k++] = T;
   constexpr int q = Pow<D, NL>::v;
   double M[q], den[D * (NL - 1) + 1];
-  moments_sep<D, NL>(L.c, u, fq, M);
+  moments_sep<D, NL>(L.cr, u, fq, M);
   den[0] = rho;
 #pragma unroll
   for (int d = 1; d <= D * (NL - 1); ++d) den[d] = den[d - 1] * sT;
@@ -171,7 +171,7 @@ __device__ void targets_t(const Tab *tab, const double *fQ, const double *gQ, do
 #pragma unroll
   for (int i = 0; i < Q; ++i) dv[i] = fQ[i] - dv[i];
   const double zero[3] = {0.0, 0.0, 0.0};
-  moments_sep<D, NH>(LQ.c, zero, dv, M);
+  moments_sep<D, NH>(LQ.cr, zero, dv, M);
   const double sT = sqrt(T);
   double den[D * (NH - 1) + 1];
   den[0] = rho;

@@ -57,8 +57,7 @@ __device__ __forceinline__ void collide_store(const Tab *__restrict__ tab, int l
   using C = typename T::C;
   constexpr int Q = D == 2 ? N * N : N * N * N;
   const LatTab &L = tab->lat[lat];
-  const C rho0 = (C)tab->rho0;
-  const C gsc0 = (C)(tab->gfac * tab->rho0 * tab->T0);
+  const C gsc0 = (C)(tab->gfac * tab->T0);   // g scale over the f scale
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int y = y0 + r * ystep, z = z0 + r * zstep;
@@ -72,10 +71,8 @@ __device__ __forceinline__ void collide_store(const Tab *__restrict__ tab, int l
     C gg[TH ? Q : 1];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const int a = i % N, b = (i / N) % N, cc = D == 3 ? i / (N * N) : 0;
-      C W = tsel<C>(L.w[a], L.wf[a]) * tsel<C>(L.w[b], L.wf[b]);
-      if (D == 3) W *= tsel<C>(L.w[cc], L.wf[cc]);
-      f[i] = T::dev ? rho0 * W * (C(1) + ft[i][r]) : ft[i][r];
+      const C W = tsel<C>(L.sc[i], L.scf[i]);   // storage scale of f_i
+      f[i] = T::dev ? W * (C(1) + ft[i][r]) : ft[i][r];
       if (TH) gg[TH ? i : 0] = T::dev ? gsc0 * W * (C(1) + ft[TH ? Q + i : 0][r]) : ft[TH ? Q + i : 0][r];
     }
     // moments (Sec. II.B)
@@ -83,8 +80,8 @@ __device__ __forceinline__ void collide_store(const Tab *__restrict__ tab, int l
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int a = i % N, b = (i / N) % N, cc = D == 3 ? i / (N * N) : 0;
-      const C cx = tsel<C>(L.c[a], L.cf[a]), cy = tsel<C>(L.c[b], L.cf[b]);
-      const C cz = D == 3 ? tsel<C>(L.c[cc], L.cf[cc]) : C(0);
+      const C cx = tsel<C>(L.v[0][a], L.vf[0][a]), cy = tsel<C>(L.v[1][b], L.vf[1][b]);
+      const C cz = D == 3 ? tsel<C>(L.v[2][cc], L.vf[2][cc]) : C(0);
       rho += f[i];
       jx += cx * f[i];
       jy += cy * f[i];
@@ -104,9 +101,9 @@ __device__ __forceinline__ void collide_store(const Tab *__restrict__ tab, int l
       om = (C)(1.0 / (mu / (rd * Tm * tab->dt) + 0.5));
     }
     double Px[N], Py[N], Pz[N];
-    eq_axis<double, N>(L, ux, Tm, Px);
-    eq_axis<double, N>(L, uy, Tm, Py);
-    if (D == 3) eq_axis<double, N>(L, uz, Tm, Pz);
+    eq_axis<double, N>(L, (ux - L.ur[0]) * L.isq, Tm * L.iTr, Px);
+    eq_axis<double, N>(L, (uy - L.ur[1]) * L.isq, Tm * L.iTr, Py);
+    if (D == 3) eq_axis<double, N>(L, (uz - L.ur[2]) * L.isq, Tm * L.iTr, Pz);
 #pragma unroll
     for (int a = 0; a < N; ++a) Px[a] *= rd;
     const C gf = (C)(tab->gfac * Tm);
@@ -120,9 +117,8 @@ __device__ __forceinline__ void collide_store(const Tab *__restrict__ tab, int l
       if (D == 3) feqd *= Pz[cc];
       const C feq = (C)feqd;
       const C fo = f[i] + om * (feq - f[i]);
-      C W = tsel<C>(L.w[a], L.wf[a]) * tsel<C>(L.w[b], L.wf[b]);
-      if (D == 3) W *= tsel<C>(L.w[cc], L.wf[cc]);
-      so[i] = T::store(T::dev ? fo / (rho0 * W) - C(1) : fo);
+      const C W = tsel<C>(L.sc[i], L.scf[i]);
+      so[i] = T::store(T::dev ? fo / W - C(1) : fo);
       if (TH) {
         const C go = gg[TH ? i : 0] + om * (gf * feq - gg[TH ? i : 0]);
         sg[TH ? i : 0] = T::store(T::dev ? go / (gsc0 * W) - C(1) : go);
@@ -182,7 +178,7 @@ k_sc2d(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in, S 
   C reg[NLD];
   auto gload = [&]<int K>() {
     constexpr int i = K % Q, a = i % N, b = i / N;
-    const int ox = L.n0[a] - 1, oy = L.n0[b] - 1;
+    const int ox = L.n0[0][a] - 1, oy = L.n0[1][b] - 1;
     const S *base = in + (long long)K * g.plane + g.idx(x0 + ox, y0 + oy, 0);
 #pragma unroll
     for (int m = 0; m < NLD; ++m)
@@ -199,10 +195,10 @@ k_sc2d(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in, S 
     if constexpr (K + 1 < NP) gload.template operator()<K + 1>();
     constexpr int i = K % Q, a = i % N, b = i / N;
     constexpr int buf = K & 1;
-    const C wx0 = tsel<C>(L.a[a][0], L.af[a][0]), wx1 = tsel<C>(L.a[a][1], L.af[a][1]),
-            wx2 = tsel<C>(L.a[a][2], L.af[a][2]);
-    const C wy0 = tsel<C>(L.a[b][0], L.af[b][0]), wy1 = tsel<C>(L.a[b][1], L.af[b][1]),
-            wy2 = tsel<C>(L.a[b][2], L.af[b][2]);
+    const C wx0 = tsel<C>(L.a[0][a][0], L.af[0][a][0]), wx1 = tsel<C>(L.a[0][a][1], L.af[0][a][1]),
+            wx2 = tsel<C>(L.a[0][a][2], L.af[0][a][2]);
+    const C wy0 = tsel<C>(L.a[1][b][0], L.af[1][b][0]), wy1 = tsel<C>(L.a[1][b][1], L.af[1][b][1]),
+            wy2 = tsel<C>(L.a[1][b][2], L.af[1][b][2]);
     // differenced form: the centre weight is 1 - w0 - w2 exactly, so a
     // uniform field is reproduced without a rounding bias in the weights
     (void)wx1;

@@ -129,7 +129,7 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   // 1. every plane's window in flight at once (direct-to-LDS loads)
   auto issue = [&]<int K>() {
     constexpr int i = K % Q, a = i % N, b = i / N;
-    const int ox = L.n0[a] - 1, oy = L.n0[b] - 1;
+    const int ox = L.n0[0][a] - 1, oy = L.n0[1][b] - 1;
     const unsigned org = (unsigned)g.idx(x0 + ox, y0 + oy, 0) * SZ;   // window origin (bytes)
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(in + (long long)K * g.plane), (short)0, (int)plane_b, MSL_RSRC_WORD3);
@@ -154,12 +154,12 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   // reconstruction of plane K at this thread's R cells (raw storage domain)
   auto recon = [&]<int K>(C (&ft)[R]) {
     constexpr int i = K % Q, a = i % N, b = i / N;
-    const int ox = L.n0[a] - 1, oy = L.n0[b] - 1;
+    const int ox = L.n0[0][a] - 1, oy = L.n0[1][b] - 1;
     const unsigned org = (unsigned)g.idx(x0 + ox, y0 + oy, 0) * SZ;
     const char *base = (const char *)(sm + K * PD) + (org & 3u);
-    const C wx0 = tsel<C>(L.a[a][0], L.af[a][0]), wx2 = tsel<C>(L.a[a][2], L.af[a][2]);
-    const C wy0 = tsel<C>(L.a[b][0], L.af[b][0]), wy2 = tsel<C>(L.a[b][2], L.af[b][2]);
-    const C wx1 = tsel<C>(L.a[a][1], L.af[a][1]), wy1 = tsel<C>(L.a[b][1], L.af[b][1]);
+    const C wx0 = tsel<C>(L.a[0][a][0], L.af[0][a][0]), wx2 = tsel<C>(L.a[0][a][2], L.af[0][a][2]);
+    const C wy0 = tsel<C>(L.a[1][b][0], L.af[1][b][0]), wy2 = tsel<C>(L.a[1][b][2], L.af[1][b][2]);
+    const C wx1 = tsel<C>(L.a[0][a][1], L.af[0][a][1]), wy1 = tsel<C>(L.a[1][b][1], L.af[1][b][1]);
     C h[R + 2];
 #pragma unroll
     for (int r = 0; r < R + 2; ++r) {
@@ -184,8 +184,7 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     }
   };
 
-  const C rho0 = (C)tab->rho0;
-  const C gsc0 = (C)(tab->gfac * tab->rho0 * tab->T0);
+  const C gsc0 = (C)(tab->gfac * tab->T0);   // g scale over the f scale
   // 2. reconstruction and moments
   C rho[R], jx[R], jy[R], en[R];
 #pragma unroll
@@ -194,12 +193,12 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   auto pass1 = [&]<int K>() {
     constexpr int i = K % Q, a = i % N, b = i / N;
     recon.template operator()<K>(ftk[K]);
-    const C W = tsel<C>(L.w[a], L.wf[a]) * tsel<C>(L.w[b], L.wf[b]);
-    const C cx = tsel<C>(L.c[a], L.cf[a]), cy = tsel<C>(L.c[b], L.cf[b]);
+    const C W = tsel<C>(L.sc[i], L.scf[i]);   // storage scale of f_i
+    const C cx = tsel<C>(L.v[0][a], L.vf[0][a]), cy = tsel<C>(L.v[1][b], L.vf[1][b]);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if constexpr (K < Q) {
-        const C f = T::dev ? rho0 * W * (C(1) + ftk[K][r]) : ftk[K][r];
+        const C f = T::dev ? W * (C(1) + ftk[K][r]) : ftk[K][r];
         rho[r] += f;
         jx[r] += cx * f;
         jy[r] += cy * f;
@@ -221,8 +220,8 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     double Tm = 1.0;
     if (TH) Tm = ((double)en[r] - 0.5 * rd * (ux * ux + uy * uy)) / (tab->cv * rd);
     double px[N], py[N];
-    eq_axis<double, N>(L, ux, Tm, px);
-    eq_axis<double, N>(L, uy, Tm, py);
+    eq_axis<double, N>(L, (ux - L.ur[0]) * L.isq, Tm * L.iTr, px);
+    eq_axis<double, N>(L, (uy - L.ur[1]) * L.isq, Tm * L.iTr, py);
 #pragma unroll
     for (int q = 0; q < N; ++q) {
       Px[r][q] = (C)(px[q] * rd);
@@ -246,9 +245,9 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   }
   auto pass2 = [&]<int K>() {
     constexpr int i = K % Q, a = i % N, b = i / N;
-    const C W = tsel<C>(L.w[a], L.wf[a]) * tsel<C>(L.w[b], L.wf[b]);
+    const C W = tsel<C>(L.sc[i], L.scf[i]);
     // decoded scale of a 16-bit deviation and its reciprocal (one per plane)
-    const C sc = K < Q ? rho0 * W : gsc0 * W;
+    const C sc = K < Q ? W : gsc0 * W;
     const C isc = T::dev ? C(1) / sc : C(1);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(out + (long long)K * g.plane), (short)0, (int)plane_b, MSL_RSRC_WORD3);

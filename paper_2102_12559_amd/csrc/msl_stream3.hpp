@@ -118,18 +118,21 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     mine[rz] = inside && (cls[inside ? ((long long)z * g.ny + y) * g.nx + x : 0] & 1) == lat;
   }
 
-  // per-node tables shared by the three axes: interpolation weights and the
-  // window offset of the departure stencil along each axis
-  C wlo[N], wmid[N], whi[N];
+  // per-node tables of each axis: interpolation weights and the window offset
+  // of the departure stencil
+  C wlo[3][N], wmid[3][N], whi[3][N];
   int offx[N], offy[N], offz[N];
 #pragma unroll
   for (int a = 0; a < N; ++a) {
-    wlo[a] = tsel<C>(L.a[a][0], L.af[a][0]);
-    wmid[a] = tsel<C>(L.a[a][1], L.af[a][1]);
-    whi[a] = tsel<C>(L.a[a][2], L.af[a][2]);
-    offx[a] = L.n0[a] - 1;
-    offy[a] = (L.n0[a] - 1) * g.pitch;
-    offz[a] = (L.n0[a] - 1) * g.rows * g.pitch;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      wlo[ax][a] = tsel<C>(L.a[ax][a][0], L.af[ax][a][0]);
+      wmid[ax][a] = tsel<C>(L.a[ax][a][1], L.af[ax][a][1]);
+      whi[ax][a] = tsel<C>(L.a[ax][a][2], L.af[ax][a][2]);
+    }
+    offx[a] = L.n0[0][a] - 1;
+    offy[a] = (L.n0[1][a] - 1) * g.pitch;
+    offz[a] = (L.n0[2][a] - 1) * g.rows * g.pitch;
   }
   const int org0 = g.idx(x0, y0, z0);
   // DMA of planes [k0, k1) into the chunk's LDS (a scalar loop: plane k's
@@ -139,7 +142,7 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     for (int k = k0; k < k1; ++k) {
       const int i = k % Q, a = i % N, b = (i / N) % N, cc = i / (N * N);
       const unsigned org =
-          (unsigned)(org0 + (L.n0[a] - 1) + (L.n0[b] - 1) * g.pitch + (L.n0[cc] - 1) * g.rows * g.pitch) *
+          (unsigned)(org0 + (L.n0[0][a] - 1) + (L.n0[1][b] - 1) * g.pitch + (L.n0[2][cc] - 1) * g.rows * g.pitch) *
           SZ;
       const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
           (void *)(in + (long long)k * g.plane), (short)0, (int)plane_b, MSL_RSRC_WORD3);
@@ -159,7 +162,8 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     unsigned lofs = (unsigned)((K % CH) * PD * 4) + (org & 3u) + (unsigned)(lane * SZ);
     asm volatile("" : "+v"(lofs));
     const char *base = (const char *)sm + lofs;
-    const C wx0 = wlo[a], wx2 = whi[a], wy0 = wlo[b], wy2 = whi[b], wz0 = wlo[cc], wz2 = whi[cc];
+    const C wx0 = wlo[0][a], wx2 = whi[0][a], wy0 = wlo[1][b], wy2 = whi[1][b], wz0 = wlo[2][cc],
+            wz2 = whi[2][cc];
     C hz[RZ + 2];   // x- then y-interpolated values of the window's z slabs
 #pragma unroll
     for (int dz = 0; dz < RZ + 2; ++dz) {
@@ -175,15 +179,15 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
         }
         // FP32 / FP64: differenced form, centre weight 1 - w0 - w2 exactly;
         // 16-bit deviations: the three weights (one operation fewer)
-        if constexpr (SZ == 2) hy[dy] = wx0 * v0 + wmid[a] * v1 + wx2 * v2;
+        if constexpr (SZ == 2) hy[dy] = wx0 * v0 + wmid[0][a] * v1 + wx2 * v2;
         else hy[dy] = v1 + wx0 * (v0 - v1) + wx2 * (v2 - v1);
       }
-      if constexpr (SZ == 2) hz[dz] = wy0 * hy[0] + wmid[b] * hy[1] + wy2 * hy[2];
+      if constexpr (SZ == 2) hz[dz] = wy0 * hy[0] + wmid[1][b] * hy[1] + wy2 * hy[2];
       else hz[dz] = hy[1] + wy0 * (hy[0] - hy[1]) + wy2 * (hy[2] - hy[1]);
     }
 #pragma unroll
     for (int rz = 0; rz < RZ; ++rz) {
-      if constexpr (SZ == 2) ftk[K][rz] = wz0 * hz[rz] + wmid[cc] * hz[rz + 1] + wz2 * hz[rz + 2];
+      if constexpr (SZ == 2) ftk[K][rz] = wz0 * hz[rz] + wmid[2][cc] * hz[rz + 1] + wz2 * hz[rz + 2];
       else ftk[K][rz] = hz[rz + 1] + wz0 * (hz[rz] - hz[rz + 1]) + wz2 * (hz[rz + 2] - hz[rz + 1]);
       // the value is final here: without this the interpolation would be sunk
       // to its first use after the last chunk, keeping every window value of
@@ -200,8 +204,7 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   };
   msl_for_planes<NCH>(chunk);
 
-  const C rho0 = (C)tab->rho0;
-  const C gsc0 = (C)(tab->gfac * tab->rho0 * tab->T0);
+  const C gsc0 = (C)(tab->gfac * tab->T0);   // g scale over the f scale
   // periodic x (xmir, nx >= 4): the cells x < 2 and x >= nx - 2 are also
   // stored into the ghost columns of the other side, which the next step's
   // windows read; only the tiles at the two x ends take the second store
@@ -213,10 +216,11 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   C rho = C(0), jx = C(0), jy = C(0), jz = C(0), en = C(0);
   auto moments = [&]<int K>() {
     constexpr int i = K % Q, a = i % N, b = (i / N) % N, cc = i / (N * N);
-    const C W = tsel<C>(L.w[a], L.wf[a]) * tsel<C>(L.w[b], L.wf[b]) * tsel<C>(L.w[cc], L.wf[cc]);
+    const C W = tsel<C>(L.sc[i], L.scf[i]);   // storage scale of f_i
     if constexpr (K < Q) {
-      const C cx = tsel<C>(L.c[a], L.cf[a]), cy = tsel<C>(L.c[b], L.cf[b]), cz = tsel<C>(L.c[cc], L.cf[cc]);
-      const C f = T::dev ? rho0 * W * (C(1) + ftk[K][rz]) : ftk[K][rz];
+      const C cx = tsel<C>(L.v[0][a], L.vf[0][a]), cy = tsel<C>(L.v[1][b], L.vf[1][b]),
+              cz = tsel<C>(L.v[2][cc], L.vf[2][cc]);
+      const C f = T::dev ? W * (C(1) + ftk[K][rz]) : ftk[K][rz];
       rho += f;
       jx += cx * f;
       jy += cy * f;
@@ -241,9 +245,9 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   C Px[N], Py[N], Pz[N];
   {
     double px[N], py[N], pz[N];
-    eq_axis<double, N>(L, ux, Tm, px);
-    eq_axis<double, N>(L, uy, Tm, py);
-    eq_axis<double, N>(L, uz, Tm, pz);
+    eq_axis<double, N>(L, (ux - L.ur[0]) * L.isq, Tm * L.iTr, px);
+    eq_axis<double, N>(L, (uy - L.ur[1]) * L.isq, Tm * L.iTr, py);
+    eq_axis<double, N>(L, (uz - L.ur[2]) * L.isq, Tm * L.iTr, pz);
 #pragma unroll
     for (int q = 0; q < N; ++q) {
       Px[q] = (C)(px[q] * rd);
@@ -258,8 +262,8 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   // collide and store
   auto store = [&]<int K>() {
     constexpr int i = K % Q, a = i % N, b = (i / N) % N, cc = i / (N * N);
-    const C W = tsel<C>(L.w[a], L.wf[a]) * tsel<C>(L.w[b], L.wf[b]) * tsel<C>(L.w[cc], L.wf[cc]);
-    const C sc = K < Q ? rho0 * W : gsc0 * W;
+    const C W = tsel<C>(L.sc[i], L.scf[i]);
+    const C sc = K < Q ? W : gsc0 * W;
     const C isc = T::dev ? C(1) / sc : C(1);
     const C feq = Px[a] * Py[b] * Pz[cc];
     const C v = T::dev ? sc * (C(1) + ftk[K][rz]) : ftk[K][rz];

@@ -227,13 +227,23 @@ def hard_sphere_tau(lam_cells, rho, T, gamma, dt):
     return mu / (rho * T * dt) + 0.5
 
 
+def shock_frame(ma1, gamma=5.0 / 3.0):
+    """Global constant frame of the shock runs: the mean of the two end
+    states' velocities and temperatures, u_ref = ((u1 + u2)/2, 0, 0),
+    T_ref = (T1 + T2)/2."""
+    rh = rankine_hugoniot(ma1, gamma)
+    return (0.5 * (rh["u1"] + rh["u2"]), 0.0, 0.0), 0.5 * (rh["T1"] + rh["T2"])
+
+
 def shock_c3(ma1=2.0, nx=8192, ny=4, store=STORE_FP64, n_high=6, lam=2.0,
-             crit_thr=1e-3, crit_every=5, dt=None):
+             crit_thr=1e-3, crit_every=5, dt=None, frame=False):
     """Quasi-1D normal shock: RH states at the x ends, step at the centre.
 
     D2Q9 far field, D2Q36 where |Pi_neq|/p exceeds the threshold; viscosity
     mu ~ T^0.5 (hard spheres) with tau set by a mean free path of `lam` cells
-    upstream.  `dt` must be the time step of the lattice pair (1 / c_max).
+    upstream.  `dt` must be the time step of the lattice pair in the run's
+    frame (CFL / the largest particle speed).  frame=True runs in the global
+    constant frame of shock_frame(); otherwise in the lattice frame.
     The run starts all low order (the step is an equilibrium on both sides,
     so the criterion sees nothing at step 0); the criterion runs every 5
     steps because the D2Q9 shock diverges within about 15 steps.
@@ -252,6 +262,8 @@ def shock_c3(ma1=2.0, nx=8192, ny=4, store=STORE_FP64, n_high=6, lam=2.0,
                  BC_PERIODIC, BC_PERIODIC]
     cfg["bc_state"][0] = [rh["rho1"], rh["u1"], 0.0, 0.0, rh["T1"]]
     cfg["bc_state"][1] = [rh["rho2"], rh["u2"], 0.0, 0.0, rh["T2"]]
+    if frame:
+        cfg["u_ref"], cfg["T_ref"] = shock_frame(ma1, g)
     x = np.arange(nx)
     left = (x < nx // 2)[None, None, :].repeat(ny, axis=1)
     rho = np.where(left, rh["rho1"], rh["rho2"]).astype(np.float64)

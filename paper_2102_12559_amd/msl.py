@@ -39,7 +39,11 @@ class MslConfig(C.Structure):
         ("slot_edge", C.c_double * 6),
         ("crit_kind", C.c_int), ("crit_thr", C.c_double), ("crit_every", C.c_int),
         ("check_every", C.c_int), ("mlp_hidden", C.c_int), ("mlp_check_every", C.c_int),
+        ("u_ref", C.c_double * 3), ("T_ref", C.c_double), ("store_u", C.c_double * 3),
     ]
+
+# fields a workload may leave out: the lattice frame and the plain storage scale
+_DEFAULTS = {"u_ref": (0.0, 0.0, 0.0), "T_ref": 1.0, "store_u": (0.0, 0.0, 0.0)}
 
 
 _lib = None
@@ -102,7 +106,7 @@ def lib():
 def make_config(cfg: dict) -> MslConfig:
     c = MslConfig()
     for name, _ in MslConfig._fields_:
-        v = cfg.get(name, 0)
+        v = cfg.get(name, _DEFAULTS.get(name, 0))
         if name == "bc":
             for k in range(6):
                 c.bc[k] = int(v[k])
@@ -118,6 +122,10 @@ def make_config(cfg: dict) -> MslConfig:
         elif name == "slot_edge":
             for k in range(6):
                 c.slot_edge[k] = float(v[k]) if v else 0.0
+        elif name in ("u_ref", "store_u"):
+            arr = getattr(c, name)
+            for k in range(3):
+                arr[k] = float(v[k]) if k < len(v) else 0.0
         else:
             setattr(c, name, v)
     return c

@@ -69,13 +69,15 @@ def compare_pops(s, o, tol, fg=0, rho0=1.0):
     return worst
 
 
-def compare_macros(s, o, tol, uscale):
+def compare_macros(s, o, tol, uscale, rscale=1.0, Tscale=1.0):
+    """max over cells of |d rho| / rscale, |d u| / uscale and |d T| / Tscale
+    (the reference density and temperature, and max(U, c_s))."""
     rg, ug, Tg = [a.cpu().numpy() for a in s.macros()]
     ro, uo, To = o.macros()
     assert all(np.all(np.isfinite(a)) for a in (rg, ug, Tg, ro, uo, To)), "non-finite macros"
-    e_rho = np.max(np.abs(rg - ro))
+    e_rho = np.max(np.abs(rg - ro)) / rscale
     e_u = np.max(np.abs(ug - uo)) / uscale
-    e_T = np.max(np.abs(Tg - To))
+    e_T = np.max(np.abs(Tg - To)) / Tscale
     say(f"  macros: rho {e_rho:.3e} u {e_u:.3e} T {e_T:.3e}")
     assert e_rho <= tol and e_u <= tol and e_T <= tol, (e_rho, e_u, e_T)
     return e_rho, e_u, e_T

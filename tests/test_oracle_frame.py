@@ -13,9 +13,9 @@ storage scale of reduced-precision deviations.
   lattice order.
 - Lifting and projection in a frame keep the low-order raw moments, lift an
   equilibrium to the equilibrium, and project after lifting to the identity.
-- The 16-bit storage scale with a storage reference velocity s is
-  rho0 prod_a w_a exp(c_a s_a - s_a^2/2), recomputed here from numpy's
-  Gauss-Hermite rule.
+- The 16-bit storage scale of the storage reference state (rho0, s, T0) is
+  rho0 prod_a w_a r(c_a), r the density ratio of N(s_a, T0) to N(0, 1) at the
+  node, recomputed here from numpy's Gauss-Hermite rule.
 """
 import math
 
@@ -162,20 +162,26 @@ def test_lift_and_project_in_a_frame():
 def test_tilted_storage_scale():
     """FP16 storage of a uniform flow with the storage reference velocity set:
     stored = s_i (1 + rne16(f_i / s_i - 1)) with s_i recomputed here."""
-    n, su = 4, (0.45, -0.2)
-    cfg = frame_cfg(nx=4, ny=4, n_low=n, store=inputs.STORE_FP16_DEV, rho0=1.1,
-                    store_u=su + (0.0,))
+    n, su, T0 = 4, (0.45, -0.2), 1.25
+    cfg = frame_cfg(nx=4, ny=4, n_low=n, store=inputs.STORE_FP16_DEV, rho0=1.1, T0=T0,
+                    store_u=su + (0.0,), thermal=1, cv=1.5)
     o = O.Oracle(cfg)
     u = np.stack([np.full((1, 4, 4), 0.5), np.full((1, 4, 4), -0.15)])
-    o.init(np.full((1, 4, 4), 1.02), u)
+    o.init(np.full((1, 4, 4), 1.02), u, np.full((1, 4, 4), 1.2))
     got = o.get_pops(0)[:, 0]
     z, w = np.polynomial.hermite_e.hermegauss(n)
     w = w / w.sum()
-    s = np.array([1.1 * w[i % n] * math.exp(z[i % n] * su[0] - su[0] ** 2 / 2) *
-                  w[i // n] * math.exp(z[i // n] * su[1] - su[1] ** 2 / 2) for i in range(n * n)])
-    feq = O.lattice_feq(2, n, 1.02, np.array([0.5, -0.15]), 1.0)
+
+    def ratio(c, m):   # N(m, T0) over N(0, 1) at c
+        return math.exp(c * c / 2 - (c - m) ** 2 / (2 * T0)) / math.sqrt(T0)
+    s = np.array([1.1 * w[i % n] * ratio(z[i % n], su[0]) * w[i // n] * ratio(z[i // n], su[1])
+                  for i in range(n * n)])
+    feq = O.lattice_feq(2, n, 1.02, np.array([0.5, -0.15]), 1.2)
     want = s * (1 + (feq / s - 1).astype(np.float16).astype(np.float64))
     assert np.max(np.abs(got - want) / s) < 1e-12
-    # the deviations from the tilted scale are far smaller than from rho0 W_i
+    gs = 0.5 * T0 * s
+    want_g = gs * (1 + (0.5 * 1.2 * feq / gs - 1).astype(np.float16).astype(np.float64))
+    assert np.max(np.abs(o.get_pops(0, fg=1)[:, 0] - want_g) / gs) < 1e-12
+    # the deviations from the carried-over scale are far smaller than from rho0 W_i
     W = np.array([w[i % n] * w[i // n] for i in range(n * n)])
     assert np.max(np.abs(feq / s - 1)) < 0.25 * np.max(np.abs(feq / (1.1 * W) - 1))
