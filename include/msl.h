@@ -196,6 +196,19 @@ int msl_mlp_train(msl_ctx *ctx, const float *X, const float *Y, int n, int batch
 /* One forward and backward pass over device X[n][F], Y[n][O]: loss (host) and
  * gradient (device float[P]).  For gradient checks.  Synchronises. */
 int msl_mlp_grad(msl_ctx *ctx, const float *X, const float *Y, int n, float *loss, float *grad);
+/* msl_mlp_grad for callers that cannot allocate device memory or touch a
+ * workspace beyond their inputs and outputs (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same loss
+ * (host) and gradient (device float[P]) from the same kernels, with the
+ * per-workgroup gradient and loss partials kept in a static device array of
+ * the library (4 MiB = 2^20 floats per GPU, held until the process ends)
+ * instead of the context's workspace.  Calls no hipMalloc / hipFree.  The
+ * scratch needs ceil(n/64) * (P + 1) + 1 floats; larger requests (and n <= 0
+ * or n > 16384) return MSL_EINVAL with msl_last_error saying why.  Every call
+ * on one GPU shares that GPU's array: calls that overlap in time on the same
+ * GPU (other streams or threads) race.  Synchronises the context's stream. */
+int msl_mlp_grad_noalloc(msl_ctx *ctx, const float *X, const float *Y, int n, float *loss,
+                         float *grad);
 /* Forward pass only: device Yout[n][O]. */
 int msl_mlp_forward(msl_ctx *ctx, const float *X, int n, float *Yout);
 /* Per check tile (64 x 64 (x 64) cells): 1 if the closure passed its error

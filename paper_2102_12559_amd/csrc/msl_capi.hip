@@ -354,6 +354,11 @@ int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_
   memset(c, 0, sizeof(*c));
   c->cfg = *cfg;
   c->stream = (hipStream_t)stream;
+  // the device of this context: its static scratch array is looked up now
+  if (hipGetDevice(&c->device) != hipSuccess || msl_noalloc_setup(c->device) != MSL_OK) {
+    delete c;
+    return MSL_EHIP;
+  }
   c->geo = L.geo;
   c->D = cfg->dim;
   c->nlat = cfg->n_high ? 2 : 1;

@@ -122,6 +122,7 @@ template <> struct StoreTraits<bf16_t> {
 struct msl_ctx {
   msl_config cfg;
   hipStream_t stream;
+  int device;             // the device current at msl_create
   char err[256];
   Geo geo;
   int D, nlat, Q[2];
@@ -205,6 +206,7 @@ int msl_mlp_forward_launch(msl_ctx *c, const float *X, int n, float *Y);
 int msl_mlp_grad_launch(msl_ctx *c, const float *X, const float *Y, int n, float *grad,
                         float *loss_dev);
 int msl_mlp_adam_launch(msl_ctx *c, int t, float lr);
+int msl_noalloc_setup(int device);
 
 #define MSL_HIP(call)                                                       \
   do {                                                                      \

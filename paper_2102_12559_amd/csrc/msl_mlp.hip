@@ -9,7 +9,10 @@
 // for i = 0..3.  One wavefront carries a tile of 16 samples through all three
 // layers; weights live in LDS as BF16, activations pass through LDS to turn
 // the D layout of one layer into the A layout of the next.
+#include <stdio.h>
 #include <string.h>
+
+#include <mutex>
 
 #include "msl_band.hpp"
 #include "msl_device.hpp"
@@ -203,7 +206,7 @@ template <int FP, int H, int OP, int MODE>
 __global__ void __launch_bounds__(256)
 k_mlp(const float *__restrict__ prm, int F, int O, const float *__restrict__ X,
       const float *__restrict__ Y, int n_host, const int *__restrict__ n_dev,
-      float *__restrict__ out, float *__restrict__ gpart, float inv_count) {
+      float *__restrict__ out, float *__restrict__ gpart, long long lbase, float inv_count) {
   __shared__ MlpLds<FP, H, OP> s;
   __shared__ float sg[MODE == 1 ? (FP * H + H + H * H + H + H * OP + OP) : 1];
   const int P = F * H + H + H * H + H + H * O + O;
@@ -526,19 +529,19 @@ k_mlp(const float *__restrict__ prm, int F, int O, const float *__restrict__ X,
     }
     gp[k] = v;
   }
-  if (threadIdx.x == 0) gpart[(long long)MSL_MLP_MAXBLK * P + blockIdx.x] = s.red[0] + s.red[1] + s.red[2] + s.red[3];
+  if (threadIdx.x == 0) gpart[lbase + blockIdx.x] = s.red[0] + s.red[1] + s.red[2] + s.red[3];
 }
 
 // sum of the workgroup partials in a fixed order; optionally Adam
 __global__ void k_mlp_reduce_adam(float *__restrict__ prm, float *__restrict__ m,
                                   float *__restrict__ v, float *__restrict__ gout,
-                                  const float *__restrict__ gpart, int P, int nblk, int apply, int t,
-                                  float lr, float b1, float b2, float eps,
+                                  const float *__restrict__ gpart, long long lbase, int P, int nblk,
+                                  int apply, int t, float lr, float b1, float b2, float eps,
                                   float *__restrict__ loss_out, float loss_scale) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k == 0 && loss_out) {
     float L = 0.f;
-    for (int b = 0; b < nblk; ++b) L += gpart[(long long)MSL_MLP_MAXBLK * P + b];
+    for (int b = 0; b < nblk; ++b) L += gpart[lbase + b];
     *loss_out = L * loss_scale;
   }
   if (k >= P) return;
@@ -789,16 +792,23 @@ k_snapshots(const Tab *__restrict__ tab, Geo g, const char *bh, long long nmax,
 // ---------------------------------------------------------------------------
 static inline int lerr() { return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP; }
 
+// gpart: gradient partials [nblk][P] followed, at lbase, by the loss partials
+// (nullptr: the workspace's, laid out for MSL_MLP_MAXBLK workgroups)
 template <int MODE>
 static int mlp_launch(msl_ctx *c, const float *X, const float *Y, int n, const int *n_dev,
-                      float *out, float inv_count, int nblk) {
+                      float *out, float inv_count, int nblk, float *gpart = nullptr,
+                      long long lbase = -1) {
   const int F = c->mlpF, O = c->mlpO, H = c->mlpH;
   const int FPd = (F + 15) / 16 * 16, OPd = (O + 15) / 16 * 16;
   const dim3 grid(nblk), block(256);
+  if (!gpart) {
+    gpart = c->mlp_gpart;
+    lbase = (long long)MSL_MLP_MAXBLK * c->mlpP;
+  }
 #define MLP_CASE(FPv, Hv, OPv)                                                                    \
   if (FPd == FPv && H == Hv && OPd == OPv) {                                                      \
     hipLaunchKernelGGL((k_mlp<FPv, Hv, OPv, MODE>), grid, block, 0, c->stream, c->mlp_w, F, O, X, \
-                       Y, n, n_dev, out, c->mlp_gpart, inv_count);                                \
+                       Y, n, n_dev, out, gpart, lbase, inv_count);                                \
     return lerr();                                                                                \
   }
   MLP_CASE(16, 64, 16)
@@ -882,6 +892,30 @@ int msl_mlp_check_launch(msl_ctx *c) {
   return lerr();
 }
 
+// ---- gradient without workspace scratch ----
+// The gradient and loss partials of msl_mlp_grad_noalloc live in this
+// file-scope device array (one copy per GPU, held until the process ends)
+// instead of the context's workspace.  Host code never passes the array's
+// name to a kernel or a copy: it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device when the first
+// context is created on that device.
+#define MSL_NOALLOC_FLOATS (1 << 20)   // 4 MiB
+static __device__ __align__(256) float scratch[MSL_NOALLOC_FLOATS];
+#define MSL_NOALLOC_MAXDEV 64
+static float *g_scratch_ptr[MSL_NOALLOC_MAXDEV];
+static std::mutex g_scratch_mu;
+
+// called by msl_create with `device` current
+int msl_noalloc_setup(int device) {
+  if (device < 0 || device >= MSL_NOALLOC_MAXDEV) return MSL_EINVAL;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return MSL_OK;
+  void *ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MSL_EHIP;
+  g_scratch_ptr[device] = (float *)ptr;
+  return MSL_OK;
+}
+
 extern "C" {
 
 int msl_mlp_dims(const msl_ctx *c, int *F, int *O, int *H, int *P) {
@@ -958,16 +992,20 @@ int msl_mlp_forward(msl_ctx *c, const float *X, int n, float *Yout) {
 }
 
 static int grad_step(msl_ctx *c, const float *X, const float *Y, int n, int apply, float lr,
-                     float *gout, float *loss_dev) {
+                     float *gout, float *loss_dev, float *gpart = nullptr, long long lbase = -1) {
   if (n <= 0 || n > MSL_MLP_MAXBLK * 64) return MSL_EINVAL;
   const int nblk = (n + 63) / 64;
+  if (!gpart) {
+    gpart = c->mlp_gpart;
+    lbase = (long long)MSL_MLP_MAXBLK * c->mlpP;
+  }
   const float invc = 1.f / ((float)n * (float)c->mlpO);
-  int rc = mlp_launch<1>(c, X, Y, n, nullptr, nullptr, invc, nblk);
+  int rc = mlp_launch<1>(c, X, Y, n, nullptr, nullptr, invc, nblk, gpart, lbase);
   if (rc) return rc;
   const int t = apply ? (int)(++c->mlp_steps) : 1;
   hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((c->mlpP + 255) / 256), dim3(256), 0, c->stream,
-                     c->mlp_w, c->mlp_m, c->mlp_v, gout, c->mlp_gpart, c->mlpP, nblk, apply, t, lr,
-                     0.9f, 0.999f, 1e-8f, loss_dev, invc);
+                     c->mlp_w, c->mlp_m, c->mlp_v, gout, gpart, lbase, c->mlpP, nblk, apply, t,
+                     lr, 0.9f, 0.999f, 1e-8f, loss_dev, invc);
   return lerr();
 }
 
@@ -977,6 +1015,31 @@ int msl_mlp_grad(msl_ctx *c, const float *X, const float *Y, int n, float *loss,
   if (rc) return rc;
   float l = 0.f;
   MSL_HIP(hipMemcpyAsync(&l, c->mlp_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  MSL_HIP(hipStreamSynchronize(c->stream));
+  if (loss) *loss = l;
+  return MSL_OK;
+}
+
+int msl_mlp_grad_noalloc(msl_ctx *c, const float *X, const float *Y, int n, float *loss,
+                         float *grad) {
+  if (!c || !X || !Y || !grad || !c->mlpP || n <= 0 || n > MSL_MLP_MAXBLK * 64) return MSL_EINVAL;
+  const int nblk = (n + 63) / 64;
+  // gradient partials [nblk][P], loss partials [nblk], the loss
+  const long long need = (long long)nblk * c->mlpP + nblk + 1;
+  if (need > MSL_NOALLOC_FLOATS) {
+    snprintf(c->err, sizeof(c->err),
+             "msl_mlp_grad_noalloc: %d rows need %lld floats of scratch, the static array holds %d",
+             n, need, MSL_NOALLOC_FLOATS);
+    return MSL_EINVAL;
+  }
+  float *sp = c->device >= 0 && c->device < MSL_NOALLOC_MAXDEV ? g_scratch_ptr[c->device] : nullptr;
+  if (!sp) return MSL_ESTATE;
+  const long long lbase = (long long)nblk * c->mlpP;
+  float *loss_dev = sp + lbase + nblk;
+  int rc = grad_step(c, X, Y, n, 0, 0.f, grad, loss_dev, sp, lbase);
+  if (rc) return rc;
+  float l = 0.f;
+  MSL_HIP(hipMemcpyAsync(&l, loss_dev, sizeof(float), hipMemcpyDeviceToHost, c->stream));
   MSL_HIP(hipStreamSynchronize(c->stream));
   if (loss) *loss = l;
   return MSL_OK;

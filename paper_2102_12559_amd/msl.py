@@ -56,7 +56,7 @@ SYMBOLS = [
     "msl_set_state", "msl_mlp_dims", "msl_collect_snapshots", "msl_mlp_set_weights",
     "msl_mlp_get_weights", "msl_mlp_train", "msl_mlp_grad", "msl_mlp_forward",
     "msl_mlp_get_flags", "msl_mlp_set_flags", "msl_num_check_tiles", "msl_profile",
-    "msl_profile_read", "msl_device_copy",
+    "msl_profile_read", "msl_device_copy", "msl_mlp_grad_noalloc",
 ]
 
 
@@ -92,6 +92,7 @@ def lib():
         L.msl_mlp_get_weights.argtypes = [vp, vp]
         L.msl_mlp_train.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_float, vp]
         L.msl_mlp_grad.argtypes = [vp, vp, vp, C.c_int, C.POINTER(C.c_float), vp]
+        L.msl_mlp_grad_noalloc.argtypes = [vp, vp, vp, C.c_int, C.POINTER(C.c_float), vp]
         L.msl_mlp_forward.argtypes = [vp, vp, C.c_int, vp]
         L.msl_mlp_get_flags.argtypes = [vp, vp]
         L.msl_mlp_set_flags.argtypes = [vp, vp]
@@ -331,6 +332,18 @@ class Solver:
         loss = C.c_float()
         self._check(lib().msl_mlp_grad(self._ctx, _ptr(X), _ptr(Y), X.shape[0], C.byref(loss), _ptr(g)),
                     "msl_mlp_grad")
+        return loss.value, g
+
+    def mlp_grad_noalloc(self, X, Y):
+        """msl_mlp_grad with its partials in the library's static scratch array."""
+        t = self.torch
+        X = X.to(self.device, t.float32).contiguous()
+        Y = Y.to(self.device, t.float32).contiguous()
+        P = self.mlp_dims()[3]
+        g = t.empty(P, dtype=t.float32, device=self.device)
+        loss = C.c_float()
+        self._check(lib().msl_mlp_grad_noalloc(self._ctx, _ptr(X), _ptr(Y), X.shape[0], C.byref(loss),
+                                               _ptr(g)), "msl_mlp_grad_noalloc")
         return loss.value, g
 
     def mlp_forward(self, X):
