@@ -3,16 +3,19 @@
 A step is one pass of the whole hot path (criterion and switching every 20
 steps, ghost fill, stream-and-collide of both velocity sets, band conversion,
 learned closure where configured) over the workload's grid.  The default
-workload is the slot jet: 1024 x 512 cells, a 32-cell slot at Mach 0.6 with
-tanh edges into gas at rest, athermal, FP32 storage, D2Q9 with D2Q36 where the
-local Mach number exceeds 0.4 (re-evaluated every 20 steps), tau = 0.52,
-20000 steps.  Inputs are synthetic and resident in HBM before the timed
-region starts.
+workload is the 3D convected vortex plus shear slab: 256^3 periodic cells,
+D3Q27 with D3Q64 where the local Mach number exceeds 0.4 (re-evaluated every
+20 steps, from step 0), Gaussian vortex eps 0.05, shear slab at Ma 0.6,
+populations stored as FP16 deviations with FP32 arithmetic, and the learned
+lifting closure at the interfaces (a network trained on the GPU before the
+timed region, on snapshots of a D3Q64 run of the same flow at 64^3).  Inputs
+are synthetic and resident in HBM before the timed region starts.
 
 Prints one JSON line: MLUPS (million cell updates per second, each cell once
 per step whatever its velocity set), the HBM roofline of the dominant kernel
-(algorithmic bytes per launch / its HIP-event-timed average duration), and the
-FP64 CPU oracle timed on a bounded sample on the host cores.
+(algorithmic bytes per launch / its average duration from HIP events on the
+library's stream over a sample of the timed steps), and the FP64 CPU oracle
+timed on a bounded sample on the host cores (all of them, and one).
 
 `--workload couette-equal-l2` runs the comparison of the learned form (network
 lift, FP16 deviation storage) with the plain form (Grad lift, FP32) at equal
@@ -68,13 +71,18 @@ def workload(name):
                     steps=100, desc=f"single D2Q{n*n} lattice 8192x8192 periodic "
                                     f"{STORE_NAMES[store]}")
     if name.startswith("vortex3d"):
-        # 3D convected vortex + shear slab, 256^3, FP16 deviations, D3Q27 + D3Q64
-        # where Ma > 0.4 (every 20 steps); vortex3d-fp32 for FP32 storage
+        # 3D convected vortex + shear slab, 256^3, D3Q27 + D3Q64 where Ma > 0.4
+        # (every 20 steps): FP16 deviations with the learned lift (default),
+        # vortex3d-grad for the Grad lift, vortex3d-fp32 for FP32 storage
         store = inputs.STORE_FP32 if name.endswith("fp32") else inputs.STORE_FP16_DEV
-        w = inputs.vortex_shear_3d(n=256, store=store)
+        mlp = name == "vortex3d"
+        w = inputs.vortex_shear_3d(n=256, store=store,
+                                   lift_mode=inputs.LIFT_MLP if mlp else inputs.LIFT_GRAD)
+        w["mlp"] = mlp
         w["desc"] = (f"3D vortex (eps 0.05, core 16) + shear slab at Ma 0.6, 256^3 periodic, "
-                     f"{STORE_NAMES[store]}, D3Q27 + D3Q64 where Ma > 0.4 (every 20 steps), "
-                     f"tau 0.6, 2000 steps")
+                     f"{STORE_NAMES[store]} storage, fp32 arithmetic, D3Q27 + D3Q64 where Ma > 0.4 "
+                     f"(every 20 steps), {'learned' if mlp else 'Grad'} lifting, tau 0.6, "
+                     f"2000 steps")
         return w
     if name == "vortex":
         w = inputs.vortex_c1()
@@ -84,15 +92,19 @@ def workload(name):
 
 
 def kernel_source_hash():
+    """Hash of the stream-collide kernel sources: a counter summary taken on
+    other sources no longer describes the kernel."""
     h = hashlib.sha256()
-    for f in ("msl_stream.hpp", "msl_stream2.hpp", "msl_device.hpp", "msl_internal.hpp"):
+    for f in ("msl_stream.hpp", "msl_stream2.hpp", "msl_stream3.hpp", "msl_device.hpp",
+              "msl_internal.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2102_12559_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def traffic_for(name, launches_cells):
+def traffic_for(name, kernel):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+    counter summary of this workload, if it was taken on the current kernel
+    source and for the same launch class (else None)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
     if not os.path.exists(path):
         return None
@@ -100,34 +112,64 @@ def traffic_for(name, launches_cells):
         d = json.load(open(path))
     except Exception:
         return None
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("launch_class") != kernel:
         return None
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(w, seconds_hint):
-    """The FP64 oracle on the host cores: a bounded sample of the workload."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, seconds_hint, net=None, sample_desc=None):
+    """The FP64 oracle on the host cores: a bounded sample of the workload,
+    timed with every host thread and with one.  `net`: the trained closure,
+    installed in the oracle too (its network runs with BF16 operands, as on
+    the GPU)."""
     import numpy as np
-    from oracle.oracle import Oracle
-    cfg = dict(w["cfg"])
-    cfg["store"] = 0
-    o = Oracle(cfg)
-    o.set_mask(w["mask"], convert=False)
-    o.init(w["rho"], w["u"], w["T"])
-    ncell = int(np.prod(o.shape))
-    o.step(1)  # warm-up (first-touch of the arrays)
-    steps, t0 = 0, time.time()
-    while True:
-        o.step(1)
-        steps += 1
-        if time.time() - t0 > seconds_hint:
-            break
-    dt = time.time() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=round(ncell * steps / dt / 1e6, 4), unit="MLUPS", cores=threads,
-                kind="oracle",
-                sample=f"{steps} steps of the full {cfg['nx']}x{cfg['ny']} grid from the "
-                       f"initial state, FP64, {dt:.1f} s")
+    from oracle import oracle as O
+
+    def rate(threads):
+        prev = O.set_threads(threads)
+        try:
+            cfg = dict(w["cfg"])
+            cfg["store"] = 0
+            o = O.Oracle(cfg)
+            if net is not None:
+                o.set_mlp(net["H"], net["params"].astype(np.float64),
+                          net["xmean"].astype(np.float64), net["xstd"].astype(np.float64),
+                          net["tmean"].astype(np.float64), net["tstd"].astype(np.float64), bf16=True)
+            o.set_mask(w["mask"], convert=False)
+            o.init(w["rho"], w["u"], w["T"])
+            ncell = int(np.prod(o.shape))
+            o.step(1)  # warm-up (first touch of the arrays); includes the step-0 criterion
+            steps, t0 = 0, time.time()
+            while True:
+                o.step(1)
+                steps += 1
+                if time.time() - t0 > seconds_hint:
+                    break
+            dt = time.time() - t0
+        finally:
+            O.set_threads(prev)
+        return ncell * steps / dt / 1e6, steps, dt
+
+    nthreads = O.set_threads(0)
+    v_all, st_all, dt_all = rate(nthreads)
+    v_one, st_one, dt_one = rate(1)
+    cfg = w["cfg"]
+    grid = f"{cfg['nx']}x{cfg['ny']}" + (f"x{cfg['nz']}" if cfg["dim"] == 3 else "")
+    return dict(value=round(v_all, 4), unit="MLUPS", cores=nthreads, kind="oracle",
+                value_1thread=round(v_one, 4), cpu_model=cpu_model(),
+                sample=(sample_desc or f"the full {grid} grid") +
+                       f" from the initial state, FP64: {st_all} steps in {dt_all:.1f} s on "
+                       f"{nthreads} threads, {st_one} steps in {dt_one:.1f} s on 1 thread")
 
 
 def profile_every(steps):
@@ -146,7 +188,7 @@ def profile_every(steps):
     return p
 
 
-def timed_steps(s, steps, warmup):
+def timed_steps(s, steps, warmup, every=None):
     """Warm up, then time `steps` steps with events on the library's stream.
     Inside the same timed region the library times, with HIP events on its
     stream, every launch of a sample of the steps: the per-class kernel
@@ -154,7 +196,7 @@ def timed_steps(s, steps, warmup):
     import torch
     s.step(warmup)
     torch.cuda.synchronize()
-    s.profile(True, every=profile_every(steps))
+    s.profile(True, every=every or profile_every(steps))
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -171,8 +213,11 @@ def timed_steps(s, steps, warmup):
 
 def roofline_of(prof, traffic_name):
     """Roofline of the dominant kernel: the stream-collide class with the
-    largest total time; algorithmic bytes per launch over its average time."""
+    largest total time; algorithmic bytes per launch over its average time.
+    None when no stream-collide launch was sampled."""
     sc = {k: v for k, v in prof.items() if k.startswith("stream_collide") and v["launches"] > 0}
+    if not sc:
+        return None
     dom = max(sc, key=lambda k: sc[k]["ms"])
     d = sc[dom]
     avg_ms = d["ms"] / d["launches"]
@@ -185,7 +230,7 @@ def roofline_of(prof, traffic_name):
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": traffic_for(traffic_name, d),
+        "traffic": traffic_for(traffic_name, dom),
         "bytes_per_launch": round(bytes_per_launch),
         "avg_launch_us": round(avg_ms * 1e3, 3),
     }
@@ -558,13 +603,28 @@ def efficiency(args):
     }))
 
 
+def c5_network():
+    """The closure of the 3D workload: snapshots of a D3Q64 run of the same
+    local flow at 64^3 (shear layer of width 4 at Mach 0.6, vortex core 4),
+    trained on the GPU with the library's BF16 kernels.  Runs before the timed
+    region."""
+    from paper_2102_12559_amd import closure, inputs
+    ws = inputs.vortex_shear_3d(n=64, rc=4.0, store=inputs.STORE_FP32, lift_mode=inputs.LIFT_MLP)
+    X, Y = closure.snapshots_of_run(ws, [10, 20, 40, 80], max_rows=50000)
+    small = dict(inputs.vortex_shear_3d(n=16, store=inputs.STORE_FP32, lift_mode=inputs.LIFT_MLP)["cfg"])
+    net = closure.train(X, Y, batch=1024, hidden=64, seed=0, cfg=small,
+                        schedule=[(30, 1e-3), (15, 3e-4), (10, 1e-4)])
+    net["rows"] = int(X.shape[0])
+    return net
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="jet")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="vortex3d")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sizes", default=None,
                     help="efficiency workload: comma-separated box sizes N (default 128 ... 8192)")
@@ -587,17 +647,32 @@ def main():
         efficiency(args)
         return
 
+    import numpy as np
     import torch
-    from paper_2102_12559_amd import msl
+    from paper_2102_12559_amd import closure, inputs, msl
+
+    def say(m):
+        print(m, file=sys.stderr, flush=True)
 
     w = workload(args.workload)
     steps = args.steps if args.steps is not None else w["steps"]
     cfg = w["cfg"]
     torch.cuda.set_device(0)
+    net = None
+    if w.get("mlp"):
+        t0 = time.time()
+        net = c5_network()
+        say(f"[bench] closure: {net['rows']} snapshots, validation mse {net['val_mse']:.4f}, "
+            f"{time.time() - t0:.1f} s")
     s = msl.Solver(cfg, device="cuda:0")
+    if net is not None:
+        closure.install(s, net)
     s.set_mask(w["mask"])
     s.init(w["rho"], w["u"], w["T"])
-    ms, prof = timed_steps(s, steps, args.warmup)
+    # per-launch HIP events on about every fifth timed step (every step of a
+    # run of up to 5 steps); the events cost the stream a few microseconds
+    ms, prof = timed_steps(s, steps, args.warmup, every=profile_every(steps) if steps > 100 else
+                           max(1, min(3, steps // 5)))
     ncell = s.ncell
     value = ncell * steps / (ms / 1e3) / 1e6
     stable = True
@@ -605,7 +680,11 @@ def main():
         s.conservation()
     except msl.MslError:
         stable = False
-    nhigh = int(s.get_mask().sum().item())
+    nhigh = int(s.get_mask().sum().item()) if cfg["n_high"] else 0
+    if cfg["n_high"] and cfg["crit_kind"] and nhigh == 0:
+        print(json.dumps({"error": f"workload {args.workload}: no high-order cell at the end of the "
+                                   f"timed steps"}))
+        sys.exit(3)
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -619,7 +698,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if cfg["store"] != 0 else "f64",
         "data": "synthetic",
-        "config": {"workload": w["desc"], "grid": [cfg["nx"], cfg["ny"], cfg["nz"]],
+        "config": {"workload": w["desc"],
+                   "grid": [cfg["nx"], cfg["ny"], cfg["nz"]],
                    "cells": ncell, "lattices": [cfg["n_low"] ** cfg["dim"],
                                                 cfg["n_high"] ** cfg["dim"] if cfg["n_high"] else 0],
                    "storage": STORE_NAMES[cfg["store"]], "parallelism": "single GPU"},
@@ -628,8 +708,23 @@ def main():
         "high_order_cells_end": nhigh,
         "stable": stable,
     }
+    if net is not None:
+        out["closure"] = {"snapshots": net["rows"], "validation_mse": round(net["val_mse"], 5),
+                          "trained": "before the timed region, on the GPU"}
+    s.close()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        if cfg["dim"] == 3 and cfg["nx"] > 24:
+            # the oracle takes about 4 s per step of a 48^3 box on 8 host threads
+            # (every D3Q64 cell converts up to 27 neighbours by 64 x 64 moment
+            # solves): a 24^3 box of the same flow, vortex core and shear layer
+            # scaled down
+            small = inputs.vortex_shear_3d(n=24, store=inputs.STORE_FP64, rc=1.5, width=1.0,
+                                           lift_mode=cfg["lift_mode"])
+            out["cpu_baseline"] = cpu_baseline(small, args.cpu_seconds, net=net,
+                                               sample_desc="a 24^3 box of the same flow (vortex "
+                                                           "core 1.5, shear layer width 1)")
+        else:
+            out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, net=net)
     print(json.dumps(out))
 
 
