@@ -15,8 +15,9 @@
  *     (Sec. II.C.2, eqs. feqL, geqL, feqL0);
  *   - lifting m_q (+) M^eq_{Q-q} and projection M_q (Sec. III.B, III.C, App. C);
  *   - semi-Lagrangian propagation with lifting / projection applied to each
- *     collocation point of the other order (Sec. III.D), then BGK collision
- *     (eqs. Pond_f, Pond_g with omega1 = omega2).
+ *     collocation point of the other order (Sec. III.D), then the collision of
+ *     eqs. Pond_f, Pond_g: BGK (omega1 = omega2), or the two-relaxation model
+ *     with the quasi-equilibria of eqs. fqeq, gqeq.
  *
  * Pins (tests/test_oracle_*.py): Table I nodes and weights, Gauss-Hermite
  * exactness, the printed diagonal moments (eqs. QxxxL, RxxL, QxxxPonD, RxxPond)
@@ -69,6 +70,10 @@ typedef struct or_config {
                                  (rho0, store_u, T0): the deviation scale of population i
                                  is rho0 prod_a w_a r(c_a), r the density ratio of
                                  N(s, T0/T_ref) to N(0, 1), s = (store_u - u_ref)/sqrt(T_ref) */
+  double tau2;                /* > 0 and != tau: two-relaxation quasi-equilibrium model
+                                 (eqs. Pond_f/g with omega2 = 1/tau2 at the reference state;
+                                 Pr = (tau - 1/2)/(tau2 - 1/2) kept where tau varies with T);
+                                 otherwise BGK */
 } or_config;
 
 typedef struct or_ctx or_ctx;
@@ -88,6 +93,10 @@ int or_lagrange3(double xi, double *a);
 double or_round_fp16(double v);
 double or_round_bf16(double v);
 
+/* quasi-equilibria f*, g* (eqs. fqeq, gqeq, in the run's frame) of one cell's
+ * populations f (and g when thermal) of lattice `which` */
+int or_qeq(const or_ctx *ctx, int which, const double *f, const double *g, double *fstar,
+           double *gstar);
 /* OpenMP threads of the stepper (n >= 1); returns the previous count */
 int or_set_threads(int n);
 

@@ -28,10 +28,11 @@ class OrConfig(C.Structure):
         ("slot_edge", C.c_double * 6),
         ("crit_kind", C.c_int), ("crit_thr", C.c_double), ("crit_every", C.c_int),
         ("u_ref", C.c_double * 3), ("T_ref", C.c_double), ("store_u", C.c_double * 3),
+        ("tau2", C.c_double),
     ]
 
 # fields of the run configuration that default when a workload leaves them out
-_DEFAULTS = {"u_ref": (0.0, 0.0, 0.0), "T_ref": 1.0, "store_u": (0.0, 0.0, 0.0)}
+_DEFAULTS = {"u_ref": (0.0, 0.0, 0.0), "T_ref": 1.0, "store_u": (0.0, 0.0, 0.0), "tau2": 0.0}
 
 
 def lib():
@@ -294,6 +295,15 @@ class Oracle:
     def set_pops(self, which, data, fg=0):
         d = np.ascontiguousarray(data, dtype=np.float64).reshape(self.Q[which], self.ncell)
         _check(lib().or_set_pops(self._ctx, which, fg, _p(d)), "set_pops")
+
+    def qeq(self, which, f, g=None):
+        """Quasi-equilibria f*, g* of one cell's populations of lattice `which`."""
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        ga = np.ascontiguousarray(g, dtype=np.float64) if g is not None else np.zeros_like(f)
+        fs = np.zeros_like(f)
+        gs = np.zeros_like(f)
+        _check(lib().or_qeq(self._ctx, which, _p(f), _p(ga), _p(fs), _p(gs)), "qeq")
+        return fs, gs
 
     def macros(self):
         rho = np.zeros(self.ncell)

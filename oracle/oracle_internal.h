@@ -33,6 +33,10 @@ int lat_set_frame(lat_t *L, const double *u_ref, double T_ref);
 int lat_frame_trivial(const lat_t *L);
 double lat_vmax(const lat_t *L, int axis);
 void lat_feq(const lat_t *L, double rho, const double *u, double theta, double *out);
+void lat_from_comoving(const lat_t *L, const double *u, double theta, const ld *co, double *out);
+void lat_qeq(const lat_t *L, int thermal, double cv, double rho, const double *u, double T,
+             const double *f, const double *g, const double *feq, const double *geq,
+             double *fstar, double *gstar);
 void lat_moments(const lat_t *L, const double *f, ld *m);
 void lat_macros(const lat_t *L, int thermal, double cv, const double *f, const double *g,
                 double *rho, double *u, double *T);

@@ -204,6 +204,15 @@ double lat_vmax(const lat_t *L, int axis) {
  * sqrt(theta) c_i + u (eqs. vi, momf), mapped to the run's frame by the inverse
  * of its moment matrix.  In the lattice frame this is f^L. */
 void lat_feq(const lat_t *L, double rho, const double *u, double theta, double *out) {
+  ld co[OR_MAXQ];
+  for (int i = 0; i < L->Q; i++) co[i] = (ld)rho * L->Wl[i];
+  lat_from_comoving(L, u, theta, co, out);
+}
+
+/* Transfer of a population vector given in the co-moving frame {u, theta}
+ * (particle velocities sqrt(theta) c_i + u) to the run's frame:
+ * out = M_ref^{-1} M_{u,theta} co (eqs. fll, momf). */
+void lat_from_comoving(const lat_t *L, const double *u, double theta, const ld *co, double *out) {
   const int Q = L->Q, D = L->D;
   ld st = sqrtl((ld)theta);
   ld mom[OR_MAXQ];
@@ -213,7 +222,7 @@ void lat_feq(const lat_t *L, double rho, const double *u, double theta, double *
   for (int j = 0; j < Q; j++) {
     ld s = 0.0L;
     for (int i = 0; i < Q; i++) {
-      ld v = (ld)rho * L->Wl[i];
+      ld v = co[i];
       for (int a = 0; a < D; a++) v *= ipow_ld(vel[i][a], L->pw[j][a]);
       s += v;
     }
@@ -224,6 +233,56 @@ void lat_feq(const lat_t *L, double rho, const double *u, double theta, double *
     for (int j = 0; j < Q; j++) s += L->Mfinv[i * Q + j] * mom[j];
     out[i] = (double)s;
   }
+}
+
+/* Quasi-equilibria of the two-relaxation model (Sec. II.B, eqs. fqeq, gqeq),
+ * in the run's frame (the quasi-equilibrium counterpart of eq. feqL).
+ *   Qbar_abc = sum_i (v_i - u)_a (v_i - u)_b (v_i - u)_c (f_i - f^eq_i),
+ *   qbar_a   = sum_i (v_i - u)_a (g_i - g^eq_i),
+ * with the particle velocities v of the run's frame; in the co-moving frame
+ * {u, T} (theta = T, R = T_L = 1, velocities sqrt(theta) c + u)
+ *   f*_i = rho W_i + W_i Qbar : (theta^{3/2} c c c - T theta^{1/2} sym(c (x) 1)) / (6 T^3),
+ *   g*_i = (cv - D/2) T rho W_i + W_i theta^{1/2} qbar . c / T,
+ * sym(c (x) 1)_abc = c_a d_bc + c_b d_ac + c_c d_ab (the three placements, so
+ * that the bracket is the third Hermite tensor and f* keeps the third central
+ * moment Qbar); both are transferred to the run's frame.  g may be NULL when
+ * athermal (then gstar is untouched). */
+void lat_qeq(const lat_t *L, int thermal, double cv, double rho, const double *u, double T,
+             const double *f, const double *g, const double *feq, const double *geq,
+             double *fstar, double *gstar) {
+  const int Q = L->Q, D = L->D;
+  ld Qb[3][3][3] = {{{0}}}, qb[3] = {0, 0, 0};
+  for (int i = 0; i < Q; i++) {
+    ld d[3];
+    for (int a = 0; a < D; a++) d[a] = L->vl[i][a] - (ld)u[a];
+    const ld nf = (ld)f[i] - (ld)feq[i];
+    for (int a = 0; a < D; a++)
+      for (int b = 0; b < D; b++)
+        for (int c = 0; c < D; c++) Qb[a][b][c] += d[a] * d[b] * d[c] * nf;
+    if (thermal)
+      for (int a = 0; a < D; a++) qb[a] += d[a] * ((ld)g[i] - (ld)geq[i]);
+  }
+  const ld th = (ld)T, Tl = (ld)T;
+  ld cof[OR_MAXQ], cog[OR_MAXQ];
+  for (int i = 0; i < Q; i++) {
+    const ld *c = L->cl[i];
+    ld s = 0.0L;
+    for (int a = 0; a < D; a++)
+      for (int b = 0; b < D; b++)
+        for (int cc = 0; cc < D; cc++) {
+          const ld ccc = c[a] * c[b] * c[cc];
+          const ld sym = (b == cc ? c[a] : 0.0L) + (a == cc ? c[b] : 0.0L) + (a == b ? c[cc] : 0.0L);
+          s += Qb[a][b][cc] * (powl(th, 1.5L) * ccc - Tl * sqrtl(th) * sym);
+        }
+    cof[i] = (ld)rho * L->Wl[i] + L->Wl[i] * s / (6.0L * Tl * Tl * Tl);
+    if (thermal) {
+      ld qc = 0.0L;
+      for (int a = 0; a < D; a++) qc += qb[a] * c[a];
+      cog[i] = ((ld)cv - 0.5L * D) * Tl * (ld)rho * L->Wl[i] + L->Wl[i] * sqrtl(th) * qc / Tl;
+    }
+  }
+  lat_from_comoving(L, u, T, cof, fstar);
+  if (thermal) lat_from_comoving(L, u, T, cog, gstar);
 }
 
 /* Raw lattice moments m_j = sum_i f_i prod_a c_ia^{p_a(j)} for every j of the

@@ -239,19 +239,37 @@ static double relax_tau(const or_ctx *c, double rho, double T) {
   return mu / (rho * T * c->dt) + 0.5;
 }
 
+/* Collision (eqs. Pond_f, Pond_g): relaxation towards the equilibrium at rate
+ * omega1 = 1/tau, plus (omega1 - omega2)(f* - f^eq) towards the
+ * quasi-equilibrium when the two rates differ.  omega2 follows tau2 at the
+ * reference state; where tau varies with T the Prandtl number
+ * Pr = (tau - 1/2)/(tau2 - 1/2) is kept. */
 static void collide(const or_ctx *c, int l, const double *ft, const double *gt,
                     double *fo, double *go) {
   const lat_t *L = c->lat[l];
+  const int th = c->cfg.thermal;
   double rho, u[3], T;
-  lat_macros(L, c->cfg.thermal, c->cfg.cv, ft, gt, &rho, u, &T);
+  lat_macros(L, th, c->cfg.cv, ft, gt, &rho, u, &T);
   double feq[OR_MAXQ], geq[OR_MAXQ];
   lat_feq(L, rho, u, T, feq);
-  double om = 1.0 / relax_tau(c, rho, T);
-  for (int i = 0; i < L->Q; i++) fo[i] = ft[i] + om * (feq[i] - ft[i]);
-  if (c->cfg.thermal) {
-    lat_geq_from_feq(L, c->cfg.cv, T, feq, geq);
-    for (int i = 0; i < L->Q; i++) go[i] = gt[i] + om * (geq[i] - gt[i]);
+  if (th) lat_geq_from_feq(L, c->cfg.cv, T, feq, geq);
+  const double tl = relax_tau(c, rho, T);
+  const double om = 1.0 / tl;
+  const int two = c->cfg.tau2 > 0.0 && c->cfg.tau2 != c->cfg.tau;
+  double fs[OR_MAXQ], gs[OR_MAXQ], om2 = om;
+  if (two) {
+    om2 = 1.0 / (0.5 + (tl - 0.5) * (c->cfg.tau2 - 0.5) / (c->cfg.tau - 0.5));
+    lat_qeq(L, th, c->cfg.cv, rho, u, T, ft, gt, feq, geq, fs, gs);
   }
+  for (int i = 0; i < L->Q; i++) {
+    fo[i] = ft[i] + om * (feq[i] - ft[i]);
+    if (two) fo[i] += (om - om2) * (fs[i] - feq[i]);
+  }
+  if (th)
+    for (int i = 0; i < L->Q; i++) {
+      go[i] = gt[i] + om * (geq[i] - gt[i]);
+      if (two) go[i] += (om - om2) * (gs[i] - geq[i]);
+    }
 }
 
 /* ---- one cell's update ---- */
@@ -328,6 +346,7 @@ int or_create(const or_config *cfg, or_ctx **out) {
   if (cfg->nx < 1 || cfg->ny < 1 || (cfg->dim == 3 && cfg->nz < 1)) return -1;
   if (cfg->n_low < 2 || (cfg->n_high && cfg->n_high <= cfg->n_low)) return -1;
   if (cfg->tau <= 0.5) return -1;
+  if (cfg->tau2 > 0.0 && cfg->tau2 <= 0.5) return -1;
   or_ctx *c = (or_ctx *)calloc(1, sizeof(or_ctx));
   c->cfg = *cfg;
   c->D = cfg->dim;
@@ -413,6 +432,18 @@ void or_destroy(or_ctx *c) {
   free(c->flags); free(c->emlp); free(c->egrad);
   free(c->mlp_p); free(c->xm); free(c->xs); free(c->tm); free(c->ts);
   free(c);
+}
+
+int or_qeq(const or_ctx *c, int which, const double *f, const double *g, double *fstar,
+           double *gstar) {
+  if (which < 0 || which >= c->nlat) return -1;
+  const lat_t *L = c->lat[which];
+  double rho, u[3], T, feq[OR_MAXQ], geq[OR_MAXQ];
+  lat_macros(L, c->cfg.thermal, c->cfg.cv, f, g, &rho, u, &T);
+  lat_feq(L, rho, u, T, feq);
+  if (c->cfg.thermal) lat_geq_from_feq(L, c->cfg.cv, T, feq, geq);
+  lat_qeq(L, c->cfg.thermal, c->cfg.cv, rho, u, T, f, g, feq, geq, fstar, gstar);
+  return 0;
 }
 
 int or_set_threads(int n) {
