@@ -99,6 +99,11 @@ typedef struct msl_config {
                                  Gaussian N(z_a, T0/T_ref) to N(0, 1) at the node and
                                  z = (store_u - u_ref) / sqrt(T_ref); s_i = rho0 W_i when
                                  the storage reference is the frame's rest state */
+  double tau2;                /* > 0 and != tau: the two-relaxation quasi-equilibrium model of
+                                 eqs. Pond_f/g (Sec. II.B, eqs. fqeq, gqeq): stress relaxes at
+                                 1/tau, the non-equilibrium third moment and heat flux at
+                                 omega2 = 1/tau2, Pr = (tau - 1/2)/(tau2 - 1/2) (kept where tau
+                                 follows mu(T)); 2D only.  Otherwise BGK (omega1 = omega2). */
 } msl_config;
 
 typedef struct msl_ctx msl_ctx;

@@ -162,6 +162,8 @@ static void build_lat(LatTab &L, int n, int dim, const ld *x, const ld *w, doubl
     }
     L.sc[i] = (double)s;
     L.scf[i] = (float)s;
+    L.isc[i] = (double)(1.0L / s);
+    L.iscf[i] = (float)(1.0L / s);
   }
 }
 
@@ -204,6 +206,8 @@ static const char *check_config(const msl_config *cfg) {
   const bool trivial_frame = cfg->u_ref[0] == 0.0 && cfg->u_ref[1] == 0.0 &&
                              (cfg->dim == 2 || cfg->u_ref[2] == 0.0) && (cfg->T_ref <= 0.0 || cfg->T_ref == 1.0);
   if (cfg->lift_mode == MSL_LIFT_MLP && !trivial_frame) return "learned lifting needs the lattice frame";
+  if (isnan(cfg->tau2) || (cfg->tau2 > 0.0 && !(cfg->tau2 > 0.5))) return "tau2 must exceed 1/2 (or be <= 0 for BGK)";
+  if (cfg->tau2 > 0.0 && cfg->tau2 != cfg->tau && cfg->dim != 2) return "the two-relaxation model is built for 2D";
   const long long cells = (long long)cfg->nx * cfg->ny * (cfg->dim == 3 ? cfg->nz : 1);
   if (cells >= (1ll << 31)) return "grid too large";
   for (int f = 0; f < 2 * cfg->dim; ++f) {
@@ -444,6 +448,10 @@ int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_
   t.rho0 = cfg->rho0 > 0 ? cfg->rho0 : 1.0;
   t.T0 = cfg->T0 > 0 ? cfg->T0 : 1.0;
   t.tau_mode = cfg->tau_mode;
+  t.igsc = t.gfac > 0.0 ? 1.0 / (t.gfac * (cfg->T0 > 0 ? cfg->T0 : 1.0)) : 0.0;
+  t.igscf = (float)t.igsc;
+  t.qe = cfg->tau2 > 0.0 && cfg->tau2 != cfg->tau;
+  t.qe_ratio = t.qe ? (cfg->tau2 - 0.5) / (cfg->tau - 0.5) : 1.0;
   t.thermal = cfg->thermal;
   t.dim = cfg->dim;
   t.nlat = c->nlat;

@@ -38,6 +38,36 @@ __device__ __forceinline__ void eq_axis(const LatTab &L, C u, C theta, C *P) {
   }
 }
 
+// Per-axis factors of the quasi-equilibria (eqs. fqeq, gqeq) in the run's
+// frame.  A co-moving population w_a He_k(c_a) (Hermite order k along one axis)
+// maps to the run's frame as theta'^{k/2} A[k][a] with
+//   A[k][a] = sum_{k <= j < N} w_a He_j(c_a)/j! * j!/(j-k)! * b_{j-k},
+// b_j the Hermite coefficients of the equilibrium factor (eq_axis), from the
+// generating function E[He_k(Z) exp(t (sqrt(theta') Z + u') - t^2/2)] =
+// theta'^{k/2} t^k exp(u' t + (theta' - 1) t^2/2).  A[0] is the equilibrium
+// factor itself.
+template <typename C, int N>
+__device__ __forceinline__ void qe_axis(const LatTab &L, double u, double theta, C (*A)[N]) {
+  double b[N];
+  b[0] = 1.0;
+  if (N > 1) b[1] = u;
+#pragma unroll
+  for (int j = 1; j + 1 < N; ++j) b[j + 1] = u * b[j] + (double)j * (theta - 1.0) * b[j - 1];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = k; j < N; ++j) {
+        double fall = 1.0;
+        for (int m = 0; m < k; ++m) fall *= (double)(j - m);
+        s += L.hw[a][j] * fall * b[j - k];
+      }
+      A[k][a] = (C)s;
+    }
+}
+
 // runtime-N variant (FP64), used by the auxiliary kernels and the host tables
 __host__ __device__ __forceinline__ void eq_axis_rt(const LatTab &L, double u, double theta, double *P) {
   double b[MSL_MAXN];

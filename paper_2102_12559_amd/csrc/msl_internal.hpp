@@ -35,10 +35,11 @@ struct LatTab {
   // temperature T iTr (isq = 1/sqrt(T_ref), iTr = 1/T_ref)
   double ur[3], isq, iTr;
   double sc[MSL_MAXQ];             // 16-bit storage scale of f_i (g_i: gfac T0 sc[i])
+  double isc[MSL_MAXQ];            // 1 / sc[i]
   float vf[3][MSL_MAXN], wf[MSL_MAXN];
   float hwf[MSL_MAXN][MSL_MAXN];
   float af[3][MSL_MAXN][3];
-  float scf[MSL_MAXQ];
+  float scf[MSL_MAXQ], iscf[MSL_MAXQ];
 };
 
 struct Tab {
@@ -50,6 +51,12 @@ struct Tab {
   double P[MSL_MAXN][MSL_MAXN];    // project: P[a'][a] = l^low_{a'}(C_a)
   double Vi[MSL_MAXN][MSL_MAXN];   // inverse Vandermonde of the high nodes: Vi[a][m]
   double dt, cv, gfac, tau, omega, mu_ref, mu_exp, tau_ref_T, rho0, T0;
+  // two-relaxation model: 1/omega2 - 1/2 = qe_ratio (1/omega1 - 1/2), with
+  // qe_ratio = (tau2 - 1/2)/(tau - 1/2) = 1/Pr; qe = 0: BGK
+  double qe_ratio;
+  int qe;
+  double igsc;    // 1 / (gfac T0): the g scale is gfac T0 sc[i] (0 when athermal)
+  float igscf;
   double mu_T1;   // mu_ref (1 / tau_ref_T)^mu_exp: the viscosity at T = 1
   float omegaf;
   int tau_mode, thermal, dim, nlat, lift_mode;

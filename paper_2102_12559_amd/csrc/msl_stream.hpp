@@ -48,7 +48,7 @@ struct SCTraits {
 
 // Collision of the R cells of one thread; ft[k][r] holds the streamed value of
 // plane k (raw storage domain) at cell r.
-template <typename S, bool TH, int N, int D, int R, int NP>
+template <typename S, bool TH, int N, int D, int R, int NP, bool QE = false>
 __device__ __forceinline__ void collide_store(const Tab *__restrict__ tab, int lat, const Geo &g,
                                               typename StoreTraits<S>::C (&ft)[NP][R],
                                               S *__restrict__ out, const uint8_t *__restrict__ cls,
@@ -96,9 +96,11 @@ __device__ __forceinline__ void collide_store(const Tab *__restrict__ tab, int l
     double Tm = 1.0;
     if (TH) Tm = ((double)e - 0.5 * rd * (ux * ux + uy * uy + uz * uz)) / (tab->cv * rd);
     C om = tsel<C>(tab->omega, tab->omegaf);
+    double tl = tab->tau;
     if (tab->tau_mode == 1) {
       const double mu = TH ? tab->mu_ref * pow(Tm / tab->tau_ref_T, tab->mu_exp) : tab->mu_T1;
-      om = (C)(1.0 / (mu / (rd * Tm * tab->dt) + 0.5));
+      tl = mu / (rd * Tm * tab->dt) + 0.5;
+      om = (C)(1.0 / tl);
     }
     double Px[N], Py[N], Pz[N];
     eq_axis<double, N>(L, (ux - L.ur[0]) * L.isq, Tm * L.iTr, Px);
@@ -107,6 +109,39 @@ __device__ __forceinline__ void collide_store(const Tab *__restrict__ tab, int l
 #pragma unroll
     for (int a = 0; a < N; ++a) Px[a] *= rd;
     const C gf = (C)(tab->gfac * Tm);
+    // two-relaxation model (2D; eqs. Pond_f/g with the quasi-equilibria of
+    // eqs. fqeq, gqeq in the run's frame): Qbar, qbar of the cell folded with
+    // (omega1 - omega2) and the constants of f* - f^eq and g* - g^eq
+    C Ax[QE ? 4 : 1][N], Ay[QE ? 4 : 1][N], Qb[4] = {C(0), C(0), C(0), C(0)}, qb[2] = {C(0), C(0)};
+    if constexpr (QE) {
+      static_assert(D == 2, "the two-relaxation model is built for 2D");
+      qe_axis<C, N>(L, (ux - L.ur[0]) * L.isq, Tm * L.iTr, Ax);
+      qe_axis<C, N>(L, (uy - L.ur[1]) * L.isq, Tm * L.iTr, Ay);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const int a = i % N, b = (i / N) % N;
+        const C dx = tsel<C>(L.v[0][a], L.vf[0][a]) - (C)ux, dy = tsel<C>(L.v[1][b], L.vf[1][b]) - (C)uy;
+        const C feq = (C)(Px[a] * Py[b]);
+        const C nf = f[i] - feq;
+        Qb[0] += dx * dx * dx * nf;
+        Qb[1] += dx * dx * dy * nf;
+        Qb[2] += dx * dy * dy * nf;
+        Qb[3] += dy * dy * dy * nf;
+        if (TH) {
+          const C ng = gg[TH ? i : 0] - gf * feq;
+          qb[0] += dx * ng;
+          qb[1] += dy * ng;
+        }
+      }
+      const C dom = (C)(1.0 / tl - 1.0 / (0.5 + (tl - 0.5) * tab->qe_ratio));
+      const C cf = (C)(L.isq * L.isq * L.isq / 6.0) * dom, cg = (C)L.isq * dom;
+      Qb[0] *= cf;
+      Qb[1] *= C(3) * cf;
+      Qb[2] *= C(3) * cf;
+      Qb[3] *= cf;
+      qb[0] *= cg;
+      qb[1] *= cg;
+    }
     const unsigned boff = (unsigned)g.idx(x, y, z) * (unsigned)sizeof(S);
     S so[Q];
     S sg[TH ? Q : 1];
@@ -116,11 +151,15 @@ __device__ __forceinline__ void collide_store(const Tab *__restrict__ tab, int l
       double feqd = Px[a] * Py[b];
       if (D == 3) feqd *= Pz[cc];
       const C feq = (C)feqd;
-      const C fo = f[i] + om * (feq - f[i]);
+      C fo = f[i] + om * (feq - f[i]);
+      if constexpr (QE)
+        fo += Qb[0] * Ax[3][a] * Ay[0][b] + Qb[1] * Ax[2][a] * Ay[1][b] + Qb[2] * Ax[1][a] * Ay[2][b] +
+              Qb[3] * Ax[0][a] * Ay[3][b];
       const C W = tsel<C>(L.sc[i], L.scf[i]);
       so[i] = T::store(T::dev ? fo / W - C(1) : fo);
       if (TH) {
-        const C go = gg[TH ? i : 0] + om * (gf * feq - gg[TH ? i : 0]);
+        C go = gg[TH ? i : 0] + om * (gf * feq - gg[TH ? i : 0]);
+        if constexpr (QE) go += qb[0] * Ax[1][a] * Ay[0][b] + qb[1] * Ax[0][a] * Ay[1][b];
         sg[TH ? i : 0] = T::store(T::dev ? go / (gsc0 * W) - C(1) : go);
       }
     }
@@ -141,7 +180,7 @@ __device__ __forceinline__ void for_planes(F &&f) {
   }(std::make_integer_sequence<int, NP>{});
 }
 
-template <typename S, bool TH, int N>
+template <typename S, bool TH, int N, bool QE = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SCTraits<S, TH, N, 2>::WAVES)))
 k_sc2d(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in, S *__restrict__ out,
        const uint8_t *__restrict__ cls, const uint8_t *__restrict__ tflag) {
@@ -218,10 +257,10 @@ k_sc2d(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in, S 
   lstore(0);
   __syncthreads();
   for_planes<NP>(step);
-  collide_store<S, TH, N, 2, R, NP>(tab, lat, g, ft, out, cls, x0 + tx, y0 + ty * R, 0, 1, 0);
+  collide_store<S, TH, N, 2, R, NP, QE>(tab, lat, g, ft, out, cls, x0 + tx, y0 + ty * R, 0, 1, 0);
 }
 
-template <typename S, bool TH, int N, int D>
+template <typename S, bool TH, int N, int D, bool QE = false>
 static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
   using Tr = SCTraits<S, TH, N, D>;
   const Geo &g = c->geo;
@@ -241,7 +280,7 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
       small = tiles8 < 2048;
       if (small) {
         dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + T2::TY - 1) / T2::TY);
-        hipLaunchKernelGGL((k_sc2d_res<S, TH, N, true>), grid, block, 0, c->stream, c->dtab, lat, g,
+        hipLaunchKernelGGL((k_sc2d_res<S, TH, N, true, false, QE>), grid, block, 0, c->stream, c->dtab, lat, g,
                            (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, nt, nullptr, nullptr);
       }
     }
@@ -266,7 +305,7 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
         }
         if (c->tl_n == 0) return MSL_OK;
         dim3 grid((unsigned)c->tl_n);
-        hipLaunchKernelGGL((k_sc2d_res<S, TH, N, false, true>), grid, block, 0, c->stream, c->dtab, lat,
+        hipLaunchKernelGGL((k_sc2d_res<S, TH, N, false, true, QE>), grid, block, 0, c->stream, c->dtab, lat,
                            g, (const S *)in, (S *)out, c->cls, c->tflag, 0, nt, c->tlist, c->tcount);
         return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
       }
@@ -274,12 +313,12 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
     if (!small) {
       using T2 = SC2Traits<S, TH, N>;
       dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + T2::TY - 1) / T2::TY);
-      hipLaunchKernelGGL((k_sc2d_res<S, TH, N, false>), grid, block, 0, c->stream, c->dtab, lat, g,
+      hipLaunchKernelGGL((k_sc2d_res<S, TH, N, false, false, QE>), grid, block, 0, c->stream, c->dtab, lat, g,
                          (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, nt, nullptr, nullptr);
     }
   } else if constexpr (D == 2) {
     dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + MSL_MTY * Tr::R - 1) / (MSL_MTY * Tr::R));
-    hipLaunchKernelGGL((k_sc2d<S, TH, N>), grid, block, 0, c->stream, c->dtab, lat, g,
+    hipLaunchKernelGGL((k_sc2d<S, TH, N, QE>), grid, block, 0, c->stream, c->dtab, lat, g,
                        (const S *)in, (S *)out, c->cls, c->tflag);
   } else {
     // 3D: planes streamed through LDS in chunks; the high-order set of a
@@ -316,6 +355,15 @@ template <typename S, bool TH>
 static int launch_n(msl_ctx *c, int lat, const char *in, char *out) {
   const int n = c->htab.lat[lat].n;
   if (c->D == 2) {
+    if (c->htab.qe) {
+      switch (n) {
+        case 3: return launch_one<S, TH, 3, 2, true>(c, lat, in, out);
+        case 4: return launch_one<S, TH, 4, 2, true>(c, lat, in, out);
+        case 5: return launch_one<S, TH, 5, 2, true>(c, lat, in, out);
+        case 6: return launch_one<S, TH, 6, 2, true>(c, lat, in, out);
+      }
+      return MSL_EINVAL;
+    }
     switch (n) {
       case 3: return launch_one<S, TH, 3, 2>(c, lat, in, out);
       case 4: return launch_one<S, TH, 4, 2>(c, lat, in, out);

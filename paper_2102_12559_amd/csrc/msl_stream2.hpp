@@ -87,7 +87,7 @@ __device__ __forceinline__ float lds_elem<bf16_t>(const char *p) {
 template <typename S>
 __device__ __forceinline__ double lds_elem_d(const char *p) { return *(const double *)p; }
 
-template <typename S, bool TH, int N, bool SMALL, bool LIST = false>
+template <typename S, bool TH, int N, bool SMALL, bool LIST = false, bool QE = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SC2Traits<S, TH, N, SMALL>::WAVES)))
 k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
            S *__restrict__ out, const uint8_t *__restrict__ cls,
@@ -213,6 +213,10 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   // 3. equilibrium factors per cell, in FP64 (no rounding bias in the
   //    equilibrium's mass and momentum), kept in the compute precision
   C Px[R][N], Py[R][N], om[R], gf[R];
+  // two-relaxation model: velocity, omega1 - omega2 and the per-axis factors
+  // of the quasi-equilibria (without rho) of each cell
+  C uxr[QE ? R : 1], uyr[QE ? R : 1], dom[QE ? R : 1];
+  C Ax[QE ? R : 1][4][N], Ay[QE ? R : 1][4][N];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const double rd = (double)rho[r], ird = 1.0 / rd;
@@ -228,13 +232,69 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
       Py[r][q] = (C)py[q];
     }
     om[r] = tsel<C>(tab->omega, tab->omegaf);
+    double tl = tab->tau;
     // temperature-dependent viscosity mu = mu_ref (T / T_ref)^s, tau = mu / (rho T dt)
     // + 1/2 (athermal: T = 1, the power is a table constant)
     if (tab->tau_mode == 1) {
       const double mu = TH ? tab->mu_ref * pow(Tm / tab->tau_ref_T, tab->mu_exp) : tab->mu_T1;
-      om[r] = (C)(1.0 / (mu / (rd * Tm * tab->dt) + 0.5));
+      tl = mu / (rd * Tm * tab->dt) + 0.5;
+      om[r] = (C)(1.0 / tl);
     }
     gf[r] = (C)(tab->gfac * Tm);
+    if constexpr (QE) {
+      uxr[r] = (C)ux;
+      uyr[r] = (C)uy;
+      dom[r] = (C)(1.0 / tl - 1.0 / (0.5 + (tl - 0.5) * tab->qe_ratio));
+      qe_axis<C, N>(L, (ux - L.ur[0]) * L.isq, Tm * L.iTr, Ax[r]);
+      qe_axis<C, N>(L, (uy - L.ur[1]) * L.isq, Tm * L.iTr, Ay[r]);
+    }
+  }
+  // two-relaxation model (eqs. Pond_f/g with the quasi-equilibria of eqs. fqeq,
+  // gqeq in the run's frame): the non-equilibrium third central moment Qbar and
+  // heat flux qbar of each cell, folded with (omega1 - omega2) and the
+  // constants of f* - f^eq = T_ref^{-3/2}/6 sum_{|k|=3} mult(k) Qbar_k prod A^(k),
+  // g* - g^eq = T_ref^{-1/2} sum_a qbar_a A^(1)_a prod A^(0)
+  C Qb[QE ? R : 1][4], qb[QE ? R : 1][2];
+  if constexpr (QE) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      Qb[r][0] = Qb[r][1] = Qb[r][2] = Qb[r][3] = C(0);
+      qb[r][0] = qb[r][1] = C(0);
+    }
+    auto qacc = [&]<int K>() {
+      constexpr int i = K % Q, a = i % N, b = i / N;
+      const C W = tsel<C>(L.sc[i], L.scf[i]);
+      const C sc = K < Q ? W : gsc0 * W;
+      const C cx = tsel<C>(L.v[0][a], L.vf[0][a]), cy = tsel<C>(L.v[1][b], L.vf[1][b]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const C feq = Px[r][a] * Py[r][b];
+        const C v = T::dev ? sc * (C(1) + ftk[K][r]) : ftk[K][r];
+        const C dx = cx - uxr[r], dy = cy - uyr[r];
+        if constexpr (K < Q) {
+          const C nf = v - feq;
+          Qb[r][0] += dx * dx * dx * nf;
+          Qb[r][1] += dx * dx * dy * nf;
+          Qb[r][2] += dx * dy * dy * nf;
+          Qb[r][3] += dy * dy * dy * nf;
+        } else {
+          const C ng = v - gf[r] * feq;
+          qb[r][0] += dx * ng;
+          qb[r][1] += dy * ng;
+        }
+      }
+    };
+    msl_for_planes<NP>(qacc);
+    const C cf = (C)(L.isq * L.isq * L.isq / 6.0), cg = (C)L.isq;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      Qb[r][0] *= dom[r] * cf;
+      Qb[r][1] *= dom[r] * C(3) * cf;
+      Qb[r][2] *= dom[r] * C(3) * cf;
+      Qb[r][3] *= dom[r] * cf;
+      qb[r][0] *= dom[r] * cg;
+      qb[r][1] *= dom[r] * cg;
+    }
   }
   // 4. collide and store
   unsigned soff_cell[R];
@@ -248,7 +308,7 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     const C W = tsel<C>(L.sc[i], L.scf[i]);
     // decoded scale of a 16-bit deviation and its reciprocal (one per plane)
     const C sc = K < Q ? W : gsc0 * W;
-    const C isc = T::dev ? C(1) / sc : C(1);
+    const C isc = T::dev ? tsel<C>(L.isc[i], L.iscf[i]) * (K < Q ? C(1) : tsel<C>(tab->igsc, tab->igscf)) : C(1);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(out + (long long)K * g.plane), (short)0, (int)plane_b, MSL_RSRC_WORD3);
 #pragma unroll
@@ -258,6 +318,13 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
       C vo;
       if constexpr (K < Q) vo = v + om[r] * (feq - v);
       else vo = v + om[r] * (gf[r] * feq - v);
+      if constexpr (QE) {
+        if constexpr (K < Q)
+          vo += Qb[r][0] * Ax[r][3][a] * Ay[r][0][b] + Qb[r][1] * Ax[r][2][a] * Ay[r][1][b] +
+                Qb[r][2] * Ax[r][1][a] * Ay[r][2][b] + Qb[r][3] * Ax[r][0][a] * Ay[r][3][b];
+        else
+          vo += qb[r][0] * Ax[r][1][a] * Ay[r][0][b] + qb[r][1] * Ax[r][0][a] * Ay[r][1][b];
+      }
       const C o = T::dev ? vo * isc - C(1) : vo;
       const S sv = T::store(o);
       // nt: non-temporal stores (cache policy bit 1) when the output buffer is

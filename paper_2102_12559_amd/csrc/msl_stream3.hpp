@@ -264,7 +264,7 @@ k_sc3d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     constexpr int i = K % Q, a = i % N, b = (i / N) % N, cc = i / (N * N);
     const C W = tsel<C>(L.sc[i], L.scf[i]);
     const C sc = K < Q ? W : gsc0 * W;
-    const C isc = T::dev ? C(1) / sc : C(1);
+    const C isc = T::dev ? tsel<C>(L.isc[i], L.iscf[i]) * (K < Q ? C(1) : tsel<C>(tab->igsc, tab->igscf)) : C(1);
     const C feq = Px[a] * Py[b] * Pz[cc];
     const C v = T::dev ? sc * (C(1) + ftk[K][rz]) : ftk[K][rz];
     C vo;

@@ -404,3 +404,22 @@ def test_sentinel_reports_instability():
     with pytest.raises(msl.MslError) as ei:
         s.step(400)
     assert ei.value.code == msl.MSL_EUNSTABLE
+
+
+@pytest.mark.parametrize("store,tol", [(inputs.STORE_FP64, 1e-12), (inputs.STORE_FP16_DEV, 2e-3)])
+def test_3d_columns_ragged_z(store, tol):
+    """A ragged box along every axis, z included: 70 x 10 x 37 (two x tiles,
+    a partial y tile, a z extent that is no multiple of the kernels' z
+    blocking) with two D3Q64 blobs and a flow along all three axes, 6 steps."""
+    nx, ny, nz = 70, 10, 37
+    rho, u, T = inputs.smooth_random_flow(nx, ny, nz, umax=0.15, seed=51, drho=0.02)
+    cfg = inputs.base_config(dim=3, nx=nx, ny=ny, nz=nz, n_low=3, n_high=4, tau=0.7, store=store,
+                             store_u=(0.0, 0.0, 0.0))
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    mask[10:20, 3:7, 20:40] = 1
+    mask[30:, :, 50:60] = 1
+    s, o = run_pair(cfg, rho, u, T, mask, 6, tag=f"3D ragged z columns store={store}")
+    if store == inputs.STORE_FP64:
+        compare_pops(s, o, tol)
+    else:
+        compare_macros(s, o, tol, uscale=1.0)
