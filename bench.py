@@ -95,7 +95,7 @@ def kernel_source_hash():
     """Hash of the stream-collide kernel sources: a counter summary taken on
     other sources no longer describes the kernel."""
     h = hashlib.sha256()
-    for f in ("msl_stream.hpp", "msl_stream2.hpp", "msl_stream3.hpp", "msl_device.hpp",
+    for f in ("msl_stream.hpp", "msl_stream2.hpp", "msl_stream3.hpp", "msl_stream3z.hpp", "msl_device.hpp",
               "msl_internal.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2102_12559_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]

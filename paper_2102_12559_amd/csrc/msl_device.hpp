@@ -21,8 +21,9 @@ __host__ __device__ constexpr int msl_rows_for(int nplanes, int words, int budge
 // exp(u t + (theta - 1) t^2 / 2):  b_0 = 1, b_1 = u,
 // b_{j+1} = u b_j + j (theta - 1) b_{j-1}.  The tensor product of the 1D factors
 // (times rho) is the lattice-frame equilibrium f^L of eqs. feqL / feqL0.
-template <typename C, int N>
-__device__ __forceinline__ void eq_axis(const LatTab &L, C u, C theta, C *P) {
+// (LT: the lattice table, possibly in the constant address space)
+template <typename C, int N, typename LT = LatTab>
+__device__ __forceinline__ void eq_axis(const LT &L, C u, C theta, C *P) {
   C b[N];
   b[0] = C(1);
   if (N > 1) b[1] = u;

@@ -24,6 +24,7 @@
 #include "msl_device.hpp"
 #include "msl_stream2.hpp"
 #include "msl_stream3.hpp"
+#include "msl_stream3z.hpp"
 
 template <typename S, bool TH, int N, int D>
 struct SCTraits {
@@ -321,8 +322,41 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
     hipLaunchKernelGGL((k_sc2d<S, TH, N, QE>), grid, block, 0, c->stream, c->dtab, lat, g,
                        (const S *)in, (S *)out, c->cls, c->tflag);
   } else {
-    // 3D: planes streamed through LDS in chunks; the high-order set of a
-    // large grid runs over the compact list of its live tiles (as in 2D)
+    if constexpr (SC3ZTraits<S, TH, N>::fits) {
+      // 3D: columns of 64 x 4 x ZC cells walked along z (all planes addressed
+      // by 31-bit offsets); the high-order set of a large grid runs over the
+      // compact list of its live columns
+      using T3 = SC3ZTraits<S, TH, N>;
+      if ((long long)T3::NP * g.plane * (long long)sizeof(S) <= 0x80000000LL) {
+        const int ncz = (g.nz + T3::ZC - 1) / T3::ZC;
+        const long long tiles = (long long)g.ntx * g.nty * ncz;
+        const long long fit = 256LL * ((160 * 1024) / T3::LDS_BYTES);
+        if (lat != 0 && tiles > 4 * fit) {
+          if (!c->tl_ok) {
+            if (msl_launch_tile_list(c, lat, 1, T3::ZC)) return MSL_EHIP;
+            int n = 0;
+            if (hipMemcpyAsync(&n, c->tcount, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+                hipStreamSynchronize(c->stream) != hipSuccess)
+              return MSL_EHIP;
+            c->tl_n = n;
+            c->tl_ok = 1;
+          }
+          if (c->tl_n == 0) return MSL_OK;
+          hipLaunchKernelGGL((k_sc3d_zm<S, TH, N, true>), dim3((unsigned)c->tl_n), block, 0, c->stream,
+                             c->dtab, lat, g, (const S *)in, (S *)out, c->cls, c->tflag, 0, c->xmir,
+                             c->tlist, c->tcount);
+          return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
+        }
+        dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + MSL_MTY - 1) / MSL_MTY, ncz);
+        hipLaunchKernelGGL((k_sc3d_zm<S, TH, N>), grid, block, 0, c->stream, c->dtab, lat, g,
+                           (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, c->xmir, nullptr, nullptr);
+        return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
+      }
+    }
+    // 3D sets whose planes do not fit the walk's register budget, or whose
+    // planes span more than 2 GB: planes streamed through LDS in chunks; the
+    // high-order set of a large grid runs over the compact list of its live
+    // tiles (as in 2D)
     using T3 = SC3Traits<S, TH, N>;
     const long long tiles = (long long)g.ntx * g.nty * ((g.ntz + T3::RZ - 1) / T3::RZ);
     const long long fit = 256LL * ((160 * 1024) / T3::LDS_BYTES);
