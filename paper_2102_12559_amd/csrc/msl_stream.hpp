@@ -323,11 +323,10 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
                        (const S *)in, (S *)out, c->cls, c->tflag);
   } else {
     if constexpr (SC3ZTraits<S, TH, N>::fits) {
-      // 3D: columns of 64 x 4 x ZC cells walked along z (all planes addressed
-      // by 31-bit offsets); the high-order set of a large grid runs over the
-      // compact list of its live columns
+      // 3D: columns of 64 x 4 x ZC cells walked along z; the high-order set
+      // of a large grid runs over the compact list of its live columns
       using T3 = SC3ZTraits<S, TH, N>;
-      if ((long long)T3::NP * g.plane * (long long)sizeof(S) <= 0x80000000LL) {
+      {
         const int ncz = (g.nz + T3::ZC - 1) / T3::ZC;
         const long long tiles = (long long)g.ntx * g.nty * ncz;
         const long long fit = 256LL * ((160 * 1024) / T3::LDS_BYTES);
@@ -353,10 +352,9 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
         return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
       }
     }
-    // 3D sets whose planes do not fit the walk's register budget, or whose
-    // planes span more than 2 GB: planes streamed through LDS in chunks; the
-    // high-order set of a large grid runs over the compact list of its live
-    // tiles (as in 2D)
+    // 3D sets whose planes do not fit the walk's register budget: planes
+    // streamed through LDS in chunks; the high-order set of a large grid runs
+    // over the compact list of its live tiles (as in 2D)
     using T3 = SC3Traits<S, TH, N>;
     const long long tiles = (long long)g.ntx * g.nty * ((g.ntz + T3::RZ - 1) / T3::RZ);
     const long long fit = 256LL * ((160 * 1024) / T3::LDS_BYTES);

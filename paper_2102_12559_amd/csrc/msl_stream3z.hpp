@@ -20,8 +20,9 @@
 //
 // Each lane holds three values per population (two partial sums or slabs and
 // the streamed value), so the kernel serves the velocity sets whose planes fit
-// that register budget at three waves per SIMD: athermal D3Q27 in 16-bit and
-// FP32 storage.  The others use the chunked kernel of msl_stream3.hpp.
+// the register file: athermal D3Q27 in 16-bit and FP32 storage (three waves
+// per SIMD) and athermal D3Q64 in 16-bit storage (one wave per SIMD).  The
+// others use the chunked kernel of msl_stream3.hpp.
 #pragma once
 #include <utility>
 
@@ -79,11 +80,15 @@ struct SC3ZTraits {
   static constexpr int CH = (NP + NCH - 1) / NCH;
   static constexpr int LDS_BYTES = CH * SD * 4;
   static constexpr int REGW = SZ == 8 ? 2 : 1;
-  static constexpr int VREG = 3 * NP * REGW + 48;
-  // athermal D3Q27 in 16-bit and FP32 storage (167 VGPRs, three waves per
-  // SIMD, no scratch); FP64 values, the g planes of the thermal model or the
-  // 64 planes of D3Q64 would spill
-  static constexpr bool fits = !TH && SZ <= 4 && VREG <= 216;
+  // registers per lane: three per plane and about 50 besides (D3Q27: 167
+  // VGPRs, three waves per SIMD); D3Q64 needs about 300, VGPRs and AGPRs
+  // together, which one wave per SIMD holds without scratch
+  static constexpr int VREG = 3 * NP * REGW + (N == 3 ? 48 : 110);
+  // athermal D3Q27 in 16-bit and FP32 storage, athermal D3Q64 in 16-bit
+  // storage (at one wave per SIMD: 3355 against 3541 us for the chunked
+  // kernel on a 256^3 grid, while FP32 D3Q64 ran slower, 4941 against 4245
+  // us); FP64 values and the g planes of the thermal model would spill
+  static constexpr bool fits = !TH && (N == 3 ? SZ <= 4 : (N == 4 && SZ == 2));
   static constexpr int WG_LDS = (160 * 1024) / LDS_BYTES;
   static constexpr int W_REG = 512 / VREG;
   static constexpr int WAVES0 = WG_LDS < W_REG ? WG_LDS : W_REG;
@@ -157,32 +162,27 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
   }
   // byte offset of the column's first slab window (before the plane's shift)
   const unsigned org0b = (unsigned)g.idx(x0, y0, z0) * SZ;
-  // one descriptor per array spanning every plane (the host launches this
-  // kernel only where all planes together span at most 2 GB): the plane is
-  // selected by the offset.  For the stores this keeps the out-of-range drop
-  // of foreign cells, 0x80000000 plus any plane offset being out of range;
-  // one descriptor per plane would hold 4 scalar registers per plane live
-  // across the walk
-  const __amdgpu_buffer_rsrc_t rsin =
-      __builtin_amdgcn_make_buffer_rsrc((void *)in, (short)0, (int)((unsigned)NP * plane_b), MSL_RSRC_WORD3);
-  const __amdgpu_buffer_rsrc_t rsout =
-      __builtin_amdgcn_make_buffer_rsrc((void *)out, (short)0, (int)((unsigned)NP * plane_b), MSL_RSRC_WORD3);
   // DMA of step t's slab of planes [K0, K1) into LDS: slab z0 + n0_z - 1 + t.
-  // The base offsets pass through an empty asm at every call, so the per-plane
-  // offsets are formed here rather than hoisted out of the walk (NP scalar
-  // registers)
+  // Each plane has its own buffer descriptor (the range of one plane); the
+  // base offsets pass through an empty asm at every call, so the per-plane
+  // descriptors and offsets are formed here rather than hoisted out of the
+  // walk (4 + 1 scalar registers per plane)
+  const long long plane_b64 = g.plane * SZ;
   auto issue = [&]<int K0, int K1>(const int t) {
-    unsigned ob = org0b + (unsigned)t * slab_b, pb = plane_b;
-    asm volatile("" : "+s"(ob), "+s"(pb));
+    unsigned ob = org0b + (unsigned)t * slab_b;
+    const char *pp = (const char *)in + K0 * plane_b64;
+    asm volatile("" : "+s"(ob), "+s"(pp));
     msl_for_range<K0, K1>([&]<int K>() {
       constexpr int i = K % Q, a = i % N, b = (i / N) % N, cc = i / (N * N);
-      const unsigned so =
-          (unsigned)K * pb + ((ob + (unsigned)(offx[a] + offy[b] + offz[cc]) * SZ) & ~3u);
+      const unsigned so = (ob + (unsigned)(offx[a] + offy[b] + offz[cc]) * SZ) & ~3u;
+      const __amdgpu_buffer_rsrc_t rs =
+          __builtin_amdgcn_make_buffer_rsrc((void *)pp, (short)0, (int)plane_b, MSL_RSRC_WORD3);
 #pragma unroll
       for (int m = 0; m < M; ++m)
         if (vld[m])
           __builtin_amdgcn_raw_ptr_buffer_load_lds(
-              rsin, (msl_lds_t *)(sm + (K - K0) * SD + 64 * (w + 4 * m)), 4, (int)voff[m], (int)so, 0, 0);
+              rs, (msl_lds_t *)(sm + (K - K0) * SD + 64 * (w + 4 * m)), 4, (int)voff[m], (int)so, 0, 0);
+      pp += plane_b64;
     });
   };
   // LDS byte offset of the lane's first element in its wave's first window
@@ -287,8 +287,8 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
     typedef const __attribute__((address_space(4))) Tab cTab;
     cLatTab *Lp = (cLatTab *)&L;
     cTab *tp = (cTab *)tab;
-    unsigned pb = plane_b;
-    asm volatile("" : "+s"(Lp), "+s"(tp), "+s"(pb));
+    const char *op = (const char *)out;   // plane K's base, advanced plane by plane
+    asm volatile("" : "+s"(Lp), "+s"(tp), "+s"(op));
     auto &L = *Lp;
     C rho = C(0), jx = C(0), jy = C(0), jz = C(0), en = C(0);
     auto moments = [&]<int K>() {
@@ -347,9 +347,10 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
       if constexpr (K < Q) vo = v + om * (feq - v);
       else vo = v + om * (gf * feq - v);
       const S sv = T::store(T::dev ? vo * isc - C(1) : vo);
-      const unsigned po = (unsigned)K * pb;
+      const __amdgpu_buffer_rsrc_t rsout =
+          __builtin_amdgcn_make_buffer_rsrc((void *)op, (short)0, (int)plane_b, MSL_RSRC_WORD3);
+      op += plane_b64;
       auto put = [&](unsigned o) {
-        o += po;
         if constexpr (SZ == 8) {
           typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
           __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, sv), rsout, (int)o, 0, 0);
@@ -373,7 +374,9 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
   // the loads issued before them (vector memory operations complete in issue
   // order, so waiting until the stores of one cell are all that is
   // outstanding waits for exactly the slab).
-  static_assert(2 * NP <= 63, "the stores of one cell must fit the vmcnt field");
+  // (vmcnt holds at most 63: with more stores per cell the wait also takes
+  // the oldest of them)
+  constexpr int VW1 = NP < 63 ? NP : 63, VW2 = 2 * NP < 63 ? 2 * NP : 63;
   constexpr int CH0 = CH < NP ? CH : NP;
   issue.template operator()<0, CH0>(0);
   msl_wait_vm<0>();
@@ -398,10 +401,10 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
     if (t >= 2) {
       if (xedge) {
         finish.template operator()<true>(z0 + t - 2);
-        msl_wait_vm<2 * NP>();
+        msl_wait_vm<VW2>();
       } else {
         finish.template operator()<false>(z0 + t - 2);
-        msl_wait_vm<NP>();
+        msl_wait_vm<VW1>();
       }
     } else {
       msl_wait_vm<0>();
