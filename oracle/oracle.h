@@ -61,7 +61,7 @@ typedef struct or_config {
   double slot_state[6][5];
   int slot[6][4];             /* [lo0,hi0) [lo1,hi1) on the tangential axes; lo>=hi: none */
   double slot_edge[6];        /* > 0: tanh edges of this width blend slot and face states */
-  int crit_kind;              /* 0 none, 1 Mach, 2 |Pi_neq|/p */
+  int crit_kind;              /* 0 none, 1 Mach, 2 |Pi_neq|/p, 3 Knudsen number lambda |grad rho| / rho */
   double crit_thr;
   int crit_every;
   double u_ref[3], T_ref;     /* global constant reference frame (eq. veli): particle

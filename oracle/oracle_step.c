@@ -514,9 +514,10 @@ int or_get_mask(const or_ctx *c, uint8_t *mask) {
   return 0;
 }
 
-/* Refinement criteria: local Mach number |u|/c_s (c_s = 1 athermal,
- * sqrt(gamma T) thermal), or the Frobenius norm of the non-equilibrium part of
- * the central second moment over the pressure p = rho T. */
+/* Refinement criteria of one cell: local Mach number |u|/c_s (c_s = 1
+ * athermal, sqrt(gamma T) thermal), or the Frobenius norm of the
+ * non-equilibrium part of the central second moment over the pressure
+ * p = rho T.  (The Knudsen-number criterion needs the neighbours: below.) */
 static double criterion_value(const or_ctx *c, int64_t k) {
   double f[OR_MAXQ], g[OR_MAXQ];
   native_state(c, k, f, g);
@@ -547,13 +548,72 @@ static double criterion_value(const or_ctx *c, int64_t k) {
   return 0.0;
 }
 
+/* Local Knudsen number (Sec. IV.A.3): Kn = lambda / L with L = |phi / (dphi/dx)|
+ * and phi the density.  The mean free path is the hard-sphere one of the
+ * same section, lambda = 16/(5 sqrt(2 pi gamma)) mu a / p, evaluated with the
+ * cell's own state: a = sqrt(gamma T), p = rho T and the viscosity of the
+ * collision, mu = (tau - 1/2) rho T dt (transport coefficients of Sec. II.B;
+ * tau the local relaxation time where it follows mu(T)).  In more than one
+ * dimension L = rho / |grad rho|.  The derivative is the central difference
+ * of the cell densities; across a face that is not periodic the missing
+ * neighbour is the cell itself (a one-sided difference over one cell). */
+static void knudsen_field(const or_ctx *c, double *kn) {
+  const int64_t n = c->ncell;
+  double *rho = (double *)malloc((size_t)n * sizeof(double));
+  double *lam = (double *)malloc((size_t)n * sizeof(double));
+  const double gam = (c->cfg.cv + 1.0) / c->cfg.cv;
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < n; k++) {
+    double f[OR_MAXQ], g[OR_MAXQ], r, u[3], T;
+    native_state(c, k, f, g);
+    lat_macros(c->lat[c->order[k]], c->cfg.thermal, c->cfg.cv, f, g, &r, u, &T);
+    const double mu = (relax_tau(c, r, T) - 0.5) * r * T * c->dt;
+    const double a = sqrt(gam * T), p = r * T;
+    rho[k] = r;
+    lam[k] = 16.0 / (5.0 * sqrt(2.0 * acos(-1.0) * gam)) * mu * a / p;
+  }
+  const int ext[3] = {c->cfg.nx, c->cfg.ny, c->D == 3 ? c->cfg.nz : 1};
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < n; k++) {
+    int p[3];
+    cell_coords(c, k, p);
+    double g2 = 0.0;
+    for (int a = 0; a < c->D; a++) {
+      if (ext[a] < 2) continue;
+      const int periodic = c->cfg.bc[2 * a] == 0 && c->cfg.bc[2 * a + 1] == 0;
+      int lo[3] = {p[0], p[1], p[2]}, hi[3] = {p[0], p[1], p[2]};
+      lo[a] = p[a] - 1;
+      hi[a] = p[a] + 1;
+      if (periodic) {
+        lo[a] = (lo[a] + ext[a]) % ext[a];
+        hi[a] = hi[a] % ext[a];
+      } else {
+        if (lo[a] < 0) lo[a] = 0;
+        if (hi[a] >= ext[a]) hi[a] = ext[a] - 1;
+      }
+      const double dist = periodic ? 2.0 : (double)(hi[a] - lo[a]);
+      const double d = (rho[cell_index(c, hi)] - rho[cell_index(c, lo)]) / dist;
+      g2 += d * d;
+    }
+    kn[k] = lam[k] * sqrt(g2) / rho[k];
+  }
+  free(rho);
+  free(lam);
+}
+
 int or_eval_criterion(const or_ctx *c, uint8_t *newmask, double *value) {
+  double *kn = NULL;
+  if (c->cfg.crit_kind == 3) {
+    kn = (double *)malloc((size_t)c->ncell * sizeof(double));
+    knudsen_field(c, kn);
+  }
 #pragma omp parallel for schedule(static)
   for (int64_t k = 0; k < c->ncell; k++) {
-    double v = criterion_value(c, k);
+    double v = kn ? kn[k] : criterion_value(c, k);
     if (value) value[k] = v;
     if (newmask) newmask[k] = (c->nlat > 1 && c->cfg.crit_kind && v > c->cfg.crit_thr) ? 1 : 0;
   }
+  free(kn);
   return 0;
 }
 

@@ -24,6 +24,7 @@ BC_DIFFUSE_WALL = 3  # diffuse-reflection wall
 CRIT_NONE = 0
 CRIT_MA = 1      # local Mach number above threshold -> high order
 CRIT_PINEQ = 2   # |Pi_neq|_F / p above threshold -> high order
+CRIT_KN = 3      # local Knudsen number lambda |grad rho| / rho above threshold -> high order
 
 STORE_FP64 = 0
 STORE_FP32 = 1
