@@ -55,8 +55,14 @@ enum { MSL_FP64 = 0, MSL_FP32 = 1, MSL_FP16_DEV = 2, MSL_BF16_DEV = 3 };
 enum { MSL_LIFT_GRAD = 0, MSL_LIFT_GRAD_HERMITE = 1, MSL_LIFT_MLP = 2 };
 /* boundary rule of a face (face = 2*axis + side) */
 enum { MSL_BC_PERIODIC = 0, MSL_BC_FIXED_EQ = 1, MSL_BC_OUTFLOW_ZG = 2, MSL_BC_DIFFUSE_WALL = 3 };
-/* refinement criterion: local Mach number; |Pi_neq|_F / p */
-enum { MSL_CRIT_NONE = 0, MSL_CRIT_MA = 1, MSL_CRIT_PINEQ = 2 };
+/* refinement criterion (Sec. III.A): local Mach number; |Pi_neq|_F / p; local
+ * Knudsen number Kn = lambda / L, L = rho / |grad rho| (Sec. IV.A.3), with
+ * the hard-sphere mean free path lambda = 16/(5 sqrt(2 pi gamma)) mu a / p of
+ * the cell's own state (a = sqrt(gamma T), p = rho T, mu = (tau - 1/2) rho T dt
+ * of the collision) and central differences of the cell densities (one-sided
+ * over one cell across a face that is not periodic).  MSL_CRIT_KN takes
+ * 16 bytes of workspace per cell. */
+enum { MSL_CRIT_NONE = 0, MSL_CRIT_MA = 1, MSL_CRIT_PINEQ = 2, MSL_CRIT_KN = 3 };
 
 typedef struct msl_config {
   int dim, nx, ny, nz;        /* nz ignored (1) when dim == 2 */

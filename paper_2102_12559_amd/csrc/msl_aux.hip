@@ -379,6 +379,72 @@ k_criterion_t(const Tab *__restrict__ tab, Geo g, const char *bl, const char *bh
 }
 
 
+// Knudsen-number criterion (Sec. IV.A.3), pass 1: the density and the
+// hard-sphere mean free path lambda = 16/(5 sqrt(2 pi gamma)) mu a / p of every
+// cell from its own populations (a = sqrt(gamma T), p = rho T, and the
+// viscosity of the collision: mu = (tau - 1/2) rho T dt, or mu_ref (T/T_ref)^s
+// where tau follows mu(T))
+template <typename S, int D, int N, bool TH>
+__device__ __forceinline__ void kn_cell(const Tab *tab, const Geo &g, const char *base, int l, int off,
+                                        double &rho, double &lam) {
+  constexpr int Q = Pow<D, N>::v;
+  const LatTab &L = tab->lat[l];
+  double f[Q], gg[TH ? Q : 1], u[3], T;
+  read_cell_t<S, D, N, TH>(tab, g, base, l, off, f, gg);
+  macros_t<D, N>(L, TH && tab->thermal, tab->cv, f, gg, rho, u, T);
+  const double mu = tab->tau_mode == 1 ? tab->mu_ref * pow(T / tab->tau_ref_T, tab->mu_exp)
+                                       : (tab->tau - 0.5) * rho * T * tab->dt;
+  const double gam = (tab->cv + 1.0) / tab->cv;
+  lam = 16.0 / (5.0 * sqrt(2.0 * M_PI * gam)) * mu * sqrt(gam * T) / (rho * T);
+}
+
+template <typename S, int D, int NL, int NH, bool TH>
+__global__ void __launch_bounds__(AUX_BLOCK)
+k_kn_fields(const Tab *__restrict__ tab, Geo g, const char *bl, const char *bh,
+            const uint8_t *__restrict__ cls, double *__restrict__ rho, double *__restrict__ lam) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.ncell) return;
+  int x, y, z;
+  cell_coords(g, k, x, y, z);
+  const int off = g.idx(x, y, z);
+  double r, l;
+  if (cls[k] & 1) kn_cell<S, D, NH, TH>(tab, g, bh, 1, off, r, l);
+  else kn_cell<S, D, NL, TH>(tab, g, bl, 0, off, r, l);
+  rho[k] = r;
+  lam[k] = l;
+}
+
+// pass 2: Kn = lambda |grad rho| / rho with central differences of the cell
+// densities; across a face that is not periodic (bit a of per clear) the
+// missing neighbour is the cell itself, a one-sided difference over one cell
+__global__ void __launch_bounds__(AUX_BLOCK)
+k_kn_mask(Geo g, const double *__restrict__ rho, const double *__restrict__ lam, int per, double thr,
+          uint8_t *__restrict__ newmask) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.ncell) return;
+  int p[3];
+  cell_coords(g, k, p[0], p[1], p[2]);
+  const int ext[3] = {g.nx, g.ny, g.nz};
+  const long long stride[3] = {1, g.nx, (long long)g.nx * g.ny};
+  double g2 = 0.0;
+  for (int a = 0; a < g.dim; ++a) {
+    if (ext[a] < 2) continue;
+    int lo = p[a] - 1, hi = p[a] + 1;
+    double dist = 2.0;
+    if ((per >> a) & 1) {
+      lo = lo < 0 ? lo + ext[a] : lo;
+      hi = hi >= ext[a] ? hi - ext[a] : hi;
+    } else {
+      lo = lo < 0 ? 0 : lo;
+      hi = hi >= ext[a] ? ext[a] - 1 : hi;
+      dist = (double)(hi - lo);
+    }
+    const double d = (rho[k + (hi - p[a]) * stride[a]] - rho[k + (lo - p[a]) * stride[a]]) / dist;
+    g2 += d * d;
+  }
+  newmask[k] = lam[k] * sqrt(g2) / rho[k] > thr ? 1 : 0;
+}
+
 __global__ void k_mask_out(const uint8_t *__restrict__ cls, long long n, uint8_t *__restrict__ m) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) m[k] = cls[k] & 1;
@@ -978,6 +1044,20 @@ template <typename S>
 static int criterion_s(msl_ctx *c) {
   return msl_pair_dispatch(c->D, c->htab.lat[0].n, c->htab.lat[1].n, [&]<int D, int NL, int NH>() {
     const char *bl = c->planes[0][c->cur], *bh = c->planes[1][c->cur];
+    if (c->cfg.crit_kind == MSL_CRIT_KN) {
+      if (c->cfg.thermal)
+        hipLaunchKernelGGL((k_kn_fields<S, D, NL, NH, true>), dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), 0,
+                           c->stream, c->dtab, c->geo, bl, bh, c->cls, c->kn_rho, c->kn_lam);
+      else
+        hipLaunchKernelGGL((k_kn_fields<S, D, NL, NH, false>), dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), 0,
+                           c->stream, c->dtab, c->geo, bl, bh, c->cls, c->kn_rho, c->kn_lam);
+      int per = 0;
+      for (int a = 0; a < c->D; ++a)
+        if (c->cfg.bc[2 * a] == MSL_BC_PERIODIC && c->cfg.bc[2 * a + 1] == MSL_BC_PERIODIC) per |= 1 << a;
+      hipLaunchKernelGGL(k_kn_mask, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), 0, c->stream, c->geo, c->kn_rho,
+                         c->kn_lam, per, c->cfg.crit_thr, c->newmask);
+      return last_err();
+    }
     if (c->cfg.thermal)
       hipLaunchKernelGGL((k_criterion_t<S, D, NL, NH, true>), dim3(nblocks(c->ncell)), dim3(AUX_BLOCK),
                          0, c->stream, c->dtab, c->geo, bl, bh, c->cls, c->newmask,

@@ -198,7 +198,7 @@ static const char *check_config(const msl_config *cfg) {
   if (cfg->thermal && !(cfg->cv > 0.5 * cfg->dim)) return "thermal model needs cv > D/2";
   if (cfg->lift_mode < 0 || cfg->lift_mode > 2) return "unknown lift mode";
   if (cfg->lift_mode == MSL_LIFT_MLP && !cfg->n_high) return "learned lifting needs two velocity sets";
-  if (cfg->crit_kind < 0 || cfg->crit_kind > 2) return "unknown criterion";
+  if (cfg->crit_kind < 0 || cfg->crit_kind > 3) return "unknown criterion";
   if (cfg->store >= MSL_FP16_DEV && !(cfg->rho0 > 0.0 && cfg->T0 > 0.0)) return "deviation storage needs rho0, T0 > 0";
   for (int a = 0; a < 3; ++a)
     if (!isfinite(cfg->u_ref[a]) || !isfinite(cfg->store_u[a])) return "frame and storage velocities must be finite";
@@ -227,7 +227,7 @@ struct Layout {
   Geo geo;
   size_t esz;
   size_t off_tab, off_planes[2], off_cls, off_newmask, off_tflag, off_blist[2], off_bcount, off_blk,
-      off_red, off_flag, off_tlist, off_mlp, total;
+      off_red, off_flag, off_tlist, off_kn, off_mlp, total;
   int nblk, Q[2], np[2];
   long long plane_bytes;
   int mlpF, mlpO, mlpH, mlpP, nctile, nct[3];
@@ -292,6 +292,9 @@ static void make_layout(const msl_config *cfg, Layout &L) {
   off = align256(off + 64);
   L.off_tlist = off;   // live-tile list of the high-order set, then its count
   off = align256(off + ((size_t)g.ntx * g.nty * g.ntz + 16) * 4);
+  // Knudsen-number criterion: each cell's density and mean free path
+  L.off_kn = off;
+  if (cfg->crit_kind == MSL_CRIT_KN && nl > 1) off = align256(off + (size_t)g.ncell * 2 * 8);
   // learned closure
   if (cfg->lift_mode == MSL_LIFT_MLP && nl > 1) {
     const int q = L.Q[0], Q = L.Q[1];
@@ -491,6 +494,8 @@ int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_
   c->red = (double *)(base + L.off_red);
   c->flag = (int *)(base + L.off_flag);
   c->tlist = (int *)(base + L.off_tlist);
+  c->kn_rho = (double *)(base + L.off_kn);
+  c->kn_lam = c->kn_rho + L.geo.ncell;
   c->tcount = c->tlist + (size_t)L.geo.ntx * L.geo.nty * L.geo.ntz;
   if (L.mlpP) {
     c->mlpF = L.mlpF; c->mlpO = L.mlpO; c->mlpH = L.mlpH; c->mlpP = L.mlpP;

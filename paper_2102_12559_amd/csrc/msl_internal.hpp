@@ -141,6 +141,7 @@ struct msl_ctx {
   int cur;
   uint8_t *cls;           // bit0 order (0 low, 1 high), bit1 band
   uint8_t *newmask;
+  double *kn_rho, *kn_lam;   // Knudsen-number criterion: density and mean free path per cell
   uint8_t *tflag;         // per micro-tile: bit0 has low cells, bit1 has high cells
   int *blist[2];          // band cells of each order, ascending cell index
   int *bcount;            // device: [0] low band, [1] high band counts

@@ -112,3 +112,14 @@ def test_plane_byte_limit(store, esz):
     c = msl.make_config(big)
     nb = C.c_size_t()
     assert msl.lib().msl_workspace_bytes(C.byref(c), C.byref(nb)) == msl.MSL_EINVAL
+
+
+def test_knudsen_criterion_workspace():
+    """MSL_CRIT_KN is accepted and takes 16 bytes per cell of workspace (the
+    density and mean free path of every cell); kinds past it are rejected."""
+    base = inputs.base_config(nx=64, ny=32, n_low=3, n_high=4, crit_every=5, crit_thr=0.02)
+    b_ma = msl.workspace_bytes(dict(base, crit_kind=inputs.CRIT_MA))
+    b_kn = msl.workspace_bytes(dict(base, crit_kind=inputs.CRIT_KN))
+    assert b_kn - b_ma >= 16 * 64 * 32
+    with pytest.raises(msl.MslError):
+        msl.workspace_bytes(dict(base, crit_kind=4))
