@@ -176,6 +176,19 @@ int msl_set_populations(msl_ctx *ctx, int which, int fg, const double *in);
  * rho E (host out[5], FP64, deterministic order).  Synchronises. */
 int msl_conservation(msl_ctx *ctx, double *out);
 
+/* Error norms of the macroscopic fields (Sec. II.B moments of each cell's own
+ * populations, as msl_macros) against caller reference fields: rho_ref
+ * [cells], u_ref [dim][cells], T_ref [cells], device FP64 in msl_macros'
+ * layout; a NULL reference skips that field.  out (host, 6 doubles): for rho,
+ * u, T in turn the relative L2 norm sqrt(sum |x - x_ref|^2 / sum |x_ref|^2)
+ * (u: Euclidean norm over the components; the root mean square of the
+ * difference where the reference is zero everywhere) and the maximum of
+ * |x - x_ref| over the cells; 0 for skipped fields.  FP64 sums: wave
+ * shuffles, LDS, then a second pass over the per-block partials (fixed order,
+ * deterministic).  Synchronises the stream. */
+int msl_error_norms(msl_ctx *ctx, const double *rho_ref, const double *u_ref, const double *T_ref,
+                    double *out);
+
 /* Checkpoint: the raw planes, mask, step counter and closure weights to a host
  * buffer; *bytes in: capacity, out: size used (buf NULL: size query).
  * Synchronises.  Restoring on a context of the same config resumes bit-exactly. */

@@ -8,6 +8,8 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import math
+
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -358,3 +360,30 @@ class Oracle:
         _check(lib().or_lift_cell(self._ctx, _p(fq), _p(gqa), int(tile), _p(fQ), _p(gQ)),
                "lift_cell")
         return (fQ, gQ) if gq is not None else fQ
+
+
+def error_norms(rho, u, T, rho_ref=None, u_ref=None, T_ref=None):
+    """Relative L2 and max error norms of macroscopic fields against reference
+    fields, written out from their definition: for each field the square root
+    of sum |x - x_ref|^2 over sum |x_ref|^2 (u: Euclidean norm over the
+    components per cell; the root mean square of the difference where the
+    reference is zero everywhere) and the largest |x - x_ref|.  Skipped
+    fields give (0, 0)."""
+    out = {}
+    for name, x, r, vec in (("rho", rho, rho_ref, False), ("u", u, u_ref, True), ("T", T, T_ref, False)):
+        if r is None:
+            out[name] = (0.0, 0.0)
+            continue
+        x = np.asarray(x, dtype=np.float64)
+        r = np.asarray(r, dtype=np.float64).reshape(x.shape)
+        d = x - r
+        if vec:
+            dn = np.sqrt(np.sum(d.reshape(d.shape[0], -1) ** 2, axis=0))
+            rn2 = np.sum(r ** 2)
+        else:
+            dn = np.abs(d).reshape(-1)
+            rn2 = np.sum(r ** 2)
+        sd = float(np.sum(dn ** 2))
+        l2 = math.sqrt(sd / rn2) if rn2 > 0 else math.sqrt(sd / dn.size)
+        out[name] = (l2, float(np.max(dn)))
+    return out

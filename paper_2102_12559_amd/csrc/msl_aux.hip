@@ -750,6 +750,53 @@ __global__ void k_pops(const Tab *__restrict__ tab, Geo g, char *base, int l, in
 // a sentinel for NaN / Inf / rho <= 0
 // ---------------------------------------------------------------------------
 #define RED_BLOCKS 1024
+// Block reduction of NV FP64 values (bit m of maxmask: a NaN-propagating
+// maximum, otherwise a sum): a butterfly over the 64 lanes of each wave
+// (shuffles, fixed order), then the waves' results in wave order through LDS.
+// Deterministic for a given launch shape; the result is in thread 0.
+__device__ __forceinline__ double red_max(double a, double b) {
+  return a != a ? a : ((b != b || b > a) ? b : a);
+}
+
+template <int NV>
+__device__ __forceinline__ void block_reduce(double (&a)[NV], unsigned maxmask) {
+  constexpr int NW = AUX_BLOCK / 64;
+  __shared__ double s[NV][NW];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      const double o = __shfl_xor(a[m], off, 64);
+      a[m] = ((maxmask >> m) & 1u) ? red_max(a[m], o) : a[m] + o;
+    }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int m = 0; m < NV; ++m) s[m][w] = a[m];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      double v = s[m][0];
+      for (int k = 1; k < NW; ++k) v = ((maxmask >> m) & 1u) ? red_max(v, s[m][k]) : v + s[m][k];
+      a[m] = v;
+    }
+}
+
+// second pass: one block reduces the per-block partials part[b * NV + m]
+template <int NV>
+__device__ __forceinline__ void reduce_partials(const double *part, int nb, unsigned maxmask, double (&a)[NV]) {
+#pragma unroll
+  for (int m = 0; m < NV; ++m) a[m] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x)
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      const double v = part[b * NV + m];
+      a[m] = ((maxmask >> m) & 1u) ? red_max(a[m], v) : a[m] + v;
+    }
+  block_reduce<NV>(a, maxmask);
+}
+
 template <typename S>
 __global__ void __launch_bounds__(AUX_BLOCK)
 k_conserve_partial(const Tab *__restrict__ tab, Geo g, const char *bl, const char *bh,
@@ -777,47 +824,84 @@ k_conserve_partial(const Tab *__restrict__ tab, Geo g, const char *bl, const cha
     acc[0] += r;
     if (!(r > 0.0) || isinf(r)) acc[5] = 1.0;
   }
-  __shared__ double s[6][AUX_BLOCK];
-  for (int m = 0; m < 6; ++m) s[m][threadIdx.x] = acc[m];
-  __syncthreads();
-  for (int w = AUX_BLOCK / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
-      for (int m = 0; m < 6; ++m) {
-        if (m == 5) s[m][threadIdx.x] = fmax(s[m][threadIdx.x], s[m][threadIdx.x + w]);
-        else s[m][threadIdx.x] += s[m][threadIdx.x + w];
-      }
-    __syncthreads();
-  }
+  block_reduce<6>(acc, 1u << 5);
   if (threadIdx.x == 0)
-    for (int m = 0; m < 6; ++m) part[blockIdx.x * 6 + m] = s[m][0];
+    for (int m = 0; m < 6; ++m) part[blockIdx.x * 6 + m] = acc[m];
 }
 
-__global__ void k_conserve_final(const double *__restrict__ part, int nb, double *__restrict__ out) {
-  __shared__ double s[6][AUX_BLOCK];
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int b = threadIdx.x; b < nb; b += blockDim.x)
-    for (int m = 0; m < 6; ++m) {
-      const double v = part[b * 6 + m];
-      if (m == 5) acc[m] = fmax(acc[m], v);
-      else acc[m] += v;
-    }
-  for (int m = 0; m < 6; ++m) s[m][threadIdx.x] = acc[m];
-  __syncthreads();
-  for (int w = AUX_BLOCK / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
-      for (int m = 0; m < 6; ++m) {
-        if (m == 5) s[m][threadIdx.x] = fmax(s[m][threadIdx.x], s[m][threadIdx.x + w]);
-        else s[m][threadIdx.x] += s[m][threadIdx.x + w];
-      }
-    __syncthreads();
-  }
+__global__ void __launch_bounds__(AUX_BLOCK)
+k_conserve_final(const double *__restrict__ part, int nb, double *__restrict__ out) {
+  double a[6];
+  reduce_partials<6>(part, nb, 1u << 5, a);
   if (threadIdx.x == 0) {
-    for (int m = 0; m < 5; ++m) out[m] = s[m][0];
+    for (int m = 0; m < 5; ++m) out[m] = a[m];
     // a NaN anywhere propagates into the sums
-    const bool bad = s[5][0] > 0.0 || isnan(s[0][0]) || isnan(s[4][0]) || isinf(s[0][0]) ||
-                     isinf(s[4][0]);
+    const bool bad = a[5] > 0.0 || isnan(a[0]) || isnan(a[4]) || isinf(a[0]) || isinf(a[4]);
     out[5] = bad ? 1.0 : 0.0;
   }
+}
+
+// Error norms of the macroscopic fields (each cell from its own populations)
+// against caller reference fields: per block the sums of |x - x_ref|^2 and
+// |x_ref|^2 and the maximum of |x - x_ref| for rho, u (Euclidean norm over
+// the components) and T
+template <typename S>
+__global__ void __launch_bounds__(AUX_BLOCK)
+k_errnorm_partial(const Tab *__restrict__ tab, Geo g, const char *bl, const char *bh,
+                  const uint8_t *__restrict__ cls, const double *__restrict__ rref,
+                  const double *__restrict__ uref, const double *__restrict__ Tref, double *__restrict__ part) {
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < g.ncell;
+       k += (long long)gridDim.x * blockDim.x) {
+    int x, y, z;
+    cell_coords(g, k, x, y, z);
+    const int l = cls[k] & 1;
+    double f[MSL_MAXQ], gg[MSL_MAXQ], r, uu[3], t;
+    read_cell<S>(tab, g, l ? bh : bl, l, g.idx(x, y, z), f, gg);
+    cell_macros(tab->lat[l], g.dim, tab->thermal, tab->cv, f, gg, r, uu, t);
+    if (rref) {
+      const double d = r - rref[k];
+      acc[0] += d * d;
+      acc[1] += rref[k] * rref[k];
+      acc[2] = red_max(acc[2], fabs(d));
+    }
+    if (uref) {
+      double d2 = 0.0, r2 = 0.0;
+      for (int a = 0; a < g.dim; ++a) {
+        const double ra = uref[a * g.ncell + k], d = uu[a] - ra;
+        d2 += d * d;
+        r2 += ra * ra;
+      }
+      acc[3] += d2;
+      acc[4] += r2;
+      acc[5] = red_max(acc[5], sqrt(d2));
+    }
+    if (Tref) {
+      const double d = t - Tref[k];
+      acc[6] += d * d;
+      acc[7] += Tref[k] * Tref[k];
+      acc[8] = red_max(acc[8], fabs(d));
+    }
+  }
+  constexpr unsigned MX = (1u << 2) | (1u << 5) | (1u << 8);
+  block_reduce<9>(acc, MX);
+  if (threadIdx.x == 0)
+    for (int m = 0; m < 9; ++m) part[blockIdx.x * 9 + m] = acc[m];
+}
+
+// out: relative L2 = sqrt(sum |x - x_ref|^2 / sum |x_ref|^2) (the root mean
+// square of the difference where the reference is zero everywhere) and max
+__global__ void __launch_bounds__(AUX_BLOCK)
+k_errnorm_final(const double *__restrict__ part, int nb, long long ncell, double *__restrict__ out) {
+  constexpr unsigned MX = (1u << 2) | (1u << 5) | (1u << 8);
+  double a[9];
+  reduce_partials<9>(part, nb, MX, a);
+  if (threadIdx.x == 0)
+    for (int f = 0; f < 3; ++f) {
+      const double sd = a[3 * f], sr = a[3 * f + 1];
+      out[2 * f] = sr > 0.0 ? sqrt(sd / sr) : sqrt(sd / (double)ncell);
+      out[2 * f + 1] = a[3 * f + 2];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1172,6 +1256,16 @@ extern "C" int msl_device_copy(void *dst, const void *src, size_t bytes, void *s
 int msl_launch_pops(msl_ctx *c, int which, int fg, double *out, const double *in) {
   DISPATCH_STORE(c, k_pops, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), c->dtab, c->geo,
                  c->planes[which][c->cur], which, fg, c->cls, out, in);
+  return last_err();
+}
+
+int msl_launch_error_norms(msl_ctx *c, const double *rref, const double *uref, const double *Tref,
+                           double *dev_out6) {
+  DISPATCH_STORE(c, k_errnorm_partial, dim3(RED_BLOCKS), dim3(AUX_BLOCK), c->dtab, c->geo,
+                 c->planes[0][c->cur], c->nlat > 1 ? c->planes[1][c->cur] : nullptr, c->cls, rref, uref, Tref,
+                 c->red);
+  hipLaunchKernelGGL(k_errnorm_final, dim3(1), dim3(AUX_BLOCK), 0, c->stream, c->red, RED_BLOCKS, c->ncell,
+                     dev_out6);
   return last_err();
 }
 

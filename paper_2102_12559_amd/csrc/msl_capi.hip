@@ -287,7 +287,7 @@ static void make_layout(const msl_config *cfg, Layout &L) {
   L.off_blk = off;
   off = align256(off + (size_t)3 * L.nblk * 4);
   L.off_red = off;
-  off = align256(off + (size_t)1024 * 6 * 8 + 64);
+  off = align256(off + (size_t)1024 * 9 * 8 + 128);   // per-block partials, then results
   L.off_flag = off;
   off = align256(off + 64);
   L.off_tlist = off;   // live-tile list of the high-order set, then its count
@@ -794,7 +794,7 @@ int msl_set_populations(msl_ctx *c, int which, int fg, const double *in) {
 int msl_conservation(msl_ctx *c, double *out) {
   if (!c || !out) return MSL_EINVAL;
   if (!c->initialized) return MSL_ESTATE;
-  double *dev = c->red + 1024 * 6;
+  double *dev = c->red + 1024 * 9;
   int rc = msl_launch_conservation(c, dev);
   if (rc) return rc;
   double h[6];
@@ -803,6 +803,19 @@ int msl_conservation(msl_ctx *c, double *out) {
     return MSL_EHIP;
   for (int m = 0; m < 5; ++m) out[m] = h[m];
   if (h[5] != 0.0) { set_err(c, "sentinel: NaN/Inf or non-positive density"); return MSL_EUNSTABLE; }
+  return MSL_OK;
+}
+
+int msl_error_norms(msl_ctx *c, const double *rho_ref, const double *u_ref, const double *T_ref,
+                    double *out) {
+  if (!c || !out) return MSL_EINVAL;
+  if (!c->initialized) return MSL_ESTATE;
+  double *dev = c->red + 1024 * 9;
+  int rc = msl_launch_error_norms(c, rho_ref, u_ref, T_ref, dev);
+  if (rc) return rc;
+  if (hipMemcpyAsync(out, dev, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return MSL_EHIP;
   return MSL_OK;
 }
 

@@ -204,6 +204,8 @@ int msl_launch_classify(msl_ctx *c);
 int msl_launch_macros(msl_ctx *c, double *rho, double *u, double *T);
 int msl_launch_pops(msl_ctx *c, int which, int fg, double *out, const double *in);
 int msl_launch_conservation(msl_ctx *c, double *dev_out5);
+int msl_launch_error_norms(msl_ctx *c, const double *rref, const double *uref, const double *Tref,
+                           double *dev_out6);
 int msl_launch_check_mask(msl_ctx *c, const uint8_t *mask);
 int msl_launch_get_mask(msl_ctx *c, uint8_t *mask);
 // closure

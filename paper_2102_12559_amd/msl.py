@@ -57,7 +57,7 @@ SYMBOLS = [
     "msl_set_state", "msl_mlp_dims", "msl_collect_snapshots", "msl_mlp_set_weights",
     "msl_mlp_get_weights", "msl_mlp_train", "msl_mlp_grad", "msl_mlp_forward",
     "msl_mlp_get_flags", "msl_mlp_set_flags", "msl_num_check_tiles", "msl_profile",
-    "msl_profile_read", "msl_device_copy", "msl_mlp_grad_noalloc",
+    "msl_profile_read", "msl_device_copy", "msl_mlp_grad_noalloc", "msl_error_norms",
 ]
 
 
@@ -85,6 +85,7 @@ def lib():
         L.msl_get_populations.argtypes = [vp, C.c_int, C.c_int, vp]
         L.msl_set_populations.argtypes = [vp, C.c_int, C.c_int, vp]
         L.msl_conservation.argtypes = [vp, C.POINTER(C.c_double)]
+        L.msl_error_norms.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double)]
         L.msl_get_state.argtypes = [vp, vp, C.POINTER(sz)]
         L.msl_set_state.argtypes = [vp, vp, sz]
         L.msl_mlp_dims.argtypes = [vp] + [C.POINTER(C.c_int)] * 4
@@ -257,6 +258,23 @@ class Solver:
         out = (C.c_double * 5)()
         self._check(lib().msl_conservation(self._ctx, out), "msl_conservation")
         return np.array(out[:])
+
+    def error_norms(self, rho_ref=None, u_ref=None, T_ref=None):
+        """Relative L2 and max error norms of rho, u, T against reference
+        fields (msl_error_norms); returns {"rho": (l2, max), "u": ..., "T": ...}."""
+        t = self.torch
+        refs = [None if r is None else self._dev(r, t.float64).contiguous().reshape(-1)
+                for r in (rho_ref, u_ref, T_ref)]
+        if refs[0] is not None and refs[0].numel() != self.ncell:
+            raise ValueError("rho_ref: one value per cell")
+        if refs[1] is not None and refs[1].numel() != self.dim * self.ncell:
+            raise ValueError("u_ref: dim values per cell")
+        if refs[2] is not None and refs[2].numel() != self.ncell:
+            raise ValueError("T_ref: one value per cell")
+        out = (C.c_double * 6)()
+        self._check(lib().msl_error_norms(self._ctx, *[None if r is None else _ptr(r) for r in refs], out),
+                    "msl_error_norms")
+        return {"rho": (out[0], out[1]), "u": (out[2], out[3]), "T": (out[4], out[5])}
 
     def get_state(self) -> bytes:
         n = C.c_size_t()
