@@ -71,14 +71,20 @@ struct SC3ZTraits {
   static constexpr int LWD = (66 * SZ + 3) / 4 + (SZ < 4 ? 1 : 0);   // dwords per window row
   static constexpr int SD = 6 * LWD;                                  // dwords of a plane's slab
   static constexpr int M = (SD + 255) / 256;                          // DMA instructions per wave
+  // LDS dwords per plane: 16-bit slabs (204 dwords) are padded to the 256
+  // that one DMA instruction of the four waves writes, so that every lane
+  // loads (no exec-mask branch per plane and step); FP32 slabs (396 dwords)
+  // keep their size, the padding would cost a wave per SIMD of LDS occupancy
+  static constexpr bool PAD = SZ == 2;
+  static constexpr int SDP = PAD ? M * 256 : SD;
   static constexpr int ZC = 32;                                       // cells per column along z
   static_assert(ZC <= 32, "the lane's cells of a column are kept as bits of a 32-bit word");
   // planes per LDS chunk: every plane of a step in one chunk where 64 KB hold them
   static constexpr int BUDGET = 64 * 1024;
-  static constexpr int CHMAX = BUDGET / (SD * 4) < 1 ? 1 : BUDGET / (SD * 4);
+  static constexpr int CHMAX = BUDGET / (SDP * 4) < 1 ? 1 : BUDGET / (SDP * 4);
   static constexpr int NCH = (NP + CHMAX - 1) / CHMAX;
   static constexpr int CH = (NP + NCH - 1) / NCH;
-  static constexpr int LDS_BYTES = CH * SD * 4;
+  static constexpr int LDS_BYTES = CH * SDP * 4;
   static constexpr int REGW = SZ == 8 ? 2 : 1;
   // registers per lane: three per plane and about 50 besides (D3Q27: 167
   // VGPRs, three waves per SIMD); D3Q64 needs about 300, VGPRs and AGPRs
@@ -104,9 +110,9 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
   using Tr = SC3ZTraits<S, TH, N>;
   using T = typename Tr::T;
   using C = typename Tr::C;
-  constexpr int Q = Tr::Q, NP = Tr::NP, SD = Tr::SD, M = Tr::M, CH = Tr::CH, NCH = Tr::NCH;
+  constexpr int Q = Tr::Q, NP = Tr::NP, SD = Tr::SD, SDP = Tr::SDP, M = Tr::M, CH = Tr::CH, NCH = Tr::NCH;
   constexpr int LWD = Tr::LWD, SZ = Tr::SZ, ZC = Tr::ZC;
-  __shared__ uint32_t sm[CH * SD];
+  __shared__ uint32_t sm[CH * SDP];
   const LatTab &L = tab->lat[lat];
   // the column: from the grid (XCD-aware order for dense launches), or one
   // workgroup per entry of the compact list of live columns (sparse launches)
@@ -128,7 +134,9 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
     for (int k = 0; k < zn; ++k) any |= tflag[((long long)(z0 + k) * g.nty + by) * g.ntx + bx];
     if (!(any & (1 << lat))) return;
   }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // (the wave index as a scalar: the LDS destinations of the DMA are formed
+  // in scalar registers)
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const unsigned pitch_b = (unsigned)g.pitch * SZ;
   const unsigned plane_b = (unsigned)g.plane * SZ;
   const unsigned slab_b = (unsigned)g.rows * pitch_b;
@@ -139,7 +147,7 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     const int d = lane + 64 * (w + 4 * m);
-    vld[m] = d < SD;
+    vld[m] = Tr::PAD || d < SD;   // padded: lanes past the slab load a valid dword into the pad
     const int dd = d < SD ? d : SD - 1;
     const int row = dd / LWD, col = dd - row * LWD;
     voff[m] = (unsigned)row * pitch_b + (unsigned)col * 4u;
@@ -181,7 +189,7 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
       for (int m = 0; m < M; ++m)
         if (vld[m])
           __builtin_amdgcn_raw_ptr_buffer_load_lds(
-              rs, (msl_lds_t *)(sm + (K - K0) * SD + 64 * (w + 4 * m)), 4, (int)voff[m], (int)so, 0, 0);
+              rs, (msl_lds_t *)(sm + (K - K0) * SDP + 64 * (w + 4 * m)), 4, (int)voff[m], (int)so, 0, 0);
       pp += plane_b64;
     });
   };
@@ -208,7 +216,7 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
   // of the three slabs into the streamed value of cell z0 + t - 2
   auto recon = [&]<int K>() {
     constexpr int i = K % Q, a = i % N, b = (i / N) % N, cc = i / (N * N);
-    const char *base = (const char *)sm + (K % CH) * SD * 4 + rb[a];
+    const char *base = (const char *)sm + (K % CH) * SDP * 4 + rb[a];
     const C wx0 = wlo[0][a], wx2 = whi[0][a], wy0 = wlo[1][b], wy2 = whi[1][b], wz0 = wlo[2][cc],
             wz2 = whi[2][cc];
     C hy[3];
