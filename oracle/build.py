@@ -7,7 +7,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["oracle_lattice.c", "oracle_step.c", "oracle_mlp.c"]
+SOURCES = ["oracle_lattice.c", "oracle_step.c", "oracle_mlp.c", "oracle_pond.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

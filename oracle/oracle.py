@@ -56,6 +56,9 @@ def lib():
                                  dp, dp, dp, dp]
         _lib.or_project.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, dp]
         _lib.or_step_count.restype = C.c_long
+        _lib.or_pond_dt.restype = C.c_double
+        _lib.or_pond_dt.argtypes = [C.c_void_p]
+        _lib.or_pond_transfer.argtypes = [C.c_int, C.c_int, dp, dp, dp, dp]
         _lib.or_set_threads.argtypes = [C.c_int]
         _lib.or_set_threads.restype = C.c_int
         _lib.or_adam.argtypes = [dp, dp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_double,
@@ -386,4 +389,70 @@ def error_norms(rho, u, T, rho_ref=None, u_ref=None, T_ref=None):
         sd = float(np.sum(dn ** 2))
         l2 = math.sqrt(sd / rn2) if rn2 > 0 else math.sqrt(sd / dn.size)
         out[name] = (l2, float(np.max(dn)))
+    return out
+
+
+class Pond:
+    """The step in co-moving reference frames (PonD, Sec. II.C.1), one velocity
+    set, on host FP64 arrays."""
+
+    def __init__(self, cfg: dict):
+        self.cfg = dict(cfg)
+        self._c = make_config(cfg)
+        self._ctx = C.c_void_p()
+        _check(lib().or_pond_create(C.byref(self._c), C.byref(self._ctx)), "pond create")
+        self.dim = cfg["dim"]
+        self.shape = (cfg["nz"] if cfg["dim"] == 3 else 1, cfg["ny"], cfg["nx"])
+        self.ncell = int(np.prod(self.shape))
+        self.Q = cfg["n_low"] ** self.dim
+
+    def __del__(self):
+        if getattr(self, "_ctx", None):
+            lib().or_pond_destroy(self._ctx)
+            self._ctx = None
+
+    @property
+    def dt(self):
+        return lib().or_pond_dt(self._ctx)
+
+    def init(self, rho, u, T=None):
+        rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+        T = np.ones(self.ncell) if T is None else np.ascontiguousarray(T, dtype=np.float64).reshape(-1)
+        _check(lib().or_pond_init(self._ctx, _p(rho), _p(u), _p(T)), "pond init")
+
+    def step(self, n=1):
+        _check(lib().or_pond_step(self._ctx, int(n)), "pond step")
+
+    def macros(self):
+        rho = np.zeros(self.ncell)
+        u = np.zeros(self.dim * self.ncell)
+        T = np.zeros(self.ncell)
+        _check(lib().or_pond_macros(self._ctx, _p(rho), _p(u), _p(T)), "pond macros")
+        return rho.reshape(self.shape), u.reshape((self.dim,) + self.shape), T.reshape(self.shape)
+
+    def get_pops(self, fg=0):
+        out = np.zeros((self.Q, self.ncell))
+        _check(lib().or_pond_get_pops(self._ctx, fg, _p(out)), "pond get_pops")
+        return out
+
+    def get_frames(self):
+        out = np.zeros((4, self.ncell))
+        _check(lib().or_pond_get_frames(self._ctx, _p(out)), "pond get_frames")
+        return out
+
+    def iterations(self):
+        m = C.c_double()
+        mx = C.c_int()
+        lib().or_pond_iterations(self._ctx, C.byref(m), C.byref(mx))
+        return m.value, mx.value
+
+
+def pond_transfer(dim, n, src, dst, f):
+    """G_src^dst f (eq. fll) of one population vector; frames (u_x, u_y, u_z, T)"""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros_like(f)
+    s = np.ascontiguousarray(src, dtype=np.float64)
+    d = np.ascontiguousarray(dst, dtype=np.float64)
+    _check(lib().or_pond_transfer(dim, n, _p(s), _p(d), _p(f), _p(out)), "pond transfer")
     return out

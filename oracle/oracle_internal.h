@@ -27,6 +27,7 @@ typedef struct lat_t {
 } lat_t;
 
 int gh_rule_ld(int n, ld *x, ld *w);
+int ld_invert(int n, const ld *A, ld *Ainv);   /* Gauss-Jordan, partial pivoting */
 lat_t *lat_build(int dim, int n);
 void lat_free(lat_t *L);
 int lat_set_frame(lat_t *L, const double *u_ref, double T_ref);

@@ -107,6 +107,8 @@ static int invert_ld(int n, const ld *A, ld *Ainv) {
   return 0;
 }
 
+int ld_invert(int n, const ld *A, ld *Ainv) { return invert_ld(n, A, Ainv); }
+
 static ld ipow_ld(ld b, int e) {
   ld r = 1.0L;
   for (int k = 0; k < e; k++) r *= b;

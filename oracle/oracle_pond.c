@@ -1,0 +1,472 @@
+/*
+ * oracle_pond.c -- the semi-Lagrangian step in co-moving reference frames
+ * (PonD, Sec. II.C.1), one velocity set, cell by cell.
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * Every cell stores its post-collision populations in its own frame
+ * lambda = {u, T} (eq. reference), with particle velocities
+ * v_i = sqrt(theta) c_i + u, theta = T / T_L, T_L = 1 (eq. vi).  One step at a
+ * monitoring cell x:
+ *   predictor: lambda_0 = the cell's frame of the previous step;
+ *   for n = 0, 1, ...:
+ *     each population i is reconstructed at its departure point
+ *     x - v_i^{lambda_n} dt by 3-point-per-axis Lagrange interpolation over the
+ *     collocation points around the nearest node, every collocation point's
+ *     population vector transferred from its own frame lambda_s to lambda_n
+ *     first (eqs. reconstructionPond, advectionPond) with the transfer matrix
+ *     G = M_{lambda_n}^{-1} M_{lambda_s} (eqs. momf, fll), M_lambda the moment
+ *     matrix of eq. momf at that frame's particle velocities;
+ *     corrector: rho, u, T of the reconstructed populations (eqs.
+ *     correctorfields) define lambda_{n+1};
+ *   until lambda stops changing (reading: the largest change of a velocity
+ *   component or of T at most 1e-14, at most 60 iterations);
+ *   collision in the converged frame, where the equilibria are f^eq = rho W_i
+ *   and g^eq = (cv - D/2) T rho W_i (eqs. feqPond, geqPond): BGK, or the
+ *   two-relaxation model with the quasi-equilibria of eqs. fqeq, gqeq.
+ * Collocation points outside the domain: periodic faces wrap, zero-gradient
+ * faces repeat the edge cell (its populations and frame), fixed-equilibrium
+ * faces give the face state's co-moving equilibrium in the face state's frame.
+ */
+#include "oracle_internal.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define POND_MAXIT 60
+#define POND_TOL 1e-14
+
+struct or_pond {
+  or_config cfg;
+  int D, N[3], Q, NP;
+  int64_t ncell;
+  lat_t *L;
+  double dt;
+  double *f, *fn;    /* [NP][ncell]: f planes then g planes, each cell in its own frame */
+  double *fr, *frn;  /* [4][ncell]: u_x, u_y, u_z, T of each cell's frame */
+  long step;
+  double it_mean;
+  int it_max, bad;
+};
+
+/* a frame's particle velocities and (for a target frame) the inverse of its
+ * moment matrix (Q x Q, allocated for target frames only) */
+typedef struct {
+  ld u[3], T;
+  ld v[OR_MAXQ][3];
+  ld *Minv;
+} pframe_t;
+
+static ld ipowl_(ld b, int e) {
+  ld r = 1.0L;
+  for (int k = 0; k < e; k++) r *= b;
+  return r;
+}
+
+static void frame_velocities(const lat_t *L, const ld *u, ld T, pframe_t *fr) {
+  const ld st = sqrtl(T);
+  for (int a = 0; a < 3; a++) fr->u[a] = a < L->D ? u[a] : 0.0L;
+  fr->T = T;
+  for (int i = 0; i < L->Q; i++)
+    for (int a = 0; a < 3; a++) fr->v[i][a] = a < L->D ? st * L->cl[i][a] + fr->u[a] : 0.0L;
+}
+
+static int frame_target(const lat_t *L, const ld *u, ld T, pframe_t *fr) {
+  frame_velocities(L, u, T, fr);
+  const int Q = L->Q;
+  ld *M = (ld *)malloc(sizeof(ld) * Q * Q);
+  for (int j = 0; j < Q; j++)
+    for (int i = 0; i < Q; i++) {
+      ld v = 1.0L;
+      for (int a = 0; a < L->D; a++) v *= ipowl_(fr->v[i][a], L->pw[j][a]);
+      M[j * Q + i] = v;
+    }
+  int rc = ld_invert(Q, M, fr->Minv);
+  free(M);
+  return rc;
+}
+
+/* out = M_dst^{-1} M_src f: the populations f given in the frame whose
+ * particle velocities are src->v, transferred to the frame dst (eq. fll) */
+static void transfer(const lat_t *L, const pframe_t *src, const pframe_t *dst, const double *f,
+                     ld *out) {
+  const int Q = L->Q;
+  ld m[OR_MAXQ];
+  for (int j = 0; j < Q; j++) {
+    ld s = 0.0L;
+    for (int i = 0; i < Q; i++) {
+      ld v = (ld)f[i];
+      for (int a = 0; a < L->D; a++) v *= ipowl_(src->v[i][a], L->pw[j][a]);
+      s += v;
+    }
+    m[j] = s;
+  }
+  for (int i = 0; i < Q; i++) {
+    ld s = 0.0L;
+    for (int j = 0; j < Q; j++) s += dst->Minv[i * Q + j] * m[j];
+    out[i] = s;
+  }
+}
+
+static int64_t pcell(const or_pond *c, const int *p) {
+  return (int64_t)p[0] + (int64_t)c->N[0] * ((int64_t)p[1] + (int64_t)c->N[1] * p[2]);
+}
+
+/* the state of collocation point q (possibly outside the domain): its f (and
+ * g) vector and its frame */
+static void point_state(const or_pond *c, const int *qin, double *f, double *g, ld *u, ld *T) {
+  int q[3] = {qin[0], qin[1], qin[2]};
+  for (int a = 0; a < c->D; a++) {
+    if (q[a] >= 0 && q[a] < c->N[a]) continue;
+    const int face = 2 * a + (q[a] < 0 ? 0 : 1);
+    const int bc = c->cfg.bc[face];
+    if (bc == 1) {   /* fixed equilibrium: the face state in its own frame */
+      const double *st = c->cfg.bc_state[face];
+      const double Tf = c->cfg.thermal ? st[4] : 1.0;
+      for (int b = 0; b < 3; b++) u[b] = b < c->D ? (ld)st[1 + b] : 0.0L;
+      *T = (ld)Tf;
+      for (int i = 0; i < c->Q; i++) {
+        f[i] = st[0] * c->L->W[i];
+        if (c->cfg.thermal) g[i] = (c->cfg.cv - 0.5 * c->D) * Tf * st[0] * c->L->W[i];
+      }
+      return;
+    }
+  }
+  for (int a = 0; a < c->D; a++) {
+    if (q[a] >= 0 && q[a] < c->N[a]) continue;
+    const int face = 2 * a + (q[a] < 0 ? 0 : 1);
+    if (c->cfg.bc[face] == 0) q[a] = ((q[a] % c->N[a]) + c->N[a]) % c->N[a];
+    else q[a] = q[a] < 0 ? 0 : c->N[a] - 1;   /* zero gradient */
+  }
+  const int64_t k = pcell(c, q);
+  for (int i = 0; i < c->Q; i++) {
+    f[i] = c->f[(int64_t)i * c->ncell + k];
+    if (c->cfg.thermal) g[i] = c->f[(int64_t)(c->Q + i) * c->ncell + k];
+  }
+  for (int b = 0; b < 3; b++) u[b] = (ld)c->fr[(int64_t)b * c->ncell + k];
+  *T = (ld)c->fr[(int64_t)3 * c->ncell + k];
+}
+
+static double relax_tau_p(const or_pond *c, double rho, double T) {
+  if (c->cfg.tau_mode == 0) return c->cfg.tau;
+  double mu_ref = (c->cfg.tau - 0.5) * c->cfg.tau_ref_rho * c->cfg.tau_ref_T * c->dt;
+  double mu = mu_ref * pow(T / c->cfg.tau_ref_T, c->cfg.mu_exp);
+  return mu / (rho * T * c->dt) + 0.5;
+}
+
+#define PSIDE 5   /* collocation points lie within 2 cells: nearest node within 1 */
+
+/* one cell's step; returns the iteration count, or -1 when a departure point
+ * leaves the two-cell reach or the state is not finite */
+static int pond_cell(const or_pond *c, int64_t k, double *fo, double *go, double *frame_out) {
+  const lat_t *L = c->L;
+  const int D = c->D, Q = c->Q, th = c->cfg.thermal;
+  int p[3];
+  p[0] = (int)(k % c->N[0]);
+  p[1] = (int)((k / c->N[0]) % c->N[1]);
+  p[2] = (int)(k / ((int64_t)c->N[0] * c->N[1]));
+  const int npts = D == 3 ? PSIDE * PSIDE * PSIDE : PSIDE * PSIDE;
+  /* the neighbourhood's states, read once */
+  double *nf = (double *)malloc(sizeof(double) * npts * OR_MAXQ);
+  double *ng = (double *)malloc(sizeof(double) * npts * OR_MAXQ);
+  pframe_t *nfr = (pframe_t *)malloc(sizeof(pframe_t) * npts);
+  ld *tf = (ld *)malloc(sizeof(ld) * npts * OR_MAXQ);   /* transferred to the current frame */
+  ld *tg = (ld *)malloc(sizeof(ld) * npts * OR_MAXQ);
+  uint8_t *have = (uint8_t *)malloc(npts);
+  pframe_t *tgt = (pframe_t *)malloc(sizeof(pframe_t));
+  tgt->Minv = (ld *)malloc(sizeof(ld) * Q * Q);
+  for (int s = 0; s < npts; s++) {
+    int q[3] = {p[0] + s % PSIDE - 2, p[1] + (s / PSIDE) % PSIDE - 2, D == 3 ? p[2] + s / (PSIDE * PSIDE) - 2 : 0};
+    ld u[3], T;
+    point_state(c, q, nf + (size_t)s * OR_MAXQ, ng + (size_t)s * OR_MAXQ, u, &T);
+    frame_velocities(L, u, T, &nfr[s]);
+  }
+  ld u[3] = {(ld)c->fr[k], (ld)c->fr[c->ncell + k], (ld)c->fr[2 * c->ncell + k]};
+  ld T = (ld)c->fr[3 * c->ncell + k];
+  double ft[OR_MAXQ], gt[OR_MAXQ], rho = 0.0, Tn = 1.0;
+  ld uf[3] = {u[0], u[1], u[2]}, Tfr = T;   /* the frame ft, gt are given in */
+  int it, ok = 1;
+  for (it = 1; it <= POND_MAXIT; it++) {
+    if (frame_target(L, u, T, tgt)) { ok = 0; break; }
+    for (int a = 0; a < 3; a++) uf[a] = u[a];
+    Tfr = T;
+    memset(have, 0, (size_t)npts);
+    /* reconstruction at the departure points, in the current frame */
+    for (int i = 0; i < Q; i++) {
+      ld accf = 0.0L, accg = 0.0L;
+      int n0[3] = {0, 0, 0};
+      double wgt[3][3] = {{1, 0, 0}, {1, 0, 0}, {1, 0, 0}};
+      for (int a = 0; a < D; a++) {
+        const double d = -(double)tgt->v[i][a] * c->dt;
+        n0[a] = (int)floor(d + 0.5);
+        if (n0[a] < -1 || n0[a] > 1) ok = 0;
+        or_lagrange3(d - n0[a], wgt[a]);
+      }
+      if (!ok) break;
+      const int nsp = D == 3 ? 27 : 9;
+      for (int sidx = 0; sidx < nsp; sidx++) {
+        int sv[3] = {sidx % 3 - 1, (sidx / 3) % 3 - 1, D == 3 ? sidx / 9 - 1 : 0};
+        ld w = 1.0L;
+        int off[3] = {0, 0, 0};
+        for (int a = 0; a < D; a++) {
+          w *= (ld)wgt[a][sv[a] + 1];
+          off[a] = n0[a] + sv[a];
+        }
+        const int s = (off[0] + 2) + PSIDE * ((off[1] + 2) + PSIDE * (D == 3 ? off[2] + 2 : 0));
+        if (!have[s]) {
+          transfer(L, &nfr[s], tgt, nf + (size_t)s * OR_MAXQ, tf + (size_t)s * OR_MAXQ);
+          if (th) transfer(L, &nfr[s], tgt, ng + (size_t)s * OR_MAXQ, tg + (size_t)s * OR_MAXQ);
+          have[s] = 1;
+        }
+        accf += w * tf[(size_t)s * OR_MAXQ + i];
+        if (th) accg += w * tg[(size_t)s * OR_MAXQ + i];
+      }
+      ft[i] = (double)accf;
+      gt[i] = th ? (double)accg : 0.0;
+    }
+    if (!ok) break;
+    /* corrector: density, velocity and temperature in this frame's velocities */
+    ld r = 0.0L, j[3] = {0, 0, 0}, e = 0.0L;
+    for (int i = 0; i < Q; i++) {
+      r += (ld)ft[i];
+      ld v2 = 0.0L;
+      for (int a = 0; a < D; a++) {
+        j[a] += tgt->v[i][a] * (ld)ft[i];
+        v2 += tgt->v[i][a] * tgt->v[i][a];
+      }
+      e += 0.5L * v2 * (ld)ft[i];
+      if (th) e += (ld)gt[i];
+    }
+    ld nu[3] = {0, 0, 0}, nT = 1.0L, u2 = 0.0L;
+    for (int a = 0; a < D; a++) {
+      nu[a] = j[a] / r;
+      u2 += nu[a] * nu[a];
+    }
+    if (th) nT = (e / r - 0.5L * u2) / (ld)c->cfg.cv;
+    if (!(r > 0.0L) || !(nT > 0.0L) || !isfinite((double)r)) { ok = 0; break; }
+    ld delta = fabsl(nT - T);
+    for (int a = 0; a < D; a++) delta = fmaxl(delta, fabsl(nu[a] - u[a]));
+    rho = (double)r;
+    Tn = (double)nT;
+    if (delta <= POND_TOL) break;
+    for (int a = 0; a < 3; a++) u[a] = nu[a];
+    T = nT;
+  }
+  free(nf); free(ng); free(nfr); free(tf); free(tg); free(have);
+  free(tgt->Minv);
+  free(tgt);
+  if (!ok) return -1;
+  /* collision in the converged frame (the last frame the populations were
+   * reconstructed in), where f^eq = rho W_i, g^eq = (cv - D/2) T rho W_i */
+  const double Tf = (double)Tfr;
+  const double tl = relax_tau_p(c, rho, Tn);
+  const double om = 1.0 / tl;
+  const int two = c->cfg.tau2 > 0.0 && c->cfg.tau2 != c->cfg.tau;
+  const double om2 = two ? 1.0 / (0.5 + (tl - 0.5) * (c->cfg.tau2 - 0.5) / (c->cfg.tau - 0.5)) : om;
+  const double gq = th ? (c->cfg.cv - 0.5 * D) * Tf : 0.0;
+  /* quasi-equilibria (eqs. fqeq, gqeq) in the co-moving frame: v - u = sqrt(T) c,
+   * Qbar = T^{3/2} sum c c c (f - f^eq), qbar = T^{1/2} sum c (g - g^eq);
+   * f* = f^eq + W T^{-3/2}/6 Qbar : (c c c - sym(c 1)), g* = g^eq + W T^{-1/2} qbar . c */
+  double Qb[3][3][3] = {{{0}}}, qb[3] = {0, 0, 0};
+  if (two) {
+    const double s3 = pow(Tf, 1.5), s1 = sqrt(Tf);
+    for (int i = 0; i < Q; i++) {
+      const double nfq = ft[i] - rho * L->W[i];
+      const double ngq = th ? gt[i] - gq * rho * L->W[i] : 0.0;
+      for (int a = 0; a < D; a++) {
+        qb[a] += s1 * L->c[i][a] * ngq;
+        for (int b = 0; b < D; b++)
+          for (int cc = 0; cc < D; cc++) Qb[a][b][cc] += s3 * L->c[i][a] * L->c[i][b] * L->c[i][cc] * nfq;
+      }
+    }
+  }
+  for (int i = 0; i < Q; i++) {
+    const double feq = rho * L->W[i];
+    fo[i] = ft[i] + om * (feq - ft[i]);
+    if (two) {
+      double s = 0.0;
+      for (int a = 0; a < D; a++)
+        for (int b = 0; b < D; b++)
+          for (int cc = 0; cc < D; cc++) {
+            const double ca = L->c[i][a], cb = L->c[i][b], ccc = L->c[i][cc];
+            const double h3 = ca * cb * ccc - (b == cc ? ca : 0.0) - (a == cc ? cb : 0.0) - (a == b ? ccc : 0.0);
+            s += Qb[a][b][cc] * h3;
+          }
+      fo[i] += (om - om2) * L->W[i] * s / (6.0 * pow(Tf, 1.5));
+    }
+    if (th) {
+      const double geq = gq * rho * L->W[i];
+      go[i] = gt[i] + om * (geq - gt[i]);
+      if (two) {
+        double s = 0.0;
+        for (int a = 0; a < D; a++) s += qb[a] * L->c[i][a];
+        go[i] += (om - om2) * L->W[i] * s / sqrt(Tf);
+      }
+    }
+  }
+  for (int a = 0; a < 3; a++) frame_out[a] = a < D ? (double)uf[a] : 0.0;
+  frame_out[3] = Tf;
+  return it > POND_MAXIT ? POND_MAXIT : it;
+}
+
+/* ------------------------------------------------------------------------ */
+
+int or_pond_create(const or_config *cfg, or_pond **out) {
+  if (!cfg || !out) return -1;
+  if (cfg->dim != 2 && cfg->dim != 3) return -1;
+  if (cfg->nx < 1 || cfg->ny < 1 || (cfg->dim == 3 && cfg->nz < 1)) return -1;
+  if (cfg->n_low < 2 || cfg->n_high != 0) return -1;   /* one velocity set */
+  if (cfg->tau <= 0.5 || (cfg->tau2 > 0.0 && cfg->tau2 <= 0.5)) return -1;
+  if (cfg->store != 0) return -1;                       /* FP64 populations */
+  for (int f = 0; f < 2 * cfg->dim; f++)
+    if (cfg->bc[f] != 0 && cfg->bc[f] != 1 && cfg->bc[f] != 2) return -1;
+  or_pond *c = (or_pond *)calloc(1, sizeof(or_pond));
+  c->cfg = *cfg;
+  c->D = cfg->dim;
+  c->N[0] = cfg->nx;
+  c->N[1] = cfg->ny;
+  c->N[2] = cfg->dim == 3 ? cfg->nz : 1;
+  c->ncell = (int64_t)c->N[0] * c->N[1] * c->N[2];
+  c->L = lat_build(c->D, cfg->n_low);
+  if (!c->L) { free(c); return -2; }
+  c->Q = c->L->Q;
+  c->NP = cfg->thermal ? 2 * c->Q : c->Q;
+  /* dt = CFL / the largest lattice speed (the lattice-frame rule; a departure
+   * point beyond the two-cell reach in some frame is reported by the step) */
+  double vmax = 0.0;
+  for (int a = 0; a < c->D; a++)
+    if (lat_vmax(c->L, a) > vmax) vmax = lat_vmax(c->L, a);
+  c->dt = cfg->cfl / vmax;
+  c->f = (double *)calloc((size_t)c->NP * c->ncell, sizeof(double));
+  c->fn = (double *)calloc((size_t)c->NP * c->ncell, sizeof(double));
+  c->fr = (double *)calloc((size_t)4 * c->ncell, sizeof(double));
+  c->frn = (double *)calloc((size_t)4 * c->ncell, sizeof(double));
+  *out = c;
+  return 0;
+}
+
+void or_pond_destroy(or_pond *c) {
+  if (!c) return;
+  lat_free(c->L);
+  free(c->f); free(c->fn); free(c->fr); free(c->frn);
+  free(c);
+}
+
+double or_pond_dt(const or_pond *c) { return c->dt; }
+
+/* every cell at the co-moving equilibrium of (rho, u, T) in its own frame */
+int or_pond_init(or_pond *c, const double *rho, const double *u, const double *T) {
+  const int th = c->cfg.thermal;
+  for (int64_t k = 0; k < c->ncell; k++) {
+    const double Tk = th ? T[k] : 1.0;
+    for (int i = 0; i < c->Q; i++) {
+      c->f[(int64_t)i * c->ncell + k] = rho[k] * c->L->W[i];
+      if (th) c->f[(int64_t)(c->Q + i) * c->ncell + k] = (c->cfg.cv - 0.5 * c->D) * Tk * rho[k] * c->L->W[i];
+    }
+    for (int a = 0; a < 3; a++) c->fr[(int64_t)a * c->ncell + k] = a < c->D ? u[(int64_t)a * c->ncell + k] : 0.0;
+    c->fr[(int64_t)3 * c->ncell + k] = Tk;
+  }
+  c->step = 0;
+  return 0;
+}
+
+int or_pond_step(or_pond *c, int nsteps) {
+  for (int s = 0; s < nsteps; s++) {
+    int bad = 0, itmax = 0;
+    double itsum = 0.0;
+#pragma omp parallel reduction(| : bad) reduction(max : itmax) reduction(+ : itsum)
+    {
+      double fo[OR_MAXQ], go[OR_MAXQ], frm[4];
+#pragma omp for schedule(dynamic, 16)
+      for (int64_t k = 0; k < c->ncell; k++) {
+        const int it = pond_cell(c, k, fo, go, frm);
+        if (it < 0) { bad = 1; continue; }
+        if (it > itmax) itmax = it;
+        itsum += it;
+        for (int i = 0; i < c->Q; i++) {
+          c->fn[(int64_t)i * c->ncell + k] = fo[i];
+          if (c->cfg.thermal) c->fn[(int64_t)(c->Q + i) * c->ncell + k] = go[i];
+        }
+        for (int a = 0; a < 4; a++) c->frn[(int64_t)a * c->ncell + k] = frm[a];
+      }
+    }
+    if (bad) return -4;
+    double *t = c->f; c->f = c->fn; c->fn = t;
+    t = c->fr; c->fr = c->frn; c->frn = t;
+    c->it_mean = itsum / (double)c->ncell;
+    c->it_max = itmax;
+    c->step++;
+  }
+  return 0;
+}
+
+int or_pond_iterations(const or_pond *c, double *mean, int *max) {
+  if (mean) *mean = c->it_mean;
+  if (max) *max = c->it_max;
+  return 0;
+}
+
+/* populations of each cell in its own frame: [NP][ncell] (fg = 1: g) */
+int or_pond_get_pops(const or_pond *c, int fg, double *out) {
+  if (fg && !c->cfg.thermal) return -1;
+  memcpy(out, c->f + (size_t)(fg ? c->Q : 0) * c->ncell, sizeof(double) * c->Q * c->ncell);
+  return 0;
+}
+
+int or_pond_get_frames(const or_pond *c, double *out) {
+  memcpy(out, c->fr, sizeof(double) * 4 * c->ncell);
+  return 0;
+}
+
+/* rho, u, T of every cell from its populations in its own frame */
+int or_pond_macros(const or_pond *c, double *rho, double *u, double *T) {
+  const lat_t *L = c->L;
+  for (int64_t k = 0; k < c->ncell; k++) {
+    const ld Tf = (ld)c->fr[3 * c->ncell + k], st = sqrtl(Tf);
+    ld r = 0, j[3] = {0, 0, 0}, e = 0;
+    for (int i = 0; i < c->Q; i++) {
+      const ld f = (ld)c->f[(int64_t)i * c->ncell + k];
+      ld v2 = 0;
+      r += f;
+      for (int a = 0; a < c->D; a++) {
+        const ld v = st * L->cl[i][a] + (ld)c->fr[(int64_t)a * c->ncell + k];
+        j[a] += v * f;
+        v2 += v * v;
+      }
+      e += 0.5L * v2 * f;
+      if (c->cfg.thermal) e += (ld)c->f[(int64_t)(c->Q + i) * c->ncell + k];
+    }
+    ld u2 = 0;
+    for (int a = 0; a < c->D; a++) {
+      if (u) u[(int64_t)a * c->ncell + k] = (double)(j[a] / r);
+      u2 += (j[a] / r) * (j[a] / r);
+    }
+    if (rho) rho[k] = (double)r;
+    if (T) T[k] = c->cfg.thermal ? (double)((e / r - 0.5L * u2) / (ld)c->cfg.cv) : 1.0;
+  }
+  return 0;
+}
+
+/* G_{src}^{dst} f for one population vector (frames as {u_x, u_y, u_z, T}) */
+int or_pond_transfer(int dim, int n, const double *src, const double *dst, const double *f,
+                     double *out) {
+  lat_t *L = lat_build(dim, n);
+  if (!L) return -1;
+  pframe_t *s = (pframe_t *)malloc(sizeof(pframe_t)), *d = (pframe_t *)malloc(sizeof(pframe_t));
+  d->Minv = (ld *)malloc(sizeof(ld) * L->Q * L->Q);
+  ld us[3] = {src[0], src[1], src[2]}, ud[3] = {dst[0], dst[1], dst[2]};
+  frame_velocities(L, us, (ld)src[3], s);
+  int rc = frame_target(L, ud, (ld)dst[3], d);
+  ld o[OR_MAXQ];
+  if (!rc) {
+    transfer(L, s, d, f, o);
+    for (int i = 0; i < L->Q; i++) out[i] = (double)o[i];
+  }
+  free(d->Minv);
+  free(s); free(d);
+  lat_free(L);
+  return rc ? -2 : 0;
+}
