@@ -110,6 +110,17 @@ typedef struct msl_config {
                                  1/tau, the non-equilibrium third moment and heat flux at
                                  omega2 = 1/tau2, Pr = (tau - 1/2)/(tau2 - 1/2) (kept where tau
                                  follows mu(T)); 2D only.  Otherwise BGK (omega1 = omega2). */
+  int pond;                   /* 1: co-moving reference frames (PonD, Sec. II.C.1): every cell
+                                 keeps its populations in its own frame {u, T}, a step runs the
+                                 predictor-corrector (eqs. correctorfields) to convergence and
+                                 collides in the converged frame (eqs. feqPond, geqPond).  Needs
+                                 dim 2, one velocity set (n_high 0), FP64 storage, no criterion,
+                                 the lattice frame, and periodic, fixed-equilibrium or
+                                 zero-gradient faces; dt = cfl / max|c| of the lattice, and a
+                                 step whose departure point leaves the two-cell reach in some
+                                 frame returns MSL_EUNSTABLE (lower cfl).  Populations in and out
+                                 (msl_get_populations) are given in each cell's own frame
+                                 (msl_pond_frames).  0: one global frame. */
 } msl_config;
 
 typedef struct msl_ctx msl_ctx;
@@ -175,6 +186,13 @@ int msl_set_populations(msl_ctx *ctx, int which, int fg, const double *in);
 /* Global sums over each cell's own populations: rho, rho u_x, rho u_y, rho u_z,
  * rho E (host out[5], FP64, deterministic order).  Synchronises. */
 int msl_conservation(msl_ctx *ctx, double *out);
+
+/* Co-moving frames (pond = 1): each cell's frame as device FP64
+ * out[4][cells] = u_x, u_y, u_z (0), T.  MSL_EINVAL for other contexts. */
+int msl_pond_frames(msl_ctx *ctx, double *out);
+/* Co-moving frames: predictor-corrector passes of the last msl_step call,
+ * mean per cell and step and maximum (host).  Synchronises. */
+int msl_pond_iterations(msl_ctx *ctx, double *mean, int *max);
 
 /* Error norms of the macroscopic fields (Sec. II.B moments of each cell's own
  * populations, as msl_macros) against caller reference fields: rho_ref

@@ -210,6 +210,16 @@ static const char *check_config(const msl_config *cfg) {
   if (cfg->tau2 > 0.0 && cfg->tau2 != cfg->tau && cfg->dim != 2) return "the two-relaxation model is built for 2D";
   const long long cells = (long long)cfg->nx * cfg->ny * (cfg->dim == 3 ? cfg->nz : 1);
   if (cells >= (1ll << 31)) return "grid too large";
+  if (cfg->pond != 0 && cfg->pond != 1) return "pond must be 0 or 1";
+  if (cfg->pond) {
+    if (cfg->dim != 2) return "co-moving frames are built for 2D";
+    if (cfg->n_high) return "co-moving frames run one velocity set";
+    if (cfg->store != MSL_FP64) return "co-moving frames keep FP64 populations";
+    if (cfg->crit_kind) return "co-moving frames run one velocity set (no criterion)";
+    if (!trivial_frame) return "co-moving frames replace the global frame";
+    for (int f = 0; f < 4; ++f)
+      if (cfg->bc[f] == MSL_BC_DIFFUSE_WALL) return "co-moving frames: no diffuse walls";
+  }
   for (int f = 0; f < 2 * cfg->dim; ++f) {
     if (cfg->bc[f] < 0 || cfg->bc[f] > 3) return "unknown boundary rule";
     if ((cfg->bc[f] == MSL_BC_PERIODIC) != (cfg->bc[f ^ 1] == MSL_BC_PERIODIC)) return "periodic faces must come in pairs";
@@ -227,7 +237,7 @@ struct Layout {
   Geo geo;
   size_t esz;
   size_t off_tab, off_planes[2], off_cls, off_newmask, off_tflag, off_blist[2], off_bcount, off_blk,
-      off_red, off_flag, off_tlist, off_kn, off_mlp, total;
+      off_red, off_flag, off_tlist, off_kn, off_pond, off_mlp, total;
   int nblk, Q[2], np[2];
   long long plane_bytes;
   int mlpF, mlpO, mlpH, mlpP, nctile, nct[3];
@@ -295,6 +305,9 @@ static void make_layout(const msl_config *cfg, Layout &L) {
   // Knudsen-number criterion: each cell's density and mean free path
   L.off_kn = off;
   if (cfg->crit_kind == MSL_CRIT_KN && nl > 1) off = align256(off + (size_t)g.ncell * 2 * 8);
+  // co-moving frames: two buffers of populations and frames, iteration counters
+  L.off_pond = off;
+  if (cfg->pond) off = align256(off + (size_t)g.ncell * 8 * 2 * (L.np[0] + 4) + 64);
   // learned closure
   if (cfg->lift_mode == MSL_LIFT_MLP && nl > 1) {
     const int q = L.Q[0], Q = L.Q[1];
@@ -496,6 +509,15 @@ int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_
   c->tlist = (int *)(base + L.off_tlist);
   c->kn_rho = (double *)(base + L.off_kn);
   c->kn_lam = c->kn_rho + L.geo.ncell;
+  if (cfg->pond) {
+    double *pb = (double *)(base + L.off_pond);
+    const size_t nf = (size_t)L.np[0] * L.geo.ncell, nfr = (size_t)4 * L.geo.ncell;
+    c->pond_f[0] = pb;
+    c->pond_f[1] = pb + nf;
+    c->pond_fr[0] = pb + 2 * nf;
+    c->pond_fr[1] = pb + 2 * nf + nfr;
+    c->pond_stats = (unsigned long long *)(pb + 2 * nf + 2 * nfr);
+  }
   c->tcount = c->tlist + (size_t)L.geo.ntx * L.geo.nty * L.geo.ntz;
   if (L.mlpP) {
     c->mlpF = L.mlpF; c->mlpO = L.mlpO; c->mlpH = L.mlpH; c->mlpP = L.mlpP;
@@ -565,6 +587,13 @@ static int refresh_band(msl_ctx *c) {
 
 int msl_init(msl_ctx *c, const double *rho, const double *u, const double *T) {
   if (!c || !rho || !u || (c->cfg.thermal && !T)) return MSL_EINVAL;
+  if (c->cfg.pond) {
+    const int rc = msl_pond_launch_init(c, rho, u, T);
+    if (rc) { set_err(c, "init kernel launch failed"); return rc; }
+    c->initialized = 1;
+    c->step = 0;
+    return MSL_OK;
+  }
   int rc = msl_launch_init_eq(c, rho, u, T);
   if (!rc) rc = msl_launch_bc_fixed(c);
   if (rc) { set_err(c, "init kernel launch failed"); return rc; }
@@ -576,7 +605,7 @@ int msl_init(msl_ctx *c, const double *rho, const double *u, const double *T) {
 }
 
 int msl_set_mask(msl_ctx *c, const uint8_t *mask) {
-  if (!c || !mask) return MSL_EINVAL;
+  if (!c || !mask || c->cfg.pond) return MSL_EINVAL;
   if (hipMemsetAsync(c->flag, 0, sizeof(int), c->stream) != hipSuccess) return MSL_EHIP;
   int rc = msl_launch_check_mask(c, mask);
   if (rc) return rc;
@@ -701,9 +730,49 @@ int msl_profile_read(msl_ctx *c, double *stats) {
   return MSL_OK;
 }
 
+// co-moving frames: one predictor-corrector launch per step; the reach and
+// positivity flags are read once at the end of the call
+static int pond_step(msl_ctx *c, int nsteps) {
+  if (hipMemsetAsync(c->flag, 0, sizeof(int), c->stream) != hipSuccess ||
+      hipMemsetAsync(c->pond_stats, 0, 16, c->stream) != hipSuccess)
+    return MSL_EHIP;
+  for (int s = 0; s < nsteps; ++s) {
+    const int rc = msl_pond_launch_step(c);
+    if (rc) { set_err(c, "co-moving step launch failed"); return rc; }
+    ++c->step;
+  }
+  c->pond_cells_steps = (long long)nsteps * c->ncell;
+  int bad = 0;
+  if (hipMemcpyAsync(&bad, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return MSL_EHIP;
+  if (bad & 1) { set_err(c, "a departure point left the two-cell reach: lower cfl"); return MSL_EUNSTABLE; }
+  if (bad & 2) { set_err(c, "non-positive or non-finite density or temperature"); return MSL_EUNSTABLE; }
+  return MSL_OK;
+}
+
+int msl_pond_frames(msl_ctx *c, double *out) {
+  if (!c || !out || !c->cfg.pond) return MSL_EINVAL;
+  if (!c->initialized) return MSL_ESTATE;
+  return hipMemcpyAsync(out, c->pond_fr[c->cur], sizeof(double) * 4 * c->ncell, hipMemcpyDeviceToDevice,
+                        c->stream) == hipSuccess ? MSL_OK : MSL_EHIP;
+}
+
+int msl_pond_iterations(msl_ctx *c, double *mean, int *max) {
+  if (!c || !c->cfg.pond) return MSL_EINVAL;
+  unsigned long long h[2] = {0, 0};
+  if (hipMemcpyAsync(h, c->pond_stats, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return MSL_EHIP;
+  if (mean) *mean = c->pond_cells_steps > 0 ? (double)h[0] / (double)c->pond_cells_steps : 0.0;
+  if (max) *max = (int)(h[1] & 0xffffffffu);
+  return MSL_OK;
+}
+
 int msl_step(msl_ctx *c, int nsteps) {
   if (!c || nsteps < 0) return MSL_EINVAL;
   if (!c->initialized) { set_err(c, "msl_step before msl_init"); return MSL_ESTATE; }
+  if (c->cfg.pond) return pond_step(c, nsteps);
   // the x ghost columns of the current buffer are taken as stale on entry
   // (the state may have been set since the last step); the live-tile list is
   // rebuilt on first use
@@ -774,16 +843,23 @@ int msl_step(msl_ctx *c, int nsteps) {
 int msl_macros(msl_ctx *c, double *rho, double *u, double *T) {
   if (!c) return MSL_EINVAL;
   if (!c->initialized) return MSL_ESTATE;
+  if (c->cfg.pond) return msl_pond_launch_macros(c, rho, u, T);
   return msl_launch_macros(c, rho, u, T);
 }
 
 int msl_get_populations(msl_ctx *c, int which, int fg, double *out) {
   if (!c || !out || which < 0 || which >= c->nlat || (fg && !c->cfg.thermal)) return MSL_EINVAL;
+  if (c->cfg.pond) {
+    if (!c->initialized) return MSL_ESTATE;
+    const size_t n = (size_t)c->Q[0] * c->ncell;
+    return hipMemcpyAsync(out, c->pond_f[c->cur] + (fg ? n : 0), sizeof(double) * n, hipMemcpyDeviceToDevice,
+                          c->stream) == hipSuccess ? MSL_OK : MSL_EHIP;
+  }
   return msl_launch_pops(c, which, fg, out, nullptr);
 }
 
 int msl_set_populations(msl_ctx *c, int which, int fg, const double *in) {
-  if (!c || !in || which < 0 || which >= c->nlat || (fg && !c->cfg.thermal)) return MSL_EINVAL;
+  if (!c || !in || which < 0 || which >= c->nlat || (fg && !c->cfg.thermal) || c->cfg.pond) return MSL_EINVAL;
   int rc = msl_launch_pops(c, which, fg, nullptr, in);
   if (!rc) rc = msl_launch_bc_fixed(c);
   if (rc) return rc;
@@ -792,7 +868,7 @@ int msl_set_populations(msl_ctx *c, int which, int fg, const double *in) {
 }
 
 int msl_conservation(msl_ctx *c, double *out) {
-  if (!c || !out) return MSL_EINVAL;
+  if (!c || !out || c->cfg.pond) return MSL_EINVAL;
   if (!c->initialized) return MSL_ESTATE;
   double *dev = c->red + 1024 * 9;
   int rc = msl_launch_conservation(c, dev);
@@ -808,7 +884,7 @@ int msl_conservation(msl_ctx *c, double *out) {
 
 int msl_error_norms(msl_ctx *c, const double *rho_ref, const double *u_ref, const double *T_ref,
                     double *out) {
-  if (!c || !out) return MSL_EINVAL;
+  if (!c || !out || c->cfg.pond) return MSL_EINVAL;
   if (!c->initialized) return MSL_ESTATE;
   double *dev = c->red + 1024 * 9;
   int rc = msl_launch_error_norms(c, rho_ref, u_ref, T_ref, dev);
@@ -829,7 +905,7 @@ struct StateHeader {
 };
 
 int msl_get_state(msl_ctx *c, void *buf, size_t *bytes) {
-  if (!c || !bytes) return MSL_EINVAL;
+  if (!c || !bytes || c->cfg.pond) return MSL_EINVAL;
   size_t pb[2] = {0, 0};
   for (int l = 0; l < c->nlat; ++l)
     pb[l] = (size_t)c->Q[l] * (c->cfg.thermal ? 2 : 1) * c->geo.plane * c->esz * 2;
@@ -864,7 +940,7 @@ int msl_get_state(msl_ctx *c, void *buf, size_t *bytes) {
 }
 
 int msl_set_state(msl_ctx *c, const void *buf, size_t bytes) {
-  if (!c || !buf || bytes < sizeof(StateHeader)) return MSL_EINVAL;
+  if (!c || !buf || bytes < sizeof(StateHeader) || c->cfg.pond) return MSL_EINVAL;
   StateHeader h;
   memcpy(&h, buf, sizeof(h));
   size_t pb[2] = {0, 0};

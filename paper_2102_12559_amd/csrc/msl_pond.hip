@@ -1,0 +1,335 @@
+// msl_pond.hip -- the step in co-moving reference frames (PonD, Sec. II.C.1),
+// one velocity set, 2D, FP64.
+//
+// Every cell keeps its post-collision populations in its own frame
+// lambda = {u, T} (eq. reference; particle velocities sqrt(T) c_i + u, eq. vi,
+// with T_L = 1).  A group of GS lanes (GS = the power of two >= Q) owns one
+// cell, one lane per population.  Per iteration of the predictor-corrector:
+// each lane finds its population's departure point x - v_i dt in the current
+// frame, and for each of the 3 x 3 collocation points around the nearest node
+// transfers that point's population vector from its own frame to the current
+// one and keeps its own component (eqs. reconstructionPond, fll).  The
+// transfer G = M_target^{-1} M_source of the moment matrices of eq. momf
+// factorises per axis, and its one-axis factor is the Lagrange basis of the
+// lattice nodes evaluated at the source nodes mapped into the target frame:
+//   G_x[a][a'] = l_a((sqrt(T_s) c_a' + u_s,x - u_x) / sqrt(T)),
+// because the inverse of a Vandermonde matrix holds the Lagrange basis
+// polynomials of its nodes.  The group then sums rho, j, E of the
+// reconstructed populations (shuffles within the group), which define the
+// next frame (eqs. correctorfields), until neither a velocity component nor T
+// changes by more than 1e-14 (at most 60 passes).  The collision runs in the
+// converged frame, where f^eq = rho W_i and g^eq = (cv - 1) T rho W_i (eqs.
+// feqPond, geqPond), BGK or two-relaxation (eqs. fqeq, gqeq in the co-moving
+// frame).
+#include <hip/hip_runtime.h>
+
+#include "msl_internal.hpp"
+
+#define POND_MAXIT 60
+#define POND_TOL 1e-14
+
+struct PondArgs {
+  int nx, ny;
+  long long ncell;
+  int bc[4];
+  double st[4][5];   // fixed-equilibrium face states rho, ux, uy, uz, T
+};
+
+template <int GS>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = GS / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GS);
+  return v;
+}
+
+template <int N>
+struct PondTraits {
+  static constexpr int Q = N * N;
+  static constexpr int GS = Q <= 16 ? 16 : (Q <= 32 ? 32 : 64);
+};
+
+// the collocation point (x, y) (possibly outside the domain): the cell index
+// whose state it takes, or -1 - face for a fixed-equilibrium face state
+__device__ __forceinline__ long long pond_resolve(const PondArgs &pa, int x, int y) {
+  if (x < 0 && pa.bc[0] == MSL_BC_FIXED_EQ) return -1;
+  if (x >= pa.nx && pa.bc[1] == MSL_BC_FIXED_EQ) return -2;
+  if (y < 0 && pa.bc[2] == MSL_BC_FIXED_EQ) return -3;
+  if (y >= pa.ny && pa.bc[3] == MSL_BC_FIXED_EQ) return -4;
+  if (x < 0 || x >= pa.nx) x = pa.bc[0] == MSL_BC_PERIODIC ? (x + pa.nx) % pa.nx : (x < 0 ? 0 : pa.nx - 1);
+  if (y < 0 || y >= pa.ny) y = pa.bc[2] == MSL_BC_PERIODIC ? (y + pa.ny) % pa.ny : (y < 0 ? 0 : pa.ny - 1);
+  return (long long)y * pa.nx + x;
+}
+
+template <int N, bool TH, bool QE>
+__global__ void __launch_bounds__(256)
+k_pond_step(const Tab *__restrict__ tab, PondArgs pa, const double *__restrict__ fin,
+            const double *__restrict__ frin, double *__restrict__ fout, double *__restrict__ frout,
+            int *__restrict__ flag, unsigned long long *__restrict__ itsum, int *__restrict__ itmax) {
+  using Tr = PondTraits<N>;
+  constexpr int Q = Tr::Q, GS = Tr::GS;
+  const LatTab &L = tab->lat[0];
+  const long long k = (long long)blockIdx.x * (256 / GS) + threadIdx.x / GS;
+  const int li = threadIdx.x % GS;
+  const bool cell_ok = k < pa.ncell;
+  const bool act = cell_ok && li < Q;
+  const int i = act ? li : 0, a = i % N, b = i / N;
+  const long long kk = cell_ok ? k : 0;
+  const int px = (int)(kk % pa.nx), py = (int)(kk / pa.nx);
+  const double dt = tab->dt, cv = tab->cv;
+  // lattice nodes and the Lagrange denominators 1 / prod_{c != a} (x_a - x_c)
+  double xn[N], den[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) xn[m] = L.cr[m];
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    double p = 1.0;
+#pragma unroll
+    for (int c = 0; c < N; ++c)
+      if (c != m) p *= xn[m] - xn[c];
+    den[m] = 1.0 / p;
+  }
+  double ux = frin[kk], uy = frin[pa.ncell + kk], T = frin[3 * pa.ncell + kk];
+  double ft = 0.0, gt = 0.0, rho = 0.0, Tn = 1.0;
+  bool done = !cell_ok;
+  int it = 0;
+  for (int pass = 1; pass <= POND_MAXIT; ++pass) {
+    double r = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
+    if (!done) {
+      it = pass;
+      const double sT = sqrt(T), isT = 1.0 / sT;
+      const double vx = sT * xn[a] + ux, vy = sT * xn[b] + uy;
+      const double dx = -vx * dt, dy = -vy * dt;
+      const int nx0 = (int)floor(dx + 0.5), ny0 = (int)floor(dy + 0.5);
+      if (act && (nx0 < -1 || nx0 > 1 || ny0 < -1 || ny0 > 1)) atomicOr(flag, 1);
+      const double xi = dx - nx0, yi = dy - ny0;
+      // 3-point Lagrange weights through -1, 0, 1
+      const double wx[3] = {0.5 * xi * (xi - 1.0), 1.0 - xi * xi, 0.5 * xi * (xi + 1.0)};
+      const double wy[3] = {0.5 * yi * (yi - 1.0), 1.0 - yi * yi, 0.5 * yi * (yi + 1.0)};
+      double accf = 0.0, accg = 0.0;
+      for (int sy = -1; sy <= 1; ++sy)
+        for (int sx = -1; sx <= 1; ++sx) {
+          const long long q = pond_resolve(pa, px + nx0 + sx, py + ny0 + sy);
+          double usx, usy, Ts, rf = 0.0;
+          if (q >= 0) {
+            usx = frin[q];
+            usy = frin[pa.ncell + q];
+            Ts = frin[3 * pa.ncell + q];
+          } else {
+            const double *st = pa.st[-1 - q];
+            rf = st[0];
+            usx = st[1];
+            usy = st[2];
+            Ts = TH ? st[4] : 1.0;
+          }
+          // the transfer's rows of this lane's nodes a (x) and b (y)
+          const double sTs = sqrt(Ts);
+          double gx[N], gy[N];
+#pragma unroll
+          for (int m = 0; m < N; ++m) {
+            const double zx = (sTs * xn[m] + usx - ux) * isT, zy = (sTs * xn[m] + usy - uy) * isT;
+            double px_ = den[a], py_ = den[b];
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+              if (c != a) px_ *= zx - xn[c];
+              if (c != b) py_ *= zy - xn[c];
+            }
+            gx[m] = px_;
+            gy[m] = py_;
+          }
+          double vf = 0.0, vg = 0.0;
+#pragma unroll
+          for (int mb = 0; mb < N; ++mb) {
+            double sf = 0.0, sg = 0.0;
+#pragma unroll
+            for (int ma = 0; ma < N; ++ma) {
+              const int j = ma + N * mb;
+              double fj, gj = 0.0;
+              if (q >= 0) {
+                fj = fin[(long long)j * pa.ncell + q];
+                if (TH) gj = fin[(long long)(Q + j) * pa.ncell + q];
+              } else {
+                fj = rf * L.w[ma] * L.w[mb];
+                if (TH) gj = (cv - 1.0) * Ts * fj;
+              }
+              sf += gx[ma] * fj;
+              if (TH) sg += gx[ma] * gj;
+            }
+            vf += gy[mb] * sf;
+            if (TH) vg += gy[mb] * sg;
+          }
+          const double w = wx[sx + 1] * wy[sy + 1];
+          accf += w * vf;
+          if (TH) accg += w * vg;
+        }
+      ft = accf;
+      gt = TH ? accg : 0.0;
+      if (act) {
+        r = ft;
+        jx = vx * ft;
+        jy = vy * ft;
+        e = 0.5 * (vx * vx + vy * vy) * ft + gt;
+      }
+    }
+    // corrector: the group's sums (every lane of the wave takes part)
+    r = group_sum<GS>(r);
+    jx = group_sum<GS>(jx);
+    jy = group_sum<GS>(jy);
+    e = group_sum<GS>(e);
+    if (!done) {
+      const double nux = jx / r, nuy = jy / r;
+      const double nT = TH ? (e / r - 0.5 * (nux * nux + nuy * nuy)) / cv : 1.0;
+      if (!(r > 0.0) || !(nT > 0.0) || !isfinite(r)) {
+        if (li == 0) atomicOr(flag, 2);
+        done = true;
+      } else {
+        const double delta = fmax(fabs(nT - T), fmax(fabs(nux - ux), fabs(nuy - uy)));
+        rho = r;
+        Tn = nT;
+        if (delta <= POND_TOL || pass == POND_MAXIT) {
+          done = true;
+        } else {
+          ux = nux;
+          uy = nuy;
+          T = nT;
+        }
+      }
+    }
+    if (__all(done)) break;
+  }
+  // collision in the converged frame {ux, uy, T}
+  double tl = tab->tau;
+  if (tab->tau_mode == 1) tl = tab->mu_ref * pow(Tn / tab->tau_ref_T, tab->mu_exp) / (rho * Tn * dt) + 0.5;
+  const double om = 1.0 / tl;
+  const double W = L.w[a] * L.w[b];
+  const double feq = rho * W, gq = (cv - 1.0) * T, geq = gq * rho * W;
+  double fo = ft + om * (feq - ft), go = gt + om * (geq - gt);
+  if constexpr (QE) {
+    // quasi-equilibria in the co-moving frame (v - u = sqrt(T) c):
+    // Qbar = T^{3/2} sum c c c (f - f^eq), qbar = T^{1/2} sum c (g - g^eq)
+    const double om2 = 1.0 / (0.5 + (tl - 0.5) * tab->qe_ratio);
+    const double cx = xn[a], cy = xn[b];
+    const double nf = act ? ft - feq : 0.0, ng = act && TH ? gt - geq : 0.0;
+    const double Qxxx = group_sum<GS>(cx * cx * cx * nf), Qxxy = group_sum<GS>(cx * cx * cy * nf);
+    const double Qxyy = group_sum<GS>(cx * cy * cy * nf), Qyyy = group_sum<GS>(cy * cy * cy * nf);
+    const double qx = group_sum<GS>(cx * ng), qy = group_sum<GS>(cy * ng);
+    // f* - f^eq = W T^{-3/2}/6 Qbar : He3(c), Qbar = T^{3/2} (sums above)
+    const double h = Qxxx * (cx * cx * cx - 3.0 * cx) + 3.0 * Qxxy * (cx * cx * cy - cy) +
+                     3.0 * Qxyy * (cx * cy * cy - cx) + Qyyy * (cy * cy * cy - 3.0 * cy);
+    fo += (om - om2) * W * h / 6.0;
+    if (TH) go += (om - om2) * W * (qx * cx + qy * cy);
+  }
+  if (act) {
+    fout[(long long)i * pa.ncell + k] = fo;
+    if (TH) fout[(long long)(Q + i) * pa.ncell + k] = go;
+    if (li == 0) {
+      frout[k] = ux;
+      frout[pa.ncell + k] = uy;
+      frout[2 * pa.ncell + k] = 0.0;
+      frout[3 * pa.ncell + k] = T;
+      atomicAdd(itsum, (unsigned long long)it);
+      atomicMax(itmax, it);
+    }
+  }
+}
+
+// every cell at the co-moving equilibrium of (rho, u, T) in its own frame
+__global__ void k_pond_init(const Tab *__restrict__ tab, long long ncell, int thermal, const double *rho,
+                            const double *u, const double *T, double *f, double *fr) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ncell) return;
+  const LatTab &L = tab->lat[0];
+  const double Tk = thermal ? T[k] : 1.0;
+  for (int i = 0; i < L.Q; ++i) {
+    const double W = L.w[i % L.n] * L.w[i / L.n];
+    f[(long long)i * ncell + k] = rho[k] * W;
+    if (thermal) f[(long long)(L.Q + i) * ncell + k] = (tab->cv - 1.0) * Tk * rho[k] * W;
+  }
+  fr[k] = u[k];
+  fr[ncell + k] = u[ncell + k];
+  fr[2 * ncell + k] = 0.0;
+  fr[3 * ncell + k] = Tk;
+}
+
+// rho, u, T of every cell from its populations in its own frame
+__global__ void k_pond_macros(const Tab *__restrict__ tab, long long ncell, int thermal, const double *f,
+                              const double *fr, double *rho, double *u, double *T) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ncell) return;
+  const LatTab &L = tab->lat[0];
+  const double sT = sqrt(fr[3 * ncell + k]), ux = fr[k], uy = fr[ncell + k];
+  double r = 0, jx = 0, jy = 0, e = 0;
+  for (int i = 0; i < L.Q; ++i) {
+    const double fi = f[(long long)i * ncell + k];
+    const double vx = sT * L.cr[i % L.n] + ux, vy = sT * L.cr[i / L.n] + uy;
+    r += fi;
+    jx += vx * fi;
+    jy += vy * fi;
+    e += 0.5 * (vx * vx + vy * vy) * fi;
+    if (thermal) e += f[(long long)(L.Q + i) * ncell + k];
+  }
+  const double nux = jx / r, nuy = jy / r;
+  if (rho) rho[k] = r;
+  if (u) {
+    u[k] = nux;
+    u[ncell + k] = nuy;
+  }
+  if (T) T[k] = thermal ? (e / r - 0.5 * (nux * nux + nuy * nuy)) / tab->cv : 1.0;
+}
+
+static PondArgs pond_args(const msl_ctx *c) {
+  PondArgs pa;
+  pa.nx = c->geo.nx;
+  pa.ny = c->geo.ny;
+  pa.ncell = c->ncell;
+  for (int f = 0; f < 4; ++f) {
+    pa.bc[f] = c->cfg.bc[f];
+    for (int m = 0; m < 5; ++m) pa.st[f][m] = c->cfg.bc_state[f][m];
+  }
+  return pa;
+}
+
+int msl_pond_launch_init(msl_ctx *c, const double *rho, const double *u, const double *T) {
+  const unsigned nb = (unsigned)((c->ncell + 255) / 256);
+  hipLaunchKernelGGL(k_pond_init, dim3(nb), dim3(256), 0, c->stream, c->dtab, c->ncell, c->cfg.thermal, rho, u,
+                     T, c->pond_f[c->cur], c->pond_fr[c->cur]);
+  return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
+}
+
+int msl_pond_launch_macros(msl_ctx *c, double *rho, double *u, double *T) {
+  const unsigned nb = (unsigned)((c->ncell + 255) / 256);
+  hipLaunchKernelGGL(k_pond_macros, dim3(nb), dim3(256), 0, c->stream, c->dtab, c->ncell, c->cfg.thermal,
+                     c->pond_f[c->cur], c->pond_fr[c->cur], rho, u, T);
+  return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
+}
+
+template <int N, bool TH, bool QE>
+static int pond_step_n(msl_ctx *c) {
+  constexpr int GS = PondTraits<N>::GS;
+  const PondArgs pa = pond_args(c);
+  const unsigned nb = (unsigned)((c->ncell + (256 / GS) - 1) / (256 / GS));
+  hipLaunchKernelGGL((k_pond_step<N, TH, QE>), dim3(nb), dim3(256), 0, c->stream, c->dtab, pa,
+                     c->pond_f[c->cur], c->pond_fr[c->cur], c->pond_f[c->cur ^ 1], c->pond_fr[c->cur ^ 1],
+                     c->flag, c->pond_stats, (int *)(c->pond_stats + 1));
+  return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
+}
+
+template <bool TH, bool QE>
+static int pond_step_th(msl_ctx *c) {
+  switch (c->htab.lat[0].n) {
+    case 3: return pond_step_n<3, TH, QE>(c);
+    case 4: return pond_step_n<4, TH, QE>(c);
+    case 5: return pond_step_n<5, TH, QE>(c);
+    case 6: return pond_step_n<6, TH, QE>(c);
+  }
+  return MSL_EINVAL;
+}
+
+// one step: the new buffers become current
+int msl_pond_launch_step(msl_ctx *c) {
+  int rc;
+  if (c->cfg.thermal) rc = c->htab.qe ? pond_step_th<true, true>(c) : pond_step_th<true, false>(c);
+  else rc = c->htab.qe ? pond_step_th<false, true>(c) : pond_step_th<false, false>(c);
+  if (rc) return rc;
+  c->cur ^= 1;
+  return MSL_OK;
+}

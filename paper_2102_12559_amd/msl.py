@@ -40,11 +40,11 @@ class MslConfig(C.Structure):
         ("crit_kind", C.c_int), ("crit_thr", C.c_double), ("crit_every", C.c_int),
         ("check_every", C.c_int), ("mlp_hidden", C.c_int), ("mlp_check_every", C.c_int),
         ("u_ref", C.c_double * 3), ("T_ref", C.c_double), ("store_u", C.c_double * 3),
-        ("tau2", C.c_double),
+        ("tau2", C.c_double), ("pond", C.c_int),
     ]
 
 # fields a workload may leave out: the lattice frame, the plain storage scale, BGK
-_DEFAULTS = {"u_ref": (0.0, 0.0, 0.0), "T_ref": 1.0, "store_u": (0.0, 0.0, 0.0), "tau2": 0.0}
+_DEFAULTS = {"u_ref": (0.0, 0.0, 0.0), "T_ref": 1.0, "store_u": (0.0, 0.0, 0.0), "tau2": 0.0, "pond": 0}
 
 
 _lib = None
@@ -58,6 +58,7 @@ SYMBOLS = [
     "msl_mlp_get_weights", "msl_mlp_train", "msl_mlp_grad", "msl_mlp_forward",
     "msl_mlp_get_flags", "msl_mlp_set_flags", "msl_num_check_tiles", "msl_profile",
     "msl_profile_read", "msl_device_copy", "msl_mlp_grad_noalloc", "msl_error_norms",
+    "msl_pond_frames", "msl_pond_iterations",
 ]
 
 
@@ -86,6 +87,8 @@ def lib():
         L.msl_set_populations.argtypes = [vp, C.c_int, C.c_int, vp]
         L.msl_conservation.argtypes = [vp, C.POINTER(C.c_double)]
         L.msl_error_norms.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double)]
+        L.msl_pond_frames.argtypes = [vp, vp]
+        L.msl_pond_iterations.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
         L.msl_get_state.argtypes = [vp, vp, C.POINTER(sz)]
         L.msl_set_state.argtypes = [vp, vp, sz]
         L.msl_mlp_dims.argtypes = [vp] + [C.POINTER(C.c_int)] * 4
@@ -275,6 +278,17 @@ class Solver:
         self._check(lib().msl_error_norms(self._ctx, *[None if r is None else _ptr(r) for r in refs], out),
                     "msl_error_norms")
         return {"rho": (out[0], out[1]), "u": (out[2], out[3]), "T": (out[4], out[5])}
+
+    def pond_frames(self):
+        """co-moving frames: each cell's frame (u_x, u_y, u_z, T) as [4][cells]"""
+        out = self.torch.empty((4, self.ncell), dtype=self.torch.float64, device=self.device)
+        self._check(lib().msl_pond_frames(self._ctx, _ptr(out)), "msl_pond_frames")
+        return out
+
+    def pond_iterations(self):
+        m, mx = C.c_double(), C.c_int()
+        self._check(lib().msl_pond_iterations(self._ctx, C.byref(m), C.byref(mx)), "msl_pond_iterations")
+        return m.value, mx.value
 
     def get_state(self) -> bytes:
         n = C.c_size_t()
