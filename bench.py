@@ -522,6 +522,76 @@ def device_copy_rate(args):
                       "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}))
 
 
+def pond(args):
+    """The step in co-moving reference frames (Sec. II.C.1) on a 1024 x 1024
+    periodic box of thermal D2Q16 (f and g, cv = 3/2, FP64): a smooth random
+    flow (|u| <= 0.2, 5 % density and temperature variation) advected at
+    (0.8, -0.3), tau 0.8, CFL 0.4.  The kernel is bound by FP64 arithmetic:
+    its roofline is the FP64 vector peak, with the algorithmic flops of the
+    reconstruction (per population, collocation point and pass: the two
+    one-axis transfer rows, 4 n (n - 1) flops, and the contraction and
+    weighting, 2 n^2 + 2 n + 2 flops for f and again for g) times the passes
+    the predictor-corrector took."""
+    import numpy as np
+    import torch
+    from paper_2102_12559_amd import inputs, msl
+    torch.cuda.set_device(0)
+    N, n, th = 1024, 4, 1
+    steps = args.steps or 20
+    cfg = inputs.base_config(nx=N, ny=N, n_low=n, tau=0.8, cfl=0.4, thermal=th, cv=1.5, pond=1)
+    rho, u, T = inputs.smooth_random_flow(N, N, umax=0.2, seed=11, drho=0.05, dT=0.05)
+    u[0] += 0.8
+    u[1] -= 0.3
+    s = msl.Solver(cfg, device="cuda:0")
+    s.init(rho, u, T)
+    s.step(max(args.warmup, 1))
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    s.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    it_mean, it_max = s.pond_iterations()
+    ncell = N * N
+    Q = n * n
+    per_point = 4 * n * (n - 1) + (2 * n * n + 2 * n + 2) * (2 if th else 1)
+    flops = Q * 9 * per_point * it_mean * ncell          # per step
+    achieved = flops / (ms / steps / 1e3) / 1e12
+    out = {"metric": METRIC, "value": round(ncell * steps / (ms / 1e3) / 1e6, 2), "unit": "MLUPS",
+           "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": round(ms / steps, 5),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "co-moving frames (PonD): thermal D2Q16 1024x1024 periodic, random flow "
+                                  "advected at (0.8, -0.3), fp64", "grid": [N, N, 1], "cells": ncell,
+                      "lattices": [Q, 0], "storage": "f64", "parallelism": "single GPU"},
+           "roofline": {"bound": "alu", "kernel": "k_pond_step", "achieved": round(achieved, 3),
+                        "peak": 78.6, "unit": "TFLOP/s", "frac": round(achieved / 78.6, 4),
+                        "traffic": None, "flops_per_step": round(flops)},
+           "predictor_corrector": {"passes_mean": round(it_mean, 3), "passes_max": it_max}}
+    s.close()
+    if not args.no_cpu:
+        from oracle import oracle as O
+        nb = 48
+        ocfg = dict(cfg, nx=nb, ny=nb)
+        nthreads = O.set_threads(0)
+        o = O.Pond(ocfg)
+        o.init(rho[:, :nb, :nb].copy(), u[:, :, :nb, :nb].copy(), T[:, :nb, :nb].copy())
+        t0 = time.time()
+        k = 0
+        while time.time() - t0 < args.cpu_seconds:
+            o.step(1)
+            k += 1
+        sec = time.time() - t0
+        out["cpu_baseline"] = {"value": round(nb * nb * k / sec / 1e6, 4), "unit": "MLUPS",
+                               "cores": nthreads, "kind": "oracle", "cpu_model": cpu_model(),
+                               "sample": f"a {nb}x{nb} box of the same flow, FP64: {k} steps in "
+                                         f"{sec:.1f} s on {nthreads} threads"}
+    print(json.dumps(out))
+
+
 def efficiency(args):
     """The computational-efficiency experiment of Sec. V (Fig. 13 layout): an
     N x N periodic box split into two rectangles, D2Q25 on a band of 10 % of
@@ -645,6 +715,9 @@ def main():
         return
     if args.workload == "efficiency-d2q25":
         efficiency(args)
+        return
+    if args.workload == "pond":
+        pond(args)
         return
 
     import numpy as np
