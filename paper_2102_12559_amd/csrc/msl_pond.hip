@@ -4,7 +4,10 @@
 // Every cell keeps its post-collision populations in its own frame
 // lambda = {u, T} (eq. reference; particle velocities sqrt(T) c_i + u, eq. vi,
 // with T_L = 1).  A group of GS lanes (GS = the power of two >= Q) owns one
-// cell, one lane per population.  Per iteration of the predictor-corrector:
+// cell, one lane per population; a workgroup's cells are one x segment of a
+// row, and the 5-row neighbourhood of the segment (populations and frames,
+// boundary rules applied) is staged in LDS once.  Per iteration of the
+// predictor-corrector:
 // each lane finds its population's departure point x - v_i dt in the current
 // frame, and for each of the 3 x 3 collocation points around the nearest node
 // transfers that point's population vector from its own frame to the current
@@ -42,10 +45,15 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
-template <int N>
+template <int N, bool TH>
 struct PondTraits {
   static constexpr int Q = N * N;
+  static constexpr int NP = TH ? 2 * Q : Q;
   static constexpr int GS = Q <= 16 ? 16 : (Q <= 32 ? 32 : 64);
+  static constexpr int TW = 256 / GS;         // cells of a workgroup: one x segment of a row
+  static constexpr int SW = TW + 4;           // staged columns (two on each side)
+  static constexpr int SP = SW * 5;           // staged collocation points (five rows)
+  static constexpr int STRIDE = NP + 4;       // doubles per staged point: populations, frame
 };
 
 // the collocation point (x, y) (possibly outside the domain): the cell index
@@ -65,17 +73,42 @@ __global__ void __launch_bounds__(256)
 k_pond_step(const Tab *__restrict__ tab, PondArgs pa, const double *__restrict__ fin,
             const double *__restrict__ frin, double *__restrict__ fout, double *__restrict__ frout,
             int *__restrict__ flag, unsigned long long *__restrict__ itsum, int *__restrict__ itmax) {
-  using Tr = PondTraits<N>;
-  constexpr int Q = Tr::Q, GS = Tr::GS;
+  using Tr = PondTraits<N, TH>;
+  constexpr int Q = Tr::Q, NP = Tr::NP, GS = Tr::GS, TW = Tr::TW, SW = Tr::SW, SP = Tr::SP,
+                STRIDE = Tr::STRIDE;
+  // the workgroup's cells: x in [x0, x0 + TW) of row y; their collocation
+  // points lie within two cells, so the SW x 5 points around the segment
+  // (populations and frames, boundary rules applied) are staged in LDS once
+  __shared__ double stg[SP * STRIDE];
   const LatTab &L = tab->lat[0];
-  const long long k = (long long)blockIdx.x * (256 / GS) + threadIdx.x / GS;
-  const int li = threadIdx.x % GS;
-  const bool cell_ok = k < pa.ncell;
+  const int x0 = blockIdx.x * TW, y = blockIdx.y;
+  const double dt = tab->dt, cv = tab->cv;
+  for (int e = threadIdx.x; e < SP * STRIDE; e += 256) {
+    const int sp = e / STRIDE, m = e - sp * STRIDE;
+    const int sx = x0 - 2 + sp % SW, sy = y - 2 + sp / SW;
+    const long long q = pond_resolve(pa, sx, sy);
+    double v;
+    if (q >= 0) {
+      v = m < NP ? fin[(long long)m * pa.ncell + q] : frin[(long long)(m - NP) * pa.ncell + q];
+    } else {
+      // a fixed-equilibrium face state: rho W_i (and (cv - 1) T rho W_i) in its own frame
+      const double *st = pa.st[-1 - q];
+      const double Ts = TH ? st[4] : 1.0;
+      const int j = m % Q;
+      const double fj = st[0] * L.w[j % N] * L.w[j / N];
+      if (m < Q) v = fj;
+      else if (m < NP) v = (cv - 1.0) * Ts * fj;
+      else v = m - NP == 0 ? st[1] : (m - NP == 1 ? st[2] : (m - NP == 2 ? 0.0 : Ts));
+    }
+    stg[e] = v;
+  }
+  __syncthreads();
+  const int c = threadIdx.x / GS, li = threadIdx.x % GS;
+  const int px = x0 + c, py = y;
+  const bool cell_ok = px < pa.nx;
+  const long long k = (long long)py * pa.nx + (cell_ok ? px : 0);
   const bool act = cell_ok && li < Q;
   const int i = act ? li : 0, a = i % N, b = i / N;
-  const long long kk = cell_ok ? k : 0;
-  const int px = (int)(kk % pa.nx), py = (int)(kk / pa.nx);
-  const double dt = tab->dt, cv = tab->cv;
   // lattice nodes and the Lagrange denominators 1 / prod_{c != a} (x_a - x_c)
   double xn[N], den[N];
 #pragma unroll
@@ -84,11 +117,12 @@ k_pond_step(const Tab *__restrict__ tab, PondArgs pa, const double *__restrict__
   for (int m = 0; m < N; ++m) {
     double p = 1.0;
 #pragma unroll
-    for (int c = 0; c < N; ++c)
-      if (c != m) p *= xn[m] - xn[c];
+    for (int cc = 0; cc < N; ++cc)
+      if (cc != m) p *= xn[m] - xn[cc];
     den[m] = 1.0 / p;
   }
-  double ux = frin[kk], uy = frin[pa.ncell + kk], T = frin[3 * pa.ncell + kk];
+  const double *own = stg + ((2) * SW + (c + 2)) * STRIDE + NP;
+  double ux = own[0], uy = own[1], T = own[3];
   double ft = 0.0, gt = 0.0, rho = 0.0, Tn = 1.0;
   bool done = !cell_ok;
   int it = 0;
@@ -100,7 +134,11 @@ k_pond_step(const Tab *__restrict__ tab, PondArgs pa, const double *__restrict__
       const double vx = sT * xn[a] + ux, vy = sT * xn[b] + uy;
       const double dx = -vx * dt, dy = -vy * dt;
       const int nx0 = (int)floor(dx + 0.5), ny0 = (int)floor(dy + 0.5);
-      if (act && (nx0 < -1 || nx0 > 1 || ny0 < -1 || ny0 > 1)) atomicOr(flag, 1);
+      const bool out = nx0 < -1 || nx0 > 1 || ny0 < -1 || ny0 > 1;
+      if (act && out) atomicOr(flag, 1);
+      // (a lane whose stencil left the reach reads the nearest staged points
+      // instead; its cell is reported and its result is not used)
+      const int ox = out ? 0 : nx0, oy = out ? 0 : ny0;
       const double xi = dx - nx0, yi = dy - ny0;
       // 3-point Lagrange weights through -1, 0, 1
       const double wx[3] = {0.5 * xi * (xi - 1.0), 1.0 - xi * xi, 0.5 * xi * (xi + 1.0)};
@@ -108,19 +146,8 @@ k_pond_step(const Tab *__restrict__ tab, PondArgs pa, const double *__restrict__
       double accf = 0.0, accg = 0.0;
       for (int sy = -1; sy <= 1; ++sy)
         for (int sx = -1; sx <= 1; ++sx) {
-          const long long q = pond_resolve(pa, px + nx0 + sx, py + ny0 + sy);
-          double usx, usy, Ts, rf = 0.0;
-          if (q >= 0) {
-            usx = frin[q];
-            usy = frin[pa.ncell + q];
-            Ts = frin[3 * pa.ncell + q];
-          } else {
-            const double *st = pa.st[-1 - q];
-            rf = st[0];
-            usx = st[1];
-            usy = st[2];
-            Ts = TH ? st[4] : 1.0;
-          }
+          const double *pt = stg + ((oy + sy + 2) * SW + (c + 2 + ox + sx)) * STRIDE;
+          const double usx = pt[NP], usy = pt[NP + 1], Ts = pt[NP + 3];
           // the transfer's rows of this lane's nodes a (x) and b (y)
           const double sTs = sqrt(Ts);
           double gx[N], gy[N];
@@ -129,9 +156,9 @@ k_pond_step(const Tab *__restrict__ tab, PondArgs pa, const double *__restrict__
             const double zx = (sTs * xn[m] + usx - ux) * isT, zy = (sTs * xn[m] + usy - uy) * isT;
             double px_ = den[a], py_ = den[b];
 #pragma unroll
-            for (int c = 0; c < N; ++c) {
-              if (c != a) px_ *= zx - xn[c];
-              if (c != b) py_ *= zy - xn[c];
+            for (int cc = 0; cc < N; ++cc) {
+              if (cc != a) px_ *= zx - xn[cc];
+              if (cc != b) py_ *= zy - xn[cc];
             }
             gx[m] = px_;
             gy[m] = py_;
@@ -143,16 +170,8 @@ k_pond_step(const Tab *__restrict__ tab, PondArgs pa, const double *__restrict__
 #pragma unroll
             for (int ma = 0; ma < N; ++ma) {
               const int j = ma + N * mb;
-              double fj, gj = 0.0;
-              if (q >= 0) {
-                fj = fin[(long long)j * pa.ncell + q];
-                if (TH) gj = fin[(long long)(Q + j) * pa.ncell + q];
-              } else {
-                fj = rf * L.w[ma] * L.w[mb];
-                if (TH) gj = (cv - 1.0) * Ts * fj;
-              }
-              sf += gx[ma] * fj;
-              if (TH) sg += gx[ma] * gj;
+              sf += gx[ma] * pt[j];
+              if (TH) sg += gx[ma] * pt[Q + j];
             }
             vf += gy[mb] * sf;
             if (TH) vg += gy[mb] * sg;
@@ -304,10 +323,10 @@ int msl_pond_launch_macros(msl_ctx *c, double *rho, double *u, double *T) {
 
 template <int N, bool TH, bool QE>
 static int pond_step_n(msl_ctx *c) {
-  constexpr int GS = PondTraits<N>::GS;
+  constexpr int TW = PondTraits<N, TH>::TW;
   const PondArgs pa = pond_args(c);
-  const unsigned nb = (unsigned)((c->ncell + (256 / GS) - 1) / (256 / GS));
-  hipLaunchKernelGGL((k_pond_step<N, TH, QE>), dim3(nb), dim3(256), 0, c->stream, c->dtab, pa,
+  const dim3 grid((unsigned)((pa.nx + TW - 1) / TW), (unsigned)pa.ny);
+  hipLaunchKernelGGL((k_pond_step<N, TH, QE>), grid, dim3(256), 0, c->stream, c->dtab, pa,
                      c->pond_f[c->cur], c->pond_fr[c->cur], c->pond_f[c->cur ^ 1], c->pond_fr[c->cur ^ 1],
                      c->flag, c->pond_stats, (int *)(c->pond_stats + 1));
   return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
