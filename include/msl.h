@@ -169,6 +169,21 @@ int msl_get_mask(msl_ctx *ctx, uint8_t *mask);      /* device out */
  * Asynchronous unless check_every > 0; then MSL_EUNSTABLE reports a failed
  * sentinel (the state is left as is). */
 int msl_step(msl_ctx *ctx, int nsteps);
+/* How msl_step issues its launches (an execution choice; every mode gives the
+ * same bits).  mode 0: launch by launch.  mode 1 (the default): 2D contexts
+ * without the learned closure and without a conservation check run blocks of
+ * steps between criterion passes (crit_every steps when that is at most 64,
+ * else 16) as HIP graphs: the first block that starts from each of the two
+ * population buffers is captured (host and device memory for the instantiated
+ * graph, held until msl_destroy or a mode change) and replayed on the
+ * context's stream.  mode 2: as 1, with the two sets' stream-collide launches
+ * on parallel branches of the graph.  Criterion passes, steps that
+ * msl_profile times and the rest of a call shorter than a block run launch by
+ * launch.  A context whose high-order set runs over a compact tile list (large
+ * grids, where the host reads the list length) turns to mode 0 at its first
+ * capture.  Under a stream capture of the caller's own, use mode 0.  EINVAL
+ * for other modes. */
+int msl_set_graph(msl_ctx *ctx, int mode);
 int msl_get_step(const msl_ctx *ctx, long *step);   /* host out */
 
 /* rho, u[dim], T per cell from each cell's own populations (Sec. II.B

@@ -13,8 +13,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmsl.so")
-SOURCES = ["msl_capi.hip", "msl_aux.hip", "msl_stream.hip", "msl_stream_f64.hip", "msl_stream_f32.hip",
-           "msl_stream_f16.hip", "msl_stream_bf16.hip", "msl_mlp.hip", "msl_pond.hip"]
+SOURCES = ["msl_capi.hip", "msl_aux.hip", "msl_stream.hip", "msl_mlp.hip", "msl_pond.hip"] + [
+    f"msl_stream_{t}{th}.hip" for t in ("f64", "f32", "f16", "bf16") for th in ("", "_th")]
 ARCH = os.environ.get("MSL_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++20",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -549,15 +549,31 @@ int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_
     return MSL_EHIP;
   }
   if (msl_launch_classify(c) != MSL_OK) { delete c; return MSL_EHIP; }
+  // 2D two-set contexts without the learned closure: the stream-collide
+  // launches convert the band cells (lift in the low-order launch, projection
+  // in the high-order one)
+  c->fuse = cfg->lift_mode != MSL_LIFT_MLP && msl_stream_fusable(c);
+  // step graphs: one block per criterion period (at most 64 steps), else 16
+  c->gmode = 1;
+  c->gB = cfg->crit_kind && cfg->crit_every > 0 && c->nlat > 1 && cfg->crit_every <= 64 ? cfg->crit_every : 16;
   // the host copy of the tables must stay valid until the upload has run
   if (hipStreamSynchronize(c->stream) != hipSuccess) { delete c; return MSL_EHIP; }
   *out = c;
   return MSL_OK;
 }
 
+static void graph_release(msl_ctx *c);
+
 void msl_destroy(msl_ctx *c) {
   if (c && c->prof) msl_profile(c, 0);
   if (c && c->prof_nh) hipHostFree(c->prof_nh);
+  if (c) {
+    graph_release(c);
+    for (int k = 0; k < 2; ++k) {
+      if (c->gs[k]) hipStreamDestroy(c->gs[k]);
+      if (c->gev[k]) hipEventDestroy(c->gev[k]);
+    }
+  }
   delete c;
 }
 
@@ -769,6 +785,147 @@ int msl_pond_iterations(msl_ctx *c, double *mean, int *max) {
   return MSL_OK;
 }
 
+static bool crit_step(const msl_ctx *c, long step) {
+  return c->cfg.crit_kind && c->cfg.crit_every > 0 && c->nlat > 1 && step % c->cfg.crit_every == 0;
+}
+
+// the launches of one step after its criterion pass: ghost fill,
+// stream-collide of each set, band conversion (and the learned lift).  fork
+// (only while capturing): the high-order set's stream-collide launch goes on
+// a parallel branch, forked after the ghost fill and joined before the band
+// conversion
+// 3D with x periodic on both faces: the x ghosts are kept current by the
+// kernels that write cells (switching, stream-collide, band conversion and
+// learned lift store the images of the cells x < 2 and x >= nx - 2); set
+// before the step's criterion pass
+static void set_xmir(msl_ctx *c) {
+  c->xmir = c->D == 3 && c->cfg.bc[0] == MSL_BC_PERIODIC && c->cfg.bc[1] == MSL_BC_PERIODIC &&
+            c->geo.nx >= 2 * MSL_G;
+}
+
+static int plain_step(msl_ctx *c, bool fork) {
+  int rc;
+  set_xmir(c);
+  const int cur = c->cur, nxt = cur ^ 1;
+  char *bl = c->planes[0][cur], *bh = c->nlat > 1 ? c->planes[1][cur] : nullptr;
+  prof_begin(c);
+  rc = msl_launch_bc(c, bl, bh);
+  if (rc) { set_err(c, "ghost fill failed"); return rc; }
+  if ((rc = prof_end(c, 0, -1, 0.0, 0.0))) return rc;
+  fork = fork && c->nlat > 1;
+  if (fork) {
+    hipStream_t s0 = c->stream;
+    MSL_HIP(hipEventRecord(c->gev[0], s0));
+    MSL_HIP(hipStreamWaitEvent(c->gs[1], c->gev[0], 0));
+    c->stream = c->gs[1];
+    rc = msl_launch_stream_collide(c, 1, c->planes[1][cur], c->planes[1][nxt],
+                                   c->fuse ? c->planes[0][nxt] : nullptr);
+    c->stream = s0;
+    MSL_HIP(hipEventRecord(c->gev[1], c->gs[1]));
+    if (rc) {
+      // join the branch before leaving, so that the capture can be ended
+      MSL_HIP(hipStreamWaitEvent(s0, c->gev[1], 0));
+      set_err(c, "stream-collide launch failed");
+      return rc;
+    }
+  }
+  for (int l = 0; l < (fork ? 1 : c->nlat); ++l) {
+    // compulsory traffic: read and write every population plane of each native cell
+    const double bpc = 2.0 * c->Q[l] * (c->cfg.thermal ? 2 : 1) * (double)c->esz;
+    prof_begin(c);
+    rc = msl_launch_stream_collide(c, l, c->planes[l][cur], c->planes[l][nxt],
+                                   c->fuse ? c->planes[l ^ 1][nxt] : nullptr);
+    if (rc) { set_err(c, "stream-collide launch failed"); return rc; }
+    if ((rc = prof_end(c, 1 + l, l, bpc, 0.0))) return rc;
+  }
+  if (fork) MSL_HIP(hipStreamWaitEvent(c->stream, c->gev[1], 0));
+  if (c->nlat > 1 && !c->fuse) {
+    char *nl = c->planes[0][nxt], *nh = c->planes[1][nxt];
+    prof_begin(c);
+    rc = msl_launch_band_convert(c, nl, nh);
+    if (rc) { set_err(c, "band conversion failed"); return rc; }
+    if ((rc = prof_end(c, 3, -1, 0.0, 0.0))) return rc;
+    if (c->cfg.lift_mode == MSL_LIFT_MLP && c->mlp_on) {
+      prof_begin(c);
+      rc = msl_mlp_band_lift(c, nl, nh);
+      if (rc) { set_err(c, "learned lifting failed"); return rc; }
+      if ((rc = prof_end(c, 5, -1, 0.0, 0.0))) return rc;
+    }
+  }
+  c->xg_ok = c->xmir;
+  c->xmir = 0;
+  c->cur = nxt;
+  ++c->step;
+  return MSL_OK;
+}
+
+// Step graphs: contexts whose steps need no host work between launches (2D,
+// no learned closure, no conservation check); timed steps (msl_profile) and
+// criterion passes run outside the graphs.
+static bool graph_ok(const msl_ctx *c) {
+  return c->gmode > 0 && c->D == 2 && c->cfg.lift_mode != MSL_LIFT_MLP && c->cfg.check_every <= 0;
+}
+
+static void graph_release(msl_ctx *c) {
+  for (int p = 0; p < 2; ++p)
+    if (c->gx[p]) { hipGraphExecDestroy(c->gx[p]); c->gx[p] = nullptr; }
+}
+
+// capture gB plain steps starting from the current buffer `cur` into gx[cur];
+// the context's host state (buffer parity, step counter) is left unchanged.
+// A step that cannot be captured (a launch over a compact tile list, whose
+// length the host reads) switches the graphs off for this context.
+static int graph_capture(msl_ctx *c) {
+  if (!c->gs[0]) {
+    for (int k = 0; k < 2; ++k) {
+      MSL_HIP(hipStreamCreateWithFlags(&c->gs[k], hipStreamNonBlocking));
+      MSL_HIP(hipEventCreateWithFlags(&c->gev[k], hipEventDisableTiming));
+    }
+  }
+  const int cur0 = c->cur;
+  const long step0 = c->step;
+  hipStream_t s0 = c->stream;
+  c->stream = c->gs[0];
+  c->capturing = 1;
+  int rc = hipStreamBeginCapture(c->gs[0], hipStreamCaptureModeThreadLocal) == hipSuccess ? MSL_OK : MSL_EHIP;
+  for (int k = 0; k < c->gB && rc == MSL_OK; ++k) rc = plain_step(c, c->gmode == 2);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->gs[0], &g);
+  c->capturing = 0;
+  c->stream = s0;
+  c->cur = cur0;
+  c->step = step0;
+  c->xg_ok = 0;
+  if (rc == MSL_ESTATE) {
+    // not capturable: launches one by one from now on
+    if (g) hipGraphDestroy(g);
+    (void)hipGetLastError();
+    c->gmode = 0;
+    c->err[0] = 0;
+    return MSL_OK;
+  }
+  if (rc || e != hipSuccess || !g) {
+    if (g) hipGraphDestroy(g);
+    set_err(c, "step graph capture failed");
+    return rc ? rc : MSL_EHIP;
+  }
+  const hipError_t ei = hipGraphInstantiate(&c->gx[cur0], g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    c->gx[cur0] = nullptr;
+    set_err(c, "step graph instantiation failed");
+    return MSL_EHIP;
+  }
+  return MSL_OK;
+}
+
+int msl_set_graph(msl_ctx *c, int mode) {
+  if (!c || mode < 0 || mode > 2) return MSL_EINVAL;
+  if (mode != c->gmode) graph_release(c);
+  c->gmode = mode;
+  return MSL_OK;
+}
+
 int msl_step(msl_ctx *c, int nsteps) {
   if (!c || nsteps < 0) return MSL_EINVAL;
   if (!c->initialized) { set_err(c, "msl_step before msl_init"); return MSL_ESTATE; }
@@ -778,14 +935,10 @@ int msl_step(msl_ctx *c, int nsteps) {
   // rebuilt on first use
   c->xg_ok = 0;
   c->tl_ok = 0;
-  for (int s = 0; s < nsteps; ++s) {
+  for (int s = 0; s < nsteps;) {
     int rc;
-    // 3D with x periodic on both faces: the x ghosts are kept current by the
-    // kernels that write cells (switching, stream-collide, band conversion and
-    // learned lift store the images of the cells x < 2 and x >= nx - 2)
-    c->xmir = c->D == 3 && c->cfg.bc[0] == MSL_BC_PERIODIC && c->cfg.bc[1] == MSL_BC_PERIODIC &&
-              c->geo.nx >= 2 * MSL_G;
-    if (c->cfg.crit_kind && c->cfg.crit_every > 0 && c->nlat > 1 && c->step % c->cfg.crit_every == 0) {
+    set_xmir(c);
+    if (crit_step(c, c->step)) {
       prof_begin(c);
       rc = mask_step(c);
       if (rc) { set_err(c, "criterion / switching failed"); return rc; }
@@ -800,37 +953,22 @@ int msl_step(msl_ctx *c, int nsteps) {
         if ((rc = prof_end(c, 5, -1, 0.0, 0.0))) return rc;
       }
     }
-    const int cur = c->cur, nxt = cur ^ 1;
-    char *bl = c->planes[0][cur], *bh = c->nlat > 1 ? c->planes[1][cur] : nullptr;
-    prof_begin(c);
-    rc = msl_launch_bc(c, bl, bh);
-    if (rc) { set_err(c, "ghost fill failed"); return rc; }
-    if ((rc = prof_end(c, 0, -1, 0.0, 0.0))) return rc;
-    for (int l = 0; l < c->nlat; ++l) {
-      // compulsory traffic: read and write every population plane of each native cell
-      const double bpc = 2.0 * c->Q[l] * (c->cfg.thermal ? 2 : 1) * (double)c->esz;
-      prof_begin(c);
-      rc = msl_launch_stream_collide(c, l, c->planes[l][cur], c->planes[l][nxt]);
-      if (rc) { set_err(c, "stream-collide launch failed"); return rc; }
-      if ((rc = prof_end(c, 1 + l, l, bpc, 0.0))) return rc;
-    }
-    if (c->nlat > 1) {
-      char *nl = c->planes[0][nxt], *nh = c->planes[1][nxt];
-      prof_begin(c);
-      rc = msl_launch_band_convert(c, nl, nh);
-      if (rc) { set_err(c, "band conversion failed"); return rc; }
-      if ((rc = prof_end(c, 3, -1, 0.0, 0.0))) return rc;
-      if (c->cfg.lift_mode == MSL_LIFT_MLP && c->mlp_on) {
-        prof_begin(c);
-        rc = msl_mlp_band_lift(c, nl, nh);
-        if (rc) { set_err(c, "learned lifting failed"); return rc; }
-        if ((rc = prof_end(c, 5, -1, 0.0, 0.0))) return rc;
+    if (graph_ok(c) && nsteps - s >= c->gB) {
+      // a whole block: no timed step and no criterion pass after its first step
+      bool block = true;
+      for (int k = 0; k < c->gB && block; ++k)
+        block = !(c->prof && (c->step + k) % c->prof == 0) && (k == 0 || !crit_step(c, c->step + k));
+      if (block && !c->gx[c->cur] && (rc = graph_capture(c))) return rc;
+      if (block && c->gx[c->cur]) {
+        MSL_HIP(hipGraphLaunch(c->gx[c->cur], c->stream));
+        c->cur ^= c->gB & 1;
+        c->step += c->gB;
+        s += c->gB;
+        continue;
       }
     }
-    c->xg_ok = c->xmir;
-    c->xmir = 0;
-    c->cur = nxt;
-    ++c->step;
+    if ((rc = plain_step(c, false))) return rc;
+    ++s;
     if (c->cfg.check_every > 0 && c->step % c->cfg.check_every == 0) {
       double out[5];
       rc = msl_conservation(c, out);

@@ -194,10 +194,26 @@ struct msl_ctx {
   double pstat[MSL_PROF_K][4];
   int *prof_nh;           // pinned host ring of high-order cell counts, written by the GPU
   long long nsnap;
+  // step graphs (2D): blocks of gB steps without a criterion pass, captured
+  // once per parity of the current buffer at the block's start and replayed.
+  // gmode 0: launches one by one; 1: one graph of the launches in stream
+  // order; 2: the same with the two sets' stream-collide launches on
+  // parallel branches.  capturing: a capture of this context is under way
+  // (paths that need the host inside a step refuse it).
+  int gmode, gB, capturing;
+  // the stream-collide launches convert the band cells themselves (no band
+  // conversion launch in a step)
+  int fuse;
+  hipStream_t gs[2];
+  hipEvent_t gev[2];
+  hipGraphExec_t gx[2];
 };
 
 // launch helpers implemented in the .hip files
-int msl_launch_stream_collide(msl_ctx *c, int lat, const char *in, char *out);
+// oth: the other set's new planes, written at this set's band cells (2D
+// two-set contexts where msl_stream_fusable holds); nullptr: no conversion
+int msl_launch_stream_collide(msl_ctx *c, int lat, const char *in, char *out, char *oth);
+int msl_stream_fusable(const msl_ctx *c);
 int msl_launch_tile_list(msl_ctx *c, int lat, int rows_per_tile, int planes_per_tile);
 int msl_launch_bc(msl_ctx *c, char *buf_low, char *buf_high);
 int msl_launch_bc_fixed(msl_ctx *c);

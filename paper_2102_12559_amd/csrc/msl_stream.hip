@@ -1,15 +1,38 @@
 // msl_stream.hip -- storage-precision dispatch of the stream-and-collide kernels
 #include "msl_internal.hpp"
 
-template <typename S>
-int msl_launch_store(msl_ctx *c, int lat, const char *in, char *out);
+template <typename S, bool TH>
+int msl_launch_store_th(msl_ctx *c, int lat, const char *in, char *out, char *oth);
+template <typename S, bool TH>
+int msl_fusable_th(const msl_ctx *c);
 
-int msl_launch_stream_collide(msl_ctx *c, int lat, const char *in, char *out) {
+template <typename S>
+static int store_s(msl_ctx *c, int lat, const char *in, char *out, char *oth) {
+  return c->cfg.thermal ? msl_launch_store_th<S, true>(c, lat, in, out, oth)
+                        : msl_launch_store_th<S, false>(c, lat, in, out, oth);
+}
+
+int msl_launch_stream_collide(msl_ctx *c, int lat, const char *in, char *out, char *oth) {
   switch (c->cfg.store) {
-    case MSL_FP64: return msl_launch_store<double>(c, lat, in, out);
-    case MSL_FP32: return msl_launch_store<float>(c, lat, in, out);
-    case MSL_FP16_DEV: return msl_launch_store<_Float16>(c, lat, in, out);
-    case MSL_BF16_DEV: return msl_launch_store<bf16_t>(c, lat, in, out);
+    case MSL_FP64: return store_s<double>(c, lat, in, out, oth);
+    case MSL_FP32: return store_s<float>(c, lat, in, out, oth);
+    case MSL_FP16_DEV: return store_s<_Float16>(c, lat, in, out, oth);
+    case MSL_BF16_DEV: return store_s<bf16_t>(c, lat, in, out, oth);
   }
   return MSL_EINVAL;
+}
+
+template <typename S>
+static int fusable_s(const msl_ctx *c) {
+  return c->cfg.thermal ? msl_fusable_th<S, true>(c) : msl_fusable_th<S, false>(c);
+}
+
+int msl_stream_fusable(const msl_ctx *c) {
+  switch (c->cfg.store) {
+    case MSL_FP64: return fusable_s<double>(c);
+    case MSL_FP32: return fusable_s<float>(c);
+    case MSL_FP16_DEV: return fusable_s<_Float16>(c);
+    case MSL_BF16_DEV: return fusable_s<bf16_t>(c);
+  }
+  return 0;
 }

@@ -261,67 +261,95 @@ k_sc2d(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in, S 
   collide_store<S, TH, N, 2, R, NP, QE>(tab, lat, g, ft, out, cls, x0 + tx, y0 + ty * R, 0, 1, 0);
 }
 
+// 2D, every plane resident in LDS (k_sc2d_res); NO > 0: the launch also
+// converts its band cells into the other set's planes `oth` (NO nodes per axis)
+template <typename S, bool TH, int N, bool QE, int NO>
+static int launch_sc2(msl_ctx *c, int lat, const char *in, char *out, char *oth) {
+  const Geo &g = c->geo;
+  dim3 block(256);
+  S *os = (S *)oth;
+  // non-temporal stores for FP32 / FP64 D2Q9 planes when the set's buffer
+  // exceeds the 256 MB last-level cache
+  const int nt = N == 3 && sizeof(S) >= 4 &&
+                 (double)g.plane * sizeof(S) * c->Q[lat] * (c->cfg.thermal ? 2 : 1) > 256.0 * (1 << 20);
+  const long long tiles8 = (long long)((g.nx + MSL_TX - 1) / MSL_TX) * ((g.ny + 7) / 8);
+  bool small = false;
+  if constexpr (N == 3) {
+    // D2Q9 on a grid of fewer than 8 tiles of 8 rows per CU: 4-row tiles,
+    // twice as many workgroups
+    using T2 = SC2Traits<S, TH, N, true>;
+    static_assert(T2::fits && T2::TY == 4, "4-row D2Q9 tile");
+    small = tiles8 < 2048;
+    if (small) {
+      dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + T2::TY - 1) / T2::TY);
+      hipLaunchKernelGGL((k_sc2d_res<S, TH, N, true, false, QE, NO>), grid, block, 0, c->stream, c->dtab, lat, g,
+                         (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, nt, nullptr, nullptr, os);
+    }
+  }
+  if constexpr (N > 3 && NO < N) {
+    using T2 = SC2Traits<S, TH, N>;
+    const long long tiles = (long long)g.ntx * ((g.ny + T2::TY - 1) / T2::TY);
+    const long long fit = 256LL * (T2::WGS < 1 ? 1 : T2::WGS);
+    if (!small && lat != 0 && tiles > 4 * fit) {
+      // the high-order set on a large grid: one workgroup per live tile of
+      // the compact list, whose length is read back (one stream
+      // synchronisation each time the tile flags change, i.e. once per
+      // criterion pass); smaller grids launch the whole tile grid, where
+      // tiles without cells of the set exit at once
+      if (c->capturing) return MSL_ESTATE;   // the list length is read by the host
+      if (!c->tl_ok) {
+        if (msl_launch_tile_list(c, lat, T2::R, 1)) return MSL_EHIP;
+        int n = 0;
+        if (hipMemcpyAsync(&n, c->tcount, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+          return MSL_EHIP;
+        c->tl_n = n;
+        c->tl_ok = 1;
+      }
+      if (c->tl_n == 0) return MSL_OK;
+      dim3 grid((unsigned)c->tl_n);
+      hipLaunchKernelGGL((k_sc2d_res<S, TH, N, false, true, QE, NO>), grid, block, 0, c->stream, c->dtab, lat,
+                         g, (const S *)in, (S *)out, c->cls, c->tflag, 0, nt, c->tlist, c->tcount, os);
+      return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
+    }
+  }
+  if (!small) {
+    using T2 = SC2Traits<S, TH, N>;
+    dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + T2::TY - 1) / T2::TY);
+    hipLaunchKernelGGL((k_sc2d_res<S, TH, N, false, false, QE, NO>), grid, block, 0, c->stream, c->dtab, lat, g,
+                       (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, nt, nullptr, nullptr, os);
+  }
+  return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
+}
+
+// whether the launches of set `lat` can convert its band cells themselves
+// (2D kernels with every plane resident in LDS)
+template <typename S, bool TH, int N>
+static bool fusable_n(int D) {
+  return D == 2 && SC2Traits<S, TH, N>::fits;
+}
+
 template <typename S, bool TH, int N, int D, bool QE = false>
-static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
+static int launch_one(msl_ctx *c, int lat, const char *in, char *out, char *oth) {
   using Tr = SCTraits<S, TH, N, D>;
   const Geo &g = c->geo;
   dim3 block(256);
   if constexpr (D == 2 && SC2Traits<S, TH, N>::fits) {
-    // every plane resident in LDS; non-temporal stores for FP32 / FP64 D2Q9
-    // planes when the set's buffer exceeds the 256 MB last-level cache
-    const int nt = N == 3 && sizeof(S) >= 4 &&
-                   (double)g.plane * sizeof(S) * c->Q[lat] * (c->cfg.thermal ? 2 : 1) > 256.0 * (1 << 20);
-    const long long tiles8 = (long long)((g.nx + MSL_TX - 1) / MSL_TX) * ((g.ny + 7) / 8);
-    bool small = false;
-    if constexpr (N == 3) {
-      // D2Q9 on a grid of fewer than 8 tiles of 8 rows per CU: 4-row tiles,
-      // twice as many workgroups
-      using T2 = SC2Traits<S, TH, N, true>;
-      static_assert(T2::fits && T2::TY == 4, "4-row D2Q9 tile");
-      small = tiles8 < 2048;
-      if (small) {
-        dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + T2::TY - 1) / T2::TY);
-        hipLaunchKernelGGL((k_sc2d_res<S, TH, N, true, false, QE>), grid, block, 0, c->stream, c->dtab, lat, g,
-                           (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, nt, nullptr, nullptr);
-      }
+    switch (oth ? c->htab.lat[lat ^ 1].n : 0) {
+      case 0: return launch_sc2<S, TH, N, QE, 0>(c, lat, in, out, nullptr);
+      case 3: if constexpr (N != 3) return launch_sc2<S, TH, N, QE, 3>(c, lat, in, out, oth); break;
+      case 4: if constexpr (N != 4) return launch_sc2<S, TH, N, QE, 4>(c, lat, in, out, oth); break;
+      case 5: if constexpr (N != 5) return launch_sc2<S, TH, N, QE, 5>(c, lat, in, out, oth); break;
+      case 6: if constexpr (N != 6) return launch_sc2<S, TH, N, QE, 6>(c, lat, in, out, oth); break;
     }
-    if constexpr (N > 3) {
-      using T2 = SC2Traits<S, TH, N>;
-      const long long tiles = (long long)g.ntx * ((g.ny + T2::TY - 1) / T2::TY);
-      const long long fit = 256LL * (T2::WGS < 1 ? 1 : T2::WGS);
-      if (!small && lat != 0 && tiles > 4 * fit) {
-        // the high-order set on a large grid: one workgroup per live tile of
-        // the compact list, whose length is read back (one stream
-        // synchronisation each time the tile flags change, i.e. once per
-        // criterion pass); smaller grids launch the whole tile grid, where
-        // tiles without cells of the set exit at once
-        if (!c->tl_ok) {
-          if (msl_launch_tile_list(c, lat, T2::R, 1)) return MSL_EHIP;
-          int n = 0;
-          if (hipMemcpyAsync(&n, c->tcount, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-              hipStreamSynchronize(c->stream) != hipSuccess)
-            return MSL_EHIP;
-          c->tl_n = n;
-          c->tl_ok = 1;
-        }
-        if (c->tl_n == 0) return MSL_OK;
-        dim3 grid((unsigned)c->tl_n);
-        hipLaunchKernelGGL((k_sc2d_res<S, TH, N, false, true, QE>), grid, block, 0, c->stream, c->dtab, lat,
-                           g, (const S *)in, (S *)out, c->cls, c->tflag, 0, nt, c->tlist, c->tcount);
-        return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
-      }
-    }
-    if (!small) {
-      using T2 = SC2Traits<S, TH, N>;
-      dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + T2::TY - 1) / T2::TY);
-      hipLaunchKernelGGL((k_sc2d_res<S, TH, N, false, false, QE>), grid, block, 0, c->stream, c->dtab, lat, g,
-                         (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, nt, nullptr, nullptr);
-    }
+    return MSL_EINVAL;
   } else if constexpr (D == 2) {
+    if (oth) return MSL_EINVAL;
     dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + MSL_MTY * Tr::R - 1) / (MSL_MTY * Tr::R));
     hipLaunchKernelGGL((k_sc2d<S, TH, N, QE>), grid, block, 0, c->stream, c->dtab, lat, g,
                        (const S *)in, (S *)out, c->cls, c->tflag);
   } else {
+    if (oth) return MSL_EINVAL;
     if constexpr (SC3ZTraits<S, TH, N>::fits) {
       // 3D: columns of 64 x 4 x ZC cells walked along z; the high-order set
       // of a large grid runs over the compact list of its live columns
@@ -331,7 +359,8 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
         const long long tiles = (long long)g.ntx * g.nty * ncz;
         const long long fit = 256LL * ((160 * 1024) / T3::LDS_BYTES);
         if (lat != 0 && tiles > 4 * fit) {
-          if (!c->tl_ok) {
+          if (c->capturing) return MSL_ESTATE;   // the list length is read by the host
+        if (!c->tl_ok) {
             if (msl_launch_tile_list(c, lat, 1, T3::ZC)) return MSL_EHIP;
             int n = 0;
             if (hipMemcpyAsync(&n, c->tcount, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
@@ -360,6 +389,7 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
     const long long fit = 256LL * ((160 * 1024) / T3::LDS_BYTES);
     {
       if (lat != 0 && tiles > 4 * fit) {
+        if (c->capturing) return MSL_ESTATE;   // the list length is read by the host
         if (!c->tl_ok) {
           if (msl_launch_tile_list(c, lat, 1, T3::RZ)) return MSL_EHIP;
           int n = 0;
@@ -384,34 +414,53 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out) {
 }
 
 template <typename S, bool TH>
-static int launch_n(msl_ctx *c, int lat, const char *in, char *out) {
+static int launch_n(msl_ctx *c, int lat, const char *in, char *out, char *oth) {
   const int n = c->htab.lat[lat].n;
   if (c->D == 2) {
     if (c->htab.qe) {
       switch (n) {
-        case 3: return launch_one<S, TH, 3, 2, true>(c, lat, in, out);
-        case 4: return launch_one<S, TH, 4, 2, true>(c, lat, in, out);
-        case 5: return launch_one<S, TH, 5, 2, true>(c, lat, in, out);
-        case 6: return launch_one<S, TH, 6, 2, true>(c, lat, in, out);
+        case 3: return launch_one<S, TH, 3, 2, true>(c, lat, in, out, oth);
+        case 4: return launch_one<S, TH, 4, 2, true>(c, lat, in, out, oth);
+        case 5: return launch_one<S, TH, 5, 2, true>(c, lat, in, out, oth);
+        case 6: return launch_one<S, TH, 6, 2, true>(c, lat, in, out, oth);
       }
       return MSL_EINVAL;
     }
     switch (n) {
-      case 3: return launch_one<S, TH, 3, 2>(c, lat, in, out);
-      case 4: return launch_one<S, TH, 4, 2>(c, lat, in, out);
-      case 5: return launch_one<S, TH, 5, 2>(c, lat, in, out);
-      case 6: return launch_one<S, TH, 6, 2>(c, lat, in, out);
+      case 3: return launch_one<S, TH, 3, 2>(c, lat, in, out, oth);
+      case 4: return launch_one<S, TH, 4, 2>(c, lat, in, out, oth);
+      case 5: return launch_one<S, TH, 5, 2>(c, lat, in, out, oth);
+      case 6: return launch_one<S, TH, 6, 2>(c, lat, in, out, oth);
     }
   } else {
     switch (n) {
-      case 3: return launch_one<S, TH, 3, 3>(c, lat, in, out);
-      case 4: return launch_one<S, TH, 4, 3>(c, lat, in, out);
+      case 3: return launch_one<S, TH, 3, 3>(c, lat, in, out, oth);
+      case 4: return launch_one<S, TH, 4, 3>(c, lat, in, out, oth);
     }
   }
   return MSL_EINVAL;
 }
 
-template <typename S>
-int msl_launch_store(msl_ctx *c, int lat, const char *in, char *out) {
-  return c->cfg.thermal ? launch_n<S, true>(c, lat, in, out) : launch_n<S, false>(c, lat, in, out);
+// stream-and-collide of set `lat` for one storage type and energy variant;
+// oth: the other set's new planes when the launch converts its band cells
+template <typename S, bool TH>
+int msl_launch_store_th(msl_ctx *c, int lat, const char *in, char *out, char *oth) {
+  return launch_n<S, TH>(c, lat, in, out, oth);
+}
+
+// both sets of a 2D two-set context run the kernel that converts band cells
+template <typename S, bool TH>
+int msl_fusable_th(const msl_ctx *c) {
+  if (c->D != 2 || c->nlat < 2) return 0;
+  for (int l = 0; l < 2; ++l) {
+    bool ok = false;
+    switch (c->htab.lat[l].n) {
+      case 3: ok = fusable_n<S, TH, 3>(2); break;
+      case 4: ok = fusable_n<S, TH, 4>(2); break;
+      case 5: ok = fusable_n<S, TH, 5>(2); break;
+      case 6: ok = fusable_n<S, TH, 6>(2); break;
+    }
+    if (!ok) return 0;
+  }
+  return 1;
 }

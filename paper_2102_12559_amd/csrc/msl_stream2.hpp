@@ -87,12 +87,17 @@ __device__ __forceinline__ float lds_elem<bf16_t>(const char *p) {
 template <typename S>
 __device__ __forceinline__ double lds_elem_d(const char *p) { return *(const double *)p; }
 
-template <typename S, bool TH, int N, bool SMALL, bool LIST = false, bool QE = false>
+// NO > 0: the other velocity set of a two-set run has NO nodes per axis, and
+// the kernel also converts its band cells (bit 1 of the class byte) into that
+// set, in the new buffer `oth` of the other set's planes: the low-order
+// launch lifts (NO > N), the high-order launch projects (NO < N), each from
+// the post-collision populations it holds in registers.
+template <typename S, bool TH, int N, bool SMALL, bool LIST = false, bool QE = false, int NO = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SC2Traits<S, TH, N, SMALL>::WAVES)))
 k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
            S *__restrict__ out, const uint8_t *__restrict__ cls,
            const uint8_t *__restrict__ tflag, int remap, int nt, const int *__restrict__ tlist,
-           const int *__restrict__ tcount) {
+           const int *__restrict__ tcount, S *__restrict__ oth) {
   using Tr = SC2Traits<S, TH, N, SMALL>;
   using T = typename Tr::T;
   using C = typename Tr::C;
@@ -141,13 +146,16 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
             rs, (msl_lds_t *)(sm + K * PD + 256 * (w + 4 * m)), 16, (int)voff[m], soff, 0, 0);
   };
   msl_for_planes<NP>(issue);
-  // my cells: inside the domain and of this velocity set
-  bool mine[R];
+  // my cells: inside the domain and of this velocity set; band: also
+  // converted into the other set
+  bool mine[R], band[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int x = x0 + tx, y = y0 + ty * R + r;
     const bool inside = x < g.nx && y < g.ny;
-    mine[r] = inside && (cls[inside ? (long long)y * g.nx + x : 0] & 1) == lat;
+    const uint8_t cb = cls[inside ? (long long)y * g.nx + x : 0];
+    mine[r] = inside && (cb & 1) == lat;
+    band[r] = NO > 0 && mine[r] && (cb & 2);
   }
   __syncthreads();   // the compiler waits for the loads before the barrier
 
@@ -296,6 +304,27 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
       qb[r][1] *= dom[r] * cg;
     }
   }
+  // band conversion state: lifting keeps the non-equilibrium part of every
+  // post-collision population (f - f^eq, g - gfac T f^eq); projection
+  // accumulates (P x P) f of each output node in FP64 while the populations
+  // are stored (only in waves that hold a band cell)
+  constexpr bool LIFT = NO > N, PROJ = NO > 0 && NO < N;
+  constexpr int QO = NO * NO;
+  C nq[LIFT ? NP : 1][R];
+  double acc[PROJ ? (TH ? 2 : 1) * QO : 1][R];
+  bool wband = false;
+  if constexpr (NO > 0) {
+    bool b = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) b |= band[r];
+    wband = __any(b);
+  }
+  if constexpr (PROJ) {
+#pragma unroll
+    for (int k = 0; k < (TH ? 2 : 1) * QO; ++k)
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[k][r] = 0.0;
+  }
   // 4. collide and store
   unsigned soff_cell[R];
 #pragma unroll
@@ -325,6 +354,17 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
         else
           vo += qb[r][0] * Ax[r][1][a] * Ay[r][0][b] + qb[r][1] * Ax[r][0][a] * Ay[r][1][b];
       }
+      if constexpr (LIFT) nq[K][r] = vo - (K < Q ? feq : gf[r] * feq);
+      if constexpr (PROJ) {
+        if (wband) {
+          const double vd = (double)vo;
+#pragma unroll
+          for (int bp = 0; bp < NO; ++bp)
+#pragma unroll
+            for (int ap = 0; ap < NO; ++ap)
+              acc[(K < Q ? 0 : QO) + ap + NO * bp][r] += tab->P[ap][a] * tab->P[bp][b] * vd;
+        }
+      }
       const C o = T::dev ? vo * isc - C(1) : vo;
       const S sv = T::store(o);
       // nt: non-temporal stores (cache policy bit 1) when the output buffer is
@@ -344,6 +384,62 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     }
   };
   msl_for_planes<NP>(pass2);
+  // 5. band cells into the other set (Sec. III.B-C, App. C): lifting
+  //    f_Q = f^eq_Q + (Kx x Ky)(f_q - f^eq_q) at the cell's rho, u, T (the
+  //    collision conserves them), projection f_q = (P x P) f_Q
+  if constexpr (NO > 0) {
+    if (wband) {
+      const LatTab &LO = tab->lat[LIFT ? 1 : 0];
+      const double gs = tab->gfac * tab->T0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (!band[r]) continue;
+        const long long off = g.idx(x0 + tx, y0 + ty * R + r, 0);
+        if constexpr (LIFT) {
+          const double rd = (double)rho[r], ux = (double)jx[r] / rd, uy = (double)jy[r] / rd;
+          double Tm = 1.0;
+          if (TH) Tm = ((double)en[r] - 0.5 * rd * (ux * ux + uy * uy)) / (tab->cv * rd);
+          double PX[NO], PY[NO];
+          eq_axis<double, NO>(LO, (ux - LO.ur[0]) * LO.isq, Tm * LO.iTr, PX);
+          eq_axis<double, NO>(LO, (uy - LO.ur[1]) * LO.isq, Tm * LO.iTr, PY);
+          const bool herm = tab->lift_mode == MSL_LIFT_GRAD_HERMITE;
+          const double (*Kx)[MSL_MAXN] = herm ? tab->KH : tab->K[0];
+          const double (*Ky)[MSL_MAXN] = herm ? tab->KH : tab->K[1];
+#pragma unroll
+          for (int h = 0; h < (TH ? 2 : 1); ++h) {
+            const double sg = h ? tab->gfac * Tm : 1.0;
+#pragma unroll
+            for (int a = 0; a < NO; ++a) {
+              double t[N];
+#pragma unroll
+              for (int bp = 0; bp < N; ++bp) {
+                double sum = 0.0;
+#pragma unroll
+                for (int ap = 0; ap < N; ++ap) sum += Kx[a][ap] * (double)nq[h * Q + ap + N * bp][r];
+                t[bp] = sum;
+              }
+#pragma unroll
+              for (int b = 0; b < NO; ++b) {
+                double cr = 0.0;
+#pragma unroll
+                for (int bp = 0; bp < N; ++bp) cr += Ky[b][bp] * t[bp];
+                const int i = a + NO * b;
+                store_pop<S>(oth + (long long)(h * QO + i) * g.plane, off, sg * rd * PX[a] * PY[b] + cr,
+                             h ? gs * LO.sc[i] : LO.sc[i]);
+              }
+            }
+          }
+        } else {
+#pragma unroll
+          for (int h = 0; h < (TH ? 2 : 1); ++h)
+#pragma unroll
+            for (int i = 0; i < QO; ++i)
+              store_pop<S>(oth + (long long)(h * QO + i) * g.plane, off, acc[h * QO + i][r],
+                           h ? gs * LO.sc[i] : LO.sc[i]);
+        }
+      }
+    }
+  }
   };
   if constexpr (LIST) {
     // sparse launch: one workgroup per entry of the compact list of live

@@ -1,4 +1,5 @@
-// msl_stream_bf16.hip -- stream-and-collide instantiations for bf16_t storage
+// msl_stream_bf16.hip -- stream-and-collide instantiations: bf16_t storage, athermal
 #include "msl_stream.hpp"
 
-template int msl_launch_store<bf16_t>(msl_ctx *c, int lat, const char *in, char *out);
+template int msl_launch_store_th<bf16_t, false>(msl_ctx *c, int lat, const char *in, char *out, char *oth);
+template int msl_fusable_th<bf16_t, false>(const msl_ctx *c);

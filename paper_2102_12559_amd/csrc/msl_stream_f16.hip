@@ -1,4 +1,5 @@
-// msl_stream_f16.hip -- stream-and-collide instantiations for _Float16 storage
+// msl_stream_f16.hip -- stream-and-collide instantiations: _Float16 storage, athermal
 #include "msl_stream.hpp"
 
-template int msl_launch_store<_Float16>(msl_ctx *c, int lat, const char *in, char *out);
+template int msl_launch_store_th<_Float16, false>(msl_ctx *c, int lat, const char *in, char *out, char *oth);
+template int msl_fusable_th<_Float16, false>(const msl_ctx *c);

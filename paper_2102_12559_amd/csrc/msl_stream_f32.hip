@@ -1,4 +1,5 @@
-// msl_stream_f32.hip -- stream-and-collide instantiations for float storage
+// msl_stream_f32.hip -- stream-and-collide instantiations: float storage, athermal
 #include "msl_stream.hpp"
 
-template int msl_launch_store<float>(msl_ctx *c, int lat, const char *in, char *out);
+template int msl_launch_store_th<float, false>(msl_ctx *c, int lat, const char *in, char *out, char *oth);
+template int msl_fusable_th<float, false>(const msl_ctx *c);

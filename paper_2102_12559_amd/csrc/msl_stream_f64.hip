@@ -1,4 +1,5 @@
-// msl_stream_f64.hip -- stream-and-collide instantiations for double storage
+// msl_stream_f64.hip -- stream-and-collide instantiations: double storage, athermal
 #include "msl_stream.hpp"
 
-template int msl_launch_store<double>(msl_ctx *c, int lat, const char *in, char *out);
+template int msl_launch_store_th<double, false>(msl_ctx *c, int lat, const char *in, char *out, char *oth);
+template int msl_fusable_th<double, false>(const msl_ctx *c);

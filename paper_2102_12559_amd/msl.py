@@ -58,7 +58,7 @@ SYMBOLS = [
     "msl_mlp_get_weights", "msl_mlp_train", "msl_mlp_grad", "msl_mlp_forward",
     "msl_mlp_get_flags", "msl_mlp_set_flags", "msl_num_check_tiles", "msl_profile",
     "msl_profile_read", "msl_device_copy", "msl_mlp_grad_noalloc", "msl_error_norms",
-    "msl_pond_frames", "msl_pond_iterations",
+    "msl_pond_frames", "msl_pond_iterations", "msl_set_graph",
 ]
 
 
@@ -81,6 +81,7 @@ def lib():
         L.msl_set_mask.argtypes = [vp, vp]
         L.msl_get_mask.argtypes = [vp, vp]
         L.msl_step.argtypes = [vp, C.c_int]
+        L.msl_set_graph.argtypes = [vp, C.c_int]
         L.msl_get_step.argtypes = [vp, C.POINTER(C.c_long)]
         L.msl_macros.argtypes = [vp, vp, vp, vp]
         L.msl_get_populations.argtypes = [vp, C.c_int, C.c_int, vp]
@@ -229,6 +230,11 @@ class Solver:
 
     def step(self, n=1):
         self._check(lib().msl_step(self._ctx, int(n)), "msl_step")
+
+    def set_graph(self, mode):
+        """0: launch by launch; 1: blocks of steps as HIP graphs (default); 2: as 1
+        with the two sets' stream-collide launches on parallel graph branches."""
+        self._check(lib().msl_set_graph(self._ctx, int(mode)), "msl_set_graph")
 
     @property
     def step_count(self):

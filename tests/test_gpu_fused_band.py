@@ -1,0 +1,145 @@
+"""Band conversion inside the stream-collide launches (2D two-set contexts)
+and the graph launch modes of msl_step.
+
+The low-order launch lifts its band cells into the high-order set and the
+high-order launch projects its band cells into the low-order set (Sec. III.B-C,
+App. C), from the post-collision populations they hold.  Each set's values at
+the band cells of the other order are compared with the oracle, which lifts or
+projects those cells' native state when asked for them.  The graph modes
+replay the same launches: the state after a run must match launch-by-launch
+execution bit for bit.
+"""
+import numpy as np
+import pytest
+
+from paper_2102_12559_amd import inputs
+from tests.gpu_util import compare_pops, run_pair, say, weights
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2102_12559_amd import msl
+    msl.lib()
+
+
+def band_cells(mask, periodic):
+    """Cells with a cell of the other order within the 3-point stencil's reach
+    (2 cells along each axis, a 5 x 5 box); periodic per axis (x, y)."""
+    m = mask.reshape(mask.shape[-2:]).astype(np.int8)
+    pad = [(2, 2), (2, 2)]
+    p = m
+    for ax, per in ((1, periodic[0]), (0, periodic[1])):
+        w = [(0, 0), (0, 0)]
+        w[ax] = pad[ax]
+        p = np.pad(p, w, mode="wrap" if per else "edge")
+    ny, nx = m.shape
+    hi = np.zeros_like(m)
+    lo = np.ones_like(m)
+    for dy in range(5):
+        for dx in range(5):
+            v = p[dy:dy + ny, dx:dx + nx]
+            hi = np.maximum(hi, v)
+            lo = np.minimum(lo, v)
+    return ((m == 0) & (hi == 1)).reshape(-1), ((m == 1) & (lo == 0)).reshape(-1)
+
+
+def compare_band(s, o, tol, fg=0, periodic=(True, True), absolute=False):
+    gm = s.get_mask().cpu().numpy()
+    assert np.array_equal(gm.reshape(-1), o.get_mask().reshape(-1))
+    b0, b1 = band_cells(gm, periodic)
+    assert b0.any() and b1.any(), "no band cells"
+    worst = 0.0
+    for which, sel in ((1, b0), (0, b1)):
+        g = s.get_populations(which, fg).cpu().numpy()[:, sel]
+        r = o.get_pops(which, fg)[:, sel]
+        assert np.all(np.isfinite(g))
+        if absolute:
+            err = float(np.max(np.abs(g - r)) / np.max(np.abs(r)))
+        else:
+            n = s.cfg["n_low"] if which == 0 else s.cfg["n_high"]
+            W = weights(s.dim, n)[:, None]
+            err = float(np.max(np.abs(g - r) / np.maximum(np.abs(r), W * (1.0 if fg == 0 else 0.5))))
+        say(f"  set {which} fg {fg} at {int(sel.sum())} band cells of the other order: {err:.3e}")
+        worst = max(worst, err)
+    assert worst <= tol, f"band parity {worst:.3e} > {tol:.1e}"
+
+
+@pytest.mark.parametrize("nq,nQ", [(3, 4), (3, 6), (4, 5), (5, 6)])
+def test_band_values_fp64(nq, nQ):
+    nx, ny = 131, 45
+    cfg = inputs.base_config(nx=nx, ny=ny, n_low=nq, n_high=nQ, tau=0.65)
+    rho, u, T = inputs.smooth_random_flow(nx, ny, umax=0.3, seed=nq * 7 + nQ, drho=0.02)
+    mask = inputs.random_mask(nx, ny, frac=0.25, seed=nQ + 1, blob=7)
+    s, o = run_pair(cfg, rho, u, T, mask, 9, tag=f"band values {nq}/{nQ}")
+    compare_pops(s, o, 1e-12)
+    compare_band(s, o, 1e-12)
+
+
+def test_band_values_thermal_two_relaxation_fp64():
+    """Thermal f + g with the two-relaxation collision (tau2 != tau): both
+    population sets of the band, lifted and projected."""
+    nx, ny = 96, 40
+    cfg = inputs.base_config(nx=nx, ny=ny, n_low=3, n_high=4, tau=0.7, thermal=1, tau2=0.9)
+    rho, u, T = inputs.smooth_random_flow(nx, ny, umax=0.2, seed=21, drho=0.03, dT=0.05)
+    mask = inputs.random_mask(nx, ny, frac=0.3, seed=5, blob=6)
+    s, o = run_pair(cfg, rho, u, T, mask, 8, tag="band values thermal qe")
+    for fg in (0, 1):
+        compare_pops(s, o, 1e-12, fg=fg)
+        compare_band(s, o, 1e-12, fg=fg)
+
+
+def test_band_values_hermite_lift_open_faces_fp64():
+    """Hermite completion, zero-gradient x faces (no wrap of the band)."""
+    nx, ny = 70, 37
+    cfg = inputs.base_config(nx=nx, ny=ny, n_low=3, n_high=6, tau=0.7,
+                             lift_mode=inputs.LIFT_GRAD_HERMITE)
+    cfg["bc"] = [inputs.BC_OUTFLOW_ZG, inputs.BC_OUTFLOW_ZG, inputs.BC_PERIODIC, inputs.BC_PERIODIC,
+                 inputs.BC_PERIODIC, inputs.BC_PERIODIC]
+    rho, u, T = inputs.smooth_random_flow(nx, ny, umax=0.2, seed=9)
+    mask = inputs.random_mask(nx, ny, frac=0.3, seed=3, blob=5)
+    s, o = run_pair(cfg, rho, u, T, mask, 7, tag="band values hermite zg")
+    compare_pops(s, o, 1e-12)
+    compare_band(s, o, 1e-12, periodic=(False, True))
+
+
+def test_band_values_fp32():
+    nx, ny = 131, 45
+    cfg = inputs.base_config(nx=nx, ny=ny, n_low=3, n_high=6, tau=0.65, store=inputs.STORE_FP32)
+    rho, u, T = inputs.smooth_random_flow(nx, ny, umax=0.3, seed=2, drho=0.02)
+    mask = inputs.random_mask(nx, ny, frac=0.25, seed=4, blob=7)
+    s, o = run_pair(cfg, rho, u, T, mask, 9, oracle_cfg=dict(cfg, store=inputs.STORE_FP64),
+                    tag="band values fp32")
+    compare_band(s, o, 1e-5, absolute=True)
+
+
+def test_graph_modes_bit_identical():
+    """A jet with the Mach criterion every 5 steps: launch by launch, step
+    graphs, and graphs with parallel branches, over calls of uneven length
+    with sampled timing, end in the same bytes."""
+    from paper_2102_12559_amd import msl
+    w = inputs.jet_c2(nx=128, ny=64, slot_w=12, crit_every=5)
+    states = []
+    for mode in (0, 1, 2):
+        say(f"[case] graph mode {mode}: jet 128x64 fp32, calls of 7, 13, 20, 1, 19 steps")
+        s = msl.Solver(w["cfg"])
+        s.set_graph(mode)
+        s.set_mask(w["mask"])
+        s.init(w["rho"], w["u"], w["T"])
+        s.profile(True, every=7)
+        for n in (7, 13, 20, 1, 19):
+            s.step(n)
+        s.profile_read()
+        s.profile(False)
+        s.step(25)
+        s.torch.cuda.synchronize()
+        assert s.step_count == 85
+        assert int(s.get_mask().sum()) > 0
+        states.append(s.get_state())
+        s.close()
+    assert states[1] == states[0], "graph mode 1 differs from launch-by-launch stepping"
+    assert states[2] == states[0], "graph mode 2 differs from launch-by-launch stepping"
