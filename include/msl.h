@@ -170,7 +170,7 @@ int msl_get_mask(msl_ctx *ctx, uint8_t *mask);      /* device out */
  * sentinel (the state is left as is). */
 int msl_step(msl_ctx *ctx, int nsteps);
 /* How msl_step issues its launches (an execution choice; every mode gives the
- * same bits).  mode 0: launch by launch.  mode 1 (the default): 2D contexts
+ * same bits).  mode 0 (the default): launch by launch.  mode 1: 2D contexts
  * without the learned closure and without a conservation check run blocks of
  * steps between criterion passes (crit_every steps when that is at most 64,
  * else 16) as HIP graphs: the first block that starts from each of the two

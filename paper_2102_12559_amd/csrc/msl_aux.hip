@@ -972,6 +972,7 @@ int msl_launch_bc(msl_ctx *c, char *bl, char *bh) {
   }
   const dim3 blk(AUX_BLOCK);
   if (c->D == 2) {
+    if (c->zgm) return last_err();   // applied by the stream-collide launches
     long long tot = 0;
     for (int ax = 0; ax < 2; ++ax) tot += host_pass_cells(g, ax);
     if (copies(0) || copies(1))

@@ -552,9 +552,21 @@ int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_
   // 2D two-set contexts without the learned closure: the stream-collide
   // launches convert the band cells (lift in the low-order launch, projection
   // in the high-order one)
-  c->fuse = cfg->lift_mode != MSL_LIFT_MLP && msl_stream_fusable(c);
+  const int sc2 = cfg->lift_mode != MSL_LIFT_MLP && msl_stream_sc2_all(c);
+  c->fuse = sc2 && c->nlat == 2;
+  // 2D faces that are all zero-gradient or fixed: the zero-gradient ones are
+  // applied inside the stream-collide launches (the fixed ghosts are
+  // constant), so a step launches no ghost fill
+  if (sc2) {
+    int m = 0, ok = 1;
+    for (int f = 0; f < 4; ++f) {
+      if (cfg->bc[f] == MSL_BC_OUTFLOW_ZG) m |= 1 << f;
+      else if (cfg->bc[f] != MSL_BC_FIXED_EQ) ok = 0;
+    }
+    c->zgm = ok ? m : 0;
+  }
   // step graphs: one block per criterion period (at most 64 steps), else 16
-  c->gmode = 1;
+  c->gmode = 0;
   c->gB = cfg->crit_kind && cfg->crit_every > 0 && c->nlat > 1 && cfg->crit_every <= 64 ? cfg->crit_every : 16;
   // the host copy of the tables must stay valid until the upload has run
   if (hipStreamSynchronize(c->stream) != hipSuccess) { delete c; return MSL_EHIP; }

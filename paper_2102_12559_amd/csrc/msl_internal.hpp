@@ -204,6 +204,10 @@ struct msl_ctx {
   // the stream-collide launches convert the band cells themselves (no band
   // conversion launch in a step)
   int fuse;
+  // 2D zero-gradient faces applied by the stream-collide launches to their
+  // staged windows (bits: x low, x high, y low, y high); set when every face
+  // is zero-gradient or fixed, and then no ghost fill runs per step
+  int zgm;
   hipStream_t gs[2];
   hipEvent_t gev[2];
   hipGraphExec_t gx[2];
@@ -211,9 +215,11 @@ struct msl_ctx {
 
 // launch helpers implemented in the .hip files
 // oth: the other set's new planes, written at this set's band cells (2D
-// two-set contexts where msl_stream_fusable holds); nullptr: no conversion
+// two-set contexts where msl_stream_sc2_all holds); nullptr: no conversion
 int msl_launch_stream_collide(msl_ctx *c, int lat, const char *in, char *out, char *oth);
-int msl_stream_fusable(const msl_ctx *c);
+// every set of a 2D context runs the stream-collide kernel with all planes
+// resident in LDS
+int msl_stream_sc2_all(const msl_ctx *c);
 int msl_launch_tile_list(msl_ctx *c, int lat, int rows_per_tile, int planes_per_tile);
 int msl_launch_bc(msl_ctx *c, char *buf_low, char *buf_high);
 int msl_launch_bc_fixed(msl_ctx *c);

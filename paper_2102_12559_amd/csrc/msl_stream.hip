@@ -4,7 +4,7 @@
 template <typename S, bool TH>
 int msl_launch_store_th(msl_ctx *c, int lat, const char *in, char *out, char *oth);
 template <typename S, bool TH>
-int msl_fusable_th(const msl_ctx *c);
+int msl_sc2_all_th(const msl_ctx *c);
 
 template <typename S>
 static int store_s(msl_ctx *c, int lat, const char *in, char *out, char *oth) {
@@ -23,16 +23,16 @@ int msl_launch_stream_collide(msl_ctx *c, int lat, const char *in, char *out, ch
 }
 
 template <typename S>
-static int fusable_s(const msl_ctx *c) {
-  return c->cfg.thermal ? msl_fusable_th<S, true>(c) : msl_fusable_th<S, false>(c);
+static int sc2_all_s(const msl_ctx *c) {
+  return c->cfg.thermal ? msl_sc2_all_th<S, true>(c) : msl_sc2_all_th<S, false>(c);
 }
 
-int msl_stream_fusable(const msl_ctx *c) {
+int msl_stream_sc2_all(const msl_ctx *c) {
   switch (c->cfg.store) {
-    case MSL_FP64: return fusable_s<double>(c);
-    case MSL_FP32: return fusable_s<float>(c);
-    case MSL_FP16_DEV: return fusable_s<_Float16>(c);
-    case MSL_BF16_DEV: return fusable_s<bf16_t>(c);
+    case MSL_FP64: return sc2_all_s<double>(c);
+    case MSL_FP32: return sc2_all_s<float>(c);
+    case MSL_FP16_DEV: return sc2_all_s<_Float16>(c);
+    case MSL_BF16_DEV: return sc2_all_s<bf16_t>(c);
   }
   return 0;
 }

@@ -283,7 +283,7 @@ static int launch_sc2(msl_ctx *c, int lat, const char *in, char *out, char *oth)
     if (small) {
       dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + T2::TY - 1) / T2::TY);
       hipLaunchKernelGGL((k_sc2d_res<S, TH, N, true, false, QE, NO>), grid, block, 0, c->stream, c->dtab, lat, g,
-                         (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, nt, nullptr, nullptr, os);
+                         (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, nt, nullptr, nullptr, os, c->zgm);
     }
   }
   if constexpr (N > 3 && NO < N) {
@@ -309,7 +309,7 @@ static int launch_sc2(msl_ctx *c, int lat, const char *in, char *out, char *oth)
       if (c->tl_n == 0) return MSL_OK;
       dim3 grid((unsigned)c->tl_n);
       hipLaunchKernelGGL((k_sc2d_res<S, TH, N, false, true, QE, NO>), grid, block, 0, c->stream, c->dtab, lat,
-                         g, (const S *)in, (S *)out, c->cls, c->tflag, 0, nt, c->tlist, c->tcount, os);
+                         g, (const S *)in, (S *)out, c->cls, c->tflag, 0, nt, c->tlist, c->tcount, os, c->zgm);
       return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
     }
   }
@@ -317,7 +317,7 @@ static int launch_sc2(msl_ctx *c, int lat, const char *in, char *out, char *oth)
     using T2 = SC2Traits<S, TH, N>;
     dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + T2::TY - 1) / T2::TY);
     hipLaunchKernelGGL((k_sc2d_res<S, TH, N, false, false, QE, NO>), grid, block, 0, c->stream, c->dtab, lat, g,
-                       (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, nt, nullptr, nullptr, os);
+                       (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, nt, nullptr, nullptr, os, c->zgm);
   }
   return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
 }
@@ -448,11 +448,12 @@ int msl_launch_store_th(msl_ctx *c, int lat, const char *in, char *out, char *ot
   return launch_n<S, TH>(c, lat, in, out, oth);
 }
 
-// both sets of a 2D two-set context run the kernel that converts band cells
+// every set of a 2D context runs the kernel with all planes resident in LDS
+// (which can convert band cells and apply zero-gradient faces itself)
 template <typename S, bool TH>
-int msl_fusable_th(const msl_ctx *c) {
-  if (c->D != 2 || c->nlat < 2) return 0;
-  for (int l = 0; l < 2; ++l) {
+int msl_sc2_all_th(const msl_ctx *c) {
+  if (c->D != 2) return 0;
+  for (int l = 0; l < c->nlat; ++l) {
     bool ok = false;
     switch (c->htab.lat[l].n) {
       case 3: ok = fusable_n<S, TH, 3>(2); break;

@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SC2Tra
 k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
            S *__restrict__ out, const uint8_t *__restrict__ cls,
            const uint8_t *__restrict__ tflag, int remap, int nt, const int *__restrict__ tlist,
-           const int *__restrict__ tcount, S *__restrict__ oth) {
+           const int *__restrict__ tcount, S *__restrict__ oth, int zgm) {
   using Tr = SC2Traits<S, TH, N, SMALL>;
   using T = typename Tr::T;
   using C = typename Tr::C;
@@ -105,6 +105,10 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   constexpr int LWD = Tr::LWD, SZ = Tr::SZ;
   constexpr int LR = TY + 2;
   __shared__ uint32_t sm[NP * PD];
+  constexpr bool LIFT = NO > N, PROJ = NO > 0 && NO < N;
+  constexpr int QO = NO * NO;
+  constexpr int NTAB = LIFT ? NO * NO + 2 * NO * N + QO : (PROJ ? NO * N + QO : 1);
+  __shared__ typename SC2Traits<S, TH, N, SMALL>::C stab[NTAB];   // compute precision
   const LatTab &L = tab->lat[lat];
   auto tile_body = [&](const int bx, const int by) {
   const int x0 = bx * MSL_TX, y0 = by * TY;
@@ -146,6 +150,29 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
             rs, (msl_lds_t *)(sm + K * PD + 256 * (w + 4 * m)), 16, (int)voff[m], soff, 0, 0);
   };
   msl_for_planes<NP>(issue);
+  // band conversion tables of the other set, staged in LDS while the windows
+  // load (uniform reads later, no scalar-load round trips in the epilogue):
+  // lifting: the Hermite basis of the high-order nodes (NO x NO), the per-axis
+  // completion matrices (NO x N, x then y), the storage scales (NO^2);
+  // projection: the low-order basis at the high-order nodes (NO x N), the scales
+  if constexpr (NO > 0) {
+    const LatTab &LO = tab->lat[LIFT ? 1 : 0];
+    const int t = threadIdx.x;
+    if constexpr (LIFT) {
+      const bool herm = tab->lift_mode == MSL_LIFT_GRAD_HERMITE;
+      if (t < NO * NO) {
+        stab[t] = (C)LO.hw[t / NO][t % NO];
+      } else if (t < NO * NO + 2 * NO * N) {
+        const int k = t - NO * NO, ax = k / (NO * N), e = k % (NO * N);
+        stab[t] = (C)(herm ? tab->KH[e / N][e % N] : tab->K[ax][e / N][e % N]);
+      } else if (t < NTAB) {
+        stab[t] = (C)LO.sc[t - NO * NO - 2 * NO * N];
+      }
+    } else {
+      if (t < NO * N) stab[t] = (C)tab->P[t / N][t % N];
+      else if (t < NTAB) stab[t] = (C)LO.sc[t - NO * N];
+    }
+  }
   // my cells: inside the domain and of this velocity set; band: also
   // converted into the other set
   bool mine[R], band[R];
@@ -158,6 +185,57 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     band[r] = NO > 0 && mine[r] && (cb & 2);
   }
   __syncthreads();   // the compiler waits for the loads before the barrier
+  // zero-gradient faces (bits of zgm: x low, x high, y low, y high) applied to
+  // the staged windows instead of a ghost fill: a ghost takes the value of
+  // the edge cell of its row (x faces), then ghost rows copy the edge row,
+  // x ghosts included (y faces), the order of the separable ghost passes.
+  // Fixed faces keep their stored ghosts.  Only tiles whose windows reach a
+  // ghost layer of such a face take part (a uniform condition).
+  if (zgm && (((zgm & 1) && x0 < MSL_G) || ((zgm & 2) && x0 + MSL_TX + MSL_G > g.nx) ||
+              ((zgm & 4) && y0 < MSL_G) || ((zgm & 8) && y0 + TY + MSL_G > g.ny))) {
+    auto origin = [&](int K, int &wx, int &wy, int &boff) {
+      const int i = K % Q, a = i % N, b = i / N;
+      wx = x0 + L.n0[0][a] - 1;
+      wy = y0 + L.n0[1][b] - 1;
+      boff = (int)(((unsigned)g.idx(wx, wy, 0) * SZ) & 3u);
+    };
+    // x ghosts of the rows inside the domain: (plane, window row, ghost column)
+    if (zgm & 3) {
+      for (int it = threadIdx.x; it < NP * LR * 2 * MSL_G; it += 256) {
+        const int K = it / (LR * 2 * MSL_G), rem = it % (LR * 2 * MSL_G);
+        const int r = rem / (2 * MSL_G), gc = rem % (2 * MSL_G);
+        const int side = gc / MSL_G;
+        if (!(zgm & (1 << side))) continue;
+        int wx, wy, boff;
+        origin(K, wx, wy, boff);
+        const int Y = wy + r;
+        const int X = side ? g.nx + (gc - MSL_G) : gc - MSL_G;
+        const int j = X - wx, js = (side ? g.nx - 1 : 0) - wx;
+        if (Y < 0 || Y >= g.ny || j < 0 || j >= MSL_TX + 2) continue;
+        char *row = (char *)(sm + K * PD + r * LWD) + boff;
+        *(S *)(row + j * SZ) = *(const S *)(row + js * SZ);
+      }
+      __syncthreads();
+    }
+    // ghost rows: whole padded rows in 16-byte chunks (a plane's rows share
+    // one alignment)
+    if (zgm & 12) {
+      for (int it = threadIdx.x; it < NP * 2 * MSL_G * CPR; it += 256) {
+        const int K = it / (2 * MSL_G * CPR), rem = it % (2 * MSL_G * CPR);
+        const int gr = rem / CPR, ch = rem % CPR;
+        const int side = gr / MSL_G;
+        if (!(zgm & (4 << side))) continue;
+        int wx, wy, boff;
+        origin(K, wx, wy, boff);
+        const int Y = side ? g.ny + (gr - MSL_G) : gr - MSL_G;
+        const int r = Y - wy, rs = (side ? g.ny - 1 : 0) - wy;
+        if (r < 0 || r >= LR) continue;
+        uint4 *dst = (uint4 *)(sm + K * PD + r * LWD) + ch;
+        *dst = *((const uint4 *)(sm + K * PD + rs * LWD) + ch);
+      }
+      __syncthreads();
+    }
+  }
 
   // reconstruction of plane K at this thread's R cells (raw storage domain)
   auto recon = [&]<int K>(C (&ft)[R]) {
@@ -304,14 +382,14 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
       qb[r][1] *= dom[r] * cg;
     }
   }
-  // band conversion state: lifting keeps the non-equilibrium part of every
-  // post-collision population (f - f^eq, g - gfac T f^eq); projection
-  // accumulates (P x P) f of each output node in FP64 while the populations
-  // are stored (only in waves that hold a band cell)
-  constexpr bool LIFT = NO > N, PROJ = NO > 0 && NO < N;
-  constexpr int QO = NO * NO;
+  // band conversion state (compute precision): lifting keeps the
+  // non-equilibrium part of every post-collision population (f - f^eq,
+  // g - gfac T f^eq); projection accumulates (P x P) f of each output node
+  // while the populations are stored (only in waves that hold a band cell)
   C nq[LIFT ? NP : 1][R];
-  double acc[PROJ ? (TH ? 2 : 1) * QO : 1][R];
+  C acc[PROJ ? (TH ? 2 : 1) * QO : 1][R];   // (P x P) f per output node
+  C tp[PROJ ? NO : 1][R];                   // P along x of the current row
+  C Pp[PROJ ? NO : 1][PROJ ? N : 1];        // P[a'][a], from LDS
   bool wband = false;
   if constexpr (NO > 0) {
     bool b = false;
@@ -323,7 +401,17 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
 #pragma unroll
     for (int k = 0; k < (TH ? 2 : 1) * QO; ++k)
 #pragma unroll
-      for (int r = 0; r < R; ++r) acc[k][r] = 0.0;
+      for (int r = 0; r < R; ++r) acc[k][r] = C(0);
+#pragma unroll
+    for (int k = 0; k < NO; ++k)
+#pragma unroll
+      for (int r = 0; r < R; ++r) tp[k][r] = C(0);
+    if (wband) {
+#pragma unroll
+      for (int ap = 0; ap < NO; ++ap)
+#pragma unroll
+        for (int a = 0; a < N; ++a) Pp[ap][a] = stab[ap * N + a];
+    }
   }
   // 4. collide and store
   unsigned soff_cell[R];
@@ -356,13 +444,19 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
       }
       if constexpr (LIFT) nq[K][r] = vo - (K < Q ? feq : gf[r] * feq);
       if constexpr (PROJ) {
+        // separable: along x within the row b, then along y at its end
         if (wband) {
-          const double vd = (double)vo;
 #pragma unroll
-          for (int bp = 0; bp < NO; ++bp)
+          for (int ap = 0; ap < NO; ++ap) tp[ap][r] += Pp[ap][a] * vo;
+          if constexpr (a == N - 1) {
 #pragma unroll
-            for (int ap = 0; ap < NO; ++ap)
-              acc[(K < Q ? 0 : QO) + ap + NO * bp][r] += tab->P[ap][a] * tab->P[bp][b] * vd;
+            for (int bp = 0; bp < NO; ++bp)
+#pragma unroll
+              for (int ap = 0; ap < NO; ++ap)
+                acc[(K < Q ? 0 : QO) + ap + NO * bp][r] += Pp[bp][b] * tp[ap][r];
+#pragma unroll
+            for (int ap = 0; ap < NO; ++ap) tp[ap][r] = C(0);
+          }
         }
       }
       const C o = T::dev ? vo * isc - C(1) : vo;
@@ -391,41 +485,65 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
     if (wband) {
       const LatTab &LO = tab->lat[LIFT ? 1 : 0];
       const double gs = tab->gfac * tab->T0;
+      const C *sct = stab + (LIFT ? NO * NO + 2 * NO * N : NO * N);   // storage scales
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (!band[r]) continue;
         const long long off = g.idx(x0 + tx, y0 + ty * R + r, 0);
         if constexpr (LIFT) {
-          const double rd = (double)rho[r], ux = (double)jx[r] / rd, uy = (double)jy[r] / rd;
-          double Tm = 1.0;
-          if (TH) Tm = ((double)en[r] - 0.5 * rd * (ux * ux + uy * uy)) / (tab->cv * rd);
-          double PX[NO], PY[NO];
-          eq_axis<double, NO>(LO, (ux - LO.ur[0]) * LO.isq, Tm * LO.iTr, PX);
-          eq_axis<double, NO>(LO, (uy - LO.ur[1]) * LO.isq, Tm * LO.iTr, PY);
-          const bool herm = tab->lift_mode == MSL_LIFT_GRAD_HERMITE;
-          const double (*Kx)[MSL_MAXN] = herm ? tab->KH : tab->K[0];
-          const double (*Ky)[MSL_MAXN] = herm ? tab->KH : tab->K[1];
+          const C rd = rho[r], ux = jx[r] / rd, uy = jy[r] / rd;
+          C Tm = C(1);
+          if (TH) Tm = (en[r] - C(0.5) * rd * (ux * ux + uy * uy)) / ((C)tab->cv * rd);
+          // equilibrium factors of the high-order nodes (eq_axis with the
+          // basis from LDS): all of y here, x per output column below
+          const C tm1 = Tm * (C)LO.iTr - C(1);
+          const C uxs = (ux - (C)LO.ur[0]) * (C)LO.isq, uys = (uy - (C)LO.ur[1]) * (C)LO.isq;
+          C bx[NO], PY[NO];
+          {
+            C by[NO];
+            bx[0] = by[0] = C(1);
+            bx[1] = uxs;
+            by[1] = uys;
 #pragma unroll
-          for (int h = 0; h < (TH ? 2 : 1); ++h) {
-            const double sg = h ? tab->gfac * Tm : 1.0;
+            for (int j = 1; j + 1 < NO; ++j) {
+              bx[j + 1] = uxs * bx[j] + C(j) * tm1 * bx[j - 1];
+              by[j + 1] = uys * by[j] + C(j) * tm1 * by[j - 1];
+            }
 #pragma unroll
-            for (int a = 0; a < NO; ++a) {
-              double t[N];
+            for (int b = 0; b < NO; ++b) {
+              C sy = C(0);
+#pragma unroll
+              for (int j = 0; j < NO; ++j) sy += stab[b * NO + j] * by[j];
+              PY[b] = sy;
+            }
+          }
+          const C *Kx = stab + NO * NO, *Ky = stab + NO * NO + NO * N;
+          // one output column a at a time (not unrolled: a few values live)
+#pragma unroll 1
+          for (int a = 0; a < NO; ++a) {
+            C px = C(0);
+#pragma unroll
+            for (int j = 0; j < NO; ++j) px += stab[a * NO + j] * bx[j];
+            px *= rd;
+#pragma unroll
+            for (int h = 0; h < (TH ? 2 : 1); ++h) {
+              const C sg = h ? (C)tab->gfac * Tm : C(1);
+              C t[N];
 #pragma unroll
               for (int bp = 0; bp < N; ++bp) {
-                double sum = 0.0;
+                C sum = C(0);
 #pragma unroll
-                for (int ap = 0; ap < N; ++ap) sum += Kx[a][ap] * (double)nq[h * Q + ap + N * bp][r];
+                for (int ap = 0; ap < N; ++ap) sum += Kx[a * N + ap] * nq[h * Q + ap + N * bp][r];
                 t[bp] = sum;
               }
 #pragma unroll
               for (int b = 0; b < NO; ++b) {
-                double cr = 0.0;
+                C cr = C(0);
 #pragma unroll
-                for (int bp = 0; bp < N; ++bp) cr += Ky[b][bp] * t[bp];
+                for (int bp = 0; bp < N; ++bp) cr += Ky[b * N + bp] * t[bp];
                 const int i = a + NO * b;
-                store_pop<S>(oth + (long long)(h * QO + i) * g.plane, off, sg * rd * PX[a] * PY[b] + cr,
-                             h ? gs * LO.sc[i] : LO.sc[i]);
+                store_pop<S>(oth + (long long)(h * QO + i) * g.plane, off, (double)(sg * px * PY[b] + cr),
+                             h ? gs * (double)sct[i] : (double)sct[i]);
               }
             }
           }
@@ -434,8 +552,8 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
           for (int h = 0; h < (TH ? 2 : 1); ++h)
 #pragma unroll
             for (int i = 0; i < QO; ++i)
-              store_pop<S>(oth + (long long)(h * QO + i) * g.plane, off, acc[h * QO + i][r],
-                           h ? gs * LO.sc[i] : LO.sc[i]);
+              store_pop<S>(oth + (long long)(h * QO + i) * g.plane, off, (double)acc[h * QO + i][r],
+                           h ? gs * (double)sct[i] : (double)sct[i]);
         }
       }
     }

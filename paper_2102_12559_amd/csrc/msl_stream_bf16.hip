@@ -2,4 +2,4 @@
 #include "msl_stream.hpp"
 
 template int msl_launch_store_th<bf16_t, false>(msl_ctx *c, int lat, const char *in, char *out, char *oth);
-template int msl_fusable_th<bf16_t, false>(const msl_ctx *c);
+template int msl_sc2_all_th<bf16_t, false>(const msl_ctx *c);

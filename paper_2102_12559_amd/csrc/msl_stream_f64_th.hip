@@ -2,4 +2,4 @@
 #include "msl_stream.hpp"
 
 template int msl_launch_store_th<double, true>(msl_ctx *c, int lat, const char *in, char *out, char *oth);
-template int msl_fusable_th<double, true>(const msl_ctx *c);
+template int msl_sc2_all_th<double, true>(const msl_ctx *c);

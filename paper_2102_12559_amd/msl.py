@@ -232,7 +232,7 @@ class Solver:
         self._check(lib().msl_step(self._ctx, int(n)), "msl_step")
 
     def set_graph(self, mode):
-        """0: launch by launch; 1: blocks of steps as HIP graphs (default); 2: as 1
+        """0: launch by launch (default); 1: blocks of steps as HIP graphs; 2: as 1
         with the two sets' stream-collide launches on parallel graph branches."""
         self._check(lib().msl_set_graph(self._ctx, int(mode)), "msl_set_graph")
 
