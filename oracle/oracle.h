@@ -122,12 +122,16 @@ int or_conservation(const or_ctx *ctx, double *out);     /* sum rho, sum j (3), 
 int or_step_cells(const or_ctx *ctx, int ncells, const int64_t *cells,
                   double *fout, double *gout);
 
-/* ---- co-moving reference frames (PonD, Sec. II.C.1), one velocity set ----
- * Each cell keeps its populations in its own frame {u, T}; a step runs the
- * predictor-corrector to convergence and collides in the converged frame.
- * Needs n_high = 0, FP64 storage (store 0) and periodic, fixed-equilibrium or
- * zero-gradient faces.  or_pond_step returns -4 when a departure point leaves
- * the two-cell reach or a state turns non-finite. */
+/* ---- co-moving reference frames (PonD, Sec. II.C.1), one or two sets ----
+ * Each cell keeps its populations, of its own velocity set, in its own frame
+ * {u, T}; a step runs the predictor-corrector to convergence and collides in
+ * the converged frame.  With two sets (n_high > n_low), a collocation point of
+ * the other set is lifted or projected into the cell's set in its own frame
+ * (lift_mode 0 or 1); crit_kind 0 keeps the sets of or_pond_set_mask, 3
+ * re-selects them every crit_every steps by the Knudsen number.  Needs FP64
+ * storage (store 0) and periodic, fixed-equilibrium or zero-gradient faces.
+ * or_pond_step returns -4 when a departure point leaves the two-cell reach or
+ * a state turns non-finite. */
 typedef struct or_pond or_pond;
 int or_pond_create(const or_config *cfg, or_pond **out);
 void or_pond_destroy(or_pond *ctx);
@@ -135,7 +139,12 @@ double or_pond_dt(const or_pond *ctx);
 int or_pond_init(or_pond *ctx, const double *rho, const double *u, const double *T);
 int or_pond_step(or_pond *ctx, int nsteps);
 int or_pond_macros(const or_pond *ctx, double *rho, double *u, double *T);
-int or_pond_get_pops(const or_pond *ctx, int fg, double *out);   /* [Q][ncell], own frames */
+/* set `which` at every cell ([Q][ncell], own frames): native values at cells of
+ * that set, the converted state elsewhere */
+int or_pond_get_pops(const or_pond *ctx, int which, int fg, double *out);
+/* sets of the cells (0/1); convert: cells whose set changes convert their state */
+int or_pond_set_mask(or_pond *ctx, const uint8_t *mask, int convert);
+int or_pond_get_mask(const or_pond *ctx, uint8_t *out);
 int or_pond_get_frames(const or_pond *ctx, double *out);         /* [4][ncell]: u_x,u_y,u_z,T */
 int or_pond_iterations(const or_pond *ctx, double *mean, int *max);   /* of the last step */
 /* G_src^dst f (eq. fll) for one population vector, frames as {u_x, u_y, u_z, T} */

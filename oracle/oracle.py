@@ -393,8 +393,8 @@ def error_norms(rho, u, T, rho_ref=None, u_ref=None, T_ref=None):
 
 
 class Pond:
-    """The step in co-moving reference frames (PonD, Sec. II.C.1), one velocity
-    set, on host FP64 arrays."""
+    """The step in co-moving reference frames (PonD, Sec. II.C.1), one or two
+    velocity sets, on host FP64 arrays."""
 
     def __init__(self, cfg: dict):
         self.cfg = dict(cfg)
@@ -405,6 +405,7 @@ class Pond:
         self.shape = (cfg["nz"] if cfg["dim"] == 3 else 1, cfg["ny"], cfg["nx"])
         self.ncell = int(np.prod(self.shape))
         self.Q = cfg["n_low"] ** self.dim
+        self.Qs = [cfg["n_low"] ** self.dim] + ([cfg["n_high"] ** self.dim] if cfg.get("n_high") else [])
 
     def __del__(self):
         if getattr(self, "_ctx", None):
@@ -431,10 +432,19 @@ class Pond:
         _check(lib().or_pond_macros(self._ctx, _p(rho), _p(u), _p(T)), "pond macros")
         return rho.reshape(self.shape), u.reshape((self.dim,) + self.shape), T.reshape(self.shape)
 
-    def get_pops(self, fg=0):
-        out = np.zeros((self.Q, self.ncell))
-        _check(lib().or_pond_get_pops(self._ctx, fg, _p(out)), "pond get_pops")
+    def get_pops(self, which=0, fg=0):
+        out = np.zeros((self.Qs[which], self.ncell))
+        _check(lib().or_pond_get_pops(self._ctx, which, fg, _p(out)), "pond get_pops")
         return out
+
+    def set_mask(self, mask, convert=True):
+        m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+        _check(lib().or_pond_set_mask(self._ctx, m.ctypes.data_as(C.c_void_p), int(convert)), "pond set_mask")
+
+    def get_mask(self):
+        out = np.zeros(self.ncell, dtype=np.uint8)
+        _check(lib().or_pond_get_mask(self._ctx, out.ctypes.data_as(C.c_void_p)), "pond get_mask")
+        return out.reshape(self.shape)
 
     def get_frames(self):
         out = np.zeros((4, self.ncell))

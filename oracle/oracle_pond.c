@@ -1,12 +1,12 @@
 /*
  * oracle_pond.c -- the semi-Lagrangian step in co-moving reference frames
- * (PonD, Sec. II.C.1), one velocity set, cell by cell.
+ * (PonD, Sec. II.C.1), one or two velocity sets, cell by cell.
  * TEST INFRASTRUCTURE ONLY (see oracle.h).
  *
- * Every cell stores its post-collision populations in its own frame
- * lambda = {u, T} (eq. reference), with particle velocities
+ * Every cell stores its post-collision populations, of its own velocity set,
+ * in its own frame lambda = {u, T} (eq. reference), with particle velocities
  * v_i = sqrt(theta) c_i + u, theta = T / T_L, T_L = 1 (eq. vi).  One step at a
- * monitoring cell x:
+ * monitoring cell x of set l:
  *   predictor: lambda_0 = the cell's frame of the previous step;
  *   for n = 0, 1, ...:
  *     each population i is reconstructed at its departure point
@@ -23,6 +23,13 @@
  *   collision in the converged frame, where the equilibria are f^eq = rho W_i
  *   and g^eq = (cv - D/2) T rho W_i (eqs. feqPond, geqPond): BGK, or the
  *   two-relaxation model with the quasi-equilibria of eqs. fqeq, gqeq.
+ * With two velocity sets (Sec. III), a collocation point of the other set is
+ * first lifted (Sec. III.B) or projected (Sec. III.C) into set l in its own
+ * frame, with the moments taken at that frame's particle velocities, then
+ * transferred like any other point.  Every `crit_every` steps the Knudsen
+ * number of Sec. IV.A.3 of each cell (from its own set in its own frame)
+ * selects the set, and a cell whose set changes converts its own state in its
+ * own frame.
  * Collocation points outside the domain: periodic faces wrap, zero-gradient
  * faces repeat the edge cell (its populations and frame), fixed-equilibrium
  * faces give the face state's co-moving equilibrium in the face state's frame.
@@ -41,12 +48,18 @@
 
 struct or_pond {
   or_config cfg;
-  int D, N[3], Q, NP;
+  int D, N[3], nlat, Q[2], NP[2];
   int64_t ncell;
-  lat_t *L;
+  lat_t *L[2];
   double dt;
-  double *f, *fn;    /* [NP][ncell]: f planes then g planes, each cell in its own frame */
+  /* per set, [NP][ncell]: f planes then g planes of the cells of that set,
+   * each in its own frame (entries of the other set's cells are unused) */
+  double *f[2], *fn[2];
+  /* per set, during a step: the cells of the other set converted into this
+   * set in their own frames */
+  double *fx[2];
   double *fr, *frn;  /* [4][ncell]: u_x, u_y, u_z, T of each cell's frame */
+  uint8_t *order;    /* velocity set of each cell */
   long step;
   double it_mean;
   int it_max, bad;
@@ -115,9 +128,11 @@ static int64_t pcell(const or_pond *c, const int *p) {
   return (int64_t)p[0] + (int64_t)c->N[0] * ((int64_t)p[1] + (int64_t)c->N[1] * p[2]);
 }
 
-/* the state of collocation point q (possibly outside the domain): its f (and
- * g) vector and its frame */
-static void point_state(const or_pond *c, const int *qin, double *f, double *g, ld *u, ld *T) {
+/* the state of collocation point q (possibly outside the domain) in set l: its
+ * f (and g) vector and its frame */
+static void point_state(const or_pond *c, int l, const int *qin, double *f, double *g, ld *u, ld *T) {
+  const lat_t *L = c->L[l];
+  const int Q = c->Q[l];
   int q[3] = {qin[0], qin[1], qin[2]};
   for (int a = 0; a < c->D; a++) {
     if (q[a] >= 0 && q[a] < c->N[a]) continue;
@@ -128,9 +143,9 @@ static void point_state(const or_pond *c, const int *qin, double *f, double *g, 
       const double Tf = c->cfg.thermal ? st[4] : 1.0;
       for (int b = 0; b < 3; b++) u[b] = b < c->D ? (ld)st[1 + b] : 0.0L;
       *T = (ld)Tf;
-      for (int i = 0; i < c->Q; i++) {
-        f[i] = st[0] * c->L->W[i];
-        if (c->cfg.thermal) g[i] = (c->cfg.cv - 0.5 * c->D) * Tf * st[0] * c->L->W[i];
+      for (int i = 0; i < Q; i++) {
+        f[i] = st[0] * L->W[i];
+        if (c->cfg.thermal) g[i] = (c->cfg.cv - 0.5 * c->D) * Tf * st[0] * L->W[i];
       }
       return;
     }
@@ -142,12 +157,80 @@ static void point_state(const or_pond *c, const int *qin, double *f, double *g, 
     else q[a] = q[a] < 0 ? 0 : c->N[a] - 1;   /* zero gradient */
   }
   const int64_t k = pcell(c, q);
-  for (int i = 0; i < c->Q; i++) {
-    f[i] = c->f[(int64_t)i * c->ncell + k];
-    if (c->cfg.thermal) g[i] = c->f[(int64_t)(c->Q + i) * c->ncell + k];
+  const double *src = c->order[k] == l ? c->f[l] : c->fx[l];
+  for (int i = 0; i < Q; i++) {
+    f[i] = src[(int64_t)i * c->ncell + k];
+    if (c->cfg.thermal) g[i] = src[(int64_t)(Q + i) * c->ncell + k];
   }
   for (int b = 0; b < 3; b++) u[b] = (ld)c->fr[(int64_t)b * c->ncell + k];
   *T = (ld)c->fr[(int64_t)3 * c->ncell + k];
+}
+
+/* one cell's state of set `from`, given in the frame {u, T}, in set `to` in
+ * the same frame: lifting (Sec. III.B; the raw completion or its Hermite
+ * variant) or projection (Sec. III.C), with the moments at that frame's
+ * particle velocities.  Lf: the two sets' lattices, whose frame this sets. */
+static int convert_in_frame(const or_pond *c, lat_t **Lf, int from, int to, const double *f,
+                            const double *g, const double *u, double T, double *fo, double *go) {
+  const int th = c->cfg.thermal;
+  if (from == to) {
+    memcpy(fo, f, sizeof(double) * c->Q[from]);
+    if (th) memcpy(go, g, sizeof(double) * c->Q[from]);
+    return 0;
+  }
+  if (lat_set_frame(Lf[0], u, T) || lat_set_frame(Lf[1], u, T)) return -1;
+  if (from < to) {
+    if (c->cfg.lift_mode == 1) lat_lift_hermite(Lf[0], Lf[1], th, c->cfg.cv, f, th ? g : NULL, fo, th ? go : NULL);
+    else lat_lift_raw(Lf[0], Lf[1], th, c->cfg.cv, f, th ? g : NULL, NULL, fo, th ? go : NULL);
+  } else {
+    lat_project(Lf[1], Lf[0], th, f, th ? g : NULL, fo, th ? go : NULL);
+  }
+  return 0;
+}
+
+/* cell k's own state converted into set l (its own frame) */
+static int cell_in_set(const or_pond *c, lat_t **Lf, int64_t k, int l, double *fo, double *go) {
+  const int o = c->order[k], Qo = c->Q[o];
+  double f[OR_MAXQ], g[OR_MAXQ], u[3];
+  for (int i = 0; i < Qo; i++) {
+    f[i] = c->f[o][(int64_t)i * c->ncell + k];
+    g[i] = c->cfg.thermal ? c->f[o][(int64_t)(Qo + i) * c->ncell + k] : 0.0;
+  }
+  for (int a = 0; a < 3; a++) u[a] = c->fr[(int64_t)a * c->ncell + k];
+  return convert_in_frame(c, Lf, o, l, f, g, u, c->fr[(int64_t)3 * c->ncell + k], fo, go);
+}
+
+static void lats_new(const or_pond *c, lat_t **Lf) {
+  Lf[0] = lat_build(c->D, c->cfg.n_low);
+  Lf[1] = c->nlat > 1 ? lat_build(c->D, c->cfg.n_high) : lat_build(c->D, c->cfg.n_low);
+}
+
+static void lats_free(lat_t **Lf) {
+  lat_free(Lf[0]);
+  lat_free(Lf[1]);
+}
+
+/* the other set's cells in each set, in their own frames */
+static int convert_all(or_pond *c) {
+  if (c->nlat < 2) return 0;
+  int bad = 0;
+#pragma omp parallel reduction(| : bad)
+  {
+    lat_t *Lf[2];
+    lats_new(c, Lf);
+    double fo[OR_MAXQ], go[OR_MAXQ];
+#pragma omp for schedule(dynamic, 64)
+    for (int64_t k = 0; k < c->ncell; k++) {
+      const int l = 1 - c->order[k];
+      if (cell_in_set(c, Lf, k, l, fo, go)) { bad = 1; continue; }
+      for (int i = 0; i < c->Q[l]; i++) {
+        c->fx[l][(int64_t)i * c->ncell + k] = fo[i];
+        if (c->cfg.thermal) c->fx[l][(int64_t)(c->Q[l] + i) * c->ncell + k] = go[i];
+      }
+    }
+    lats_free(Lf);
+  }
+  return bad ? -4 : 0;
 }
 
 static double relax_tau_p(const or_pond *c, double rho, double T) {
@@ -162,8 +245,9 @@ static double relax_tau_p(const or_pond *c, double rho, double T) {
 /* one cell's step; returns the iteration count, or -1 when a departure point
  * leaves the two-cell reach or the state is not finite */
 static int pond_cell(const or_pond *c, int64_t k, double *fo, double *go, double *frame_out) {
-  const lat_t *L = c->L;
-  const int D = c->D, Q = c->Q, th = c->cfg.thermal;
+  const int l = c->order[k];
+  const lat_t *L = c->L[l];
+  const int D = c->D, Q = c->Q[l], th = c->cfg.thermal;
   int p[3];
   p[0] = (int)(k % c->N[0]);
   p[1] = (int)((k / c->N[0]) % c->N[1]);
@@ -181,7 +265,7 @@ static int pond_cell(const or_pond *c, int64_t k, double *fo, double *go, double
   for (int s = 0; s < npts; s++) {
     int q[3] = {p[0] + s % PSIDE - 2, p[1] + (s / PSIDE) % PSIDE - 2, D == 3 ? p[2] + s / (PSIDE * PSIDE) - 2 : 0};
     ld u[3], T;
-    point_state(c, q, nf + (size_t)s * OR_MAXQ, ng + (size_t)s * OR_MAXQ, u, &T);
+    point_state(c, l, q, nf + (size_t)s * OR_MAXQ, ng + (size_t)s * OR_MAXQ, u, &T);
     frame_velocities(L, u, T, &nfr[s]);
   }
   ld u[3] = {(ld)c->fr[k], (ld)c->fr[c->ncell + k], (ld)c->fr[2 * c->ncell + k]};
@@ -318,7 +402,9 @@ int or_pond_create(const or_config *cfg, or_pond **out) {
   if (!cfg || !out) return -1;
   if (cfg->dim != 2 && cfg->dim != 3) return -1;
   if (cfg->nx < 1 || cfg->ny < 1 || (cfg->dim == 3 && cfg->nz < 1)) return -1;
-  if (cfg->n_low < 2 || cfg->n_high != 0) return -1;   /* one velocity set */
+  if (cfg->n_low < 2 || (cfg->n_high != 0 && cfg->n_high <= cfg->n_low)) return -1;
+  if (cfg->n_high != 0 && (cfg->lift_mode != 0 && cfg->lift_mode != 1)) return -1;
+  if (cfg->crit_kind != 0 && cfg->crit_kind != 3) return -1;   /* fixed sets or the Knudsen number */
   if (cfg->tau <= 0.5 || (cfg->tau2 > 0.0 && cfg->tau2 <= 0.5)) return -1;
   if (cfg->store != 0) return -1;                       /* FP64 populations */
   for (int f = 0; f < 2 * cfg->dim; f++)
@@ -330,42 +416,53 @@ int or_pond_create(const or_config *cfg, or_pond **out) {
   c->N[1] = cfg->ny;
   c->N[2] = cfg->dim == 3 ? cfg->nz : 1;
   c->ncell = (int64_t)c->N[0] * c->N[1] * c->N[2];
-  c->L = lat_build(c->D, cfg->n_low);
-  if (!c->L) { free(c); return -2; }
-  c->Q = c->L->Q;
-  c->NP = cfg->thermal ? 2 * c->Q : c->Q;
-  /* dt = CFL / the largest lattice speed (the lattice-frame rule; a departure
-   * point beyond the two-cell reach in some frame is reported by the step) */
+  c->nlat = cfg->n_high ? 2 : 1;
+  /* dt = CFL / the largest lattice speed of the sets (the lattice-frame rule;
+   * a departure point beyond the two-cell reach in some frame is reported by
+   * the step) */
   double vmax = 0.0;
-  for (int a = 0; a < c->D; a++)
-    if (lat_vmax(c->L, a) > vmax) vmax = lat_vmax(c->L, a);
+  for (int l = 0; l < c->nlat; l++) {
+    c->L[l] = lat_build(c->D, l ? cfg->n_high : cfg->n_low);
+    if (!c->L[l]) { or_pond_destroy(c); return -2; }
+    c->Q[l] = c->L[l]->Q;
+    c->NP[l] = cfg->thermal ? 2 * c->Q[l] : c->Q[l];
+    for (int a = 0; a < c->D; a++)
+      if (lat_vmax(c->L[l], a) > vmax) vmax = lat_vmax(c->L[l], a);
+    c->f[l] = (double *)calloc((size_t)c->NP[l] * c->ncell, sizeof(double));
+    c->fn[l] = (double *)calloc((size_t)c->NP[l] * c->ncell, sizeof(double));
+    if (c->nlat > 1) c->fx[l] = (double *)calloc((size_t)c->NP[l] * c->ncell, sizeof(double));
+  }
   c->dt = cfg->cfl / vmax;
-  c->f = (double *)calloc((size_t)c->NP * c->ncell, sizeof(double));
-  c->fn = (double *)calloc((size_t)c->NP * c->ncell, sizeof(double));
   c->fr = (double *)calloc((size_t)4 * c->ncell, sizeof(double));
   c->frn = (double *)calloc((size_t)4 * c->ncell, sizeof(double));
+  c->order = (uint8_t *)calloc((size_t)c->ncell, 1);
   *out = c;
   return 0;
 }
 
 void or_pond_destroy(or_pond *c) {
   if (!c) return;
-  lat_free(c->L);
-  free(c->f); free(c->fn); free(c->fr); free(c->frn);
+  for (int l = 0; l < 2; l++) {
+    lat_free(c->L[l]);
+    free(c->f[l]); free(c->fn[l]); free(c->fx[l]);
+  }
+  free(c->fr); free(c->frn); free(c->order);
   free(c);
 }
 
 double or_pond_dt(const or_pond *c) { return c->dt; }
 
-/* every cell at the co-moving equilibrium of (rho, u, T) in its own frame */
+/* every cell at the co-moving equilibrium of (rho, u, T) in its own frame,
+ * in each set (an equilibrium is the same state in both) */
 int or_pond_init(or_pond *c, const double *rho, const double *u, const double *T) {
   const int th = c->cfg.thermal;
   for (int64_t k = 0; k < c->ncell; k++) {
     const double Tk = th ? T[k] : 1.0;
-    for (int i = 0; i < c->Q; i++) {
-      c->f[(int64_t)i * c->ncell + k] = rho[k] * c->L->W[i];
-      if (th) c->f[(int64_t)(c->Q + i) * c->ncell + k] = (c->cfg.cv - 0.5 * c->D) * Tk * rho[k] * c->L->W[i];
-    }
+    for (int l = 0; l < c->nlat; l++)
+      for (int i = 0; i < c->Q[l]; i++) {
+        c->f[l][(int64_t)i * c->ncell + k] = rho[k] * c->L[l]->W[i];
+        if (th) c->f[l][(int64_t)(c->Q[l] + i) * c->ncell + k] = (c->cfg.cv - 0.5 * c->D) * Tk * rho[k] * c->L[l]->W[i];
+      }
     for (int a = 0; a < 3; a++) c->fr[(int64_t)a * c->ncell + k] = a < c->D ? u[(int64_t)a * c->ncell + k] : 0.0;
     c->fr[(int64_t)3 * c->ncell + k] = Tk;
   }
@@ -373,8 +470,122 @@ int or_pond_init(or_pond *c, const double *rho, const double *u, const double *T
   return 0;
 }
 
+/* the velocity set of each cell; convert: cells whose set changes lift or
+ * project their own state in their own frame */
+int or_pond_set_mask(or_pond *c, const uint8_t *mask, int convert) {
+  for (int64_t k = 0; k < c->ncell; k++)
+    if (mask[k] > 1 || (mask[k] && c->nlat < 2)) return -1;
+  int bad = 0;
+  if (convert && c->nlat > 1) {
+#pragma omp parallel reduction(| : bad)
+    {
+      lat_t *Lf[2];
+      lats_new(c, Lf);
+      double fo[OR_MAXQ], go[OR_MAXQ];
+#pragma omp for schedule(dynamic, 64)
+      for (int64_t k = 0; k < c->ncell; k++) {
+        const int to = mask[k];
+        if (to == c->order[k]) continue;
+        if (cell_in_set(c, Lf, k, to, fo, go)) { bad = 1; continue; }
+        for (int i = 0; i < c->Q[to]; i++) {
+          c->f[to][(int64_t)i * c->ncell + k] = fo[i];
+          if (c->cfg.thermal) c->f[to][(int64_t)(c->Q[to] + i) * c->ncell + k] = go[i];
+        }
+      }
+      lats_free(Lf);
+    }
+  }
+  memcpy(c->order, mask, (size_t)c->ncell);
+  return bad ? -4 : 0;
+}
+
+int or_pond_get_mask(const or_pond *c, uint8_t *out) {
+  memcpy(out, c->order, (size_t)c->ncell);
+  return 0;
+}
+
+/* rho, u, T of cell k from its own populations in its own frame */
+static void cell_macros(const or_pond *c, int64_t k, ld *rho, ld *uo, ld *To) {
+  const int l = c->order[k];
+  const lat_t *L = c->L[l];
+  const ld Tf = (ld)c->fr[3 * c->ncell + k], st = sqrtl(Tf);
+  ld r = 0, j[3] = {0, 0, 0}, e = 0;
+  for (int i = 0; i < c->Q[l]; i++) {
+    const ld f = (ld)c->f[l][(int64_t)i * c->ncell + k];
+    ld v2 = 0;
+    r += f;
+    for (int a = 0; a < c->D; a++) {
+      const ld v = st * L->cl[i][a] + (ld)c->fr[(int64_t)a * c->ncell + k];
+      j[a] += v * f;
+      v2 += v * v;
+    }
+    e += 0.5L * v2 * f;
+    if (c->cfg.thermal) e += (ld)c->f[l][(int64_t)(c->Q[l] + i) * c->ncell + k];
+  }
+  ld u2 = 0;
+  for (int a = 0; a < 3; a++) {
+    uo[a] = a < c->D ? j[a] / r : 0.0L;
+    u2 += uo[a] * uo[a];
+  }
+  *rho = r;
+  *To = c->cfg.thermal ? (e / r - 0.5L * u2) / (ld)c->cfg.cv : 1.0L;
+}
+
+/* Knudsen-number criterion (Sec. IV.A.3): Kn = lambda |grad rho| / rho with the
+ * hard-sphere mean free path lambda = 16/(5 sqrt(2 pi gamma)) mu a / p, a the
+ * sound speed sqrt(gamma T), p = rho T, mu = (tau - 1/2) rho T dt at the local
+ * relaxation time; central differences of the cell densities, one-sided over
+ * one cell at a face that is not periodic.  Sets with Kn > crit_thr are the
+ * high-order set. */
+static void pond_criterion(const or_pond *c, uint8_t *newmask) {
+  const int64_t n = c->ncell;
+  double *rho = (double *)malloc((size_t)n * sizeof(double));
+  double *lam = (double *)malloc((size_t)n * sizeof(double));
+  const double gam = (c->cfg.cv + 1.0) / c->cfg.cv;
+  for (int64_t k = 0; k < n; k++) {
+    ld r, u[3], T;
+    cell_macros(c, k, &r, u, &T);
+    const double rd = (double)r, Td = (double)T;
+    const double mu = (relax_tau_p(c, rd, Td) - 0.5) * rd * Td * c->dt;
+    rho[k] = rd;
+    lam[k] = 16.0 / (5.0 * sqrt(2.0 * acos(-1.0) * gam)) * mu * sqrt(gam * Td) / (rd * Td);
+  }
+  for (int64_t k = 0; k < n; k++) {
+    const int p[3] = {(int)(k % c->N[0]), (int)((k / c->N[0]) % c->N[1]), (int)(k / ((int64_t)c->N[0] * c->N[1]))};
+    double g2 = 0.0;
+    for (int a = 0; a < c->D; a++) {
+      if (c->N[a] < 2) continue;
+      const int periodic = c->cfg.bc[2 * a] == 0 && c->cfg.bc[2 * a + 1] == 0;
+      int lo[3] = {p[0], p[1], p[2]}, hi[3] = {p[0], p[1], p[2]};
+      lo[a] = p[a] - 1;
+      hi[a] = p[a] + 1;
+      if (periodic) {
+        lo[a] = (lo[a] + c->N[a]) % c->N[a];
+        hi[a] = hi[a] % c->N[a];
+      } else {
+        if (lo[a] < 0) lo[a] = 0;
+        if (hi[a] >= c->N[a]) hi[a] = c->N[a] - 1;
+      }
+      const double dist = periodic ? 2.0 : (double)(hi[a] - lo[a]);
+      const double d = (rho[pcell(c, hi)] - rho[pcell(c, lo)]) / dist;
+      g2 += d * d;
+    }
+    newmask[k] = lam[k] * sqrt(g2) / rho[k] > c->cfg.crit_thr ? 1 : 0;
+  }
+  free(rho);
+  free(lam);
+}
+
 int or_pond_step(or_pond *c, int nsteps) {
   for (int s = 0; s < nsteps; s++) {
+    if (c->nlat > 1 && c->cfg.crit_kind == 3 && c->cfg.crit_every > 0 && c->step % c->cfg.crit_every == 0) {
+      uint8_t *nm = (uint8_t *)malloc((size_t)c->ncell);
+      pond_criterion(c, nm);
+      const int rc = or_pond_set_mask(c, nm, 1);
+      free(nm);
+      if (rc) return rc;
+    }
+    if (convert_all(c)) return -4;
     int bad = 0, itmax = 0;
     double itsum = 0.0;
 #pragma omp parallel reduction(| : bad) reduction(max : itmax) reduction(+ : itsum)
@@ -382,20 +593,23 @@ int or_pond_step(or_pond *c, int nsteps) {
       double fo[OR_MAXQ], go[OR_MAXQ], frm[4];
 #pragma omp for schedule(dynamic, 16)
       for (int64_t k = 0; k < c->ncell; k++) {
+        const int l = c->order[k];
         const int it = pond_cell(c, k, fo, go, frm);
         if (it < 0) { bad = 1; continue; }
         if (it > itmax) itmax = it;
         itsum += it;
-        for (int i = 0; i < c->Q; i++) {
-          c->fn[(int64_t)i * c->ncell + k] = fo[i];
-          if (c->cfg.thermal) c->fn[(int64_t)(c->Q + i) * c->ncell + k] = go[i];
+        for (int i = 0; i < c->Q[l]; i++) {
+          c->fn[l][(int64_t)i * c->ncell + k] = fo[i];
+          if (c->cfg.thermal) c->fn[l][(int64_t)(c->Q[l] + i) * c->ncell + k] = go[i];
         }
         for (int a = 0; a < 4; a++) c->frn[(int64_t)a * c->ncell + k] = frm[a];
       }
     }
     if (bad) return -4;
-    double *t = c->f; c->f = c->fn; c->fn = t;
-    t = c->fr; c->fr = c->frn; c->frn = t;
+    for (int l = 0; l < c->nlat; l++) {
+      double *t = c->f[l]; c->f[l] = c->fn[l]; c->fn[l] = t;
+    }
+    double *t = c->fr; c->fr = c->frn; c->frn = t;
     c->it_mean = itsum / (double)c->ncell;
     c->it_max = itmax;
     c->step++;
@@ -409,11 +623,26 @@ int or_pond_iterations(const or_pond *c, double *mean, int *max) {
   return 0;
 }
 
-/* populations of each cell in its own frame: [NP][ncell] (fg = 1: g) */
-int or_pond_get_pops(const or_pond *c, int fg, double *out) {
-  if (fg && !c->cfg.thermal) return -1;
-  memcpy(out, c->f + (size_t)(fg ? c->Q : 0) * c->ncell, sizeof(double) * c->Q * c->ncell);
-  return 0;
+/* populations of set `which` at every cell, in each cell's own frame: native
+ * where the cell uses that set, its state lifted / projected elsewhere:
+ * [Q][ncell] (fg = 1: g) */
+int or_pond_get_pops(const or_pond *c, int which, int fg, double *out) {
+  if (which < 0 || which >= c->nlat || (fg && !c->cfg.thermal)) return -1;
+  const int Q = c->Q[which];
+  int bad = 0;
+#pragma omp parallel reduction(| : bad)
+  {
+    lat_t *Lf[2];
+    lats_new(c, Lf);
+    double fo[OR_MAXQ], go[OR_MAXQ];
+#pragma omp for schedule(dynamic, 64)
+    for (int64_t k = 0; k < c->ncell; k++) {
+      if (cell_in_set(c, Lf, k, which, fo, go)) { bad = 1; continue; }
+      for (int i = 0; i < Q; i++) out[(int64_t)i * c->ncell + k] = fg ? go[i] : fo[i];
+    }
+    lats_free(Lf);
+  }
+  return bad ? -4 : 0;
 }
 
 int or_pond_get_frames(const or_pond *c, double *out) {
@@ -423,29 +652,13 @@ int or_pond_get_frames(const or_pond *c, double *out) {
 
 /* rho, u, T of every cell from its populations in its own frame */
 int or_pond_macros(const or_pond *c, double *rho, double *u, double *T) {
-  const lat_t *L = c->L;
   for (int64_t k = 0; k < c->ncell; k++) {
-    const ld Tf = (ld)c->fr[3 * c->ncell + k], st = sqrtl(Tf);
-    ld r = 0, j[3] = {0, 0, 0}, e = 0;
-    for (int i = 0; i < c->Q; i++) {
-      const ld f = (ld)c->f[(int64_t)i * c->ncell + k];
-      ld v2 = 0;
-      r += f;
-      for (int a = 0; a < c->D; a++) {
-        const ld v = st * L->cl[i][a] + (ld)c->fr[(int64_t)a * c->ncell + k];
-        j[a] += v * f;
-        v2 += v * v;
-      }
-      e += 0.5L * v2 * f;
-      if (c->cfg.thermal) e += (ld)c->f[(int64_t)(c->Q + i) * c->ncell + k];
-    }
-    ld u2 = 0;
-    for (int a = 0; a < c->D; a++) {
-      if (u) u[(int64_t)a * c->ncell + k] = (double)(j[a] / r);
-      u2 += (j[a] / r) * (j[a] / r);
-    }
+    ld r, uu[3], t;
+    cell_macros(c, k, &r, uu, &t);
     if (rho) rho[k] = (double)r;
-    if (T) T[k] = c->cfg.thermal ? (double)((e / r - 0.5L * u2) / (ld)c->cfg.cv) : 1.0;
+    if (u)
+      for (int a = 0; a < c->D; a++) u[(int64_t)a * c->ncell + k] = (double)uu[a];
+    if (T) T[k] = (double)t;
   }
   return 0;
 }
