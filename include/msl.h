@@ -113,14 +113,20 @@ typedef struct msl_config {
   int pond;                   /* 1: co-moving reference frames (PonD, Sec. II.C.1): every cell
                                  keeps its populations in its own frame {u, T}, a step runs the
                                  predictor-corrector (eqs. correctorfields) to convergence and
-                                 collides in the converged frame (eqs. feqPond, geqPond).  Needs
-                                 dim 2, one velocity set (n_high 0), FP64 storage, no criterion,
-                                 the lattice frame, and periodic, fixed-equilibrium or
-                                 zero-gradient faces; dt = cfl / max|c| of the lattice, and a
-                                 step whose departure point leaves the two-cell reach in some
-                                 frame returns MSL_EUNSTABLE (lower cfl).  Populations in and out
-                                 (msl_get_populations) are given in each cell's own frame
-                                 (msl_pond_frames).  0: one global frame. */
+                                 collides in the converged frame (eqs. feqPond, geqPond).  With
+                                 two velocity sets, a collocation point of the other set is
+                                 lifted or projected into the cell's set in its own frame
+                                 (lift_mode Grad or Hermite), and the sets are those of
+                                 msl_set_mask or, with crit_kind MSL_CRIT_KN, re-selected every
+                                 crit_every steps from each cell's own state.  Needs dim 2, FP64
+                                 storage, no other criterion, the lattice frame, and periodic,
+                                 fixed-equilibrium or zero-gradient faces; dt = cfl / max|c| of
+                                 the sets, and a step whose departure point leaves the two-cell
+                                 reach in some frame returns MSL_EUNSTABLE (lower cfl).
+                                 Populations out (msl_get_populations) are given in each cell's
+                                 own frame (msl_pond_frames); populations in, conservation sums,
+                                 error norms and checkpoints are not offered.  0: one global
+                                 frame. */
 } msl_config;
 
 typedef struct msl_ctx msl_ctx;

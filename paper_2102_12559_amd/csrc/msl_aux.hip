@@ -1125,6 +1125,17 @@ int msl_launch_band_convert(msl_ctx *c, char *bl, char *bh) {
   return MSL_EINVAL;
 }
 
+// Kn > crit_thr from the cell densities and mean free paths in kn_rho, kn_lam
+// (written by the previous launch) into newmask
+int msl_launch_kn_mask(msl_ctx *c) {
+  int per = 0;
+  for (int a = 0; a < c->D; ++a)
+    if (c->cfg.bc[2 * a] == MSL_BC_PERIODIC && c->cfg.bc[2 * a + 1] == MSL_BC_PERIODIC) per |= 1 << a;
+  hipLaunchKernelGGL(k_kn_mask, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), 0, c->stream, c->geo, c->kn_rho,
+                     c->kn_lam, per, c->cfg.crit_thr, c->newmask);
+  return last_err();
+}
+
 template <typename S>
 static int criterion_s(msl_ctx *c) {
   return msl_pair_dispatch(c->D, c->htab.lat[0].n, c->htab.lat[1].n, [&]<int D, int NL, int NH>() {
@@ -1136,12 +1147,7 @@ static int criterion_s(msl_ctx *c) {
       else
         hipLaunchKernelGGL((k_kn_fields<S, D, NL, NH, false>), dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), 0,
                            c->stream, c->dtab, c->geo, bl, bh, c->cls, c->kn_rho, c->kn_lam);
-      int per = 0;
-      for (int a = 0; a < c->D; ++a)
-        if (c->cfg.bc[2 * a] == MSL_BC_PERIODIC && c->cfg.bc[2 * a + 1] == MSL_BC_PERIODIC) per |= 1 << a;
-      hipLaunchKernelGGL(k_kn_mask, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), 0, c->stream, c->geo, c->kn_rho,
-                         c->kn_lam, per, c->cfg.crit_thr, c->newmask);
-      return last_err();
+      return msl_launch_kn_mask(c);
     }
     if (c->cfg.thermal)
       hipLaunchKernelGGL((k_criterion_t<S, D, NL, NH, true>), dim3(nblocks(c->ncell)), dim3(AUX_BLOCK),

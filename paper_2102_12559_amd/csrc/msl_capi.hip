@@ -213,9 +213,10 @@ static const char *check_config(const msl_config *cfg) {
   if (cfg->pond != 0 && cfg->pond != 1) return "pond must be 0 or 1";
   if (cfg->pond) {
     if (cfg->dim != 2) return "co-moving frames are built for 2D";
-    if (cfg->n_high) return "co-moving frames run one velocity set";
+    if (cfg->n_high && cfg->lift_mode == MSL_LIFT_MLP) return "co-moving frames: Grad or Hermite lifting";
     if (cfg->store != MSL_FP64) return "co-moving frames keep FP64 populations";
-    if (cfg->crit_kind) return "co-moving frames run one velocity set (no criterion)";
+    if (cfg->crit_kind != MSL_CRIT_NONE && cfg->crit_kind != MSL_CRIT_KN)
+      return "co-moving frames: fixed sets or the Knudsen-number criterion";
     if (!trivial_frame) return "co-moving frames replace the global frame";
     for (int f = 0; f < 4; ++f)
       if (cfg->bc[f] == MSL_BC_DIFFUSE_WALL) return "co-moving frames: no diffuse walls";
@@ -307,7 +308,7 @@ static void make_layout(const msl_config *cfg, Layout &L) {
   if (cfg->crit_kind == MSL_CRIT_KN && nl > 1) off = align256(off + (size_t)g.ncell * 2 * 8);
   // co-moving frames: two buffers of populations and frames, iteration counters
   L.off_pond = off;
-  if (cfg->pond) off = align256(off + (size_t)g.ncell * 8 * 2 * (L.np[0] + 4) + 64);
+  if (cfg->pond) off = align256(off + (size_t)g.ncell * 8 * 2 * (L.np[0] + (nl > 1 ? L.np[1] : 0) + 4) + 64);
   // learned closure
   if (cfg->lift_mode == MSL_LIFT_MLP && nl > 1) {
     const int q = L.Q[0], Q = L.Q[1];
@@ -511,12 +512,16 @@ int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_
   c->kn_lam = c->kn_rho + L.geo.ncell;
   if (cfg->pond) {
     double *pb = (double *)(base + L.off_pond);
-    const size_t nf = (size_t)L.np[0] * L.geo.ncell, nfr = (size_t)4 * L.geo.ncell;
-    c->pond_f[0] = pb;
-    c->pond_f[1] = pb + nf;
-    c->pond_fr[0] = pb + 2 * nf;
-    c->pond_fr[1] = pb + 2 * nf + nfr;
-    c->pond_stats = (unsigned long long *)(pb + 2 * nf + 2 * nfr);
+    for (int l = 0; l < c->nlat; ++l) {
+      const size_t nf = (size_t)L.np[l] * L.geo.ncell;
+      c->pond_f[l][0] = pb;
+      c->pond_f[l][1] = pb + nf;
+      pb += 2 * nf;
+    }
+    const size_t nfr = (size_t)4 * L.geo.ncell;
+    c->pond_fr[0] = pb;
+    c->pond_fr[1] = pb + nfr;
+    c->pond_stats = (unsigned long long *)(pb + 2 * nfr);
   }
   c->tcount = c->tlist + (size_t)L.geo.ntx * L.geo.nty * L.geo.ntz;
   if (L.mlpP) {
@@ -633,7 +638,7 @@ int msl_init(msl_ctx *c, const double *rho, const double *u, const double *T) {
 }
 
 int msl_set_mask(msl_ctx *c, const uint8_t *mask) {
-  if (!c || !mask || c->cfg.pond) return MSL_EINVAL;
+  if (!c || !mask) return MSL_EINVAL;
   if (hipMemsetAsync(c->flag, 0, sizeof(int), c->stream) != hipSuccess) return MSL_EHIP;
   int rc = msl_launch_check_mask(c, mask);
   if (rc) return rc;
@@ -642,6 +647,7 @@ int msl_set_mask(msl_ctx *c, const uint8_t *mask) {
       hipStreamSynchronize(c->stream) != hipSuccess)
     return MSL_EHIP;
   if (bad) { set_err(c, "mask values must be 0/1 (1 only with a high order)"); return MSL_EINVAL; }
+  if (c->cfg.pond) return msl_pond_launch_set_mask(c, mask, c->initialized);
   rc = msl_launch_switch(c, mask);
   if (rc) return rc;
   return refresh_band(c);
@@ -1001,8 +1007,8 @@ int msl_get_populations(msl_ctx *c, int which, int fg, double *out) {
   if (!c || !out || which < 0 || which >= c->nlat || (fg && !c->cfg.thermal)) return MSL_EINVAL;
   if (c->cfg.pond) {
     if (!c->initialized) return MSL_ESTATE;
-    const size_t n = (size_t)c->Q[0] * c->ncell;
-    return hipMemcpyAsync(out, c->pond_f[c->cur] + (fg ? n : 0), sizeof(double) * n, hipMemcpyDeviceToDevice,
+    const size_t n = (size_t)c->Q[which] * c->ncell;
+    return hipMemcpyAsync(out, c->pond_f[which][c->cur] + (fg ? n : 0), sizeof(double) * n, hipMemcpyDeviceToDevice,
                           c->stream) == hipSuccess ? MSL_OK : MSL_EHIP;
   }
   return msl_launch_pops(c, which, fg, out, nullptr);

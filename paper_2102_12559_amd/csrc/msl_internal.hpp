@@ -142,9 +142,10 @@ struct msl_ctx {
   uint8_t *cls;           // bit0 order (0 low, 1 high), bit1 band
   uint8_t *newmask;
   double *kn_rho, *kn_lam;   // Knudsen-number criterion: density and mean free path per cell
-  // co-moving frames: populations [NP][ncell] and frames [4][ncell] of each
-  // buffer; stats: iteration sum (u64), then maximum (int)
-  double *pond_f[2], *pond_fr[2];
+  // co-moving frames: populations [NP][ncell] of each velocity set and
+  // buffer ([set][buffer]) and frames [4][ncell] of each buffer; stats:
+  // iteration sum (u64), then maximum (int)
+  double *pond_f[2][2], *pond_fr[2];
   unsigned long long *pond_stats;
   long long pond_cells_steps;
   uint8_t *tflag;         // per micro-tile: bit0 has low cells, bit1 has high cells
@@ -234,6 +235,11 @@ int msl_launch_conservation(msl_ctx *c, double *dev_out5);
 int msl_pond_launch_init(msl_ctx *c, const double *rho, const double *u, const double *T);
 int msl_pond_launch_macros(msl_ctx *c, double *rho, double *u, double *T);
 int msl_pond_launch_step(msl_ctx *c);
+// co-moving frames, two sets: cells whose set differs from `mask` convert their
+// own state in their own frame (convert = 0: only the sets change), then the
+// band is rebuilt and converted
+int msl_pond_launch_set_mask(msl_ctx *c, const uint8_t *mask, int convert);
+int msl_launch_kn_mask(msl_ctx *c);
 int msl_launch_error_norms(msl_ctx *c, const double *rref, const double *uref, const double *Tref,
                            double *dev_out6);
 int msl_launch_check_mask(msl_ctx *c, const uint8_t *mask);

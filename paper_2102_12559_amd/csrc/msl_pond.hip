@@ -1,5 +1,5 @@
 // msl_pond.hip -- the step in co-moving reference frames (PonD, Sec. II.C.1),
-// one velocity set, 2D, FP64.
+// one or two velocity sets, 2D, FP64.
 //
 // Every cell keeps its post-collision populations in its own frame
 // lambda = {u, T} (eq. reference; particle velocities sqrt(T) c_i + u, eq. vi,
@@ -24,9 +24,17 @@
 // converged frame, where f^eq = rho W_i and g^eq = (cv - 1) T rho W_i (eqs.
 // feqPond, geqPond), BGK or two-relaxation (eqs. fqeq, gqeq in the co-moving
 // frame).
+// With two velocity sets (Sec. III) the step launches once per set, over the
+// cells of that set; afterwards every band cell (within two cells of the other
+// set) converts its new state into the other set in its own new frame
+// (lifting or projection, Sec. III.B-C), so a collocation point of the other
+// set holds this set's populations in its own frame when the next step reads
+// it.  The Knudsen-number criterion re-selects the sets every crit_every
+// steps from each cell's own state; a cell whose set changes converts its
+// state in its own frame.
 #include <hip/hip_runtime.h>
 
-#include "msl_internal.hpp"
+#include "msl_band.hpp"
 
 #define POND_MAXIT 60
 #define POND_TOL 1e-14
@@ -70,9 +78,10 @@ __device__ __forceinline__ long long pond_resolve(const PondArgs &pa, int x, int
 
 template <int N, bool TH, bool QE>
 __global__ void __launch_bounds__(256)
-k_pond_step(const Tab *__restrict__ tab, PondArgs pa, const double *__restrict__ fin,
-            const double *__restrict__ frin, double *__restrict__ fout, double *__restrict__ frout,
-            int *__restrict__ flag, unsigned long long *__restrict__ itsum, int *__restrict__ itmax) {
+k_pond_step(const Tab *__restrict__ tab, int lat, const uint8_t *__restrict__ cls, PondArgs pa,
+            const double *__restrict__ fin, const double *__restrict__ frin, double *__restrict__ fout,
+            double *__restrict__ frout, int *__restrict__ flag, unsigned long long *__restrict__ itsum,
+            int *__restrict__ itmax) {
   using Tr = PondTraits<N, TH>;
   constexpr int Q = Tr::Q, NP = Tr::NP, GS = Tr::GS, TW = Tr::TW, SW = Tr::SW, SP = Tr::SP,
                 STRIDE = Tr::STRIDE;
@@ -80,7 +89,7 @@ k_pond_step(const Tab *__restrict__ tab, PondArgs pa, const double *__restrict__
   // points lie within two cells, so the SW x 5 points around the segment
   // (populations and frames, boundary rules applied) are staged in LDS once
   __shared__ double stg[SP * STRIDE];
-  const LatTab &L = tab->lat[0];
+  const LatTab &L = tab->lat[lat];
   const int x0 = blockIdx.x * TW, y = blockIdx.y;
   const double dt = tab->dt, cv = tab->cv;
   for (int e = threadIdx.x; e < SP * STRIDE; e += 256) {
@@ -105,8 +114,9 @@ k_pond_step(const Tab *__restrict__ tab, PondArgs pa, const double *__restrict__
   __syncthreads();
   const int c = threadIdx.x / GS, li = threadIdx.x % GS;
   const int px = x0 + c, py = y;
-  const bool cell_ok = px < pa.nx;
-  const long long k = (long long)py * pa.nx + (cell_ok ? px : 0);
+  const long long k = (long long)py * pa.nx + (px < pa.nx ? px : 0);
+  // cells of this launch's velocity set (with two sets)
+  const bool cell_ok = px < pa.nx && (cls[k] & 1) == lat;
   const bool act = cell_ok && li < Q;
   const int i = act ? li : 0, a = i % N, b = i / N;
   // lattice nodes and the Lagrange denominators 1 / prod_{c != a} (x_a - x_c)
@@ -251,17 +261,22 @@ k_pond_step(const Tab *__restrict__ tab, PondArgs pa, const double *__restrict__
   }
 }
 
-// every cell at the co-moving equilibrium of (rho, u, T) in its own frame
-__global__ void k_pond_init(const Tab *__restrict__ tab, long long ncell, int thermal, const double *rho,
-                            const double *u, const double *T, double *f, double *fr) {
+// every cell at the co-moving equilibrium of (rho, u, T) in its own frame, in
+// each set (an equilibrium is the same state in both)
+__global__ void k_pond_init(const Tab *__restrict__ tab, long long ncell, int thermal, int nlat,
+                            const double *rho, const double *u, const double *T, double *f0, double *f1,
+                            double *fr) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= ncell) return;
-  const LatTab &L = tab->lat[0];
   const double Tk = thermal ? T[k] : 1.0;
-  for (int i = 0; i < L.Q; ++i) {
-    const double W = L.w[i % L.n] * L.w[i / L.n];
-    f[(long long)i * ncell + k] = rho[k] * W;
-    if (thermal) f[(long long)(L.Q + i) * ncell + k] = (tab->cv - 1.0) * Tk * rho[k] * W;
+  for (int l = 0; l < nlat; ++l) {
+    const LatTab &L = tab->lat[l];
+    double *f = l ? f1 : f0;
+    for (int i = 0; i < L.Q; ++i) {
+      const double W = L.w[i % L.n] * L.w[i / L.n];
+      f[(long long)i * ncell + k] = rho[k] * W;
+      if (thermal) f[(long long)(L.Q + i) * ncell + k] = (tab->cv - 1.0) * Tk * rho[k] * W;
+    }
   }
   fr[k] = u[k];
   fr[ncell + k] = u[ncell + k];
@@ -269,30 +284,259 @@ __global__ void k_pond_init(const Tab *__restrict__ tab, long long ncell, int th
   fr[3 * ncell + k] = Tk;
 }
 
-// rho, u, T of every cell from its populations in its own frame
-__global__ void k_pond_macros(const Tab *__restrict__ tab, long long ncell, int thermal, const double *f,
-                              const double *fr, double *rho, double *u, double *T) {
-  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= ncell) return;
-  const LatTab &L = tab->lat[0];
-  const double sT = sqrt(fr[3 * ncell + k]), ux = fr[k], uy = fr[ncell + k];
-  double r = 0, jx = 0, jy = 0, e = 0;
+// rho, u, T of cell k from its populations (set l) in its own frame
+__device__ __forceinline__ void pond_cell_macros(const Tab *tab, int l, long long ncell, int thermal,
+                                                 const double *f, const double *fr, long long k, double &r,
+                                                 double &ux, double &uy, double &T) {
+  const LatTab &L = tab->lat[l];
+  const double sT = sqrt(fr[3 * ncell + k]), fx = fr[k], fy = fr[ncell + k];
+  double jx = 0, jy = 0, e = 0;
+  r = 0;
   for (int i = 0; i < L.Q; ++i) {
     const double fi = f[(long long)i * ncell + k];
-    const double vx = sT * L.cr[i % L.n] + ux, vy = sT * L.cr[i / L.n] + uy;
+    const double vx = sT * L.cr[i % L.n] + fx, vy = sT * L.cr[i / L.n] + fy;
     r += fi;
     jx += vx * fi;
     jy += vy * fi;
     e += 0.5 * (vx * vx + vy * vy) * fi;
     if (thermal) e += f[(long long)(L.Q + i) * ncell + k];
   }
-  const double nux = jx / r, nuy = jy / r;
+  ux = jx / r;
+  uy = jy / r;
+  T = thermal ? (e / r - 0.5 * (ux * ux + uy * uy)) / tab->cv : 1.0;
+}
+
+// rho, u, T of every cell from its own set's populations in its own frame
+__global__ void k_pond_macros(const Tab *__restrict__ tab, long long ncell, int thermal, const double *f0,
+                              const double *f1, const uint8_t *__restrict__ cls, const double *fr, double *rho,
+                              double *u, double *T) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ncell) return;
+  const int l = cls[k] & 1;
+  double r, ux, uy, t;
+  pond_cell_macros(tab, l, ncell, thermal, l ? f1 : f0, fr, k, r, ux, uy, t);
   if (rho) rho[k] = r;
   if (u) {
-    u[k] = nux;
-    u[ncell + k] = nuy;
+    u[k] = ux;
+    u[ncell + k] = uy;
   }
-  if (T) T[k] = thermal ? (e / r - 0.5 * (nux * nux + nuy * nuy)) / tab->cv : 1.0;
+  if (T) T[k] = t;
+}
+
+// Knudsen-number criterion (Sec. IV.A.3), pass 1 on the co-moving state: each
+// cell's density and hard-sphere mean free path
+// lambda = 16/(5 sqrt(2 pi gamma)) mu a / p from its own set in its own frame
+__global__ void k_pond_kn_fields(const Tab *__restrict__ tab, long long ncell, int thermal, const double *f0,
+                                 const double *f1, const uint8_t *__restrict__ cls, const double *fr,
+                                 double *__restrict__ rho, double *__restrict__ lam) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ncell) return;
+  const int l = cls[k] & 1;
+  double r, ux, uy, T;
+  pond_cell_macros(tab, l, ncell, thermal, l ? f1 : f0, fr, k, r, ux, uy, T);
+  const double mu = tab->tau_mode == 1 ? tab->mu_ref * pow(T / tab->tau_ref_T, tab->mu_exp)
+                                       : (tab->tau - 0.5) * r * T * tab->dt;
+  const double gam = (tab->cv + 1.0) / tab->cv;
+  rho[k] = r;
+  lam[k] = 16.0 / (5.0 * sqrt(2.0 * M_PI * gam)) * mu * sqrt(gam * T) / (r * T);
+}
+
+// Raw completion along one axis in the frame v = s c + u: the degree < NL
+// part of each high-order Lagrange basis polynomial written in the particle
+// velocity v, evaluated at the low-order velocities.  The basis in c has the
+// monomial coefficients Vi (the inverse Vandermonde matrix of the high-order
+// nodes); ((v - u)/s)^k = s^-k sum_p C(k, p) v^p (-u)^(k-p) re-expands it in v.
+template <int NL, int NH>
+__device__ __forceinline__ void frame_completion(const Tab *tab, double s, double u, double (*K)[NL]) {
+  const LatTab &Lq = tab->lat[0];
+  double C[NH][NH], mu[NH];
+#pragma unroll
+  for (int k = 0; k < NH; ++k)
+#pragma unroll
+    for (int p = 0; p < NH; ++p) C[k][p] = (p == 0 || p == k) ? 1.0 : (p > k ? 0.0 : C[k - 1][p - 1] + C[k - 1][p]);
+  mu[0] = 1.0;
+#pragma unroll
+  for (int k = 1; k < NH; ++k) mu[k] = mu[k - 1] * (-u);
+  const double is = 1.0 / s;
+#pragma unroll
+  for (int A = 0; A < NH; ++A) {
+    double beta[NL];
+#pragma unroll
+    for (int p = 0; p < NL; ++p) beta[p] = 0.0;
+    double isk = 1.0;
+#pragma unroll
+    for (int k = 0; k < NH; ++k) {
+      const double ck = tab->Vi[A][k] * isk;
+#pragma unroll
+      for (int p = 0; p < NL; ++p)
+        if (p <= k) beta[p] += ck * C[k][p] * mu[k - p];
+      isk *= is;
+    }
+#pragma unroll
+    for (int a = 0; a < NL; ++a) {
+      const double v = s * Lq.cr[a] + u;
+      double acc = 0.0, vp = 1.0;
+#pragma unroll
+      for (int p = 0; p < NL; ++p) {
+        acc += beta[p] * vp;
+        vp *= v;
+      }
+      K[A][a] = acc;
+    }
+  }
+}
+
+// One cell's state of one set, given in its own frame {ufx, ufy, Tf}, in the
+// other set in the same frame (Sec. III.B-C, App. C).  Lifting keeps the
+// moments of the low-order set taken at the frame's particle velocities and
+// completes the others from the high-order equilibrium: the low-order
+// non-equilibrium part through the frame's completion matrices on top of the
+// high-order equilibrium, both equilibria at the cell's rho, u, T taken in the
+// frame (equilibrium factors at the reduced velocity (u - u_f)/sqrt(T_f) and
+// temperature T/T_f); the Hermite variant keeps Hermite coefficients in the
+// reduced velocities, whose matrix serves every frame.  Projection applies
+// the low-order Lagrange basis at the high-order nodes (the moments it keeps
+// span the same polynomials in every frame).
+template <int NL, int NH, bool TH>
+__device__ void pond_lift(const Tab *tab, const double *f, const double *g, double ufx, double ufy, double Tf,
+                          double *fo, double *go) {
+  constexpr int q = NL * NL;
+  const LatTab &Lq = tab->lat[0], &LQ = tab->lat[1];
+  const double sT = sqrt(Tf);
+  double r = 0, jx = 0, jy = 0, e = 0;
+#pragma unroll
+  for (int i = 0; i < q; ++i) {
+    const double vx = sT * Lq.cr[i % NL] + ufx, vy = sT * Lq.cr[i / NL] + ufy;
+    r += f[i];
+    jx += vx * f[i];
+    jy += vy * f[i];
+    e += 0.5 * (vx * vx + vy * vy) * f[i];
+    if (TH) e += g[i];
+  }
+  const double ux = jx / r, uy = jy / r;
+  const double T = TH ? (e / r - 0.5 * (ux * ux + uy * uy)) / tab->cv : 1.0;
+  const double uxr = (ux - ufx) / sT, uyr = (uy - ufy) / sT, th = T / Tf;
+  double pxl[NL], pyl[NL], pxh[NH], pyh[NH];
+  eq_axis<double, NL>(Lq, uxr, th, pxl);
+  eq_axis<double, NL>(Lq, uyr, th, pyl);
+  eq_axis<double, NH>(LQ, uxr, th, pxh);
+  eq_axis<double, NH>(LQ, uyr, th, pyh);
+  double Kx[NH][NL], Ky[NH][NL];
+  if (tab->lift_mode == MSL_LIFT_GRAD_HERMITE) {
+#pragma unroll
+    for (int A = 0; A < NH; ++A)
+#pragma unroll
+      for (int a = 0; a < NL; ++a) Kx[A][a] = Ky[A][a] = tab->KH[A][a];
+  } else {
+    frame_completion<NL, NH>(tab, sT, ufx, Kx);
+    frame_completion<NL, NH>(tab, sT, ufy, Ky);
+  }
+#pragma unroll
+  for (int h = 0; h < (TH ? 2 : 1); ++h) {
+    const double s = h ? tab->gfac * T : 1.0;
+    const double *in = h ? g : f;
+    double *out = h ? go : fo;
+    double neq[q];
+#pragma unroll
+    for (int i = 0; i < q; ++i) neq[i] = in[i] - s * r * pxl[i % NL] * pyl[i / NL];
+#pragma unroll
+    for (int A = 0; A < NH; ++A) {
+      double t[NL];
+#pragma unroll
+      for (int b = 0; b < NL; ++b) {
+        double sum = 0.0;
+#pragma unroll
+        for (int a = 0; a < NL; ++a) sum += Kx[A][a] * neq[a + NL * b];
+        t[b] = sum;
+      }
+#pragma unroll
+      for (int B = 0; B < NH; ++B) {
+        double cr = 0.0;
+#pragma unroll
+        for (int b = 0; b < NL; ++b) cr += Ky[B][b] * t[b];
+        out[A + NH * B] = s * r * pxh[A] * pyh[B] + cr;
+      }
+    }
+  }
+}
+
+template <int NL, int NH, bool TH>
+__device__ void pond_project(const Tab *tab, const double *f, const double *g, double *fo, double *go) {
+#pragma unroll
+  for (int h = 0; h < (TH ? 2 : 1); ++h) {
+    const double *in = h ? g : f;
+    double *out = h ? go : fo;
+#pragma unroll
+    for (int bp = 0; bp < NL; ++bp) {
+      double t[NH];   // along y first: t[A] = sum_B P[bp][B] f[A + NH B]
+#pragma unroll
+      for (int A = 0; A < NH; ++A) {
+        double sum = 0.0;
+#pragma unroll
+        for (int B = 0; B < NH; ++B) sum += tab->P[bp][B] * in[A + NH * B];
+        t[A] = sum;
+      }
+#pragma unroll
+      for (int ap = 0; ap < NL; ++ap) {
+        double sum = 0.0;
+#pragma unroll
+        for (int A = 0; A < NH; ++A) sum += tab->P[ap][A] * t[A];
+        out[ap + NL * bp] = sum;
+      }
+    }
+  }
+}
+
+// mode 0: every band cell of buffer (f0, f1, fr) converts its own set's state
+// into the other set; mode 1: every cell whose set differs from mask[] converts
+// its state into the new set (conv = 0: only its set changes) and takes it
+template <int NL, int NH, bool TH>
+__global__ void __launch_bounds__(256)
+k_pond_convert(const Tab *__restrict__ tab, long long ncell, int mode, int conv, double *f0, double *f1,
+               const double *__restrict__ fr, uint8_t *__restrict__ cls, const uint8_t *__restrict__ mask) {
+  constexpr int q = NL * NL, Q = NH * NH;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ncell) return;
+  const uint8_t cb = cls[k];
+  const int o = cb & 1;
+  int to;
+  if (mode == 0) {
+    if (!(cb & 2)) return;
+    to = o ^ 1;
+  } else {
+    to = mask[k] & 1;
+    if (to == o) return;
+    cls[k] = (uint8_t)to;
+    if (!conv) return;
+  }
+  const double ufx = fr[k], ufy = fr[ncell + k], Tf = fr[3 * ncell + k];
+  if (o == 0) {
+    double f[q], g[TH ? q : 1], fo[Q], go[TH ? Q : 1];
+#pragma unroll
+    for (int i = 0; i < q; ++i) {
+      f[i] = f0[(long long)i * ncell + k];
+      if (TH) g[i] = f0[(long long)(q + i) * ncell + k];
+    }
+    pond_lift<NL, NH, TH>(tab, f, g, ufx, ufy, Tf, fo, go);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      f1[(long long)i * ncell + k] = fo[i];
+      if (TH) f1[(long long)(Q + i) * ncell + k] = go[i];
+    }
+  } else {
+    double f[Q], g[TH ? Q : 1], fo[q], go[TH ? q : 1];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      f[i] = f1[(long long)i * ncell + k];
+      if (TH) g[i] = f1[(long long)(Q + i) * ncell + k];
+    }
+    pond_project<NL, NH, TH>(tab, f, g, fo, go);
+#pragma unroll
+    for (int i = 0; i < q; ++i) {
+      f0[(long long)i * ncell + k] = fo[i];
+      if (TH) f0[(long long)(q + i) * ncell + k] = go[i];
+    }
+  }
 }
 
 static PondArgs pond_args(const msl_ctx *c) {
@@ -307,48 +551,86 @@ static PondArgs pond_args(const msl_ctx *c) {
   return pa;
 }
 
+static unsigned pond_blocks(const msl_ctx *c) { return (unsigned)((c->ncell + 255) / 256); }
+
 int msl_pond_launch_init(msl_ctx *c, const double *rho, const double *u, const double *T) {
-  const unsigned nb = (unsigned)((c->ncell + 255) / 256);
-  hipLaunchKernelGGL(k_pond_init, dim3(nb), dim3(256), 0, c->stream, c->dtab, c->ncell, c->cfg.thermal, rho, u,
-                     T, c->pond_f[c->cur], c->pond_fr[c->cur]);
+  hipLaunchKernelGGL(k_pond_init, dim3(pond_blocks(c)), dim3(256), 0, c->stream, c->dtab, c->ncell,
+                     c->cfg.thermal, c->nlat, rho, u, T, c->pond_f[0][c->cur],
+                     c->nlat > 1 ? c->pond_f[1][c->cur] : nullptr, c->pond_fr[c->cur]);
   return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
 }
 
 int msl_pond_launch_macros(msl_ctx *c, double *rho, double *u, double *T) {
-  const unsigned nb = (unsigned)((c->ncell + 255) / 256);
-  hipLaunchKernelGGL(k_pond_macros, dim3(nb), dim3(256), 0, c->stream, c->dtab, c->ncell, c->cfg.thermal,
-                     c->pond_f[c->cur], c->pond_fr[c->cur], rho, u, T);
+  hipLaunchKernelGGL(k_pond_macros, dim3(pond_blocks(c)), dim3(256), 0, c->stream, c->dtab, c->ncell,
+                     c->cfg.thermal, c->pond_f[0][c->cur], c->nlat > 1 ? c->pond_f[1][c->cur] : nullptr,
+                     c->cls, c->pond_fr[c->cur], rho, u, T);
   return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
 }
 
+// conversion launch over buffer `buf` (mode and mask as in k_pond_convert)
+static int pond_convert(msl_ctx *c, int buf, int mode, int conv, const uint8_t *mask) {
+  return msl_pair_dispatch(2, c->htab.lat[0].n, c->htab.lat[1].n, [&]<int D, int NL, int NH>() {
+    if (c->cfg.thermal)
+      hipLaunchKernelGGL((k_pond_convert<NL, NH, true>), dim3(pond_blocks(c)), dim3(256), 0, c->stream, c->dtab,
+                         c->ncell, mode, conv, c->pond_f[0][buf], c->pond_f[1][buf], c->pond_fr[buf], c->cls, mask);
+    else
+      hipLaunchKernelGGL((k_pond_convert<NL, NH, false>), dim3(pond_blocks(c)), dim3(256), 0, c->stream, c->dtab,
+                         c->ncell, mode, conv, c->pond_f[0][buf], c->pond_f[1][buf], c->pond_fr[buf], c->cls, mask);
+    return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
+  });
+}
+
+// new sets from `mask` (converting the cells that change when conv), then the
+// band of the current buffer
+int msl_pond_launch_set_mask(msl_ctx *c, const uint8_t *mask, int conv) {
+  if (c->nlat < 2) return MSL_OK;   // the mask check admits only zeros
+  int rc = pond_convert(c, c->cur, 1, conv, mask);
+  if (!rc) rc = msl_launch_classify(c);
+  if (!rc && conv) rc = pond_convert(c, c->cur, 0, 1, nullptr);
+  return rc;
+}
+
 template <int N, bool TH, bool QE>
-static int pond_step_n(msl_ctx *c) {
+static int pond_step_n(msl_ctx *c, int lat) {
   constexpr int TW = PondTraits<N, TH>::TW;
   const PondArgs pa = pond_args(c);
   const dim3 grid((unsigned)((pa.nx + TW - 1) / TW), (unsigned)pa.ny);
-  hipLaunchKernelGGL((k_pond_step<N, TH, QE>), grid, dim3(256), 0, c->stream, c->dtab, pa,
-                     c->pond_f[c->cur], c->pond_fr[c->cur], c->pond_f[c->cur ^ 1], c->pond_fr[c->cur ^ 1],
-                     c->flag, c->pond_stats, (int *)(c->pond_stats + 1));
+  hipLaunchKernelGGL((k_pond_step<N, TH, QE>), grid, dim3(256), 0, c->stream, c->dtab, lat, c->cls, pa,
+                     c->pond_f[lat][c->cur], c->pond_fr[c->cur], c->pond_f[lat][c->cur ^ 1],
+                     c->pond_fr[c->cur ^ 1], c->flag, c->pond_stats, (int *)(c->pond_stats + 1));
   return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
 }
 
 template <bool TH, bool QE>
-static int pond_step_th(msl_ctx *c) {
-  switch (c->htab.lat[0].n) {
-    case 3: return pond_step_n<3, TH, QE>(c);
-    case 4: return pond_step_n<4, TH, QE>(c);
-    case 5: return pond_step_n<5, TH, QE>(c);
-    case 6: return pond_step_n<6, TH, QE>(c);
+static int pond_step_th(msl_ctx *c, int lat) {
+  switch (c->htab.lat[lat].n) {
+    case 3: return pond_step_n<3, TH, QE>(c, lat);
+    case 4: return pond_step_n<4, TH, QE>(c, lat);
+    case 5: return pond_step_n<5, TH, QE>(c, lat);
+    case 6: return pond_step_n<6, TH, QE>(c, lat);
   }
   return MSL_EINVAL;
 }
 
-// one step: the new buffers become current
+// one step: [the Knudsen-number criterion pass], one launch per set, the band
+// of the new buffer; the new buffers become current
 int msl_pond_launch_step(msl_ctx *c) {
   int rc;
-  if (c->cfg.thermal) rc = c->htab.qe ? pond_step_th<true, true>(c) : pond_step_th<true, false>(c);
-  else rc = c->htab.qe ? pond_step_th<false, true>(c) : pond_step_th<false, false>(c);
-  if (rc) return rc;
+  if (c->nlat > 1 && c->cfg.crit_kind == MSL_CRIT_KN && c->cfg.crit_every > 0 &&
+      c->step % c->cfg.crit_every == 0) {
+    hipLaunchKernelGGL(k_pond_kn_fields, dim3(pond_blocks(c)), dim3(256), 0, c->stream, c->dtab, c->ncell,
+                       c->cfg.thermal, c->pond_f[0][c->cur], c->pond_f[1][c->cur], c->cls, c->pond_fr[c->cur],
+                       c->kn_rho, c->kn_lam);
+    if (hipGetLastError() != hipSuccess) return MSL_EHIP;
+    if ((rc = msl_launch_kn_mask(c))) return rc;
+    if ((rc = msl_pond_launch_set_mask(c, c->newmask, 1))) return rc;
+  }
+  for (int l = 0; l < c->nlat; ++l) {
+    if (c->cfg.thermal) rc = c->htab.qe ? pond_step_th<true, true>(c, l) : pond_step_th<true, false>(c, l);
+    else rc = c->htab.qe ? pond_step_th<false, true>(c, l) : pond_step_th<false, false>(c, l);
+    if (rc) return rc;
+  }
+  if (c->nlat > 1 && (rc = pond_convert(c, c->cur ^ 1, 0, 1, nullptr))) return rc;
   c->cur ^= 1;
   return MSL_OK;
 }

@@ -81,3 +81,24 @@ def compare_macros(s, o, tol, uscale, rscale=1.0, Tscale=1.0):
     say(f"  macros: rho {e_rho:.3e} u {e_u:.3e} T {e_T:.3e}")
     assert e_rho <= tol and e_u <= tol and e_T <= tol, (e_rho, e_u, e_T)
     return e_rho, e_u, e_T
+
+
+def band_cells(mask, periodic):
+    """Cells with a cell of the other order within the 3-point stencil's reach
+    (2 cells along each axis, a 5 x 5 box); periodic per axis (x, y)."""
+    m = mask.reshape(mask.shape[-2:]).astype(np.int8)
+    pad = [(2, 2), (2, 2)]
+    p = m
+    for ax, per in ((1, periodic[0]), (0, periodic[1])):
+        w = [(0, 0), (0, 0)]
+        w[ax] = pad[ax]
+        p = np.pad(p, w, mode="wrap" if per else "edge")
+    ny, nx = m.shape
+    hi = np.zeros_like(m)
+    lo = np.ones_like(m)
+    for dy in range(5):
+        for dx in range(5):
+            v = p[dy:dy + ny, dx:dx + nx]
+            hi = np.maximum(hi, v)
+            lo = np.minimum(lo, v)
+    return ((m == 0) & (hi == 1)).reshape(-1), ((m == 1) & (lo == 0)).reshape(-1)

@@ -123,3 +123,21 @@ def test_knudsen_criterion_workspace():
     assert b_kn - b_ma >= 16 * 64 * 32
     with pytest.raises(msl.MslError):
         msl.workspace_bytes(dict(base, crit_kind=4))
+
+
+def test_comoving_two_set_configs():
+    """Co-moving frames take two velocity sets with Grad or Hermite lifting and
+    fixed sets or the Knudsen-number criterion (FP64, 2D, lattice frame); the
+    learned closure and the other criteria are rejected.  The workspace holds
+    both sets' populations in two buffers and the frames."""
+    base = inputs.base_config(nx=40, ny=8, n_low=4, n_high=5, thermal=1, pond=1)
+    one = msl.workspace_bytes(dict(base, n_low=4, n_high=0))
+    two = msl.workspace_bytes(base)
+    assert two - one >= 8 * 2 * 2 * 25 * 40 * 8   # two buffers of f and g of D2Q25
+    msl.workspace_bytes(dict(base, lift_mode=inputs.LIFT_GRAD_HERMITE))
+    msl.workspace_bytes(dict(base, crit_kind=inputs.CRIT_KN, crit_every=5, crit_thr=0.02))
+    for bad in (dict(lift_mode=inputs.LIFT_MLP), dict(crit_kind=inputs.CRIT_MA, crit_every=5),
+                dict(crit_kind=inputs.CRIT_PINEQ, crit_every=5), dict(store=inputs.STORE_FP32),
+                dict(dim=3, nz=8)):
+        with pytest.raises(msl.MslError):
+            msl.workspace_bytes(dict(base, **bad))

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 from paper_2102_12559_amd import inputs
-from tests.gpu_util import compare_pops, run_pair, say, weights
+from tests.gpu_util import band_cells, compare_pops, run_pair, say, weights
 
 pytestmark = pytest.mark.gpu
 
@@ -25,27 +25,6 @@ def _gpu():
         pytest.skip("no GPU")
     from paper_2102_12559_amd import msl
     msl.lib()
-
-
-def band_cells(mask, periodic):
-    """Cells with a cell of the other order within the 3-point stencil's reach
-    (2 cells along each axis, a 5 x 5 box); periodic per axis (x, y)."""
-    m = mask.reshape(mask.shape[-2:]).astype(np.int8)
-    pad = [(2, 2), (2, 2)]
-    p = m
-    for ax, per in ((1, periodic[0]), (0, periodic[1])):
-        w = [(0, 0), (0, 0)]
-        w[ax] = pad[ax]
-        p = np.pad(p, w, mode="wrap" if per else "edge")
-    ny, nx = m.shape
-    hi = np.zeros_like(m)
-    lo = np.ones_like(m)
-    for dy in range(5):
-        for dx in range(5):
-            v = p[dy:dy + ny, dx:dx + nx]
-            hi = np.maximum(hi, v)
-            lo = np.minimum(lo, v)
-    return ((m == 0) & (hi == 1)).reshape(-1), ((m == 1) & (lo == 0)).reshape(-1)
 
 
 def compare_band(s, o, tol, fg=0, periodic=(True, True), absolute=False):
