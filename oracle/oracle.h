@@ -129,7 +129,8 @@ int or_step_cells(const or_ctx *ctx, int ncells, const int64_t *cells,
  * the other set is lifted or projected into the cell's set in its own frame
  * (lift_mode 0 or 1); crit_kind 0 keeps the sets of or_pond_set_mask, 3
  * re-selects them every crit_every steps by the Knudsen number.  Needs FP64
- * storage (store 0) and periodic, fixed-equilibrium or zero-gradient faces.
+ * storage (store 0) and periodic, fixed-equilibrium, zero-gradient or (not on
+ * x faces) diffuse-wall faces.
  * or_pond_step returns -4 when a departure point leaves the two-cell reach or
  * a state turns non-finite. */
 typedef struct or_pond or_pond;

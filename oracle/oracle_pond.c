@@ -32,7 +32,10 @@
  * own frame.
  * Collocation points outside the domain: periodic faces wrap, zero-gradient
  * faces repeat the edge cell (its populations and frame), fixed-equilibrium
- * faces give the face state's co-moving equilibrium in the face state's frame.
+ * faces give the face state's co-moving equilibrium in the face state's frame,
+ * and diffuse walls give the wall state's co-moving equilibrium in the wall's
+ * frame, with the density that balances the wall-normal particle flux of the
+ * adjacent fluid cell.
  */
 #include "oracle_internal.h"
 
@@ -149,6 +152,59 @@ static void point_state(const or_pond *c, int l, const int *qin, double *f, doub
       }
       return;
     }
+  }
+  /* a diffuse wall (the highest such axis): the wall state's co-moving
+   * equilibrium in the wall's frame {u_w, T_w}, scaled by rho_w so that the
+   * wall-normal particle flux it sends into the fluid equals the flux arriving
+   * from the adjacent fluid cell, both counted in the wall's frame (the
+   * adjacent cell's populations transferred there, eq. fll) */
+  for (int a = c->D - 1; a >= 0; a--) {
+    if (q[a] >= 0 && q[a] < c->N[a]) continue;
+    const int side = q[a] < 0 ? 0 : 1, face = 2 * a + side;
+    if (c->cfg.bc[face] != 3) continue;
+    int qa[3] = {q[0], q[1], q[2]};
+    qa[a] = side ? c->N[a] - 1 : 0;
+    for (int b = 0; b < c->D; b++) {
+      if (qa[b] >= 0 && qa[b] < c->N[b]) continue;
+      const int fb = 2 * b + (qa[b] < 0 ? 0 : 1);
+      if (c->cfg.bc[fb] == 0) qa[b] = ((qa[b] % c->N[b]) + c->N[b]) % c->N[b];
+      else qa[b] = qa[b] < 0 ? 0 : c->N[b] - 1;
+    }
+    const int64_t ka = pcell(c, qa);
+    const int o = c->order[ka];
+    const lat_t *Lo = c->L[o];
+    const double *ws = c->cfg.bc_state[face];
+    const double Tw = c->cfg.thermal ? ws[4] : 1.0;
+    const ld sTw = sqrtl((ld)Tw), uwn = (ld)ws[1 + a];
+    /* the adjacent cell's populations transferred into the wall's frame */
+    pframe_t *src = (pframe_t *)malloc(sizeof(pframe_t)), *dst = (pframe_t *)malloc(sizeof(pframe_t));
+    dst->Minv = (ld *)malloc(sizeof(ld) * c->Q[o] * c->Q[o]);
+    ld uk[3], uw[3];
+    for (int b = 0; b < 3; b++) {
+      uk[b] = (ld)c->fr[(int64_t)b * c->ncell + ka];
+      uw[b] = b < c->D ? (ld)ws[1 + b] : 0.0L;
+    }
+    frame_velocities(Lo, uk, (ld)c->fr[(int64_t)3 * c->ncell + ka], src);
+    frame_target(Lo, uw, (ld)Tw, dst);
+    double fk[OR_MAXQ];
+    ld fw[OR_MAXQ];
+    for (int i = 0; i < c->Q[o]; i++) fk[i] = c->f[o][(int64_t)i * c->ncell + ka];
+    transfer(Lo, src, dst, fk, fw);
+    free(dst->Minv); free(src); free(dst);
+    ld in = 0.0L, out = 0.0L;
+    for (int i = 0; i < c->Q[o]; i++) {
+      const ld vw = sTw * Lo->cl[i][a] + uwn;
+      if (side ? vw > 0.0L : vw < 0.0L) in += fabsl(vw) * fw[i];
+      if (side ? vw < 0.0L : vw > 0.0L) out += fabsl(vw) * Lo->Wl[i];
+    }
+    const double rw = (double)(in / out);
+    for (int b = 0; b < 3; b++) u[b] = b < c->D ? (ld)ws[1 + b] : 0.0L;
+    *T = (ld)Tw;
+    for (int i = 0; i < Q; i++) {
+      f[i] = rw * L->W[i];
+      if (c->cfg.thermal) g[i] = (c->cfg.cv - 0.5 * c->D) * Tw * rw * L->W[i];
+    }
+    return;
   }
   for (int a = 0; a < c->D; a++) {
     if (q[a] >= 0 && q[a] < c->N[a]) continue;
@@ -407,8 +463,14 @@ int or_pond_create(const or_config *cfg, or_pond **out) {
   if (cfg->crit_kind != 0 && cfg->crit_kind != 3) return -1;   /* fixed sets or the Knudsen number */
   if (cfg->tau <= 0.5 || (cfg->tau2 > 0.0 && cfg->tau2 <= 0.5)) return -1;
   if (cfg->store != 0) return -1;                       /* FP64 populations */
-  for (int f = 0; f < 2 * cfg->dim; f++)
-    if (cfg->bc[f] != 0 && cfg->bc[f] != 1 && cfg->bc[f] != 2) return -1;
+  for (int f = 0; f < 2 * cfg->dim; f++) {
+    if (cfg->bc[f] < 0 || cfg->bc[f] > 3) return -1;
+    if (cfg->bc[f] == 3) {   /* diffuse walls: not on x faces, lower faces periodic or zero-gradient */
+      if (f < 2) return -1;
+      for (int g = 0; g < 2 * (f / 2); g++)
+        if (cfg->bc[g] != 0 && cfg->bc[g] != 2) return -1;
+    }
+  }
   or_pond *c = (or_pond *)calloc(1, sizeof(or_pond));
   c->cfg = *cfg;
   c->D = cfg->dim;
