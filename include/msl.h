@@ -119,8 +119,11 @@ typedef struct msl_config {
                                  (lift_mode Grad or Hermite), and the sets are those of
                                  msl_set_mask or, with crit_kind MSL_CRIT_KN, re-selected every
                                  crit_every steps from each cell's own state.  Needs dim 2, FP64
-                                 storage, no other criterion, the lattice frame, and periodic,
-                                 fixed-equilibrium or zero-gradient faces; dt = cfl / max|c| of
+                                 storage, no other criterion and the lattice frame; faces
+                                 periodic, fixed-equilibrium, zero-gradient or diffuse walls
+                                 (y faces; the wall's co-moving equilibrium in the wall's frame
+                                 at the density balancing the wall-normal flux of the adjacent
+                                 cell, both counted in the wall's frame); dt = cfl / max|c| of
                                  the sets, and a step whose departure point leaves the two-cell
                                  reach in some frame returns MSL_EUNSTABLE (lower cfl).
                                  Populations out (msl_get_populations) are given in each cell's

@@ -218,8 +218,6 @@ static const char *check_config(const msl_config *cfg) {
     if (cfg->crit_kind != MSL_CRIT_NONE && cfg->crit_kind != MSL_CRIT_KN)
       return "co-moving frames: fixed sets or the Knudsen-number criterion";
     if (!trivial_frame) return "co-moving frames replace the global frame";
-    for (int f = 0; f < 4; ++f)
-      if (cfg->bc[f] == MSL_BC_DIFFUSE_WALL) return "co-moving frames: no diffuse walls";
   }
   for (int f = 0; f < 2 * cfg->dim; ++f) {
     if (cfg->bc[f] < 0 || cfg->bc[f] > 3) return "unknown boundary rule";
@@ -308,7 +306,9 @@ static void make_layout(const msl_config *cfg, Layout &L) {
   if (cfg->crit_kind == MSL_CRIT_KN && nl > 1) off = align256(off + (size_t)g.ncell * 2 * 8);
   // co-moving frames: two buffers of populations and frames, iteration counters
   L.off_pond = off;
-  if (cfg->pond) off = align256(off + (size_t)g.ncell * 8 * 2 * (L.np[0] + (nl > 1 ? L.np[1] : 0) + 4) + 64);
+  // (then the wall densities of the two y faces, 2 nx doubles)
+  if (cfg->pond)
+    off = align256(off + (size_t)g.ncell * 8 * 2 * (L.np[0] + (nl > 1 ? L.np[1] : 0) + 4) + 64 + (size_t)16 * g.nx);
   // learned closure
   if (cfg->lift_mode == MSL_LIFT_MLP && nl > 1) {
     const int q = L.Q[0], Q = L.Q[1];
@@ -522,6 +522,7 @@ int msl_create(const msl_config *cfg, void *ws, size_t bytes, void *stream, msl_
     c->pond_fr[0] = pb;
     c->pond_fr[1] = pb + nfr;
     c->pond_stats = (unsigned long long *)(pb + 2 * nfr);
+    c->pond_wall = pb + 2 * nfr + 8;
   }
   c->tcount = c->tlist + (size_t)L.geo.ntx * L.geo.nty * L.geo.ntz;
   if (L.mlpP) {

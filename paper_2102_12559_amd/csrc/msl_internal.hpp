@@ -146,6 +146,7 @@ struct msl_ctx {
   // buffer ([set][buffer]) and frames [4][ncell] of each buffer; stats:
   // iteration sum (u64), then maximum (int)
   double *pond_f[2][2], *pond_fr[2];
+  double *pond_wall;      // diffuse y walls: wall density per column [2][nx] (low, high face)
   unsigned long long *pond_stats;
   long long pond_cells_steps;
   uint8_t *tflag;         // per micro-tile: bit0 has low cells, bit1 has high cells

@@ -65,13 +65,17 @@ struct PondTraits {
 };
 
 // the collocation point (x, y) (possibly outside the domain): the cell index
-// whose state it takes, or -1 - face for a fixed-equilibrium face state
+// whose state it takes, -1 - face for a fixed-equilibrium face state, or
+// -5 - (side nx + x) for the diffuse wall point of column x on the low (side
+// 0) or high y face
 __device__ __forceinline__ long long pond_resolve(const PondArgs &pa, int x, int y) {
   if (x < 0 && pa.bc[0] == MSL_BC_FIXED_EQ) return -1;
   if (x >= pa.nx && pa.bc[1] == MSL_BC_FIXED_EQ) return -2;
   if (y < 0 && pa.bc[2] == MSL_BC_FIXED_EQ) return -3;
   if (y >= pa.ny && pa.bc[3] == MSL_BC_FIXED_EQ) return -4;
   if (x < 0 || x >= pa.nx) x = pa.bc[0] == MSL_BC_PERIODIC ? (x + pa.nx) % pa.nx : (x < 0 ? 0 : pa.nx - 1);
+  if (y < 0 && pa.bc[2] == MSL_BC_DIFFUSE_WALL) return -5 - (long long)x;
+  if (y >= pa.ny && pa.bc[3] == MSL_BC_DIFFUSE_WALL) return -5 - ((long long)pa.nx + x);
   if (y < 0 || y >= pa.ny) y = pa.bc[2] == MSL_BC_PERIODIC ? (y + pa.ny) % pa.ny : (y < 0 ? 0 : pa.ny - 1);
   return (long long)y * pa.nx + x;
 }
@@ -81,7 +85,7 @@ __global__ void __launch_bounds__(256)
 k_pond_step(const Tab *__restrict__ tab, int lat, const uint8_t *__restrict__ cls, PondArgs pa,
             const double *__restrict__ fin, const double *__restrict__ frin, double *__restrict__ fout,
             double *__restrict__ frout, int *__restrict__ flag, unsigned long long *__restrict__ itsum,
-            int *__restrict__ itmax) {
+            int *__restrict__ itmax, const double *__restrict__ wrho) {
   using Tr = PondTraits<N, TH>;
   constexpr int Q = Tr::Q, NP = Tr::NP, GS = Tr::GS, TW = Tr::TW, SW = Tr::SW, SP = Tr::SP,
                 STRIDE = Tr::STRIDE;
@@ -100,11 +104,16 @@ k_pond_step(const Tab *__restrict__ tab, int lat, const uint8_t *__restrict__ cl
     if (q >= 0) {
       v = m < NP ? fin[(long long)m * pa.ncell + q] : frin[(long long)(m - NP) * pa.ncell + q];
     } else {
-      // a fixed-equilibrium face state: rho W_i (and (cv - 1) T rho W_i) in its own frame
-      const double *st = pa.st[-1 - q];
+      // a fixed-equilibrium face state, or a diffuse wall point at the wall
+      // state with the column's wall density: rho W_i (and (cv - 1) T rho W_i)
+      // in its own frame
+      const bool wall = q <= -5;
+      const long long wi = wall ? -5 - q : 0;
+      const double *st = wall ? pa.st[wi < pa.nx ? 2 : 3] : pa.st[-1 - q];
+      const double rs = wall ? wrho[wi] : st[0];
       const double Ts = TH ? st[4] : 1.0;
       const int j = m % Q;
-      const double fj = st[0] * L.w[j % N] * L.w[j / N];
+      const double fj = rs * L.w[j % N] * L.w[j / N];
       if (m < Q) v = fj;
       else if (m < NP) v = (cv - 1.0) * Ts * fj;
       else v = m - NP == 0 ? st[1] : (m - NP == 1 ? st[2] : (m - NP == 2 ? 0.0 : Ts));
@@ -539,6 +548,98 @@ k_pond_convert(const Tab *__restrict__ tab, long long ncell, int mode, int conv,
   }
 }
 
+// Diffuse y walls: per column, the density rho_w of the wall state's co-moving
+// equilibrium {u_w, T_w} that balances the wall-normal particle flux of the
+// adjacent fluid cell, both fluxes counted in the wall's frame: the cell's
+// populations (its own set, its own frame) are transferred to the wall's frame
+// with the per-axis Lagrange rows of the step kernel.
+template <int N>
+__device__ double pond_wall_density(const Tab *tab, int l, const double *f, long long ncell, long long k,
+                                    const double *fr, const double *ws, int side, int thermal) {
+  constexpr int Q = N * N;
+  const LatTab &L = tab->lat[l];
+  double xn[N], den[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) xn[m] = L.cr[m];
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    double p = 1.0;
+#pragma unroll
+    for (int cc = 0; cc < N; ++cc)
+      if (cc != m) p *= xn[m] - xn[cc];
+    den[m] = 1.0 / p;
+  }
+  const double Tw = thermal ? ws[4] : 1.0, sTw = sqrt(Tw), isTw = 1.0 / sTw;
+  const double sTk = sqrt(fr[3 * ncell + k]), ukx = fr[k], uky = fr[ncell + k];
+  // G[a][a'] = l_a((sqrt(T_k) c_a' + u_k - u_w) / sqrt(T_w)) along x and y
+  double Gx[N][N], Gy[N][N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    const double zx = (sTk * xn[m] + ukx - ws[1]) * isTw, zy = (sTk * xn[m] + uky - ws[2]) * isTw;
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      double px = den[a], py = den[a];
+#pragma unroll
+      for (int cc = 0; cc < N; ++cc)
+        if (cc != a) {
+          px *= zx - xn[cc];
+          py *= zy - xn[cc];
+        }
+      Gx[a][m] = px;
+      Gy[a][m] = py;
+    }
+  }
+  double in = 0.0, out = 0.0;
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    // the wall-normal (y) velocity of the wall frame's node b
+    const double vw = sTw * xn[b] + ws[2];
+    const bool towall = side ? vw > 0.0 : vw < 0.0, fromwall = side ? vw < 0.0 : vw > 0.0;
+    if (!towall && !fromwall) continue;
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      if (towall) {
+        double s = 0.0;
+#pragma unroll
+        for (int bp = 0; bp < N; ++bp) {
+          double t = 0.0;
+#pragma unroll
+          for (int ap = 0; ap < N; ++ap) t += Gx[a][ap] * f[(long long)(ap + N * bp) * ncell + k];
+          s += Gy[b][bp] * t;
+        }
+        in += fabs(vw) * s;
+      } else {
+        out += fabs(vw) * L.w[a] * L.w[b];
+      }
+    }
+  }
+  (void)Q;
+  return in / out;
+}
+
+__global__ void k_pond_wall(const Tab *__restrict__ tab, PondArgs pa, int thermal, int faces, const double *f0,
+                            const double *f1, const uint8_t *__restrict__ cls, const double *__restrict__ fr,
+                            double *__restrict__ wrho) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nx = pa.nx, ny = pa.ny;
+  const long long ncell = pa.ncell;
+  if (t >= 2 * nx) return;
+  const int side = t / nx, x = t % nx;
+  if (!(faces & (1 << side))) return;
+  const long long k = (long long)(side ? ny - 1 : 0) * nx + x;
+  const int l = cls[k] & 1;
+  const double *f = l ? f1 : f0;
+  const double *ws = pa.st[2 + side];
+  double r = 0.0;
+  switch (tab->lat[l].n) {
+    case 3: r = pond_wall_density<3>(tab, l, f, ncell, k, fr, ws, side, thermal); break;
+    case 4: r = pond_wall_density<4>(tab, l, f, ncell, k, fr, ws, side, thermal); break;
+    case 5: r = pond_wall_density<5>(tab, l, f, ncell, k, fr, ws, side, thermal); break;
+    case 6: r = pond_wall_density<6>(tab, l, f, ncell, k, fr, ws, side, thermal); break;
+  }
+  wrho[t] = r;
+}
+
 static PondArgs pond_args(const msl_ctx *c) {
   PondArgs pa;
   pa.nx = c->geo.nx;
@@ -597,7 +698,7 @@ static int pond_step_n(msl_ctx *c, int lat) {
   const dim3 grid((unsigned)((pa.nx + TW - 1) / TW), (unsigned)pa.ny);
   hipLaunchKernelGGL((k_pond_step<N, TH, QE>), grid, dim3(256), 0, c->stream, c->dtab, lat, c->cls, pa,
                      c->pond_f[lat][c->cur], c->pond_fr[c->cur], c->pond_f[lat][c->cur ^ 1],
-                     c->pond_fr[c->cur ^ 1], c->flag, c->pond_stats, (int *)(c->pond_stats + 1));
+                     c->pond_fr[c->cur ^ 1], c->flag, c->pond_stats, (int *)(c->pond_stats + 1), c->pond_wall);
   return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
 }
 
@@ -624,6 +725,16 @@ int msl_pond_launch_step(msl_ctx *c) {
     if (hipGetLastError() != hipSuccess) return MSL_EHIP;
     if ((rc = msl_launch_kn_mask(c))) return rc;
     if ((rc = msl_pond_launch_set_mask(c, c->newmask, 1))) return rc;
+  }
+  const int faces = (c->cfg.bc[2] == MSL_BC_DIFFUSE_WALL ? 1 : 0) | (c->cfg.bc[3] == MSL_BC_DIFFUSE_WALL ? 2 : 0);
+  if (faces) {
+    // the wall densities from the current state (the wall states travel in
+    // the kernel arguments)
+    const PondArgs pa = pond_args(c);
+    hipLaunchKernelGGL(k_pond_wall, dim3((unsigned)((2 * pa.nx + 255) / 256)), dim3(256), 0, c->stream, c->dtab,
+                       pa, c->cfg.thermal, faces, c->pond_f[0][c->cur],
+                       c->nlat > 1 ? c->pond_f[1][c->cur] : nullptr, c->cls, c->pond_fr[c->cur], c->pond_wall);
+    if (hipGetLastError() != hipSuccess) return MSL_EHIP;
   }
   for (int l = 0; l < c->nlat; ++l) {
     if (c->cfg.thermal) rc = c->htab.qe ? pond_step_th<true, true>(c, l) : pond_step_th<true, false>(c, l);
