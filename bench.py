@@ -596,18 +596,18 @@ def pond_paper(args):
     """The paper's two co-moving-frame set-ups with two velocity sets (Sec. IV,
     two-population model, Pr = 2/3 through tau2, gamma = 5/3, FP64):
     pond-shock: the Mach-1.6 shock structure, hard-sphere viscosity with the
-      upstream mean free path 10 cells (dx = 0.1 lambda_1; the paper resolves
-      0.02 lambda_1, where the coupled run here diverges after about 200 steps
-      while either set alone runs), D2Q16 with D2Q25 where the Knudsen number
-      exceeds 0.02 (re-selected every 20 steps), 4096 x 4, Rankine-Hugoniot
-      states at fixed x faces, 4000 steps;
+      upstream mean free path 50 cells (dx = 0.02 lambda_1), D2Q16 with D2Q25
+      where the Knudsen number exceeds 0.02 and within 10 cells of such cells
+      (re-selected every 20 steps; without the margin the interface sits inside
+      the developing shock and the run diverges after about 200 steps), 4096 x 4,
+      Rankine-Hugoniot states at fixed x faces, 4000 steps;
     pond-couette: the micro-Couette flow at Kn = 0.1 between diffuse walls
       moving at -+0.1, 300 cells across (4 x 300, x periodic), D2Q9 with D2Q16
       in 30-cell layers next to the walls, 4000 steps.
-    Lifting keeps Hermite coefficients in the frame's reduced velocities: at
-    lambda_1 = 50 cells the raw completion at the frame's particle velocities
-    diverged within 35 steps (oracle and GPU alike), the Hermite one after
-    about 200.
+    Lifting keeps Hermite coefficients in the frame's reduced velocities (at
+    lambda_1 = 50 cells without the margin the raw completion at the frame's
+    particle velocities diverged within 35 steps, the Hermite one after about
+    200).
     Both grids are small (16 k and 1.2 k cells): the step time is launch and
     latency bound, so the line reports the step rate and the predictor-corrector
     passes; the FP64 work per step is given for reference."""
@@ -624,14 +624,14 @@ def pond_paper(args):
                            device="cuda:0")
         dt = probe.dt
         probe.close()
-        w = inputs.shock_c3(ma1=1.6, nx=nx, ny=ny, dt=dt, n_high=nh, lam=10.0)
+        w = inputs.shock_c3(ma1=1.6, nx=nx, ny=ny, dt=dt, n_high=nh, lam=50.0)
         cfg = dict(w["cfg"], pond=1, n_low=nl, cfl=cfl, crit_kind=inputs.CRIT_KN, crit_thr=0.02,
-                   crit_every=20, lift_mode=inputs.LIFT_GRAD_HERMITE)
+                   crit_every=20, crit_margin=10, lift_mode=inputs.LIFT_GRAD_HERMITE)
         cfg["tau2"] = 0.5 + 1.5 * (cfg["tau"] - 0.5)
         rho, u, T = w["rho"], w["u"], w["T"]
         mask = np.zeros((1, ny, nx), np.uint8)
         desc = ("shock structure in co-moving frames: Mach 1.6, D2Q16 + D2Q25 where Kn > 0.02 (every 20 "
-                "steps, Hermite lifting), lambda_1 = 10 cells, Pr 2/3, 4096x4, fp64")
+                "steps, 10-cell margin, Hermite lifting), lambda_1 = 50 cells, Pr 2/3, 4096x4, fp64")
     else:
         nx, ny, nl, nh, cfl, layer = 4, 300, 3, 4, 0.45, 30
         probe = msl.Solver(inputs.base_config(nx=8, ny=8, n_low=nl, n_high=nh, cfl=cfl, pond=1),

@@ -130,6 +130,10 @@ typedef struct msl_config {
                                  own frame (msl_pond_frames); populations in, conservation sums,
                                  error norms and checkpoints are not offered.  0: one global
                                  frame. */
+  int crit_margin;            /* >= 0: the high-order set also takes every cell within this many
+                                 cells (per axis, a box; periodic faces wrap) of a cell the
+                                 criterion selects; 0: the criterion's cells only (the paper's
+                                 rule).  At most 1024. */
 } msl_config;
 
 typedef struct msl_ctx msl_ctx;

@@ -74,6 +74,8 @@ typedef struct or_config {
                                  (eqs. Pond_f/g with omega2 = 1/tau2 at the reference state;
                                  Pr = (tau - 1/2)/(tau2 - 1/2) kept where tau varies with T);
                                  otherwise BGK */
+  int crit_margin;            /* > 0: the high-order set also takes every cell within this
+                                 many cells (per axis) of a cell the criterion selects */
 } or_config;
 
 typedef struct or_ctx or_ctx;
@@ -121,6 +123,10 @@ int or_conservation(const or_ctx *ctx, double *out);     /* sum rho, sum j (3), 
 /* next-step populations (native lattice) of selected cells, state untouched */
 int or_step_cells(const or_ctx *ctx, int ncells, const int64_t *cells,
                   double *fout, double *gout);
+
+/* out[k] = max of in over the cells within `margin` cells of k along each axis
+ * (a box; periodic faces wrap, other faces end the box): the criterion's margin */
+int or_dilate_mask(const or_config *cfg, const uint8_t *in, uint8_t *out);
 
 /* ---- co-moving reference frames (PonD, Sec. II.C.1), one or two sets ----
  * Each cell keeps its populations, of its own velocity set, in its own frame

@@ -30,11 +30,12 @@ class OrConfig(C.Structure):
         ("slot_edge", C.c_double * 6),
         ("crit_kind", C.c_int), ("crit_thr", C.c_double), ("crit_every", C.c_int),
         ("u_ref", C.c_double * 3), ("T_ref", C.c_double), ("store_u", C.c_double * 3),
-        ("tau2", C.c_double),
+        ("tau2", C.c_double), ("crit_margin", C.c_int),
     ]
 
 # fields of the run configuration that default when a workload leaves them out
-_DEFAULTS = {"u_ref": (0.0, 0.0, 0.0), "T_ref": 1.0, "store_u": (0.0, 0.0, 0.0), "tau2": 0.0}
+_DEFAULTS = {"u_ref": (0.0, 0.0, 0.0), "T_ref": 1.0, "store_u": (0.0, 0.0, 0.0), "tau2": 0.0,
+             "crit_margin": 0}
 
 
 def lib():
@@ -456,6 +457,16 @@ class Pond:
         mx = C.c_int()
         lib().or_pond_iterations(self._ctx, C.byref(m), C.byref(mx))
         return m.value, mx.value
+
+
+def dilate_mask(cfg, mask):
+    """The criterion's margin applied to a 0/1 mask (or_dilate_mask)."""
+    c = make_config(cfg)
+    m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+    out = np.zeros_like(m)
+    _check(lib().or_dilate_mask(C.byref(c), m.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p)),
+           "dilate_mask")
+    return out.reshape(np.shape(mask))
 
 
 def pond_transfer(dim, n, src, dst, f):

@@ -641,10 +641,12 @@ static void pond_criterion(const or_pond *c, uint8_t *newmask) {
 int or_pond_step(or_pond *c, int nsteps) {
   for (int s = 0; s < nsteps; s++) {
     if (c->nlat > 1 && c->cfg.crit_kind == 3 && c->cfg.crit_every > 0 && c->step % c->cfg.crit_every == 0) {
-      uint8_t *nm = (uint8_t *)malloc((size_t)c->ncell);
+      uint8_t *nm = (uint8_t *)malloc((size_t)c->ncell), *dm = (uint8_t *)malloc((size_t)c->ncell);
       pond_criterion(c, nm);
-      const int rc = or_pond_set_mask(c, nm, 1);
+      or_dilate_mask(&c->cfg, nm, dm);
+      const int rc = or_pond_set_mask(c, dm, 1);
       free(nm);
+      free(dm);
       if (rc) return rc;
     }
     if (convert_all(c)) return -4;

@@ -638,6 +638,37 @@ int or_init(or_ctx *c, const double *rho, const double *u, const double *T) {
   return 0;
 }
 
+/* the criterion's margin: a box maximum of the selection, one axis after the
+ * other (the box is separable) */
+int or_dilate_mask(const or_config *cfg, const uint8_t *in, uint8_t *out) {
+  const int D = cfg->dim, m = cfg->crit_margin;
+  const int N[3] = {cfg->nx, cfg->ny, D == 3 ? cfg->nz : 1};
+  const int64_t n = (int64_t)N[0] * N[1] * N[2];
+  memcpy(out, in, (size_t)n);
+  if (m <= 0) return 0;
+  uint8_t *tmp = (uint8_t *)malloc((size_t)n);
+  for (int a = 0; a < D; a++) {
+    memcpy(tmp, out, (size_t)n);
+    const int periodic = cfg->bc[2 * a] == 0 && cfg->bc[2 * a + 1] == 0;
+    const int64_t stride = a == 0 ? 1 : (a == 1 ? N[0] : (int64_t)N[0] * N[1]);
+    for (int64_t k = 0; k < n; k++) {
+      const int p = (int)((k / stride) % N[a]);
+      uint8_t v = 0;
+      for (int d = -m; d <= m; d++) {
+        int q = p + d;
+        if (q < 0 || q >= N[a]) {
+          if (!periodic) continue;
+          q = ((q % N[a]) + N[a]) % N[a];
+        }
+        v |= tmp[k + (int64_t)(q - p) * stride];
+      }
+      out[k] = v;
+    }
+  }
+  free(tmp);
+  return 0;
+}
+
 int or_step(or_ctx *c, int nsteps) {
   const int th = c->cfg.thermal;
   uint8_t *nm = NULL;
@@ -646,6 +677,12 @@ int or_step(or_ctx *c, int nsteps) {
   for (int s = 0; s < nsteps; s++) {
     if (nm && c->step % c->cfg.crit_every == 0) {
       or_eval_criterion(c, nm, NULL);
+      if (c->cfg.crit_margin > 0) {
+        uint8_t *dm = (uint8_t *)malloc((size_t)c->ncell);
+        or_dilate_mask(&c->cfg, nm, dm);
+        memcpy(nm, dm, (size_t)c->ncell);
+        free(dm);
+      }
       or_set_mask(c, nm);
     }
     if (c->mlp_on && c->step % 20 == 0 && !(c->mlp_bf16 & 2)) or_mlp_check(c);

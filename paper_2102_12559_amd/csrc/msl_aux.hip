@@ -1125,6 +1125,52 @@ int msl_launch_band_convert(msl_ctx *c, char *bl, char *bh) {
   return MSL_EINVAL;
 }
 
+__global__ void __launch_bounds__(AUX_BLOCK)
+k_copy_bytes(const uint8_t *__restrict__ in, uint8_t *__restrict__ out, long long n) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = in[k];
+}
+
+// the criterion's margin along one axis: out[k] = max of in over the cells
+// within m cells of k along that axis (periodic: wrapped; otherwise the box
+// ends at the face)
+__global__ void __launch_bounds__(AUX_BLOCK)
+k_dilate(Geo g, int ax, int m, int periodic, const uint8_t *__restrict__ in, uint8_t *__restrict__ out) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.ncell) return;
+  int p[3];
+  cell_coords(g, k, p[0], p[1], p[2]);
+  const int n = ax == 0 ? g.nx : (ax == 1 ? g.ny : g.nz);
+  const long long stride = ax == 0 ? 1 : (ax == 1 ? (long long)g.nx : (long long)g.nx * g.ny);
+  uint8_t v = 0;
+  for (int d = -m; d <= m && !v; ++d) {
+    int q = p[ax] + d;
+    if (q < 0 || q >= n) {
+      if (!periodic) continue;
+      q = ((q % n) + n) % n;
+    }
+    v = in[k + (long long)(q - p[ax]) * stride] & 1;
+  }
+  out[k] = v;
+}
+
+int msl_launch_dilate(msl_ctx *c) {
+  const int m = c->cfg.crit_margin;
+  if (m <= 0) return MSL_OK;
+  // ping-pong through the first band list's bytes (rebuilt after the switch)
+  uint8_t *t[2] = {c->newmask, (uint8_t *)c->blist[0]};
+  int cur = 0;
+  for (int ax = 0; ax < c->D; ++ax) {
+    const int per = c->cfg.bc[2 * ax] == MSL_BC_PERIODIC && c->cfg.bc[2 * ax + 1] == MSL_BC_PERIODIC;
+    hipLaunchKernelGGL(k_dilate, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), 0, c->stream, c->geo, ax, m, per,
+                       t[cur], t[cur ^ 1]);
+    cur ^= 1;
+  }
+  if (cur) hipLaunchKernelGGL(k_copy_bytes, dim3(nblocks(c->ncell)), dim3(AUX_BLOCK), 0, c->stream, t[1], t[0],
+                              c->ncell);
+  return last_err();
+}
+
 // Kn > crit_thr from the cell densities and mean free paths in kn_rho, kn_lam
 // (written by the previous launch) into newmask
 int msl_launch_kn_mask(msl_ctx *c) {

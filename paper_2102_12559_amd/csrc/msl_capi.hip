@@ -211,6 +211,7 @@ static const char *check_config(const msl_config *cfg) {
   const long long cells = (long long)cfg->nx * cfg->ny * (cfg->dim == 3 ? cfg->nz : 1);
   if (cells >= (1ll << 31)) return "grid too large";
   if (cfg->pond != 0 && cfg->pond != 1) return "pond must be 0 or 1";
+  if (cfg->crit_margin < 0 || cfg->crit_margin > 1024) return "crit_margin must lie in [0, 1024]";
   if (cfg->pond) {
     if (cfg->dim != 2) return "co-moving frames are built for 2D";
     if (cfg->n_high && cfg->lift_mode == MSL_LIFT_MLP) return "co-moving frames: Grad or Hermite lifting";
@@ -662,6 +663,7 @@ int msl_get_mask(msl_ctx *c, uint8_t *mask) {
 
 static int mask_step(msl_ctx *c) {
   int rc = msl_launch_criterion(c);
+  if (!rc) rc = msl_launch_dilate(c);
   if (rc) return rc;
   rc = msl_launch_switch(c, c->newmask);
   if (rc) return rc;

@@ -241,6 +241,8 @@ int msl_pond_launch_step(msl_ctx *c);
 // band is rebuilt and converted
 int msl_pond_launch_set_mask(msl_ctx *c, const uint8_t *mask, int convert);
 int msl_launch_kn_mask(msl_ctx *c);
+// the criterion's margin (crit_margin > 0): newmask dilated by a box per axis
+int msl_launch_dilate(msl_ctx *c);
 int msl_launch_error_norms(msl_ctx *c, const double *rref, const double *uref, const double *Tref,
                            double *dev_out6);
 int msl_launch_check_mask(msl_ctx *c, const uint8_t *mask);

@@ -724,6 +724,7 @@ int msl_pond_launch_step(msl_ctx *c) {
                        c->kn_rho, c->kn_lam);
     if (hipGetLastError() != hipSuccess) return MSL_EHIP;
     if ((rc = msl_launch_kn_mask(c))) return rc;
+    if ((rc = msl_launch_dilate(c))) return rc;
     if ((rc = msl_pond_launch_set_mask(c, c->newmask, 1))) return rc;
   }
   const int faces = (c->cfg.bc[2] == MSL_BC_DIFFUSE_WALL ? 1 : 0) | (c->cfg.bc[3] == MSL_BC_DIFFUSE_WALL ? 2 : 0);

@@ -40,11 +40,12 @@ class MslConfig(C.Structure):
         ("crit_kind", C.c_int), ("crit_thr", C.c_double), ("crit_every", C.c_int),
         ("check_every", C.c_int), ("mlp_hidden", C.c_int), ("mlp_check_every", C.c_int),
         ("u_ref", C.c_double * 3), ("T_ref", C.c_double), ("store_u", C.c_double * 3),
-        ("tau2", C.c_double), ("pond", C.c_int),
+        ("tau2", C.c_double), ("pond", C.c_int), ("crit_margin", C.c_int),
     ]
 
 # fields a workload may leave out: the lattice frame, the plain storage scale, BGK
-_DEFAULTS = {"u_ref": (0.0, 0.0, 0.0), "T_ref": 1.0, "store_u": (0.0, 0.0, 0.0), "tau2": 0.0, "pond": 0}
+_DEFAULTS = {"u_ref": (0.0, 0.0, 0.0), "T_ref": 1.0, "store_u": (0.0, 0.0, 0.0), "tau2": 0.0, "pond": 0,
+             "crit_margin": 0}
 
 
 _lib = None
