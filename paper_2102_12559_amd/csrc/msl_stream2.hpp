@@ -87,6 +87,24 @@ __device__ __forceinline__ float lds_elem<bf16_t>(const char *p) {
 template <typename S>
 __device__ __forceinline__ double lds_elem_d(const char *p) { return *(const double *)p; }
 
+// The value a lane of the wave holds (a wave-uniform copy, v_readlane).
+template <typename V>
+__device__ __forceinline__ V msl_lane_get(V v, int lane) {
+  if constexpr (sizeof(V) == 8) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+    return __builtin_bit_cast(V, ((unsigned long long)hi << 32) | lo);
+  } else {
+    return __builtin_bit_cast(V, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+  }
+}
+
+// A wave whose band cells number at most this many lifts them one cell at a
+// time across its lanes (one output node per lane); more, and every lane
+// lifts its own cell.
+#define MSL_LIFT_COOP 4
+
 // NO > 0: the other velocity set of a two-set run has NO nodes per axis, and
 // the kernel also converts its band cells (bit 1 of the class byte) into that
 // set, in the new buffer `oth` of the other set's planes: the low-order
@@ -108,7 +126,7 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   constexpr bool LIFT = NO > N, PROJ = NO > 0 && NO < N;
   constexpr int QO = NO * NO;
   constexpr int NTAB = LIFT ? NO * NO + 2 * NO * N + QO : (PROJ ? NO * N + QO : 1);
-  __shared__ typename SC2Traits<S, TH, N, SMALL>::C stab[NTAB];   // compute precision
+  __shared__ double stab[NTAB];
   const LatTab &L = tab->lat[lat];
   auto tile_body = [&](const int bx, const int by) {
   const int x0 = bx * MSL_TX, y0 = by * TY;
@@ -153,24 +171,25 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   // band conversion tables of the other set, staged in LDS while the windows
   // load (uniform reads later, no scalar-load round trips in the epilogue):
   // lifting: the Hermite basis of the high-order nodes (NO x NO), the per-axis
-  // completion matrices (NO x N, x then y), the storage scales (NO^2);
-  // projection: the low-order basis at the high-order nodes (NO x N), the scales
+  // completion matrices (NO x N, x then y), the reciprocal storage scales
+  // (NO^2); projection: the low-order basis at the high-order nodes (NO x N),
+  // the reciprocal scales
   if constexpr (NO > 0) {
     const LatTab &LO = tab->lat[LIFT ? 1 : 0];
     const int t = threadIdx.x;
     if constexpr (LIFT) {
       const bool herm = tab->lift_mode == MSL_LIFT_GRAD_HERMITE;
       if (t < NO * NO) {
-        stab[t] = (C)LO.hw[t / NO][t % NO];
+        stab[t] = LO.hw[t / NO][t % NO];
       } else if (t < NO * NO + 2 * NO * N) {
         const int k = t - NO * NO, ax = k / (NO * N), e = k % (NO * N);
-        stab[t] = (C)(herm ? tab->KH[e / N][e % N] : tab->K[ax][e / N][e % N]);
+        stab[t] = herm ? tab->KH[e / N][e % N] : tab->K[ax][e / N][e % N];
       } else if (t < NTAB) {
-        stab[t] = (C)LO.sc[t - NO * NO - 2 * NO * N];
+        stab[t] = LO.isc[t - NO * NO - 2 * NO * N];
       }
     } else {
-      if (t < NO * N) stab[t] = (C)tab->P[t / N][t % N];
-      else if (t < NTAB) stab[t] = (C)LO.sc[t - NO * N];
+      if (t < NO * N) stab[t] = tab->P[t / N][t % N];
+      else if (t < NTAB) stab[t] = LO.isc[t - NO * N];
     }
   }
   // my cells: inside the domain and of this velocity set; band: also
@@ -382,14 +401,15 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
       qb[r][1] *= dom[r] * cg;
     }
   }
-  // band conversion state (compute precision): lifting keeps the
-  // non-equilibrium part of every post-collision population (f - f^eq,
-  // g - gfac T f^eq); projection accumulates (P x P) f of each output node
-  // while the populations are stored (only in waves that hold a band cell)
+  // band conversion state: lifting keeps the non-equilibrium part of every
+  // post-collision population (f - f^eq, g - gfac T f^eq); projection
+  // accumulates (P x P) f of each output node while the populations are
+  // stored (only in waves that hold a band cell).  The conversions compute in
+  // FP64 whatever the storage precision.
   C nq[LIFT ? NP : 1][R];
-  C acc[PROJ ? (TH ? 2 : 1) * QO : 1][R];   // (P x P) f per output node
-  C tp[PROJ ? NO : 1][R];                   // P along x of the current row
-  C Pp[PROJ ? NO : 1][PROJ ? N : 1];        // P[a'][a], from LDS
+  double acc[PROJ ? (TH ? 2 : 1) * QO : 1][R];   // (P x P) f per output node
+  double tp[PROJ ? NO : 1][R];                   // P along x of the current row
+  double Pp[PROJ ? NO : 1][PROJ ? N : 1];        // P[a'][a], from LDS
   bool wband = false;
   if constexpr (NO > 0) {
     bool b = false;
@@ -401,11 +421,11 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
 #pragma unroll
     for (int k = 0; k < (TH ? 2 : 1) * QO; ++k)
 #pragma unroll
-      for (int r = 0; r < R; ++r) acc[k][r] = C(0);
+      for (int r = 0; r < R; ++r) acc[k][r] = 0.0;
 #pragma unroll
     for (int k = 0; k < NO; ++k)
 #pragma unroll
-      for (int r = 0; r < R; ++r) tp[k][r] = C(0);
+      for (int r = 0; r < R; ++r) tp[k][r] = 0.0;
     if (wband) {
 #pragma unroll
       for (int ap = 0; ap < NO; ++ap)
@@ -446,8 +466,9 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
       if constexpr (PROJ) {
         // separable: along x within the row b, then along y at its end
         if (wband) {
+          const double vd = (double)vo;
 #pragma unroll
-          for (int ap = 0; ap < NO; ++ap) tp[ap][r] += Pp[ap][a] * vo;
+          for (int ap = 0; ap < NO; ++ap) tp[ap][r] += Pp[ap][a] * vd;
           if constexpr (a == N - 1) {
 #pragma unroll
             for (int bp = 0; bp < NO; ++bp)
@@ -455,7 +476,7 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
               for (int ap = 0; ap < NO; ++ap)
                 acc[(K < Q ? 0 : QO) + ap + NO * bp][r] += Pp[bp][b] * tp[ap][r];
 #pragma unroll
-            for (int ap = 0; ap < NO; ++ap) tp[ap][r] = C(0);
+            for (int ap = 0; ap < NO; ++ap) tp[ap][r] = 0.0;
           }
         }
       }
@@ -484,66 +505,153 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
   if constexpr (NO > 0) {
     if (wband) {
       const LatTab &LO = tab->lat[LIFT ? 1 : 0];
-      const double gs = tab->gfac * tab->T0;
-      const C *sct = stab + (LIFT ? NO * NO + 2 * NO * N : NO * N);   // storage scales
+      const double igs = tab->igsc;
+      const double *isct = stab + (LIFT ? NO * NO + 2 * NO * N : NO * N);   // 1 / storage scales
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        if (!band[r]) continue;
-        const long long off = g.idx(x0 + tx, y0 + ty * R + r, 0);
         if constexpr (LIFT) {
-          const C rd = rho[r], ux = jx[r] / rd, uy = jy[r] / rd;
-          C Tm = C(1);
-          if (TH) Tm = (en[r] - C(0.5) * rd * (ux * ux + uy * uy)) / ((C)tab->cv * rd);
-          // equilibrium factors of the high-order nodes (eq_axis with the
-          // basis from LDS): all of y here, x per output column below
-          const C tm1 = Tm * (C)LO.iTr - C(1);
-          const C uxs = (ux - (C)LO.ur[0]) * (C)LO.isq, uys = (uy - (C)LO.ur[1]) * (C)LO.isq;
-          C bx[NO], PY[NO];
+          if (!__ballot(band[r])) continue;
+        } else {
+          if (!band[r]) continue;
+        }
+        // buffer stores: the plane's base in scalar registers, one 32-bit
+        // byte offset per lane (a 64-bit address per store would not fit in
+        // the registers of an eight-wave launch)
+        const int cidx = (int)g.idx(x0 + tx, y0 + ty * R + r, 0);
+        const int boff = (int)((unsigned)cidx * SZ);
+        auto put = [&](const int k, const double v, const double is) {
+          const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+              (void *)(oth + (long long)k * g.plane), (short)0, (int)plane_b, MSL_RSRC_WORD3);
+          const S sv = T::store(T::dev ? (C)(v * is - 1.0) : (C)v);
+          if constexpr (SZ == 8) {
+            typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, sv), rs, boff, 0, 0);
+          } else if constexpr (SZ == 4) {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, sv), rs, boff, 0, 0);
+          } else {
+            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, sv), rs, boff, 0, 0);
+          }
+        };
+        if constexpr (LIFT) {
+          // every lane widens its cell's moments (only band lanes' are used)
+          const double rd = (double)rho[r], ux = (double)jx[r] / rd, uy = (double)jy[r] / rd;
+          double Tm = 1.0;
+          if (TH) Tm = ((double)en[r] - 0.5 * rd * (ux * ux + uy * uy)) / (tab->cv * rd);
+          const double tm1 = Tm * LO.iTr - 1.0;
+          const double uxs = (ux - LO.ur[0]) * LO.isq, uys = (uy - LO.ur[1]) * LO.isq;
+          unsigned long long bmask = __ballot(band[r]);
+          if (__popcll(bmask) <= MSL_LIFT_COOP) {
+            // few band cells in the wave: the wave lifts them one at a time,
+            // lane i computing output node i (its Hermite factors and the
+            // separable completion at that node), with the cell's moments
+            // and non-equilibrium populations read from its lane
+            while (bmask) {
+              const int src = __builtin_ctzll(bmask);
+              bmask &= bmask - 1;
+              const double crd = msl_lane_get(rd, src), cux = msl_lane_get(uxs, src);
+              const double cuy = msl_lane_get(uys, src), ctm = msl_lane_get(tm1, src);
+              const double cT = TH ? msl_lane_get(Tm, src) : 1.0;
+              const long long cid = (long long)__builtin_amdgcn_readlane(cidx, src);
+              C cq[TH ? 2 * Q : Q];
+#pragma unroll
+              for (int k = 0; k < (TH ? 2 * Q : Q); ++k) cq[k] = msl_lane_get(nq[k][r], src);
+              if (lane < QO) {
+                const int a = lane % NO, b = lane / NO;
+                double px = stab[a * NO], py = stab[b * NO];
+                double xm = 1.0, xj = cux, ym = 1.0, yj = cuy;
+#pragma unroll
+                for (int j = 1; j < NO; ++j) {
+                  px += stab[a * NO + j] * xj;
+                  py += stab[b * NO + j] * yj;
+                  const double xn = cux * xj + (double)j * ctm * xm;
+                  const double yn = cuy * yj + (double)j * ctm * ym;
+                  xm = xj;
+                  xj = xn;
+                  ym = yj;
+                  yj = yn;
+                }
+                const double feq = crd * px * py;
+#pragma unroll
+                for (int h = 0; h < (TH ? 2 : 1); ++h) {
+                  double cr = 0.0;
+#pragma unroll
+                  for (int bp = 0; bp < N; ++bp) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int ap = 0; ap < N; ++ap) t += stab[NO * NO + a * N + ap] * (double)cq[h * Q + ap + N * bp];
+                    cr += stab[NO * NO + NO * N + b * N + bp] * t;
+                  }
+                  const double v = (h ? tab->gfac * cT : 1.0) * feq + cr;
+                  const double is = h ? igs * isct[lane] : isct[lane];
+                  oth[(long long)(h * QO + lane) * g.plane + cid] = T::store(T::dev ? (C)(v * is - 1.0) : (C)v);
+                }
+              }
+            }
+            continue;
+          }
+          if (!band[r]) continue;
+          // many band cells: each lane lifts its own.  Equilibrium factors
+          // of the high-order nodes (eq_axis with the basis from LDS): all of
+          // y here, x per output column below (its Hermite coefficients
+          // recomputed there: fewer values live)
+          double PY[NO];
           {
-            C by[NO];
-            bx[0] = by[0] = C(1);
-            bx[1] = uxs;
+            double by[NO];
+            by[0] = 1.0;
             by[1] = uys;
 #pragma unroll
-            for (int j = 1; j + 1 < NO; ++j) {
-              bx[j + 1] = uxs * bx[j] + C(j) * tm1 * bx[j - 1];
-              by[j + 1] = uys * by[j] + C(j) * tm1 * by[j - 1];
-            }
+            for (int j = 1; j + 1 < NO; ++j) by[j + 1] = uys * by[j] + (double)j * tm1 * by[j - 1];
 #pragma unroll
             for (int b = 0; b < NO; ++b) {
-              C sy = C(0);
+              double sy = 0.0;
 #pragma unroll
               for (int j = 0; j < NO; ++j) sy += stab[b * NO + j] * by[j];
               PY[b] = sy;
             }
           }
-          const C *Kx = stab + NO * NO, *Ky = stab + NO * NO + NO * N;
-          // one output column a at a time (not unrolled: a few values live)
+          // one output column a at a time (not unrolled: a few values live).
+          // The tables come from the uniform table memory (scalar loads into
+          // scalar registers, the same for every lane: no LDS round trips in
+          // the loop), the populations are widened inside the loop (an empty
+          // statement tied to the column index keeps the conversion there:
+          // hoisted, the FP64 copies would exceed the registers of an
+          // eight-wave launch and spill)
+          const bool herm = tab->lift_mode == MSL_LIFT_GRAD_HERMITE;
+          const double *KxT = herm ? &tab->KH[0][0] : &tab->K[0][0][0];
+          const double *KyT = herm ? &tab->KH[0][0] : &tab->K[1][0][0];
 #pragma unroll 1
           for (int a = 0; a < NO; ++a) {
-            C px = C(0);
+            double px = LO.hw[a][0], bm = 1.0, bj = uxs;
 #pragma unroll
-            for (int j = 0; j < NO; ++j) px += stab[a * NO + j] * bx[j];
+            for (int j = 1; j < NO; ++j) {
+              px += LO.hw[a][j] * bj;
+              const double bn = uxs * bj + (double)j * tm1 * bm;
+              bm = bj;
+              bj = bn;
+            }
             px *= rd;
 #pragma unroll
             for (int h = 0; h < (TH ? 2 : 1); ++h) {
-              const C sg = h ? (C)tab->gfac * Tm : C(1);
-              C t[N];
+              const double sg = h ? tab->gfac * Tm : 1.0;
+              double t[N];
 #pragma unroll
               for (int bp = 0; bp < N; ++bp) {
-                C sum = C(0);
+                double sum = 0.0;
 #pragma unroll
-                for (int ap = 0; ap < N; ++ap) sum += Kx[a * N + ap] * nq[h * Q + ap + N * bp][r];
+                for (int ap = 0; ap < N; ++ap) {
+                  C q = nq[h * Q + ap + N * bp][r];
+                  asm("" : "+v"(q) : "s"(a));
+                  sum += KxT[a * MSL_MAXN + ap] * (double)q;
+                }
                 t[bp] = sum;
               }
 #pragma unroll
               for (int b = 0; b < NO; ++b) {
-                C cr = C(0);
+                double cr = 0.0;
 #pragma unroll
-                for (int bp = 0; bp < N; ++bp) cr += Ky[b * N + bp] * t[bp];
+                for (int bp = 0; bp < N; ++bp) cr += KyT[b * MSL_MAXN + bp] * t[bp];
                 const int i = a + NO * b;
-                store_pop<S>(oth + (long long)(h * QO + i) * g.plane, off, (double)(sg * px * PY[b] + cr),
-                             h ? gs * (double)sct[i] : (double)sct[i]);
+                put(h * QO + i, sg * px * PY[b] + cr, h ? igs * isct[i] : isct[i]);
               }
             }
           }
@@ -552,8 +660,7 @@ k_sc2d_res(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in
           for (int h = 0; h < (TH ? 2 : 1); ++h)
 #pragma unroll
             for (int i = 0; i < QO; ++i)
-              store_pop<S>(oth + (long long)(h * QO + i) * g.plane, off, (double)acc[h * QO + i][r],
-                           h ? gs * (double)sct[i] : (double)sct[i]);
+              put(h * QO + i, acc[h * QO + i][r], h ? igs * isct[i] : isct[i]);
         }
       }
     }

@@ -96,6 +96,59 @@ def test_band_values_fp32():
     compare_band(s, o, 1e-5, absolute=True)
 
 
+def _strip_mask(nx, ny):
+    """A horizontal strip of the high-order set across the whole width (its
+    low-order band rows put 64 band cells in a wave) and a vertical strip
+    (4 band cells per wave row)."""
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[20:28, :] = 1
+    mask[:, 100:108] = 1
+    return mask
+
+
+def _band_cells_per_wave_row(mask):
+    """Low-order band cells in each 64-cell row segment that holds any (a wave
+    of the 2D kernel covers whole 64-cell rows of its tile)."""
+    ny, nx = mask.shape
+    b0, _ = band_cells(mask, (True, True))
+    b0 = b0.reshape(ny, nx)
+    nxp = -(-nx // 64) * 64
+    b = np.zeros((ny, nxp), bool)
+    b[:, :nx] = b0
+    c = b.reshape(ny, nxp // 64, 64).sum(-1).ravel()
+    return c[c > 0]
+
+
+@pytest.mark.parametrize("nq,nQ,th", [(3, 6, 0), (3, 4, 1), (4, 5, 0)])
+def test_band_lift_both_wave_paths_fp64(nq, nQ, th):
+    """Waves with at most 4 band cells lift them one cell at a time across
+    their lanes; waves with more lift one cell per lane.  The strip mask gives
+    waves of both kinds; both must match the oracle's lift."""
+    nx, ny = 192, 48
+    mask = _strip_mask(nx, ny)
+    c = _band_cells_per_wave_row(mask)
+    assert (c <= 4).any() and (c > 4).any()
+    cfg = inputs.base_config(nx=nx, ny=ny, n_low=nq, n_high=nQ, tau=0.7, thermal=th, crit_every=0)
+    rho, u, T = inputs.smooth_random_flow(nx, ny, umax=0.25, seed=31 + nQ, drho=0.02,
+                                          dT=0.04 if th else 0.0)
+    s, o = run_pair(cfg, rho, u, T, mask, 5, tag=f"lift wave paths {nq}/{nQ} thermal {th}")
+    for fg in ((0, 1) if th else (0,)):
+        compare_pops(s, o, 1e-12, fg=fg)
+        compare_band(s, o, 1e-12, fg=fg)
+
+
+def test_band_lift_both_wave_paths_fp16():
+    """The same two kinds of waves with FP16 deviation storage: the lifted
+    values go through the storage scale of each high-order node."""
+    nx, ny = 192, 48
+    mask = _strip_mask(nx, ny)
+    cfg = inputs.base_config(nx=nx, ny=ny, n_low=3, n_high=6, tau=0.7, crit_every=0,
+                             store=inputs.STORE_FP16_DEV)
+    rho, u, T = inputs.smooth_random_flow(nx, ny, umax=0.25, seed=41, drho=0.02)
+    s, o = run_pair(cfg, rho, u, T, mask, 5, tag="lift wave paths fp16")
+    compare_band(s, o, 2e-3, absolute=True)
+
+
 def test_graph_modes_bit_identical():
     """A jet with the Mach criterion every 5 steps: launch by launch, step
     graphs, and graphs with parallel branches, over calls of uneven length
