@@ -61,6 +61,15 @@ constexpr int nfeat() {
 }
 template <int D, int NL, int NH>
 constexpr int nout() { return Pow<D, NH>::v - Pow<D, NL>::v; }
+// position of high-order moment index j (3D) among the network's outputs: the
+// indices outside the low-order block, in ascending order
+template <int NL, int NH>
+__host__ __device__ constexpr int out_index(int j) {
+  int o = 0;
+  for (int k = 0; k < j; ++k)
+    if (!(k % NH < NL && (k / NH) % NH < NL && k / (NH * NH) < NL)) ++o;
+  return o;
+}
 
 // M[p] = sum_i f_i prod_a (c_{i_a} - s_a)^{p_a} for every moment index p < N per
 // axis, by one contraction per axis of the tensor-product population array
@@ -631,6 +640,192 @@ k_band_lift_mlp(const Tab *__restrict__ tab, Geo g, const char *bl, char *bh,
   }
 }
 
+// The learned lift of 3D athermal band cells, 64 cells per workgroup: wave 0
+// reads the cells' populations, forms rho, u and the non-equilibrium parts
+// f - f^eq (LDS), waves 1-3 stage the network outputs (LDS); then wave w
+// computes the output layer c = w (the NH^2 high-order populations with
+// z node c) of every cell, one cell per lane: the z, y, x passes of the
+// separable completion and of the inverse-Vandermonde map of the learned
+// moments, restricted to that layer (the same operations as the whole-cell
+// form), so the stores of a wave are 64 consecutive cells of one plane.
+// One wave per cell and set would hold every population and both transforms
+// in registers (one wave per SIMD, with spills).
+template <typename S, int NL, int NH>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_band_lift_mlp3(const Tab *__restrict__ tab, Geo g, const char *bl, char *bh,
+                 const int *__restrict__ list, const int *__restrict__ count,
+                 const float *__restrict__ stats, const float *__restrict__ yout,
+                 const uint8_t *__restrict__ flags, int nct0, int nct1, int xmir) {
+  constexpr int q = NL * NL * NL, Q = NH * NH * NH, F = nfeat<3, NL>(), O = nout<3, NL, NH>();
+  static_assert(NH == 4, "one output layer per wave of four");
+  __shared__ double s_neq[q][64];
+  __shared__ float s_y[O][64];
+  __shared__ double s_m[4][64];   // rho, u of each cell
+  __shared__ int s_off[64], s_ioff[64];
+  __shared__ uint8_t s_use[64], s_img[64];
+  const LatTab &Lq = tab->lat[0], &LQ = tab->lat[1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n = *count;
+  const int nct[3] = {nct0, nct1, 1};
+  // the completion matrices, the inverse Vandermonde matrix and the output
+  // statistics in LDS (read as broadcasts where they are used; as scalar
+  // loads they were hoisted out of the walk over the cells into more scalar
+  // registers than there are)
+  __shared__ double s_K[3][NH][NL], s_V[NH][NH];
+  __shared__ float s_mu[O], s_sd[O];
+  // and the Hermite bases (for eq_axis) and storage scales of both sets
+  struct EqTab {
+    double hw[MSL_MAXN][MSL_MAXN];
+    float hwf[MSL_MAXN][MSL_MAXN];
+  };
+  __shared__ EqTab s_eq[2];
+  __shared__ double s_sc[2][Q];
+  {
+    for (int e = threadIdx.x; e < 2 * MSL_MAXN * MSL_MAXN; e += blockDim.x) {
+      const int l = e / (MSL_MAXN * MSL_MAXN), r = (e / MSL_MAXN) % MSL_MAXN, cc = e % MSL_MAXN;
+      s_eq[l].hw[r][cc] = tab->lat[l].hw[r][cc];
+      s_eq[l].hwf[r][cc] = tab->lat[l].hwf[r][cc];
+    }
+    for (int e = threadIdx.x; e < 2 * Q; e += blockDim.x) s_sc[e / Q][e % Q] = tab->lat[e / Q].sc[e % Q];
+    const bool herm = tab->lift_mode == MSL_LIFT_GRAD_HERMITE;
+    for (int e = threadIdx.x; e < 3 * NH * NL; e += blockDim.x) {
+      const int ax = e / (NH * NL), r = (e / NL) % NH, cc = e % NL;
+      s_K[ax][r][cc] = herm ? tab->KH[r][cc] : tab->K[ax][r][cc];
+    }
+    for (int e = threadIdx.x; e < NH * NH; e += blockDim.x) s_V[e / NH][e % NH] = tab->Vi[e / NH][e % NH];
+    for (int e = threadIdx.x; e < O; e += blockDim.x) {
+      s_mu[e] = stats[2 * F + e];
+      s_sd[e] = stats[2 * F + O + e];
+    }
+  }
+  __syncthreads();
+  for (long long t0 = (long long)blockIdx.x * 64; t0 < n; t0 += (long long)gridDim.x * 64) {
+    const double (*Kx)[NL] = s_K[0];
+    const double (*Ky)[NL] = s_K[1];
+    const double (*Kz)[NL] = s_K[2];
+    const double (*Vi)[NH] = s_V;
+    const float *mu = s_mu, *sd = s_sd;
+    const double *scq = s_sc[0], *scQ = s_sc[1];
+    const EqTab *eqt = s_eq;
+    const long long t = t0 + lane;
+    const bool live = t < n;
+    if (w == 0) {
+      double f[q];
+      double rho = 1.0, u[3] = {0.0, 0.0, 0.0};
+      int off = 0, x = 0, y = 0, z = 0;
+      if (live) {
+        cell_coords(g, list[t], x, y, z);
+        off = g.idx(x, y, z);
+        const S *pl = (const S *)bl;
+#pragma unroll
+        for (int i = 0; i < q; ++i) f[i] = load_pop<S>(pl + (long long)i * g.plane, off, scq[i]);
+        double T;
+        macros_t<3, NL>(Lq, false, tab->cv, f, nullptr, rho, u, T);
+      } else {
+#pragma unroll
+        for (int i = 0; i < q; ++i) f[i] = 0.0;
+      }
+      double Pq[3][NL];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) eq_axis<double, NL>(eqt[0], (u[a] - Lq.ur[a]) * Lq.isq, Lq.iTr, Pq[a]);
+#pragma unroll
+      for (int i = 0; i < q; ++i) {
+        const double e = rho * Pq[0][i % NL] * Pq[1][(i / NL) % NL] * Pq[2][i / (NL * NL)];
+        s_neq[i][lane] = live ? f[i] - e : 0.0;
+      }
+      s_m[0][lane] = rho;
+      s_m[1][lane] = u[0];
+      s_m[2][lane] = u[1];
+      s_m[3][lane] = u[2];
+      s_off[lane] = off;
+      s_ioff[lane] = x < MSL_G ? off + g.nx : off - g.nx;   // x image (periodic x)
+      s_use[lane] = live && flags[check_tile(g, x, y, z, nct)] != 0;
+      s_img[lane] = live && xmir && (x < MSL_G || x >= g.nx - MSL_G);
+    } else {
+      for (int o = w - 1; o < O; o += 3) s_y[o][lane] = live ? yout[t * O + o] : 0.f;
+    }
+    __syncthreads();
+    const int c = __builtin_amdgcn_readfirstlane(w);   // this wave's output layer along z
+    const double rho = s_m[0][lane];
+    const double u[3] = {s_m[1][lane], s_m[2][lane], s_m[3][lane]};
+    // equilibrium factors of the high-order set (T = 1)
+    double PQ[3][NH];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) eq_axis<double, NH>(eqt[1], (u[a] - LQ.ur[a]) * LQ.isq, LQ.iTr, PQ[a]);
+    double pz = PQ[2][0];   // the layer's z factor
+#pragma unroll
+    for (int k = 1; k < NH; ++k)
+      if (c == k) pz = PQ[2][k];
+    // completion of the non-equilibrium part: z (to layer c), then y, then x
+    double t1[NL * NL], t2[NL * NH];
+#pragma unroll
+    for (int k = 0; k < NL * NL; ++k) {
+      double acc = 0;
+#pragma unroll
+      for (int cp = 0; cp < NL; ++cp) acc += Kz[c][cp] * s_neq[k + NL * NL * cp][lane];
+      t1[k] = acc;
+    }
+#pragma unroll
+    for (int b = 0; b < NH; ++b)
+#pragma unroll
+      for (int ap = 0; ap < NL; ++ap) {
+        double acc = 0;
+#pragma unroll
+        for (int bp = 0; bp < NL; ++bp) acc += Ky[b][bp] * t1[ap + NL * bp];
+        t2[ap + NL * b] = acc;
+      }
+    // the learned moments dM_p = rho T^{|p|/2} t_p (T = 1: rho) of the
+    // indices p outside the low-order block, mapped by (Vi x Vi x Vi)
+    const double sc0 = s_use[lane] ? rho : 0.0;
+    double v1[NH * NH], v2[NH * NH];
+#pragma unroll
+    for (int k = 0; k < NH * NH; ++k) {
+      double acc = 0;
+#pragma unroll
+      for (int cp = 0; cp < NH; ++cp) {
+        const int j = k + NH * NH * cp, p0 = j % NH, p1 = (j / NH) % NH;
+        if (p0 < NL && p1 < NL && cp < NL) continue;   // dM = 0 in the low-order block
+        const int o = out_index<NL, NH>(j);
+        const double tn = (double)s_y[o][lane] * sd[o] + mu[o];
+        acc += Vi[c][cp] * (sc0 * tn);
+      }
+      v1[k] = acc;
+    }
+#pragma unroll
+    for (int b = 0; b < NH; ++b)
+#pragma unroll
+      for (int ap = 0; ap < NH; ++ap) {
+        double acc = 0;
+#pragma unroll
+        for (int bp = 0; bp < NH; ++bp) acc += Vi[b][bp] * v1[ap + NH * bp];
+        v2[ap + NH * b] = acc;
+      }
+    const bool live2 = t0 + lane < n;
+    const int off = s_off[lane];
+    const bool img = s_img[lane];
+    const int ioff = s_ioff[lane];
+    S *p = (S *)bh;
+#pragma unroll
+    for (int b = 0; b < NH; ++b)
+#pragma unroll
+      for (int a = 0; a < NH; ++a) {
+        double ck = 0, cv = 0;   // the x passes of the two maps
+#pragma unroll
+        for (int ap = 0; ap < NL; ++ap) ck += Kx[a][ap] * t2[ap + NL * b];
+#pragma unroll
+        for (int ap = 0; ap < NH; ++ap) cv += Vi[a][ap] * v2[ap + NH * b];
+        const int i = a + NH * (b + NH * c);
+        double fo = rho * PQ[0][a] * PQ[1][b] * pz + ck;
+        fo += cv;
+        if (live2) {
+          store_pop<S>(p + (long long)i * g.plane, off, fo, scQ[i]);
+          if (img) store_pop<S>(p + (long long)i * g.plane, ioff, fo, scQ[i]);
+        }
+      }
+    __syncthreads();   // the next group overwrites the staged values
+  }
+}
+
 // error check, stage 1: for the high-order band cells, the standardised
 // features of their projected state and their true normalised targets
 template <typename S, int D, int NL, int NH, bool TH>
@@ -859,9 +1054,15 @@ int msl_mlp_band_lift(msl_ctx *c, char *bl, char *bh) {
   return store_dispatch(c->cfg.store, [&]<typename S>() {
     return msl_pair_dispatch(c->D, c->htab.lat[0].n, c->htab.lat[1].n, [&]<int D, int NL, int NH>() {
       return thermal_dispatch(c->cfg.thermal, [&]<bool TH>() {
-        hipLaunchKernelGGL((k_band_lift_mlp<S, D, NL, NH, TH>), dim3(2048), dim3(64), 0, c->stream,
-                           c->dtab, c->geo, bl, bh, c->blist[0], c->bcount, c->mlp_stats,
-                           c->mlp_out, c->mlp_flag, c->nct[0], c->nct[1], c->xmir);
+        if constexpr (D == 3 && !TH) {
+          hipLaunchKernelGGL((k_band_lift_mlp3<S, NL, NH>), dim3(512), dim3(256), 0, c->stream,
+                             c->dtab, c->geo, bl, bh, c->blist[0], c->bcount, c->mlp_stats,
+                             c->mlp_out, c->mlp_flag, c->nct[0], c->nct[1], c->xmir);
+        } else {
+          hipLaunchKernelGGL((k_band_lift_mlp<S, D, NL, NH, TH>), dim3(2048), dim3(64), 0, c->stream,
+                             c->dtab, c->geo, bl, bh, c->blist[0], c->bcount, c->mlp_stats,
+                             c->mlp_out, c->mlp_flag, c->nct[0], c->nct[1], c->xmir);
+        }
         return lerr();
       });
     });
