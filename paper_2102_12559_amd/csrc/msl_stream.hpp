@@ -370,13 +370,13 @@ static int launch_one(msl_ctx *c, int lat, const char *in, char *out, char *oth)
             c->tl_ok = 1;
           }
           if (c->tl_n == 0) return MSL_OK;
-          hipLaunchKernelGGL((k_sc3d_zm<S, TH, N, true>), dim3((unsigned)c->tl_n), block, 0, c->stream,
+          hipLaunchKernelGGL((k_sc3d_zm<S, TH, N, true>), dim3((unsigned)c->tl_n), dim3(T3::NT), 0, c->stream,
                              c->dtab, lat, g, (const S *)in, (S *)out, c->cls, c->tflag, 0, c->xmir,
                              c->tlist, c->tcount);
           return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
         }
         dim3 grid((g.nx + MSL_TX - 1) / MSL_TX, (g.ny + MSL_MTY - 1) / MSL_MTY, ncz);
-        hipLaunchKernelGGL((k_sc3d_zm<S, TH, N>), grid, block, 0, c->stream, c->dtab, lat, g,
+        hipLaunchKernelGGL((k_sc3d_zm<S, TH, N>), grid, dim3(T3::NT), 0, c->stream, c->dtab, lat, g,
                            (const S *)in, (S *)out, c->cls, c->tflag, lat == 0, c->xmir, nullptr, nullptr);
         return hipGetLastError() == hipSuccess ? MSL_OK : MSL_EHIP;
       }

@@ -1,7 +1,8 @@
 // msl_stream3z.hpp -- the 3D stream-and-collide kernel that marches along z.
 //
 // A workgroup owns a column of 64 x 4 x ZC cells (one y row per wave, one x
-// cell per lane) and walks it from its lowest z cell upwards.  At each step
+// cell per lane; 16-bit D3Q64: two waves per row, each with half of the
+// planes) and walks it from its lowest z cell upwards.  At each step
 // of the walk it brings one z slab of every plane's departure window into
 // LDS (direct-to-LDS buffer loads of 6 rows x 66 cells: the departure offset
 // x - v_i dt is the same for every cell of a plane, so the slab is the
@@ -86,10 +87,18 @@ struct SC3ZTraits {
   static constexpr int CH = (NP + NCH - 1) / NCH;
   static constexpr int LDS_BYTES = CH * SDP * 4;
   static constexpr int REGW = SZ == 8 ? 2 : 1;
+  // 16-bit D3Q64: two waves per row of cells, each holding half of the
+  // planes (the halves differ by a plane offset and a z-node offset; partial
+  // moments exchanged through LDS), so that two waves per SIMD fit the
+  // register file instead of one
+  static constexpr bool SPLIT = !TH && N == 4 && SZ == 2;
+  static constexpr int NHW = SPLIT ? 2 : 1;   // waves per row of cells
+  static constexpr int NT = 256 * NHW;        // threads per workgroup
+  static constexpr int NPW = NP / NHW;        // planes per wave
   // registers per lane: three per plane and about 50 besides (D3Q27: 167
-  // VGPRs, three waves per SIMD); D3Q64 needs about 300, VGPRs and AGPRs
-  // together, which one wave per SIMD holds without scratch
-  static constexpr int VREG = 3 * NP * REGW + (N == 3 ? 48 : 110);
+  // VGPRs, three waves per SIMD); D3Q64 with all planes in one wave needs
+  // about 300, VGPRs and AGPRs together
+  static constexpr int VREG = 3 * NPW * REGW + (N == 3 ? 48 : 110);
   // athermal D3Q27 in 16-bit and FP32 storage, athermal D3Q64 in 16-bit
   // storage (at one wave per SIMD: 3355 against 3541 us for the chunked
   // kernel on a 256^3 grid, while FP32 D3Q64 ran slower, 4941 against 4245
@@ -102,7 +111,8 @@ struct SC3ZTraits {
 };
 
 template <typename S, bool TH, int N, bool LIST = false>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SC3ZTraits<S, TH, N>::WAVES)))
+__global__ void __launch_bounds__((SC3ZTraits<S, TH, N>::NT))
+    __attribute__((amdgpu_waves_per_eu(SC3ZTraits<S, TH, N>::WAVES)))
 k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
           S *__restrict__ out, const uint8_t *__restrict__ cls,
           const uint8_t *__restrict__ tflag, int remap, int xmir, const int *__restrict__ tlist,
@@ -112,7 +122,11 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
   using C = typename Tr::C;
   constexpr int Q = Tr::Q, NP = Tr::NP, SD = Tr::SD, SDP = Tr::SDP, M = Tr::M, CH = Tr::CH, NCH = Tr::NCH;
   constexpr int LWD = Tr::LWD, SZ = Tr::SZ, ZC = Tr::ZC;
+  constexpr bool SPL = Tr::SPLIT;
+  constexpr int NPW = Tr::NPW;
+  static_assert(!SPL || (NCH == 1 && NP == Q), "the split walk: one chunk, f planes only");
   __shared__ uint32_t sm[CH * SDP];
+  __shared__ float smom[SPL ? 2 : 1][SPL ? 4 : 1][SPL ? 256 : 1];   // partial moments per half
   const LatTab &L = tab->lat[lat];
   // the column: from the grid (XCD-aware order for dense launches), or one
   // workgroup per entry of the compact list of live columns (sparse launches)
@@ -136,7 +150,11 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
   }
   // (the wave index as a scalar: the LDS destinations of the DMA are formed
   // in scalar registers)
-  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // w: the wave's row of cells; hf: its half of the planes (split walk), which
+  // starts at plane kb and z node ccb
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int w = wv & 3, hf = SPL ? wv >> 2 : 0;
+  const int kb = hf * NPW, ccb = kb / (N * N);
   const unsigned pitch_b = (unsigned)g.pitch * SZ;
   const unsigned plane_b = (unsigned)g.plane * SZ;
   const unsigned slab_b = (unsigned)g.rows * pitch_b;
@@ -168,6 +186,17 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
     offy[a] = (L.n0[1][a] - 1) * g.pitch;
     offz[a] = (L.n0[2][a] - 1) * g.rows * g.pitch;
   }
+  // z tables from the wave's first z node on (split walk; ccb = 0 otherwise)
+  if constexpr (SPL) {
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      const int az = a + ccb < N ? a + ccb : N - 1;
+      wlo[2][a] = tsel<C>(L.a[2][az][0], L.af[2][az][0]);
+      wmid[2][a] = tsel<C>(L.a[2][az][1], L.af[2][az][1]);
+      whi[2][a] = tsel<C>(L.a[2][az][2], L.af[2][az][2]);
+      offz[a] = (L.n0[2][az] - 1) * g.rows * g.pitch;
+    }
+  }
   // byte offset of the column's first slab window (before the plane's shift)
   const unsigned org0b = (unsigned)g.idx(x0, y0, z0) * SZ;
   // DMA of step t's slab of planes [K0, K1) into LDS: slab z0 + n0_z - 1 + t.
@@ -178,7 +207,7 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
   const long long plane_b64 = g.plane * SZ;
   auto issue = [&]<int K0, int K1>(const int t) {
     unsigned ob = org0b + (unsigned)t * slab_b;
-    const char *pp = (const char *)in + K0 * plane_b64;
+    const char *pp = (const char *)in + (kb + K0) * plane_b64;
     asm volatile("" : "+s"(ob), "+s"(pp));
     msl_for_range<K0, K1>([&]<int K>() {
       constexpr int i = K % Q, a = i % N, b = (i / N) % N, cc = i / (N * N);
@@ -189,7 +218,7 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
       for (int m = 0; m < M; ++m)
         if (vld[m])
           __builtin_amdgcn_raw_ptr_buffer_load_lds(
-              rs, (msl_lds_t *)(sm + (K - K0) * SDP + 64 * (w + 4 * m)), 4, (int)voff[m], (int)so, 0, 0);
+              rs, (msl_lds_t *)(sm + (SPL ? kb + K : K - K0) * SDP + 64 * (w + 4 * m)), 4, (int)voff[m], (int)so, 0, 0);
       pp += plane_b64;
     });
   };
@@ -209,14 +238,14 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
   // the z interpolation's partial sums of the next two cells
   // (ha = w0 h_{t-2} + w1 h_{t-1}, hb = w0 h_{t-1}), which need no register moves
   // as the walk advances; ftk: the streamed value
-  C ha[NP], hb[NP], ftk[NP];
+  C ha[NPW], hb[NPW], ftk[NPW];   // (the wave's planes: all, or its half)
 #pragma unroll
-  for (int k = 0; k < NP; ++k) ha[k] = hb[k] = C(0);
+  for (int k = 0; k < NPW; ++k) ha[k] = hb[k] = C(0);
   // the new slab of plane K: x then y interpolation, then the z interpolation
   // of the three slabs into the streamed value of cell z0 + t - 2
   auto recon = [&]<int K>() {
     constexpr int i = K % Q, a = i % N, b = (i / N) % N, cc = i / (N * N);
-    const char *base = (const char *)sm + (K % CH) * SDP * 4 + rb[a];
+    const char *base = (const char *)sm + ((SPL ? kb : 0) + K % CH) * SDP * 4 + rb[a];
     const C wx0 = wlo[0][a], wx2 = whi[0][a], wy0 = wlo[1][b], wy2 = whi[1][b], wz0 = wlo[2][cc],
             wz2 = whi[2][cc];
     C hy[3];
@@ -295,16 +324,18 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
     typedef const __attribute__((address_space(4))) Tab cTab;
     cLatTab *Lp = (cLatTab *)&L;
     cTab *tp = (cTab *)tab;
-    const char *op = (const char *)out;   // plane K's base, advanced plane by plane
+    // plane K's base, advanced plane by plane (from the wave's first plane)
+    const char *op = (const char *)out + (long long)kb * plane_b64;
     asm volatile("" : "+s"(Lp), "+s"(tp), "+s"(op));
     auto &L = *Lp;
     C rho = C(0), jx = C(0), jy = C(0), jz = C(0), en = C(0);
     auto moments = [&]<int K>() {
       constexpr int i = K % Q, a = i % N, b = (i / N) % N, cc = i / (N * N);
-      const C W = tsel<C>(L.sc[i], L.scf[i]);   // storage scale of f_i
+      // (split walk: population kb + i, z node ccb + cc)
+      const C W = tsel<C>(L.sc[kb + i], L.scf[kb + i]);   // storage scale of f_i
       if constexpr (K < Q) {
         const C cx = tsel<C>(L.v[0][a], L.vf[0][a]), cy = tsel<C>(L.v[1][b], L.vf[1][b]),
-                cz = tsel<C>(L.v[2][cc], L.vf[2][cc]);
+                cz = tsel<C>(L.v[2][ccb + cc], L.vf[2][ccb + cc]);
         const C f = T::dev ? W * (C(1) + ftk[K]) : ftk[K];
         ftk[K] = f;   // the population itself from here on
         rho += f;
@@ -317,7 +348,21 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
         en += ftk[K];
       }
     };
-    msl_for_planes<NP>(moments);
+    msl_for_planes<NPW>(moments);
+    if constexpr (SPL) {
+      // the other half's partial sums (a + b == b + a: both waves of a row
+      // hold the same sums)
+      const int ci = w * 64 + lane;
+      smom[hf][0][ci] = rho;
+      smom[hf][1][ci] = jx;
+      smom[hf][2][ci] = jy;
+      smom[hf][3][ci] = jz;
+      msl_lds_barrier();
+      rho += smom[hf ^ 1][0][ci];
+      jx += smom[hf ^ 1][1][ci];
+      jy += smom[hf ^ 1][2][ci];
+      jz += smom[hf ^ 1][3][ci];
+    }
     // equilibrium factors in FP64 (no rounding bias in the equilibrium's mass
     // and momentum), kept in the compute precision
     const double rd = (double)rho, ird = 1.0 / rd;
@@ -341,6 +386,16 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
         Py[q] = (C)py[q];
         Pz[q] = (C)pz[q];
       }
+      if constexpr (SPL) {   // z factors from the wave's first z node on
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          C v = Pz[q];
+#pragma unroll
+          for (int r = q + 1; r < N; ++r)
+            if (r == q + ccb) v = (C)pz[r];
+          Pz[q] = v;
+        }
+      }
     }
     const C gf = (C)(tp->gfac * Tm);
     const unsigned soff = mine ? cell0 + (unsigned)(z - z0) * zstride : 0x80000000u;
@@ -348,7 +403,7 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
                           : (mine && x >= g.nx - MSL_G) ? soff - (unsigned)g.nx * SZ : 0x80000000u;
     auto store = [&]<int K>() {
       constexpr int i = K % Q, a = i % N, b = (i / N) % N, cc = i / (N * N);
-      const C isc = T::dev ? tsel<C>(L.isc[i], L.iscf[i]) * (K < Q ? C(1) : tsel<C>(tp->igsc, tp->igscf)) : C(1);
+      const C isc = T::dev ? tsel<C>(L.isc[kb + i], L.iscf[kb + i]) * (K < Q ? C(1) : tsel<C>(tp->igsc, tp->igscf)) : C(1);
       const C feq = Px[a] * Py[b] * Pz[cc];
       const C v = ftk[K];
       C vo;
@@ -371,7 +426,7 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
       put(soff);
       if constexpr (XE) put(ioff);
     };
-    msl_for_planes<NP>(store);
+    msl_for_planes<NPW>(store);
   };
 
   // the walk: slabs t = 0 .. zn + 1; from t = 2 on, cell z0 + t - 2 is complete.
@@ -384,8 +439,8 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
   // outstanding waits for exactly the slab).
   // (vmcnt holds at most 63: with more stores per cell the wait also takes
   // the oldest of them)
-  constexpr int VW1 = NP < 63 ? NP : 63, VW2 = 2 * NP < 63 ? 2 * NP : 63;
-  constexpr int CH0 = CH < NP ? CH : NP;
+  constexpr int VW1 = NPW < 63 ? NPW : 63, VW2 = 2 * NPW < 63 ? 2 * NPW : 63;
+  constexpr int CH0 = CH < NPW ? CH : NPW;   // (split walk: the wave's half)
   issue.template operator()<0, CH0>(0);
   msl_wait_vm<0>();
   for (int t = 0; t < zn + 2; ++t) {
@@ -401,7 +456,7 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
         msl_wait_vm<0>();
       }
       msl_lds_barrier();   // every wave's share of the slab is in LDS
-      msl_for_range<k0, k1>(recon);
+      msl_for_range<k0, (k1 < NPW ? k1 : NPW)>(recon);
       msl_lds_barrier();   // the chunk's LDS values are read; the next load may overwrite them
     };
     msl_for_planes<NCH>(chunk);
