@@ -104,7 +104,8 @@ def kernel_source_hash():
 def traffic_for(name, kernel):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter summary of this workload, if it was taken on the current kernel
-    source and for the same launch class (else None)."""
+    source and for the same launch class (else None).  The summary holds one
+    entry per launch class it measured."""
     path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
     if not os.path.exists(path):
         return None
@@ -112,9 +113,10 @@ def traffic_for(name, kernel):
         d = json.load(open(path))
     except Exception:
         return None
-    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("launch_class") != kernel:
+    if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    e = d.get("launches", {}).get(kernel)
+    return e.get("hbm_bytes_per_launch") if e else None
 
 
 def cpu_model():

@@ -68,3 +68,23 @@ def test_roofline_of_takes_the_dominant_stream_collide_class():
     assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-4
     assert r["traffic"] is None                          # no counter summary for it
 
+
+
+def test_traffic_summary_attaches_by_launch_class(tmp_path, monkeypatch):
+    """A counter summary holds one entry per launch class; it is attached only
+    to the class it measured and only while the kernel sources hash to the
+    value it was taken on."""
+    import bench
+    prof_dir = tmp_path / "profiles"
+    prof_dir.mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "h-now")
+    d = {"kernel_source_hash": "h-now",
+         "launches": {"stream_collide_low": {"kernel": "k", "hbm_bytes_per_launch": 123}}}
+    (prof_dir / "traffic_w.json").write_text(json.dumps(d))
+    assert bench.traffic_for("w", "stream_collide_low") == 123
+    assert bench.traffic_for("w", "stream_collide_high") is None
+    assert bench.traffic_for("other", "stream_collide_low") is None
+    d["kernel_source_hash"] = "h-then"
+    (prof_dir / "traffic_w.json").write_text(json.dumps(d))
+    assert bench.traffic_for("w", "stream_collide_low") is None
