@@ -1,8 +1,8 @@
 // msl_stream3z.hpp -- the 3D stream-and-collide kernel that marches along z.
 //
 // A workgroup owns a column of 64 x 4 x ZC cells (one y row per wave, one x
-// cell per lane; 16-bit D3Q64: two waves per row, each with half of the
-// planes) and walks it from its lowest z cell upwards.  At each step
+// cell per lane; 16-bit D3Q64: four waves per row, each with the planes of
+// one z node) and walks it from its lowest z cell upwards.  At each step
 // of the walk it brings one z slab of every plane's departure window into
 // LDS (direct-to-LDS buffer loads of 6 rows x 66 cells: the departure offset
 // x - v_i dt is the same for every cell of a plane, so the slab is the
@@ -87,12 +87,12 @@ struct SC3ZTraits {
   static constexpr int CH = (NP + NCH - 1) / NCH;
   static constexpr int LDS_BYTES = CH * SDP * 4;
   static constexpr int REGW = SZ == 8 ? 2 : 1;
-  // 16-bit D3Q64: two waves per row of cells, each holding half of the
-  // planes (the halves differ by a plane offset and a z-node offset; partial
-  // moments exchanged through LDS), so that two waves per SIMD fit the
+  // 16-bit D3Q64: four waves per row of cells, each holding the 16 planes of
+  // one z node (the parts differ by a plane offset and a z-node offset;
+  // partial moments summed through LDS), so that four waves per SIMD fit the
   // register file instead of one
   static constexpr bool SPLIT = !TH && N == 4 && SZ == 2;
-  static constexpr int NHW = SPLIT ? 2 : 1;   // waves per row of cells
+  static constexpr int NHW = SPLIT ? 4 : 1;   // waves per row of cells
   static constexpr int NT = 256 * NHW;        // threads per workgroup
   static constexpr int NPW = NP / NHW;        // planes per wave
   // registers per lane: three per plane and about 50 besides (D3Q27: 167
@@ -106,8 +106,10 @@ struct SC3ZTraits {
   static constexpr bool fits = !TH && (N == 3 ? SZ <= 4 : (N == 4 && SZ == 2));
   static constexpr int WG_LDS = (160 * 1024) / LDS_BYTES;
   static constexpr int W_REG = 512 / VREG;
-  static constexpr int WAVES0 = WG_LDS < W_REG ? WG_LDS : W_REG;
-  static constexpr int WAVES = WAVES0 > 8 ? 8 : (WAVES0 < 1 ? 1 : WAVES0);
+  // waves per SIMD: NHW per resident workgroup
+  static constexpr int WAVES0 = WG_LDS * NHW < W_REG ? WG_LDS * NHW : W_REG;
+  static constexpr int WAVES1 = WAVES0 / NHW * NHW < NHW ? NHW : WAVES0 / NHW * NHW;
+  static constexpr int WAVES = WAVES1 > 8 ? 8 : WAVES1;
 };
 
 template <typename S, bool TH, int N, bool LIST = false>
@@ -126,7 +128,7 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
   constexpr int NPW = Tr::NPW;
   static_assert(!SPL || (NCH == 1 && NP == Q), "the split walk: one chunk, f planes only");
   __shared__ uint32_t sm[CH * SDP];
-  __shared__ float smom[SPL ? 2 : 1][SPL ? 4 : 1][SPL ? 256 : 1];   // partial moments per half
+  __shared__ float smom[SPL ? Tr::NHW : 1][SPL ? 4 : 1][SPL ? 256 : 1];   // partial moments per part
   const LatTab &L = tab->lat[lat];
   // the column: from the grid (XCD-aware order for dense launches), or one
   // workgroup per entry of the compact list of live columns (sparse launches)
@@ -358,10 +360,17 @@ k_sc3d_zm(const Tab *__restrict__ tab, int lat, Geo g, const S *__restrict__ in,
       smom[hf][2][ci] = jy;
       smom[hf][3][ci] = jz;
       msl_lds_barrier();
-      rho += smom[hf ^ 1][0][ci];
-      jx += smom[hf ^ 1][1][ci];
-      jy += smom[hf ^ 1][2][ci];
-      jz += smom[hf ^ 1][3][ci];
+      rho = smom[0][0][ci];
+      jx = smom[0][1][ci];
+      jy = smom[0][2][ci];
+      jz = smom[0][3][ci];
+#pragma unroll
+      for (int h = 1; h < Tr::NHW; ++h) {
+        rho += smom[h][0][ci];
+        jx += smom[h][1][ci];
+        jy += smom[h][2][ci];
+        jz += smom[h][3][ci];
+      }
     }
     // equilibrium factors in FP64 (no rounding bias in the equilibrium's mass
     // and momentum), kept in the compute precision
