@@ -851,6 +851,12 @@ def main():
         closure.install(s, net)
     s.set_mask(w["mask"])
     s.init(w["rho"], w["u"], w["T"])
+    if cfg["dim"] == 3 and cfg["n_high"]:
+        # the two sets' column walks on two streams (steps whose launches are
+        # timed one by one excepted): each fills the other's last round of
+        # columns (1.3 % per step on the 256^3 run; in 2D the step graphs
+        # with parallel branches measured slower)
+        s.set_graph(2)
     # per-launch HIP events on about every fifth timed step (every step of a
     # run of up to 5 steps); the events cost the stream a few microseconds
     ms, prof = timed_steps(s, steps, args.warmup, every=profile_every(steps) if steps > 100 else

@@ -190,7 +190,10 @@ int msl_step(msl_ctx *ctx, int nsteps);
  * population buffers is captured (host and device memory for the instantiated
  * graph, held until msl_destroy or a mode change) and replayed on the
  * context's stream.  mode 2: as 1, with the two sets' stream-collide launches
- * on parallel branches of the graph.  Criterion passes, steps that
+ * on parallel branches of the graph; in contexts that run no graphs (3D, the
+ * learned closure, a conservation check) the two launches of each step still
+ * run on two streams, forked and joined by events (a second stream and two
+ * events, created once, held until msl_destroy).  Criterion passes, steps that
  * msl_profile times and the rest of a call shorter than a block run launch by
  * launch.  A context whose high-order set runs over a compact tile list (large
  * grids, where the host reads the list length) turns to mode 0 at its first

@@ -896,13 +896,19 @@ static void graph_release(msl_ctx *c) {
 // the context's host state (buffer parity, step counter) is left unchanged.
 // A step that cannot be captured (a launch over a compact tile list, whose
 // length the host reads) switches the graphs off for this context.
-static int graph_capture(msl_ctx *c) {
+// the second stream and the fork / join events of the parallel branches
+static int fork_streams(msl_ctx *c) {
   if (!c->gs[0]) {
     for (int k = 0; k < 2; ++k) {
       MSL_HIP(hipStreamCreateWithFlags(&c->gs[k], hipStreamNonBlocking));
       MSL_HIP(hipEventCreateWithFlags(&c->gev[k], hipEventDisableTiming));
     }
   }
+  return MSL_OK;
+}
+
+static int graph_capture(msl_ctx *c) {
+  if (int rc = fork_streams(c)) return rc;
   const int cur0 = c->cur;
   const long step0 = c->step;
   hipStream_t s0 = c->stream;
@@ -988,7 +994,12 @@ int msl_step(msl_ctx *c, int nsteps) {
         continue;
       }
     }
-    if ((rc = plain_step(c, false))) return rc;
+    // mode 2 outside graphs (3D, learned closure): the two stream-collide
+    // launches on parallel branches as well, except in the steps whose
+    // launches are timed one by one (msl_profile)
+    const bool fork = c->gmode == 2 && c->nlat > 1 && !prof_on(c);
+    if (fork && (rc = fork_streams(c))) return rc;
+    if ((rc = plain_step(c, fork))) return rc;
     ++s;
     if (c->cfg.check_every > 0 && c->step % c->cfg.check_every == 0) {
       double out[5];
