@@ -177,18 +177,25 @@ def test_graph_modes_bit_identical():
     assert states[2] == states[0], "graph mode 2 differs from launch-by-launch stepping"
 
 
-def test_parallel_branches_3d_bit_identical():
+@pytest.mark.parametrize("lift", [inputs.LIFT_GRAD, inputs.LIFT_MLP])
+def test_parallel_branches_3d_bit_identical(lift):
     """3D two-set context (D3Q27 + D3Q64, FP16 deviations, the column walks):
     with mode 2 the two stream-collide launches of each untimed step run on
-    two streams; the state after calls of uneven length, with sampled timing
-    and criterion passes, matches launch-by-launch stepping byte for byte."""
-    from paper_2102_12559_amd import msl
+    two streams (Grad lift, and the learned closure with a random network);
+    the state after calls of uneven length, with sampled timing and criterion
+    passes, matches launch-by-launch stepping byte for byte."""
+    from paper_2102_12559_amd import closure, msl
     w = inputs.vortex_shear_3d(n=32, rc=4.0, store=inputs.STORE_FP16_DEV)
-    cfg = dict(w["cfg"], crit_every=5, lift_mode=inputs.LIFT_GRAD)
+    cfg = dict(w["cfg"], crit_every=5, lift_mode=lift)
     states = []
     for mode in (0, 2):
-        say(f"[case] parallel branches 3D mode {mode}: 32^3 fp16, calls of 7, 13, 1, 9 steps")
+        say(f"[case] parallel branches 3D mode {mode} lift {lift}: 32^3 fp16, calls of 7, 13, 1, 9 steps")
         s = msl.Solver(cfg)
+        if lift == inputs.LIFT_MLP:
+            F, Od, H, P = s.mlp_dims()
+            p = (closure.init_params(F, H, Od, seed=3) * 0.3).astype(np.float32)
+            s.mlp_set_weights(p, np.zeros(F, np.float32), np.ones(F, np.float32),
+                              np.zeros(Od, np.float32), np.full(Od, 1e-3, np.float32))
         s.set_graph(mode)
         s.set_mask(w["mask"])
         s.init(w["rho"], w["u"], w["T"])
